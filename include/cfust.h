@@ -1,0 +1,168 @@
+/*
+ * cfust.h -- C ABI of the MI355X (gfx950) CFUST mixture E-step / M-step library.
+ *
+ * The model is the finite mixture of canonical fundamental skew t (CFUST)
+ * distributions of Lee, Leemaqz & McLachlan, "A simple multithreaded
+ * implementation of the EM algorithm for mixture models":
+ *   component density  Sec. 2 eq. (4):
+ *     f_h(y) = 2^q t_p(y; mu, Omega, nu) T_q(c(y) sqrt((nu+p)/(nu+d(y))); 0, Lambda, nu+p),
+ *     Omega = Sigma + Delta Delta^T, c(y) = Delta^T Omega^{-1}(y-mu),
+ *     Lambda = I_q - Delta^T Omega^{-1} Delta, d(y) = (y-mu)^T Omega^{-1}(y-mu);
+ *   E-step  Sec. 3.1 eqs. (7)-(17); M-step  Sec. 3.2 eqs. (18)-(22);
+ *   log-likelihood  Sec. 4.3 eq. (27).
+ * The q-variate t CDFs (T_q, and the T_{q-1}, T_{q-2} that the truncated-t
+ * moments of eqs. (16)-(17) need) are estimated by separation of variables on
+ * a randomly shifted rank-1 lattice whose generating vector and shifts the
+ * caller supplies (cfust_qmc).
+ *
+ * Conventions for every call:
+ *   - All array arguments are DEVICE pointers owned by the caller unless marked
+ *     "host".  Matrices are row-major FP64.  Per-(component, observation)
+ *     outputs use the structure-of-arrays layout [g][k][n].
+ *   - Calls are asynchronous on `stream` (a hipStream_t passed as void*; NULL
+ *     is the default stream).  They return synchronously only the result of
+ *     host-side argument checks; numeric failures found on the device are
+ *     reported through the optional int32 status words (see cfust_status).
+ *   - No call throws.  The handle owns a workspace that grows on demand;
+ *     cfust_reserve() sizes it up front so that later calls do not allocate.
+ *   - Results depend only on the inputs, (N, S, z, shifts) and the precision.
+ */
+#ifndef CFUST_H
+#define CFUST_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CFUST_MAX_P 16      /* data dimension p */
+#define CFUST_MAX_Q 8       /* skewing dimension q; also the largest T_m dimension */
+#define CFUST_MAX_G 64      /* mixture components */
+#define CFUST_LATTICE_DIM 7 /* lattice coordinates; an m-variate T_m uses the first m-1 */
+#define CFUST_MAX_SHIFTS 64
+
+typedef enum {
+    CFUST_OK = 0,
+    CFUST_EINVAL = -1,       /* bad dimensions, null pointer, unsupported size */
+    CFUST_ENOTSPD = -2,      /* Omega_h, Lambda_h, Sigma_h or sum tau e3 not positive definite */
+    CFUST_ENUMERIC = -3,     /* non-finite result */
+    CFUST_EDEVICE = -4,      /* HIP runtime error */
+    CFUST_ENOMEM = -5,       /* workspace allocation failed */
+    CFUST_EUNSUPPORTED = -6  /* device is not gfx950 */
+} cfust_status;
+
+/* Device status word bits (int32, written by the kernels; 0 = all good). */
+#define CFUST_DEV_NOTSPD_OMEGA   (1 << 0)
+#define CFUST_DEV_NOTSPD_LAMBDA  (1 << 1)
+#define CFUST_DEV_BADPARAM       (1 << 2)   /* nu <= 0, pi < 0, non-finite parameter */
+#define CFUST_DEV_NOTSPD_E3      (1 << 3)   /* M-step: sum tau e3 not SPD -> Delta_h kept */
+#define CFUST_DEV_NOTSPD_SIGMA   (1 << 4)   /* M-step: new Sigma_h not SPD -> theta_h kept */
+#define CFUST_DEV_FROZEN         (1 << 5)   /* M-step: n_h < p+1 -> theta_h kept */
+#define CFUST_DEV_NU_CLAMPED     (1 << 6)   /* M-step: nu root outside [1, 200] -> clamped */
+
+typedef struct cfust_ctx *cfust_handle;
+
+/* Create a handle bound to HIP device `device` (must be gfx950). */
+cfust_status cfust_create(cfust_handle *handle, int device);
+cfust_status cfust_destroy(cfust_handle handle);
+/* Text of the last host-side error on this handle (never NULL). */
+const char *cfust_last_error(cfust_handle handle);
+
+typedef struct {
+    int32_t n;   /* observations, n >= 0 */
+    int32_t p;   /* 1 <= p <= CFUST_MAX_P */
+    int32_t q;   /* 1 <= q <= CFUST_MAX_Q */
+    int32_t g;   /* 1 <= g <= CFUST_MAX_G */
+} cfust_dims;
+
+/* Psi = (pi, theta_1..theta_g), Sec. 2: device FP64, row-major.
+ * pi[g], mu[g][p], Sigma[g][p][p], Delta[g][p][q], nu[g]. */
+typedef struct {
+    const double *pi, *mu, *Sigma, *Delta, *nu;
+} cfust_params;
+
+typedef struct {
+    double *pi, *mu, *Sigma, *Delta, *nu;
+} cfust_params_out;
+
+enum { CFUST_FP64 = 0, CFUST_MIXED = 1 };
+
+/* Lattice rule.  Point k (0 <= k < N) of shift s in coordinate j is
+ *   t = frac(k z[j] / N + shifts[s][j]),  x = 1 - |2t - 1|  (clamped to [2^-24, 1-2^-24]).
+ * precision: CFUST_FP64 evaluates everything in FP64; CFUST_MIXED evaluates
+ * the lattice integrand in FP32 (per-shift FP32 sums, combined in FP64) and
+ * keeps the Cholesky factors, log-densities, log-sum-exp and M-step in FP64. */
+typedef struct {
+    int32_t N;               /* 2 <= N <= 65536 points per shift */
+    int32_t S;               /* 1 <= S <= CFUST_MAX_SHIFTS shifts */
+    const int32_t *z;        /* device [CFUST_LATTICE_DIM], 0 < z[j] < N */
+    const double *shifts;    /* device [S][CFUST_LATTICE_DIM], each in [0,1) */
+    int32_t precision;       /* CFUST_FP64 or CFUST_MIXED */
+} cfust_qmc;
+
+/* E-step outputs.  w, e1, e2, e3 are double* when precision == CFUST_FP64
+ * and float* when CFUST_MIXED.  e3 holds the packed upper triangle (i <= k,
+ * row-major order) of the symmetric q x q matrix. */
+typedef struct {
+    double *tau;         /* [g][n]  posterior membership, eq. (12) */
+    double *logf_obs;    /* [n]     log f(y_j; Psi), the summands of eq. (27) */
+    double *loglik;      /* [1]     log-likelihood, eq. (27) */
+    void *w;             /* [g][n]      eq. (13) */
+    void *e1;            /* [g][n]      eq. (15) */
+    void *e2;            /* [g][q][n]   eq. (16) */
+    void *e3;            /* [g][q(q+1)/2][n] eq. (17) */
+    double *logf_comp;   /* optional [g][n]: log f_h(y_j), eq. (4) */
+    double *cdf_stderr;  /* optional [g][n]: lattice standard error of the T_q of eq. (4) */
+    int32_t *status;     /* optional [1]: device status bits, OR-ed in */
+} cfust_estep_out;
+
+/* E-step, Sec. 3.1: for every (component h, observation j) the CFUST
+ * log-density (eq. 4), tau (eq. 12), w (eq. 13, with "nu d" read as nu + d),
+ * e1 (eq. 15, one-step-late form as printed), e2, e3 (eqs. 16-17, moments of
+ * the truncated t of Sec. 3.1), and the log-likelihood (eq. 27).
+ * y: device FP64 [p][n] (feature-major).  Components whose log-density is
+ * -inf get tau = 0 and zero e-terms. */
+cfust_status cfust_estep(cfust_handle handle, const double *y, cfust_dims dims,
+                         const cfust_params *params, const cfust_qmc *qmc,
+                         const cfust_estep_out *out, void *stream);
+
+/* M-step, Sec. 3.2 eqs. (18)-(22), in the order pi, mu (with Delta^(k)),
+ * Delta (with mu^(k+1)), Sigma (with both), nu.  Eq. (22) is solved with the
+ * last sum added ("+"), by 100 bisection steps on [1, 200] (clamped outside).
+ * `es` is the output of cfust_estep at the same dims/precision; `in` is
+ * Psi^(k) (only mu, Delta, Sigma, nu are read), `out` receives Psi^(k+1)
+ * (`out` may alias `in`).  A component with n_h < p+1, or whose update is not
+ * SPD, keeps theta_h and sets a status bit.  status: optional device int32[1]. */
+cfust_status cfust_mstep(cfust_handle handle, const double *y, cfust_dims dims,
+                         const cfust_estep_out *es, int32_t precision,
+                         const cfust_params *in, const cfust_params_out *out,
+                         int32_t *status, void *stream);
+
+/* Log-likelihood only (eq. 27): evaluates the density (4) of every pair and
+ * the log-sum-exp over components, without the moments.  logf_obs: optional
+ * device [n]; loglik: device [1]; status: optional device int32[1]. */
+cfust_status cfust_loglik(cfust_handle handle, const double *y, cfust_dims dims,
+                          const cfust_params *params, const cfust_qmc *qmc,
+                          double *loglik, double *logf_obs, int32_t *status, void *stream);
+
+/* Batch of multivariate t probabilities T_m(b; 0, L L^T, nu) (the T_q of
+ * Sec. 2 eq. 4), one per item.  1 <= m <= CFUST_MAX_Q.
+ * b: device [batch][m] upper limits; L: device [nmat][m][m] lower Cholesky
+ * factors; mat_idx: device int32 [batch] in [0, nmat); nu: device [batch] > 0.
+ * p: device [batch] estimates; logp (optional): log of the estimate computed
+ * without underflow of the first factor; stderr_ (optional): standard error
+ * over shifts (0 for m = 1). */
+cfust_status mvt_cdf_batch(cfust_handle handle, int32_t m, int32_t batch, const double *b,
+                           const double *L, const int32_t *mat_idx, int32_t nmat,
+                           const double *nu, const cfust_qmc *qmc,
+                           double *p, double *logp, double *stderr_, void *stream);
+
+/* Size the workspace for calls up to these dims and lattice sizes, so that
+ * later calls allocate nothing (e.g. under stream capture). */
+cfust_status cfust_reserve(cfust_handle handle, cfust_dims dims, const cfust_qmc *qmc);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CFUST_H */

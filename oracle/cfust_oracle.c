@@ -47,6 +47,7 @@
  * psi(x) ~ ln x - 1/(2x) - sum_k B_2k / (2k x^2k)  (DLMF 5.11.2). */
 double or_digamma(double x)
 {
+    if (!(x > 0.0) || isinf(x)) return NAN;   /* only positive arguments occur */
     double acc = 0.0;
     while (x < 10.0) { acc -= 1.0 / x; x += 1.0; }
     double r = 1.0 / (x * x);

@@ -1,0 +1,101 @@
+"""ctypes binding of libcfust.so (include/cfust.h).  Argument marshalling only:
+every step of the E-step / M-step runs in the library's HIP kernels.
+
+PyTorch is used for device memory and streams.  The library must be built
+(``python -m paper_1606_02054_amd.build``); importing this module without it
+raises, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcfust.so")
+
+CFUST_FP64 = 0
+CFUST_MIXED = 1
+LATTICE_DIM = 7
+MAX_P, MAX_Q, MAX_G, MAX_SHIFTS = 16, 8, 64, 64
+
+STATUS = {0: "CFUST_OK", -1: "CFUST_EINVAL", -2: "CFUST_ENOTSPD", -3: "CFUST_ENUMERIC",
+          -4: "CFUST_EDEVICE", -5: "CFUST_ENOMEM", -6: "CFUST_EUNSUPPORTED"}
+
+DEV_BITS = {1: "NOTSPD_OMEGA", 2: "NOTSPD_LAMBDA", 4: "BADPARAM", 8: "NOTSPD_E3",
+            16: "NOTSPD_SIGMA", 32: "FROZEN", 64: "NU_CLAMPED"}
+
+EXPORTS = ["cfust_create", "cfust_destroy", "cfust_last_error", "cfust_estep", "cfust_mstep",
+           "cfust_loglik", "mvt_cdf_batch", "cfust_reserve"]
+
+
+class Dims(C.Structure):
+    _fields_ = [("n", C.c_int32), ("p", C.c_int32), ("q", C.c_int32), ("g", C.c_int32)]
+
+
+class ParamsC(C.Structure):
+    _fields_ = [("pi", C.c_void_p), ("mu", C.c_void_p), ("Sigma", C.c_void_p),
+                ("Delta", C.c_void_p), ("nu", C.c_void_p)]
+
+
+class QmcC(C.Structure):
+    _fields_ = [("N", C.c_int32), ("S", C.c_int32), ("z", C.c_void_p), ("shifts", C.c_void_p),
+                ("precision", C.c_int32)]
+
+
+class EstepOutC(C.Structure):
+    _fields_ = [("tau", C.c_void_p), ("logf_obs", C.c_void_p), ("loglik", C.c_void_p),
+                ("w", C.c_void_p), ("e1", C.c_void_p), ("e2", C.c_void_p), ("e3", C.c_void_p),
+                ("logf_comp", C.c_void_p), ("cdf_stderr", C.c_void_p), ("status", C.c_void_p)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libcfust.so and declare the C signatures.  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libcfust.so not found at {path}: build it with "
+                           "`python -m paper_1606_02054_amd.build` (no CPU fallback exists)")
+    lib = C.CDLL(path)
+    vp, i32 = C.c_void_p, C.c_int32
+    lib.cfust_create.restype = C.c_int; lib.cfust_create.argtypes = [C.POINTER(vp), C.c_int]
+    lib.cfust_destroy.restype = C.c_int; lib.cfust_destroy.argtypes = [vp]
+    lib.cfust_last_error.restype = C.c_char_p; lib.cfust_last_error.argtypes = [vp]
+    lib.cfust_estep.restype = C.c_int
+    lib.cfust_estep.argtypes = [vp, vp, Dims, C.POINTER(ParamsC), C.POINTER(QmcC), C.POINTER(EstepOutC), vp]
+    lib.cfust_mstep.restype = C.c_int
+    lib.cfust_mstep.argtypes = [vp, vp, Dims, C.POINTER(EstepOutC), i32, C.POINTER(ParamsC),
+                                C.POINTER(ParamsC), vp, vp]
+    lib.cfust_loglik.restype = C.c_int
+    lib.cfust_loglik.argtypes = [vp, vp, Dims, C.POINTER(ParamsC), C.POINTER(QmcC), vp, vp, vp, vp]
+    lib.mvt_cdf_batch.restype = C.c_int
+    lib.mvt_cdf_batch.argtypes = [vp, i32, i32, vp, vp, vp, i32, vp, C.POINTER(QmcC), vp, vp, vp, vp]
+    lib.cfust_reserve.restype = C.c_int
+    lib.cfust_reserve.argtypes = [vp, Dims, C.POINTER(QmcC)]
+    _lib = lib
+    return lib
+
+
+def exported_symbols(path: str = LIB_PATH):
+    """Names of the C-ABI entry points that resolve in the library (no GPU needed)."""
+    lib = C.CDLL(path)
+    found = []
+    for name in EXPORTS:
+        try:
+            getattr(lib, name)
+            found.append(name)
+        except AttributeError:
+            pass
+    return found
+
+
+def check(status: int, handle=None, what: str = "") -> None:
+    if status != 0:
+        msg = ""
+        if handle is not None and _lib is not None:
+            m = _lib.cfust_last_error(handle)
+            msg = m.decode() if m else ""
+        raise RuntimeError(f"{what}: {STATUS.get(status, status)} {msg}")

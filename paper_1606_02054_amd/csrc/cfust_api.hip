@@ -1,0 +1,328 @@
+// cfust_api.hip -- host side of the C ABI declared in include/cfust.h:
+// argument checks, workspace, and the launch sequence of each call.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "cfust_kernels.h"
+
+struct cfust_ctx {
+    int device = 0;
+    std::string err;
+    void *ws = nullptr;
+    size_t ws_size = 0;
+};
+
+namespace {
+
+using namespace cfust;
+
+cfust_status fail(cfust_handle h, cfust_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (h) h->err = buf;
+    return st;
+}
+
+cfust_status hip_check(cfust_handle h, hipError_t e, const char *what) {
+    if (e == hipSuccess) return CFUST_OK;
+    return fail(h, CFUST_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Bump allocator over the handle's workspace.
+struct Carve {
+    size_t off = 0;
+    template <class T> size_t take(size_t count) {
+        const size_t o = off;
+        off = align256(off + count * sizeof(T));
+        return o;
+    }
+};
+
+cfust_status ensure_ws(cfust_handle h, size_t bytes) {
+    if (bytes <= h->ws_size) return CFUST_OK;
+    if (h->ws) {
+        hipError_t e = hipFree(h->ws);   // synchronises the device
+        h->ws = nullptr;
+        h->ws_size = 0;
+        if (e != hipSuccess) return hip_check(h, e, "hipFree(workspace)");
+    }
+    const size_t sz = align256(bytes + bytes / 4);
+    if (hipMalloc(&h->ws, sz) != hipSuccess) {
+        h->ws = nullptr;
+        return fail(h, CFUST_ENOMEM, "workspace allocation of %zu bytes failed", sz);
+    }
+    h->ws_size = sz;
+    return CFUST_OK;
+}
+
+template <class T> T *at(cfust_handle h, size_t off) { return (T *)((char *)h->ws + off); }
+
+cfust_status check_dims(cfust_handle h, const cfust_dims &d) {
+    if (d.n < 0) return fail(h, CFUST_EINVAL, "n = %d < 0", d.n);
+    if (d.p < 1 || d.p > MAXP) return fail(h, CFUST_EINVAL, "p = %d outside [1, %d]", d.p, MAXP);
+    if (d.q < 1 || d.q > MAXQ) return fail(h, CFUST_EINVAL, "q = %d outside [1, %d]", d.q, MAXQ);
+    if (d.g < 1 || d.g > MAXG) return fail(h, CFUST_EINVAL, "g = %d outside [1, %d]", d.g, MAXG);
+    return CFUST_OK;
+}
+
+int ilog2_exact(int N) {
+    if (N <= 0 || (N & (N - 1))) return -1;
+    int k = 0;
+    while ((1 << k) < N) ++k;
+    return k;
+}
+
+cfust_status check_qmc(cfust_handle h, const cfust_qmc *Q, bool lattice_needed) {
+    if (!Q) return fail(h, CFUST_EINVAL, "qmc is NULL");
+    if (Q->precision != CFUST_FP64 && Q->precision != CFUST_MIXED)
+        return fail(h, CFUST_EINVAL, "precision %d is neither CFUST_FP64 nor CFUST_MIXED", Q->precision);
+    if (!lattice_needed) return CFUST_OK;
+    if (Q->N < 2 || Q->N > 65536) return fail(h, CFUST_EINVAL, "lattice size N = %d outside [2, 65536]", Q->N);
+    if (Q->S < 1 || Q->S > MAXS) return fail(h, CFUST_EINVAL, "shift count S = %d outside [1, %d]", Q->S, MAXS);
+    if (!Q->z || !Q->shifts) return fail(h, CFUST_EINVAL, "lattice vector or shifts are NULL");
+    if (Q->precision == CFUST_MIXED && ilog2_exact(Q->N) < 0)
+        return fail(h, CFUST_EINVAL, "mixed precision needs N a power of two (N = %d)", Q->N);
+    return CFUST_OK;
+}
+
+LatticeArgs lattice_of(const cfust_qmc *Q) {
+    LatticeArgs L;
+    L.N = Q->N;
+    L.S = Q->S;
+    L.log2N = ilog2_exact(Q->N);
+    L.z = Q->z;
+    L.shifts = Q->shifts;
+    return L;
+}
+
+cfust_status check_params(cfust_handle h, const cfust_params *P) {
+    if (!P || !P->pi || !P->mu || !P->Sigma || !P->Delta || !P->nu)
+        return fail(h, CFUST_EINVAL, "a parameter array is NULL");
+    return CFUST_OK;
+}
+
+// Workspace layout of an E-step (or log-likelihood) call.
+struct EstepWs {
+    size_t pre, tabs, est, lnA, flag, logf, partial, total;
+};
+
+EstepWs estep_layout(const cfust_dims &d, int J, bool own_logf) {
+    Carve c;
+    EstepWs w;
+    w.pre = c.take<CompPre>(d.g);
+    w.tabs = c.take<float>((size_t)d.g * NDOF * TAB_FLOATS);
+    w.est = c.take<double>((size_t)d.g * (J > 0 ? J : 1) * (d.n > 0 ? d.n : 1));
+    w.lnA = c.take<double>((size_t)d.g * (d.n > 0 ? d.n : 1));
+    w.flag = c.take<int32_t>((size_t)d.g * (J > 0 ? J : 1) * (d.n > 0 ? d.n : 1));
+    w.logf = c.take<double>(own_logf ? (size_t)d.g * (d.n > 0 ? d.n : 1) : 1);
+    w.partial = c.take<double>((size_t)(d.n + 255) / 256 + 1);
+    w.total = c.off;
+    return w;
+}
+
+int mstep_nblk(const cfust_dims &d) {
+    const int ntiles = (d.n + 63) / 64;
+    int nb = (ntiles + 3) / 4;
+    if (nb < 1) nb = 1;
+    if (nb > 256) nb = 256;
+    return nb;
+}
+
+size_t mstep_bytes(const cfust_dims &d) {
+    return align256((size_t)d.g * mstep_nblk(d) * nstat(d.p, d.q) * sizeof(double) + (size_t)d.g * sizeof(int32_t));
+}
+
+// Shared launch sequence of cfust_estep / cfust_loglik.
+cfust_status run_estep(cfust_handle h, const double *y, const cfust_dims &d, const cfust_params *P,
+                       const cfust_qmc *Q, bool density_only, double *tau, double *logf_obs, double *loglik,
+                       void *w, void *e1, void *e2, void *e3, double *logf_comp, double *se,
+                       int32_t *status, hipStream_t s) {
+    cfust_status st;
+    if ((st = check_dims(h, d)) != CFUST_OK) return st;
+    if ((st = check_params(h, P)) != CFUST_OK) return st;
+    const bool lattice = d.q >= 2;
+    if ((st = check_qmc(h, Q, lattice)) != CFUST_OK) return st;
+    if (d.n > 0 && !y) return fail(h, CFUST_EINVAL, "y is NULL");
+    if (!loglik) return fail(h, CFUST_EINVAL, "loglik is NULL");
+    if (!density_only && d.n > 0 && (!tau || !w || !e1 || !e2 || !e3))
+        return fail(h, CFUST_EINVAL, "an E-step output array is NULL");
+    const bool mixed = Q->precision == CFUST_MIXED;
+    const int J = density_only ? (lattice ? 1 : 0) : nint_qmc(d.q);
+    const EstepWs L = estep_layout(d, J, logf_comp == nullptr);
+    if ((st = ensure_ws(h, L.total)) != CFUST_OK) return st;
+    if ((st = hip_check(h, hipSetDevice(h->device), "hipSetDevice")) != CFUST_OK) return st;
+    CompPre *pre = at<CompPre>(h, L.pre);
+    double *lfc = logf_comp ? logf_comp : at<double>(h, L.logf);
+    hipError_t e = launch_precompute(*P, d.p, d.q, d.g, pre, s);
+    if (e == hipSuccess && mixed && J > 0) e = launch_tables(pre, d.p, d.g, d.q + 2, at<float>(h, L.tabs), s);
+    if (e == hipSuccess && J > 0) {
+        EstepQmcArgs a;
+        a.y = y; a.mu = P->mu; a.pre = pre; a.tabs = at<float>(h, L.tabs);
+        a.lat = lattice_of(Q);
+        a.n = d.n; a.p = d.p; a.q = d.q; a.g = d.g; a.J = J; a.mixed = mixed ? 1 : 0;
+        a.est = at<double>(h, L.est); a.lnA = at<double>(h, L.lnA); a.se = se;
+        a.flag = at<int32_t>(h, L.flag);
+        // integrals of equal dimension share a launch: (A, B) m = q, C_i m = q-1, D_ik m = q-2
+        a.idx0 = 0;
+        e = launch_estep_qmc(a, d.q, density_only ? 1 : 2, s);
+        if (e == hipSuccess && !density_only && d.q - 1 >= 2) {
+            a.idx0 = 2;
+            e = launch_estep_qmc(a, d.q - 1, d.q, s);
+        }
+        if (e == hipSuccess && !density_only && d.q - 2 >= 2) {
+            a.idx0 = 2 + d.q;
+            e = launch_estep_qmc(a, d.q - 2, npairs(d.q), s);
+        }
+    }
+    if (e == hipSuccess) {
+        EstepAsmArgs a;
+        a.y = y; a.mu = P->mu; a.pre = pre;
+        a.n = d.n; a.p = d.p; a.q = d.q; a.g = d.g; a.J = J > 0 ? J : 1;
+        a.mixed = mixed ? 1 : 0; a.density_only = density_only ? 1 : 0;
+        a.est = at<double>(h, L.est); a.lnA = at<double>(h, L.lnA);
+        a.logf_comp = lfc;
+        a.w = w; a.e1 = e1; a.e2 = e2; a.e3 = e3;
+        e = launch_assemble(a, s);
+    }
+    if (e == hipSuccess) {
+        EstepLseArgs a;
+        a.pi = P->pi; a.logf_comp = lfc;
+        a.n = d.n; a.g = d.g; a.q = d.q; a.mixed = mixed ? 1 : 0;
+        a.tau = density_only ? nullptr : tau;
+        a.logf_obs = logf_obs;
+        a.w = density_only ? nullptr : w; a.e1 = e1; a.e2 = e2; a.e3 = e3;
+        a.partial = at<double>(h, L.partial);
+        e = launch_lse(a, loglik, s);
+    }
+    if (e == hipSuccess && status) e = launch_status_fold(pre, d.g, status, s);
+    return hip_check(h, e, density_only ? "cfust_loglik launch" : "cfust_estep launch");
+}
+
+}  // namespace
+
+extern "C" {
+
+cfust_status cfust_create(cfust_handle *handle, int device) {
+    if (!handle) return CFUST_EINVAL;
+    *handle = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return CFUST_EDEVICE;
+    if (device < 0 || device >= ndev) return CFUST_EINVAL;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return CFUST_EDEVICE;
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return CFUST_EUNSUPPORTED;
+    cfust_ctx *c = new (std::nothrow) cfust_ctx;
+    if (!c) return CFUST_ENOMEM;
+    c->device = device;
+    *handle = c;
+    return CFUST_OK;
+}
+
+cfust_status cfust_destroy(cfust_handle h) {
+    if (!h) return CFUST_EINVAL;
+    if (h->ws) {
+        hipSetDevice(h->device);
+        hipFree(h->ws);
+    }
+    delete h;
+    return CFUST_OK;
+}
+
+const char *cfust_last_error(cfust_handle h) {
+    return h ? h->err.c_str() : "null handle";
+}
+
+cfust_status cfust_estep(cfust_handle h, const double *y, cfust_dims dims, const cfust_params *params,
+                         const cfust_qmc *qmc, const cfust_estep_out *out, void *stream) {
+    if (!h) return CFUST_EINVAL;
+    if (!out) return fail(h, CFUST_EINVAL, "out is NULL");
+    return run_estep(h, y, dims, params, qmc, false, out->tau, out->logf_obs, out->loglik, out->w, out->e1,
+                     out->e2, out->e3, out->logf_comp, out->cdf_stderr, out->status, (hipStream_t)stream);
+}
+
+cfust_status cfust_loglik(cfust_handle h, const double *y, cfust_dims dims, const cfust_params *params,
+                          const cfust_qmc *qmc, double *loglik, double *logf_obs, int32_t *status,
+                          void *stream) {
+    if (!h) return CFUST_EINVAL;
+    return run_estep(h, y, dims, params, qmc, true, nullptr, logf_obs, loglik, nullptr, nullptr, nullptr,
+                     nullptr, nullptr, nullptr, status, (hipStream_t)stream);
+}
+
+cfust_status cfust_mstep(cfust_handle h, const double *y, cfust_dims d, const cfust_estep_out *es,
+                         int32_t precision, const cfust_params *in, const cfust_params_out *out,
+                         int32_t *status, void *stream) {
+    if (!h) return CFUST_EINVAL;
+    cfust_status st;
+    if ((st = check_dims(h, d)) != CFUST_OK) return st;
+    if ((st = check_params(h, in)) != CFUST_OK) return st;
+    if (!out || !out->pi || !out->mu || !out->Sigma || !out->Delta || !out->nu)
+        return fail(h, CFUST_EINVAL, "an output parameter array is NULL");
+    if (precision != CFUST_FP64 && precision != CFUST_MIXED)
+        return fail(h, CFUST_EINVAL, "precision %d is neither CFUST_FP64 nor CFUST_MIXED", precision);
+    if (d.n > 0 && (!y || !es || !es->tau || !es->w || !es->e1 || !es->e2 || !es->e3))
+        return fail(h, CFUST_EINVAL, "y or an E-step array is NULL");
+    const int nblk = mstep_nblk(d);
+    if ((st = ensure_ws(h, mstep_bytes(d))) != CFUST_OK) return st;
+    if ((st = hip_check(h, hipSetDevice(h->device), "hipSetDevice")) != CFUST_OK) return st;
+    MstepArgs r;
+    r.y = y; r.tau = es ? es->tau : nullptr;
+    r.w = es ? es->w : nullptr; r.e1 = es ? es->e1 : nullptr;
+    r.e2 = es ? es->e2 : nullptr; r.e3 = es ? es->e3 : nullptr;
+    r.mu0 = in->mu;
+    r.n = d.n; r.p = d.p; r.q = d.q; r.g = d.g; r.mixed = precision == CFUST_MIXED;
+    r.nblk = nblk;
+    r.partial = at<double>(h, 0);
+    MsolveArgs sv;
+    sv.partial = r.partial;
+    sv.n = d.n; sv.p = d.p; sv.q = d.q; sv.g = d.g; sv.nblk = nblk;
+    sv.mu0 = in->mu; sv.Sigma0 = in->Sigma; sv.Delta0 = in->Delta; sv.nu0 = in->nu;
+    sv.pi1 = out->pi; sv.mu1 = out->mu; sv.Sigma1 = out->Sigma; sv.Delta1 = out->Delta; sv.nu1 = out->nu;
+    sv.status = status;
+    return hip_check(h, launch_mstep(r, sv, (hipStream_t)stream), "cfust_mstep launch");
+}
+
+cfust_status mvt_cdf_batch(cfust_handle h, int32_t m, int32_t batch, const double *b, const double *L,
+                           const int32_t *mat_idx, int32_t nmat, const double *nu, const cfust_qmc *qmc,
+                           double *p, double *logp, double *stderr_, void *stream) {
+    if (!h) return CFUST_EINVAL;
+    if (m < 1 || m > MAXQ) return fail(h, CFUST_EINVAL, "m = %d outside [1, %d]", m, MAXQ);
+    if (batch < 0) return fail(h, CFUST_EINVAL, "batch = %d < 0", batch);
+    if (nmat < 1) return fail(h, CFUST_EINVAL, "nmat = %d < 1", nmat);
+    cfust_status st;
+    if ((st = check_qmc(h, qmc, m >= 2)) != CFUST_OK) return st;
+    if (batch > 0 && (!b || !L || !mat_idx || !nu || !p))
+        return fail(h, CFUST_EINVAL, "an mvt_cdf_batch array is NULL");
+    const bool mixed = qmc->precision == CFUST_MIXED;
+    if ((st = ensure_ws(h, align256((size_t)(batch > 0 ? batch : 1) * sizeof(int32_t)))) != CFUST_OK) return st;
+    if ((st = hip_check(h, hipSetDevice(h->device), "hipSetDevice")) != CFUST_OK) return st;
+    MvtArgs a;
+    a.m = m; a.batch = batch; a.mixed = mixed ? 1 : 0; a.nmat = nmat;
+    a.b = b; a.L = L; a.nu = nu; a.mat_idx = mat_idx;
+    a.lat = lattice_of(qmc);
+    a.p = p; a.logp = logp; a.se = stderr_;
+    a.flag = at<int32_t>(h, 0);
+    return hip_check(h, launch_mvt(a, (hipStream_t)stream), "mvt_cdf_batch launch");
+}
+
+cfust_status cfust_reserve(cfust_handle h, cfust_dims d, const cfust_qmc *qmc) {
+    if (!h) return CFUST_EINVAL;
+    cfust_status st;
+    if ((st = check_dims(h, d)) != CFUST_OK) return st;
+    (void)qmc;
+    size_t need = estep_layout(d, nint_qmc(d.q), true).total;
+    const size_t ms = mstep_bytes(d);
+    if (ms > need) need = ms;
+    if ((st = hip_check(h, hipSetDevice(h->device), "hipSetDevice")) != CFUST_OK) return st;
+    return ensure_ws(h, need);
+}
+
+}  // extern "C"

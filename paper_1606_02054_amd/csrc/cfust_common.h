@@ -1,0 +1,97 @@
+// cfust_common.h -- layouts shared by the HIP kernels and the host side of the
+// library (private; the public boundary is include/cfust.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/cfust.h"
+
+namespace cfust {
+
+constexpr int MAXP = CFUST_MAX_P;
+constexpr int MAXQ = CFUST_MAX_Q;
+constexpr int MAXG = CFUST_MAX_G;
+constexpr int LATD = CFUST_LATTICE_DIM;
+constexpr int MAXS = CFUST_MAX_SHIFTS;
+constexpr int MAXPAIR = MAXQ * (MAXQ - 1) / 2;
+constexpr int MAXJ = 2 + MAXQ + MAXPAIR;          // integrals per (obs, comp)
+constexpr int NDOF = MAXQ + 2;                    // dofs nu+p .. nu+p+q+1 per component
+
+// FP32 piecewise-polynomial tables of the univariate t law for one dof:
+//   rows 0..7  : lower-tail CDF, F(tau) = log2 T_lower(tau) - a log2(tau) on
+//                8 equal intervals of tau = 1 - |s| in [0,1], s = u / sqrt(nu+u^2);
+//   rows 8..18 : quantile, log2 tau as a function of lambda = -log2(2p) on the
+//                11 intervals [c(2^k - 1), c(2^{k+1} - 1)], c = 1/4.
+// Each row holds 7 monomial coefficients in x in [-1,1] (x = 2t - 1, t the
+// position inside the interval) plus one pad float.
+constexpr int TAB_CDF_ROWS = 8;
+constexpr int TAB_INV_ROWS = 11;
+constexpr int TAB_ROWS = 20;                      // 8 + 11 + 1 pad row
+constexpr int TAB_FLOATS = TAB_ROWS * 8;          // 160 floats per dof
+constexpr float INV_LAMBDA_MAX = 511.0f;
+
+// Per-component quantities that every observation shares (Sec. 2 eq. 4 and the
+// conditional pieces of the truncated-t moments).  FP64 unless noted.
+struct CompPre {
+    double nu;          // nu_h
+    double ltp_const;   // lgamma((nu+p)/2) - lgamma(nu/2) - p/2 log(pi nu) - 1/2 log|Omega|
+    double digam;       // psi((nu+p)/2)
+    double lt1_s;       // log of t_1 normaliser for dof nu+p+2: lgamma((v+1)/2)-lgamma(v/2)-1/2 log(pi v)
+    double lt1_s1;      // same for dof nu+p+1
+    double LO[MAXP * MAXP];          // chol Omega (lower)
+    double B[MAXP * MAXQ];           // Omega^{-1} Delta, [p][q]
+    double Lam[MAXQ * MAXQ];         // Lambda
+    double LL[MAXQ * MAXQ];          // chol Lambda
+    double LC[MAXQ][(MAXQ - 1) * (MAXQ - 1)];   // chol Lambda_{-i|i}
+    double LD[MAXPAIR][(MAXQ - 2) * (MAXQ - 2)];// chol Lambda_{-ik|ik}
+    double RD[MAXPAIR][(MAXQ - 2) * 2];         // Lambda_{-ik,ik} Lambda_{ik,ik}^{-1}
+    double ID[MAXPAIR][3];                      // Lambda_{ik,ik}^{-1}: (00, 01, 11)
+    float LLf[MAXQ * MAXQ];                     // FP32 copies for the lattice kernel
+    float LCf[MAXQ][(MAXQ - 1) * (MAXQ - 1)];
+    float LDf[MAXPAIR][(MAXQ - 2) * (MAXQ - 2)];
+    int32_t status;
+    int32_t pad;
+};
+
+// Integral list of one (observation, component) pair: 0 = A (density CDF,
+// dim q, dof nu+p), 1 = B (w numerator, dim q, dof nu+p+2), 2..q+1 = C_i
+// (dim q-1, dof nu+p+1), then D_ik for i<k (dim q-2, dof nu+p).
+enum IntType : int { INT_A = 0, INT_B = 1, INT_C = 2, INT_D = 3 };
+
+struct IntDesc {
+    int type, i, k, pair, m, dofoff;
+};
+
+__host__ __device__ inline int npairs(int q) { return q * (q - 1) / 2; }
+__host__ __device__ inline int nint_all(int q) { return 2 + q + npairs(q); }
+
+__host__ __device__ inline IntDesc int_desc(int q, int idx) {
+    IntDesc d{0, 0, 0, 0, 0, 0};
+    if (idx == 0) { d.type = INT_A; d.m = q; d.dofoff = 0; return d; }
+    if (idx == 1) { d.type = INT_B; d.m = q; d.dofoff = 2; return d; }
+    if (idx < 2 + q) { d.type = INT_C; d.i = idx - 2; d.m = q - 1; d.dofoff = 1; return d; }
+    int pr = idx - 2 - q;
+    d.type = INT_D; d.pair = pr; d.m = q - 2; d.dofoff = 0;
+    int i = 0, r = pr;
+    while (r >= q - 1 - i) { r -= q - 1 - i; ++i; }
+    d.i = i; d.k = i + 1 + r;
+    return d;
+}
+
+// Integrals estimated on the lattice are those of dimension >= 2; they are the
+// first nint_qmc(q) entries of the list above restricted to m >= 2, which is
+// a prefix in the order A, B, C, D because m decreases along the list.
+__host__ __device__ inline int nint_qmc(int q) {
+    int J = 0;
+    if (q >= 2) J += 2;
+    if (q >= 3) J += q;
+    if (q >= 4) J += npairs(q);
+    return J;
+}
+
+// Number of M-step sufficient statistics per component.
+__host__ __device__ inline int nstat(int p, int q) {
+    return 3 + p + q + p * (p + 1) / 2 + p * q + q * (q + 1) / 2;
+}
+
+}  // namespace cfust

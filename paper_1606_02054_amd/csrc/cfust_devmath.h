@@ -1,0 +1,182 @@
+// cfust_devmath.h -- device special functions for the univariate Student t law
+// with real degrees of freedom, in the variables the lattice integrand uses.
+//
+// For u real and dof nu, write s = u / sqrt(nu + u^2) in (-1,1) and
+// tau = 1 - |s| in (0,1].  The smaller of T_nu(u) and 1 - T_nu(u) is
+//     T_lower(tau) = 1/2 I_z(nu/2, 1/2),   z = 1 - s^2 = tau (2 - tau),
+// with I the regularised incomplete beta function.  Working in tau keeps
+// both tails to full relative accuracy.
+//
+// FP64 routines (used by the FP64 mode and to build the FP32 tables):
+//   - I_z(a, b) by the continued fraction of DLMF 8.17.22 evaluated with the
+//     modified Lentz method, switching to I_z(a,b) = 1 - I_{1-z}(b,a) where
+//     the fraction converges slowly;
+//   - the quantile by Newton's method on ln T_lower as a function of ln tau
+//     (nearly linear in ln tau in the far tail), kept inside a bracket;
+//   - digamma by upward recurrence and its asymptotic Bernoulli series
+//     (DLMF 5.11.2); lgamma is the device math library's.
+// FP32 routines evaluate per-dof piecewise Chebyshev tables of
+//   F(tau) = log2 T_lower(tau) - (nu/2) log2 tau     (smooth on [0,1]) and
+//   G(lam) = log2 tau(p),  lam = -log2(2p)            (smooth on [0, inf)),
+// built on the device from the FP64 routines.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "cfust_common.h"
+
+namespace cfust {
+
+constexpr double LN2 = 0.69314718055994530942;
+constexpr double LNSQRTPI = 0.57236494292470008707;  // ln sqrt(pi) = lgamma(1/2)
+
+// ---------------------------------------------------------------- FP64 ------
+
+__device__ inline double dm_digamma(double x) {
+    // psi(x) = psi(x + 1) - 1/x; psi(x) ~ ln x - 1/(2x) - sum_k B_2k/(2k x^2k)
+    if (!(x > 0.0) || !isfinite(x)) return NAN;   // only positive arguments occur
+    double shift = 0.0;
+    while (x < 9.0) { shift += 1.0 / x; x += 1.0; }
+    const double r = 1.0 / (x * x);
+    // B_2k / (2k) for k = 7..1, highest power first
+    const double c[7] = {7.0 / 6.0 / 14.0, -691.0 / 2730.0 / 12.0, 5.0 / 66.0 / 10.0,
+                         -1.0 / 30.0 / 8.0, 1.0 / 42.0 / 6.0, -1.0 / 30.0 / 4.0, 1.0 / 6.0 / 2.0};
+    double sr = c[0];
+    for (int k = 1; k < 7; ++k) sr = sr * r + c[k];
+    return log(x) - 0.5 / x - sr * r - shift;
+}
+
+// ln B(a, 1/2)
+__device__ inline double dm_lbeta_half(double a) {
+    return lgamma(a) + LNSQRTPI - lgamma(a + 0.5);
+}
+
+// Continued fraction K = 1 + d1/(1 + d2/(1 + ...)) of I_x(a,b), DLMF 8.17.22:
+// d_{2k+1} = -(a+k)(a+b+k)x/((a+2k)(a+2k+1)), d_{2k} = k(b-k)x/((a+2k-1)(a+2k)).
+__device__ inline double dm_beta_cf(double a, double b, double x) {
+    const double tiny = 1e-300;
+    double f = 1.0, Cc = 1.0, Dd = 0.0;
+    for (int j = 1; j < 2000; ++j) {
+        const int k = j >> 1;
+        const double d = (j & 1) ? -(a + k) * (a + b + k) * x / ((a + 2 * k) * (a + 2 * k + 1))
+                                 : k * (b - k) * x / ((a + 2 * k - 1) * (a + 2 * k));
+        Dd = 1.0 + d * Dd;
+        Dd = fabs(Dd) < tiny ? tiny : Dd;
+        Dd = 1.0 / Dd;
+        Cc = 1.0 + d / Cc;
+        Cc = fabs(Cc) < tiny ? tiny : Cc;
+        const double del = Cc * Dd;
+        f *= del;
+        if (fabs(del - 1.0) < 2e-16) break;
+    }
+    return f;
+}
+
+// ln T_lower given z = tau(2-tau) and zc = (1-tau)^2 = s^2; a = nu/2, lb = ln B(a,1/2).
+__device__ inline double dm_lnT_lower(double z, double zc, double a, double lb) {
+    if (!(z > 0.0)) return -INFINITY;
+    if (!(zc > 0.0)) return -LN2;
+    const double lz = log(z), lzc = log(zc);
+    if (z < (a + 1.0) / (a + 2.5)) {
+        return a * lz + 0.5 * lzc - log(a) - lb - log(dm_beta_cf(a, 0.5, z)) - LN2;
+    }
+    const double v = exp(0.5 * lzc + a * lz + LN2 - lb) / dm_beta_cf(0.5, a, zc);
+    return log1p(-v) - LN2;
+}
+
+// Quantile in the tau variable: tau in (0,1] with ln T_lower(tau) = lnq (lnq <= -ln 2).
+__device__ inline double dm_tau_of_lnq(double lnq, double a, double lb) {
+    if (!(lnq < -LN2)) return 1.0;
+    if (lnq == -INFINITY) return 0.0;
+    auto g = [&](double l, double *dg) {
+        const double tau = exp(l);
+        const double s = -expm1(l);          // 1 - tau
+        const double z = tau * (2.0 - tau);
+        const double lt = dm_lnT_lower(z, s * s, a, lb);
+        // d ln T / d ln tau = tau z^(a-1) / (B(a,1/2) T)
+        *dg = exp(l + (a - 1.0) * log(z) - lb - lt - LN2) * 2.0;
+        return lt - lnq;
+    };
+    double hi = 0.0, lo = (lnq + LN2) / a;   // T ~ tau^a h(tau), h(1) = 1/2
+    double dg;
+    double glo = g(lo, &dg);
+    int guard = 0;
+    while (glo > 0.0 && guard++ < 2000) { hi = lo; lo = 2.0 * lo - 1.0; glo = g(lo, &dg); }
+    double l = lo;
+    double gl = glo;
+    for (int it = 0; it < 200; ++it) {
+        if (gl > 0.0) hi = l; else lo = l;
+        double ln = l - gl / dg;
+        if (!(ln > lo && ln < hi)) ln = 0.5 * (lo + hi);
+        const double step = fabs(ln - l);
+        l = ln;
+        if (step <= 4e-16 * fmax(1.0, fabs(l)) || hi - lo <= 4e-16 * fmax(1.0, fabs(lo))) break;
+        gl = g(l, &dg);
+    }
+    return exp(l);
+}
+
+// log of the univariate t_1 density with scale S (variance-like) and dof v,
+// given the log normaliser lnc = lgamma((v+1)/2) - lgamma(v/2) - 1/2 ln(pi v).
+__device__ inline double dm_lt1pdf(double x, double S, double v, double lnc) {
+    return lnc - 0.5 * log(S) - 0.5 * (v + 1.0) * log1p(x * x / (v * S));
+}
+
+__device__ inline double dm_lt1_const(double v) {
+    return lgamma(0.5 * (v + 1.0)) - lgamma(0.5 * v) - 0.5 * log(M_PI * v);
+}
+
+// Univariate t CDF T_v(x) in FP64 (the one-dimensional T_m).
+__device__ inline double dm_tcdf(double x, double v) {
+    if (isnan(x)) return x;
+    if (isinf(x)) return x > 0 ? 1.0 : 0.0;
+    const double a = 0.5 * v, lb = dm_lbeta_half(a);
+    // s = x / sqrt(v + x^2): z = v/(v+x^2), zc = x^2/(v+x^2)
+    double z, zc;
+    const double ax = fabs(x);
+    if (ax > 1.0) { const double r = (v / ax) / ax; z = r / (1.0 + r); zc = 1.0 / (1.0 + r); }
+    else { const double den = v + x * x; z = v / den; zc = x * x / den; }
+    const double lo = exp(dm_lnT_lower(z, zc, a, lb));
+    return x <= 0.0 ? lo : 1.0 - lo;
+}
+
+// ---------------------------------------------------------------- FP32 ------
+
+__device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float flog2(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+__device__ __forceinline__ float tab_poly(const float *row, float x) {
+    const float4 lo = *reinterpret_cast<const float4 *>(row);
+    const float4 hi = *reinterpret_cast<const float4 *>(row + 4);
+    float r = hi.z;
+    r = fmaf(r, x, hi.y);
+    r = fmaf(r, x, hi.x);
+    r = fmaf(r, x, lo.w);
+    r = fmaf(r, x, lo.z);
+    r = fmaf(r, x, lo.y);
+    r = fmaf(r, x, lo.x);
+    return r;
+}
+
+// F(tau) from the CDF rows of one dof's table; tau in [0, 1].
+__device__ __forceinline__ float tab_cdf_F(const float *tab, float tau) {
+    const float pos = tau * 8.0f;
+    const int k = min((int)pos, TAB_CDF_ROWS - 1);
+    const float x = fmaf(2.0f, pos - (float)k, -1.0f);
+    return tab_poly(tab + 8 * k, x);
+}
+
+// log2 tau from the quantile rows; lam = -log2(2p) >= 0.
+__device__ __forceinline__ float tab_inv_G(const float *tab, float lam) {
+    const float zz = fminf(fmaxf(lam, 0.0f), INV_LAMBDA_MAX) + 0.25f;
+    const int e = __builtin_amdgcn_frexp_expf(zz);     // zz = mant 2^e, mant in [0.5, 1)
+    const float mant = __builtin_amdgcn_frexp_mantf(zz);
+    const int k = e + 1;                               // interval 0..10
+    const float x = fmaf(4.0f, mant, -3.0f);
+    return tab_poly(tab + 8 * (TAB_CDF_ROWS + k), x);
+}
+
+}  // namespace cfust

@@ -1,0 +1,688 @@
+// cfust_estep.hip -- E-step kernels of the CFUST mixture (Sec. 3.1) and the
+// batched multivariate t probabilities.
+//
+//   k_precompute   per component: Omega = Sigma + Delta Delta^T, chol Omega,
+//                  Omega^{-1} Delta, Lambda = I - Delta^T Omega^{-1} Delta
+//                  (Sec. 2 eq. 4), chol Lambda and the Cholesky factors of the
+//                  conditional matrices Lambda_{-i|i}, Lambda_{-ik|ik} that
+//                  the truncated-t moments need; log-density constants.
+//   k_tables       per (component, dof): FP32 tables of the t law (mixed mode).
+//   k_estep_qmc    one wave per (observation, component, integral): the
+//                  lattice estimate of one T_m (the hot loop).
+//   k_assemble     one thread per (observation, component): log f_h (eq. 4),
+//                  w (eq. 13), e1 (eq. 15), e2, e3 (eqs. 16-17).
+//   k_lse          one thread per observation: tau (eq. 12), log f(y_j) and
+//                  per-block partial sums of the log-likelihood (eq. 27).
+//   k_mvt          one wave per item of mvt_cdf_batch.
+#include "cfust_kernels.h"
+#include "cfust_sov.h"
+
+namespace cfust {
+
+// ------------------------------------------------------------------ helpers
+
+// Lower Cholesky of an n x n matrix (row-major, stride n), in place on L.
+__device__ inline bool chol_inplace(double *A, int n) {
+    for (int i = 0; i < n; ++i) {
+        for (int j = 0; j <= i; ++j) {
+            double s = A[i * n + j];
+            for (int k = 0; k < j; ++k) s -= A[i * n + k] * A[j * n + k];
+            if (i == j) {
+                if (!(s > 0.0)) return false;
+                A[i * n + i] = sqrt(s);
+            } else {
+                A[i * n + j] = s / A[j * n + j];
+            }
+        }
+        for (int j = i + 1; j < n; ++j) A[i * n + j] = 0.0;
+    }
+    return true;
+}
+
+__device__ inline void pair_of(int q, int pr, int &i, int &k) {
+    i = 0;
+    int r = pr;
+    while (r >= q - 1 - i) { r -= q - 1 - i; ++i; }
+    k = i + 1 + r;
+}
+
+__device__ inline int pair_index(int q, int i, int k) {  // i < k
+    return i * (2 * q - i - 1) / 2 + (k - i - 1);
+}
+
+// ------------------------------------------------------------ precompute ---
+
+__global__ __launch_bounds__(64) void k_precompute(const double *__restrict__ pi, const double *__restrict__ mu,
+                                                   const double *__restrict__ Sigma,
+                                                   const double *__restrict__ Delta,
+                                                   const double *__restrict__ nu, int p, int q,
+                                                   CompPre *__restrict__ pre) {
+    const int h = blockIdx.x;
+    CompPre &P = pre[h];
+    __shared__ double Lam[MAXQ * MAXQ];
+    __shared__ int st;
+    if (threadIdx.x == 0) {
+        int status = 0;
+        const double v = nu[h];
+        if (!(v > 0.0) || !isfinite(v) || !(pi[h] >= 0.0) || !isfinite(pi[h])) status |= CFUST_DEV_BADPARAM;
+        double Om[MAXP * MAXP];
+        const double *Sg = Sigma + (size_t)h * p * p;
+        const double *Dl = Delta + (size_t)h * p * q;
+        for (int i = 0; i < p; ++i)
+            for (int k = 0; k < p; ++k) {
+                double s = Sg[i * p + k];
+                for (int l = 0; l < q; ++l) s += Dl[i * q + l] * Dl[k * q + l];
+                Om[i * p + k] = s;
+            }
+        // symmetrise (Sigma is symmetric in exact arithmetic)
+        for (int i = 0; i < p; ++i)
+            for (int k = 0; k < i; ++k) Om[i * p + k] = Om[k * p + i] = 0.5 * (Om[i * p + k] + Om[k * p + i]);
+        double Lo[MAXP * MAXP];
+        for (int i = 0; i < p * p; ++i) Lo[i] = Om[i];
+        if (!chol_inplace(Lo, p)) { status |= CFUST_DEV_NOTSPD_OMEGA; for (int i = 0; i < p; ++i) Lo[i * p + i] = 1.0; }
+        double logdet = 0.0;
+        for (int i = 0; i < p; ++i) logdet += 2.0 * log(Lo[i * p + i]);
+        for (int i = 0; i < p * p; ++i) P.LO[i] = Lo[i];
+        // B = Omega^{-1} Delta: forward then backward substitution per column
+        double Bm[MAXP * MAXQ];
+        for (int c = 0; c < q; ++c) {
+            for (int i = 0; i < p; ++i) {
+                double s = Dl[i * q + c];
+                for (int k = 0; k < i; ++k) s -= Lo[i * p + k] * Bm[k * q + c];
+                Bm[i * q + c] = s / Lo[i * p + i];
+            }
+            for (int i = p - 1; i >= 0; --i) {
+                double s = Bm[i * q + c];
+                for (int k = i + 1; k < p; ++k) s -= Lo[k * p + i] * Bm[k * q + c];
+                Bm[i * q + c] = s / Lo[i * p + i];
+            }
+        }
+        for (int i = 0; i < p * q; ++i) P.B[i] = Bm[i];
+        for (int i = 0; i < q; ++i)
+            for (int k = 0; k < q; ++k) {
+                double s = (i == k) ? 1.0 : 0.0;
+                for (int l = 0; l < p; ++l) s -= Dl[l * q + i] * Bm[l * q + k];
+                Lam[i * q + k] = s;
+            }
+        for (int i = 0; i < q; ++i)
+            for (int k = 0; k < i; ++k) Lam[i * q + k] = Lam[k * q + i] = 0.5 * (Lam[i * q + k] + Lam[k * q + i]);
+        double LL[MAXQ * MAXQ];
+        for (int i = 0; i < q * q; ++i) { LL[i] = Lam[i]; P.Lam[i] = Lam[i]; }
+        if (!chol_inplace(LL, q)) { status |= CFUST_DEV_NOTSPD_LAMBDA; for (int i = 0; i < q; ++i) LL[i * q + i] = 1.0; }
+        for (int i = 0; i < q * q; ++i) { P.LL[i] = LL[i]; P.LLf[i] = (float)LL[i]; }
+        P.nu = v;
+        P.ltp_const = lgamma(0.5 * (v + p)) - lgamma(0.5 * v) - 0.5 * p * log(M_PI * v) - 0.5 * logdet;
+        P.digam = dm_digamma(0.5 * (v + p));
+        P.lt1_s = dm_lt1_const(v + p + 2.0);
+        P.lt1_s1 = dm_lt1_const(v + p + 1.0);
+        st = status;
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    int mystat = 0;
+    if (t < q && q >= 2) {   // Lambda_{-i|i}
+        const int i = t, m = q - 1;
+        double A[(MAXQ - 1) * (MAXQ - 1)];
+        int r = 0;
+        for (int k = 0; k < q; ++k) {
+            if (k == i) continue;
+            int c = 0;
+            for (int l = 0; l < q; ++l) {
+                if (l == i) continue;
+                A[r * m + c] = Lam[k * q + l] - Lam[k * q + i] * Lam[i * q + l] / Lam[i * q + i];
+                ++c;
+            }
+            ++r;
+        }
+        if (!chol_inplace(A, m)) { mystat |= CFUST_DEV_NOTSPD_LAMBDA; for (int d = 0; d < m; ++d) A[d * m + d] = 1.0; }
+        for (int e = 0; e < m * m; ++e) { P.LC[i][e] = A[e]; P.LCf[i][e] = (float)A[e]; }
+    }
+    if (t < npairs(q)) {     // Lambda_{-ik|ik}
+        int i, k;
+        pair_of(q, t, i, k);
+        const double a00 = Lam[i * q + i], a01 = Lam[i * q + k], a11 = Lam[k * q + k];
+        const double det = a00 * a11 - a01 * a01;
+        const double i00 = a11 / det, i01 = -a01 / det, i11 = a00 / det;
+        P.ID[t][0] = i00; P.ID[t][1] = i01; P.ID[t][2] = i11;
+        const int m = q - 2;
+        double Rg[(MAXQ - 2) * 2];
+        int r = 0;
+        for (int l = 0; l < q; ++l) {
+            if (l == i || l == k) continue;
+            Rg[r * 2 + 0] = Lam[l * q + i] * i00 + Lam[l * q + k] * i01;
+            Rg[r * 2 + 1] = Lam[l * q + i] * i01 + Lam[l * q + k] * i11;
+            ++r;
+        }
+        double A[(MAXQ - 2) * (MAXQ - 2)];
+        r = 0;
+        for (int l = 0; l < q; ++l) {
+            if (l == i || l == k) continue;
+            int c = 0;
+            for (int u = 0; u < q; ++u) {
+                if (u == i || u == k) continue;
+                A[r * m + c] = Lam[l * q + u] - Rg[r * 2 + 0] * Lam[i * q + u] - Rg[r * 2 + 1] * Lam[k * q + u];
+                ++c;
+            }
+            ++r;
+        }
+        // symmetrise before factorising
+        for (int a = 0; a < m; ++a)
+            for (int b = 0; b < a; ++b) A[a * m + b] = A[b * m + a] = 0.5 * (A[a * m + b] + A[b * m + a]);
+        for (int e = 0; e < 2 * m; ++e) P.RD[t][e] = Rg[e];
+        if (m > 0 && !chol_inplace(A, m)) { mystat |= CFUST_DEV_NOTSPD_LAMBDA; for (int d = 0; d < m; ++d) A[d * m + d] = 1.0; }
+        for (int e = 0; e < m * m; ++e) { P.LD[t][e] = A[e]; P.LDf[t][e] = (float)A[e]; }
+    }
+    // fold the per-thread status bits (no atomics: a shared-memory tree)
+    __shared__ int sst[64];
+    sst[t] = mystat;
+    __syncthreads();
+    if (t == 0) {
+        int s = st;
+        for (int u = 0; u < 64; ++u) s |= sst[u];
+        P.status = s;
+    }
+}
+
+// Fold the per-component status words into the caller's status word.
+__global__ void k_status_fold(const CompPre *__restrict__ pre, int g, int32_t *__restrict__ status) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        int s = status[0];
+        for (int h = 0; h < g; ++h) s |= pre[h].status;
+        status[0] = s;
+    }
+}
+
+// --------------------------------------------------------------- tables ----
+
+// One block per (component, dof offset): 19 rows x 7 nodes evaluated in
+// parallel, then one thread per row fits and writes the row.
+__device__ inline double table_node_value(double nu, int row, int n) {
+    const double a = 0.5 * nu, lb = dm_lbeta_half(a);
+    const double x = cos(M_PI * (n + 0.5) / 7.0);
+    if (row < TAB_CDF_ROWS) {
+        const double tau = (row + 0.5 * (x + 1.0)) / 8.0;
+        const double s = 1.0 - tau;
+        const double lt = dm_lnT_lower(tau * (2.0 - tau), s * s, a, lb);
+        return lt / LN2 - a * log2(tau);
+    }
+    const int k = row - TAB_CDF_ROWS;
+    const double w = 0.25 * (double)(1 << k);
+    const double lam = w - 0.25 + w * 0.5 * (x + 1.0);
+    return log2(dm_tau_of_lnq(-(lam + 1.0) * LN2, a, lb));
+}
+
+__device__ inline void table_fit_row(const double *f, float *dst) {
+    double c[7];
+    for (int j = 0; j < 7; ++j) {
+        double sacc = 0.0;
+        for (int n = 0; n < 7; ++n) sacc += f[n] * cos(M_PI * j * (n + 0.5) / 7.0);
+        c[j] = sacc * (2.0 / 7.0);
+    }
+    c[0] *= 0.5;
+    double mono[7] = {0, 0, 0, 0, 0, 0, 0};
+    double Tm2[7] = {1, 0, 0, 0, 0, 0, 0}, Tm1[7] = {0, 1, 0, 0, 0, 0, 0}, Tj[7];
+    for (int i = 0; i < 7; ++i) mono[i] = c[0] * Tm2[i] + c[1] * Tm1[i];
+    for (int j = 2; j < 7; ++j) {
+        for (int i = 0; i < 7; ++i) Tj[i] = (i > 0 ? 2.0 * Tm1[i - 1] : 0.0) - Tm2[i];
+        for (int i = 0; i < 7; ++i) { mono[i] += c[j] * Tj[i]; Tm2[i] = Tm1[i]; Tm1[i] = Tj[i]; }
+    }
+    for (int i = 0; i < 7; ++i) dst[i] = (float)mono[i];
+    dst[7] = 0.0f;
+}
+
+constexpr int TAB_NODES = (TAB_CDF_ROWS + TAB_INV_ROWS) * 7;   // 133
+
+__global__ __launch_bounds__(192) void k_tables(const CompPre *__restrict__ pre, int p, int ndof,
+                                                float *__restrict__ tabs) {
+    const int h = blockIdx.x / ndof, off = blockIdx.x % ndof;
+    const double nu = pre[h].nu + p + off;
+    __shared__ double fv[TAB_NODES];
+    const int t = threadIdx.x;
+    if (t < TAB_NODES) fv[t] = table_node_value(nu, t / 7, t % 7);
+    __syncthreads();
+    float *dst = tabs + ((size_t)h * NDOF + off) * TAB_FLOATS;
+    if (t < TAB_CDF_ROWS + TAB_INV_ROWS) table_fit_row(fv + 7 * t, dst + 8 * t);
+    if (t >= TAB_CDF_ROWS + TAB_INV_ROWS && t < TAB_ROWS) {   // pad row
+        for (int i = 0; i < 8; ++i) dst[8 * t + i] = 0.0f;
+    }
+}
+
+// ------------------------------------------------------------- geometry ----
+
+// r = y_j - mu_h, d = r^T Omega^{-1} r, c = Delta^T Omega^{-1} r (Sec. 2 eq. 4).
+__device__ inline void pair_geometry(const double *__restrict__ y, int n, int p, int q, int j,
+                                     const double *__restrict__ mu, const CompPre &P, double *c, double &d) {
+    double r[MAXP], v[MAXP];
+    for (int i = 0; i < p; ++i) r[i] = y[(size_t)i * n + j] - mu[i];
+    d = 0.0;
+    for (int i = 0; i < p; ++i) {
+        double s = r[i];
+        for (int k = 0; k < i; ++k) s -= P.LO[i * p + k] * v[k];
+        v[i] = s / P.LO[i * p + i];
+        d += v[i] * v[i];
+    }
+    for (int l = 0; l < q; ++l) {
+        double s = 0.0;
+        for (int k = 0; k < p; ++k) s += P.B[k * q + l] * r[k];
+        c[l] = s;
+    }
+}
+
+// Standardised limits of integral D of the pair: T_m(b; 0, L L^T, nu0) with L
+// a per-component Cholesky factor (stride m) and the per-observation scale
+// folded into b.  Returns L (FP64).
+__device__ inline const double *integral_limits(const IntDesc &D, const CompPre &P, int p, int q,
+                                                const double *c, double d, double *b) {
+    const double v = P.nu;
+    const double nus = v + p + 2.0;
+    const double sc = (v + d) / nus;
+    if (D.type == INT_A || D.type == INT_B) {
+        const double f = sqrt((D.type == INT_A ? v + p : nus) / (v + d));
+        for (int l = 0; l < q; ++l) b[l] = c[l] * f;
+        return P.LL;
+    }
+    if (D.type == INT_C) {
+        const int i = D.i;
+        const double Lii = P.Lam[i * q + i];
+        const double kap = (nus + c[i] * c[i] / (sc * Lii)) / (nus - 1.0);
+        const double f = 1.0 / sqrt(kap * sc);
+        int r = 0;
+        for (int k = 0; k < q; ++k) {
+            if (k == i) continue;
+            b[r++] = (c[k] - P.Lam[k * q + i] / Lii * c[i]) * f;
+        }
+        return P.LC[i];
+    }
+    const int i = D.i, k = D.k, t = D.pair;
+    const double Qf = (c[i] * c[i] * P.ID[t][0] + 2.0 * c[i] * c[k] * P.ID[t][1] + c[k] * c[k] * P.ID[t][2]) / sc;
+    const double kk = (nus + Qf) / (nus - 2.0);
+    const double f = 1.0 / sqrt(kk * sc);
+    int r = 0;
+    for (int l = 0; l < q; ++l) {
+        if (l == i || l == k) continue;
+        b[r] = (c[l] - P.RD[t][2 * r] * c[i] - P.RD[t][2 * r + 1] * c[k]) * f;
+        ++r;
+    }
+    return P.LD[t];
+}
+
+// --------------------------------------------------------------- lattice ---
+
+// One wave per (observation j, integral idx, component h); 4 observations per
+// block share the integral's tables.  MIXED: FP32 integrand, items whose FP32
+// product underflows are flagged for the FP64 pass.  !MIXED: FP64 integrand;
+// with FLAGGED_ONLY it processes only the flagged items.
+template <int M, bool MIXED, bool FLAGGED_ONLY>
+__global__ __launch_bounds__(256) void k_estep_qmc(EstepQmcArgs a) {
+    __shared__ __align__(16) float tab[MIXED ? M * TAB_FLOATS : 4];
+    __shared__ double smean[4][MAXS];
+    const int h = blockIdx.z, idx = a.idx0 + blockIdx.y;
+    const IntDesc D = int_desc(a.q, idx);
+    const CompPre &P = a.pre[h];
+    if (MIXED) {
+        const float *src = a.tabs + ((size_t)h * NDOF + D.dofoff) * TAB_FLOATS;
+        for (int t = threadIdx.x; t < M * TAB_FLOATS; t += blockDim.x) tab[t] = src[t];
+        __syncthreads();
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int j = blockIdx.x * 4 + wave;
+    if (j >= a.n) return;
+    const size_t o = ((size_t)h * a.J + idx) * a.n + j;
+    if (FLAGGED_ONLY && a.flag[o] == 0) return;
+    double c[MAXQ], d, b[MAXQ];
+    pair_geometry(a.y, a.n, a.p, a.q, j, a.mu + (size_t)h * a.p, P, c, d);
+    const double *L = integral_limits(D, P, a.p, a.q, c, d, b);
+    const double nu0 = P.nu + a.p + D.dofoff;
+    const SovHead H = sov_head(b, L, nu0);
+    double est = 0.0, se = 0.0, lnest = -INFINITY;
+    if (H.e0 > 0.0 || H.lne0 > -INFINITY) {
+        if (MIXED) {
+            const bool ok = sov_mixed<M>(H, b, L, nu0, a.lat, tab, smean[wave], lane);
+            if (lane == 0) a.flag[o] = ok ? 0 : 1;
+            if (!ok) return;
+        } else {
+            sov_fp64<M>(H, b, L, nu0, a.lat, smean[wave], lane);
+        }
+        sov_finish(H, smean[wave], a.lat.S, &est, &se, &lnest);
+    }
+    if (lane == 0) {
+        a.est[o] = est;
+        if (idx == 0) {
+            a.lnA[(size_t)h * a.n + j] = lnest;
+            if (a.se) a.se[(size_t)h * a.n + j] = se;
+        }
+    }
+}
+
+// ------------------------------------------------------------- assembly ----
+
+// Value of integral idx of the pair: lattice estimate (m >= 2) or closed form.
+__device__ inline double integral_value(const EstepAsmArgs &a, const CompPre &P, int h, int j, int idx,
+                                        const double *c, double d) {
+    const IntDesc D = int_desc(a.q, idx);
+    if (D.m >= 2) return a.est[((size_t)h * a.J + idx) * a.n + j];
+    if (D.m == 0) return 1.0;
+    double b[MAXQ];
+    const double *L = integral_limits(D, P, a.p, a.q, c, d, b);
+    return dm_tcdf(b[0] / L[0], P.nu + a.p + D.dofoff);
+}
+
+__global__ __launch_bounds__(128) void k_assemble(EstepAsmArgs a) {
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= a.n * a.g) return;
+    const int h = gid / a.n, j = gid % a.n;
+    const CompPre &P = a.pre[h];
+    const int p = a.p, q = a.q;
+    double c[MAXQ], d;
+    pair_geometry(a.y, a.n, p, q, j, a.mu + (size_t)h * p, P, c, d);
+    const double v = P.nu;
+    // ln A: lattice (finite even when A underflows) or closed form
+    double lnA;
+    if (q >= 2) lnA = a.lnA[(size_t)h * a.n + j];
+    else lnA = log(integral_value(a, P, h, j, 0, c, d));
+    const double logf = q * LN2 + P.ltp_const - 0.5 * (v + p) * log1p(d / v) + lnA;
+    a.logf_comp[(size_t)h * a.n + j] = logf;
+    if (a.density_only) return;
+    const size_t o = (size_t)h * a.n + j;
+    const int nq2 = q * (q + 1) / 2;
+    double w = 0.0, e1 = 0.0, e2[MAXQ], e3[MAXQ * (MAXQ + 1) / 2];
+    for (int i = 0; i < q; ++i) e2[i] = 0.0;
+    for (int i = 0; i < nq2; ++i) e3[i] = 0.0;
+    const double A = (q >= 2) ? integral_value(a, P, h, j, 0, c, d) : exp(lnA);
+    const double Bv = integral_value(a, P, h, j, 1, c, d);
+    if (A > 0.0 && Bv > 0.0 && isfinite(logf)) {
+        const double nus = v + p + 2.0, sc = (v + d) / nus;
+        w = (v + p) / (v + d) * Bv / A;                                   // eq. (13)
+        e1 = w - log(0.5 * (v + d)) - (v + p) / (v + d) + P.digam;        // eq. (15)
+        // xi_i and the conditional pieces of each i
+        double xi[MAXQ], t1k[MAXQ];
+        for (int i = 0; i < q; ++i) {
+            const double Rii = sc * P.Lam[i * q + i];
+            const double kap = (nus + c[i] * c[i] / Rii) / (nus - 1.0);
+            const double t1 = exp(dm_lt1pdf(c[i], Rii, nus, P.lt1_s));
+            t1k[i] = t1 * kap;
+            xi[i] = t1k[i] * integral_value(a, P, h, j, 2 + i, c, d);
+        }
+        // G, column by column
+        double G[MAXQ * MAXQ];
+        for (int i = 0; i < q; ++i) {
+            const double Lii = P.Lam[i * q + i];
+            const double kap = (nus + c[i] * c[i] / (sc * Lii)) / (nus - 1.0);
+            double bb[MAXQ], xs[MAXQ];
+            for (int k = 0; k < q; ++k) bb[k] = c[k] - P.Lam[k * q + i] / Lii * c[i];
+            for (int k = 0; k < q; ++k) {
+                if (k == i) { xs[k] = 0.0; continue; }
+                const double Vkk = kap * sc * (P.Lam[k * q + k] - P.Lam[k * q + i] * P.Lam[i * q + k] / Lii);
+                const double kp = ((nus - 1.0) + bb[k] * bb[k] / Vkk) / (nus - 2.0);
+                const double t1 = exp(dm_lt1pdf(bb[k], Vkk, nus - 1.0, P.lt1_s1));
+                const int pr = i < k ? pair_index(q, i, k) : pair_index(q, k, i);
+                xs[k] = t1 * kp * integral_value(a, P, h, j, 2 + q + pr, c, d);
+            }
+            for (int k = 0; k < q; ++k) {
+                double g = P.Lam[k * q + i] / Lii * c[i] * xi[i];
+                if (k != i) {
+                    double vx = 0.0;
+                    for (int l = 0; l < q; ++l) {
+                        if (l == i) continue;
+                        vx += kap * sc * (P.Lam[k * q + l] - P.Lam[k * q + i] * P.Lam[i * q + l] / Lii) * xs[l];
+                    }
+                    g -= t1k[i] * vx;
+                }
+                G[k * q + i] = g;
+            }
+        }
+        double M1[MAXQ], M2[MAXQ * MAXQ];
+        for (int i = 0; i < q; ++i) {
+            double s = 0.0;
+            for (int k = 0; k < q; ++k) s += sc * P.Lam[i * q + k] * xi[k];
+            M1[i] = -s;
+        }
+        for (int i = 0; i < q; ++i)
+            for (int k = 0; k < q; ++k) {
+                double s = 0.0;
+                for (int l = 0; l < q; ++l) s += G[i * q + l] * sc * P.Lam[l * q + k];
+                M2[i * q + k] = nus / (nus - 2.0) * A * sc * P.Lam[i * q + k] - s;
+            }
+        for (int i = 0; i < q; ++i) e2[i] = w * (c[i] - M1[i] / Bv);
+        int t = 0;
+        for (int i = 0; i < q; ++i)
+            for (int k = i; k < q; ++k, ++t) {
+                const double euu = c[i] * c[k] - (c[i] * M1[k] + M1[i] * c[k]) / Bv
+                                   + 0.5 * (M2[i * q + k] + M2[k * q + i]) / Bv;
+                e3[t] = w * euu;
+            }
+    }
+    if (a.mixed) {
+        float *W = (float *)a.w, *E1 = (float *)a.e1, *E2 = (float *)a.e2, *E3 = (float *)a.e3;
+        W[o] = (float)w; E1[o] = (float)e1;
+        for (int i = 0; i < q; ++i) E2[((size_t)h * q + i) * a.n + j] = (float)e2[i];
+        for (int i = 0; i < nq2; ++i) E3[((size_t)h * nq2 + i) * a.n + j] = (float)e3[i];
+    } else {
+        double *W = (double *)a.w, *E1 = (double *)a.e1, *E2 = (double *)a.e2, *E3 = (double *)a.e3;
+        W[o] = w; E1[o] = e1;
+        for (int i = 0; i < q; ++i) E2[((size_t)h * q + i) * a.n + j] = e2[i];
+        for (int i = 0; i < nq2; ++i) E3[((size_t)h * nq2 + i) * a.n + j] = e3[i];
+    }
+}
+
+// ------------------------------------------------------------------ LSE ----
+
+__global__ __launch_bounds__(256) void k_lse(EstepLseArgs a) {
+    __shared__ double red[256];
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    double lj = 0.0;
+    if (j < a.n) {
+        double mx = -INFINITY;
+        for (int h = 0; h < a.g; ++h) {
+            const double v = log(a.pi[h]) + a.logf_comp[(size_t)h * a.n + j];
+            mx = fmax(mx, v);
+        }
+        double l = -INFINITY;
+        if (mx > -INFINITY && isfinite(mx)) {
+            double s = 0.0;
+            for (int h = 0; h < a.g; ++h) s += exp(log(a.pi[h]) + a.logf_comp[(size_t)h * a.n + j] - mx);
+            l = mx + log(s);
+        }
+        if (a.logf_obs) a.logf_obs[j] = l;
+        lj = l;
+        if (a.tau) {
+            const int nq2 = a.q * (a.q + 1) / 2;
+            for (int h = 0; h < a.g; ++h) {
+                const double t = isfinite(l) ? exp(log(a.pi[h]) + a.logf_comp[(size_t)h * a.n + j] - l) : 0.0;
+                a.tau[(size_t)h * a.n + j] = t;
+                if (!(t > 0.0) && a.w) {   // no weight: zero the e-terms
+                    const size_t o = (size_t)h * a.n + j;
+                    if (a.mixed) {
+                        ((float *)a.w)[o] = 0.0f; ((float *)a.e1)[o] = 0.0f;
+                        for (int i = 0; i < a.q; ++i) ((float *)a.e2)[((size_t)h * a.q + i) * a.n + j] = 0.0f;
+                        for (int i = 0; i < nq2; ++i) ((float *)a.e3)[((size_t)h * nq2 + i) * a.n + j] = 0.0f;
+                    } else {
+                        ((double *)a.w)[o] = 0.0; ((double *)a.e1)[o] = 0.0;
+                        for (int i = 0; i < a.q; ++i) ((double *)a.e2)[((size_t)h * a.q + i) * a.n + j] = 0.0;
+                        for (int i = 0; i < nq2; ++i) ((double *)a.e3)[((size_t)h * nq2 + i) * a.n + j] = 0.0;
+                    }
+                }
+            }
+        }
+    }
+    red[threadIdx.x] = lj;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) a.partial[blockIdx.x] = red[0];
+}
+
+// Sum of per-block partials in a fixed order (deterministic).
+__global__ __launch_bounds__(256) void k_sum_partials(const double *__restrict__ part, int np,
+                                                      double *__restrict__ out) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < np; i += 256) s += part[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
+// ------------------------------------------------------------ mvt batch ----
+
+// One wave per item.  MIXED: the wave first builds, in its own LDS slice, the
+// FP32 tables of the dofs nu .. nu+M-1 it needs; FP32 underflow is flagged for
+// the FP64 pass (FLAGGED_ONLY).
+template <int M, bool MIXED, bool FLAGGED_ONLY>
+__global__ __launch_bounds__(256) void k_mvt(MvtArgs a) {
+    __shared__ __align__(16) float tab[4][MIXED ? M * TAB_FLOATS : 4];
+    __shared__ double fv[4][MIXED ? TAB_NODES : 1];
+    __shared__ double smean[4][MAXS];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int it = blockIdx.x * 4 + wave;
+    if (it >= a.batch) return;
+    if (FLAGGED_ONLY && a.flag[it] == 0) return;
+    const double nu = a.nu[it];
+    double b[M], L[M * M];
+    const int mi = a.mat_idx[it];
+    if (mi < 0 || mi >= a.nmat) {   // invalid matrix index: NaN result, no access
+        if (lane == 0) { a.p[it] = NAN; if (a.logp) a.logp[it] = NAN; if (a.se) a.se[it] = NAN; }
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < M; ++i) b[i] = a.b[(size_t)it * M + i];
+#pragma unroll
+    for (int i = 0; i < M * M; ++i) L[i] = a.L[(size_t)mi * M * M + i];
+    const SovHead H = sov_head(b, L, nu);
+    double est = 0.0, se = 0.0, lnest = -INFINITY;
+    if (H.e0 > 0.0 || H.lne0 > -INFINITY) {
+        if (MIXED) {
+            for (int dof = 0; dof < M; ++dof) {
+                for (int t = lane; t < TAB_NODES; t += 64) fv[wave][t] = table_node_value(nu + dof, t / 7, t % 7);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                if (lane < TAB_CDF_ROWS + TAB_INV_ROWS)
+                    table_fit_row(fv[wave] + 7 * lane, tab[wave] + dof * TAB_FLOATS + 8 * lane);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+            const bool ok = sov_mixed<M>(H, b, L, nu, a.lat, tab[wave], smean[wave], lane);
+            if (lane == 0) a.flag[it] = ok ? 0 : 1;
+            if (!ok) return;
+        } else {
+            sov_fp64<M>(H, b, L, nu, a.lat, smean[wave], lane);
+        }
+        sov_finish(H, smean[wave], a.lat.S, &est, &se, &lnest);
+    }
+    if (lane == 0) {
+        a.p[it] = est;
+        if (a.logp) a.logp[it] = lnest;
+        if (a.se) a.se[it] = se;
+    }
+}
+
+// m = 1: the univariate t CDF in closed form, one thread per item.
+__global__ __launch_bounds__(256) void k_mvt1(MvtArgs a) {
+    const int it = blockIdx.x * blockDim.x + threadIdx.x;
+    if (it >= a.batch) return;
+    const double nu = a.nu[it];
+    const int mi = a.mat_idx[it];
+    if (mi < 0 || mi >= a.nmat) {
+        a.p[it] = NAN; if (a.logp) a.logp[it] = NAN; if (a.se) a.se[it] = NAN;
+        return;
+    }
+    const double b = a.b[it], L = a.L[mi];
+    const SovHead H = sov_head(&b, &L, nu);
+    a.p[it] = H.e0;
+    if (a.logp) a.logp[it] = H.lne0;
+    if (a.se) a.se[it] = 0.0;
+}
+
+// --------------------------------------------------------------- launch ----
+
+hipError_t launch_precompute(const cfust_params &P, int p, int q, int g, CompPre *pre, hipStream_t s) {
+    hipLaunchKernelGGL(k_precompute, dim3(g), dim3(64), 0, s, P.pi, P.mu, P.Sigma, P.Delta, P.nu, p, q, pre);
+    return hipGetLastError();
+}
+
+hipError_t launch_status_fold(const CompPre *pre, int g, int32_t *status, hipStream_t s) {
+    hipLaunchKernelGGL(k_status_fold, dim3(1), dim3(64), 0, s, pre, g, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_tables(const CompPre *pre, int p, int g, int ndof, float *tabs, hipStream_t s) {
+    hipLaunchKernelGGL(k_tables, dim3(g * ndof), dim3(192), 0, s, pre, p, ndof, tabs);
+    return hipGetLastError();
+}
+
+template <int M>
+static void launch_qmc_m(const EstepQmcArgs &a, int nidx, hipStream_t s) {
+    dim3 grid((a.n + 3) / 4, nidx, a.g);
+    if (a.mixed) {
+        hipLaunchKernelGGL((k_estep_qmc<M, true, false>), grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_estep_qmc<M, false, true>), grid, dim3(256), 0, s, a);
+    } else {
+        hipLaunchKernelGGL((k_estep_qmc<M, false, false>), grid, dim3(256), 0, s, a);
+    }
+}
+
+hipError_t launch_estep_qmc(const EstepQmcArgs &a, int m, int nidx, hipStream_t s) {
+    if (a.n == 0 || nidx == 0) return hipSuccess;
+    switch (m) {
+    case 2: launch_qmc_m<2>(a, nidx, s); break;
+    case 3: launch_qmc_m<3>(a, nidx, s); break;
+    case 4: launch_qmc_m<4>(a, nidx, s); break;
+    case 5: launch_qmc_m<5>(a, nidx, s); break;
+    case 6: launch_qmc_m<6>(a, nidx, s); break;
+    case 7: launch_qmc_m<7>(a, nidx, s); break;
+    case 8: launch_qmc_m<8>(a, nidx, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_assemble(const EstepAsmArgs &a, hipStream_t s) {
+    const long tot = (long)a.n * a.g;
+    if (tot == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_assemble, dim3((unsigned)((tot + 127) / 128)), dim3(128), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_lse(const EstepLseArgs &a, double *loglik, hipStream_t s) {
+    const int nb = (a.n + 255) / 256;
+    if (nb > 0) hipLaunchKernelGGL(k_lse, dim3(nb), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, a.partial, nb, loglik);
+    return hipGetLastError();
+}
+
+template <int M>
+static void launch_mvt_m(const MvtArgs &a, hipStream_t s) {
+    dim3 grid((a.batch + 3) / 4);
+    if (a.mixed) {
+        hipLaunchKernelGGL((k_mvt<M, true, false>), grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_mvt<M, false, true>), grid, dim3(256), 0, s, a);
+    } else {
+        hipLaunchKernelGGL((k_mvt<M, false, false>), grid, dim3(256), 0, s, a);
+    }
+}
+
+hipError_t launch_mvt(const MvtArgs &a, hipStream_t s) {
+    if (a.batch == 0) return hipSuccess;
+    switch (a.m) {
+    case 1: hipLaunchKernelGGL(k_mvt1, dim3((a.batch + 255) / 256), dim3(256), 0, s, a); break;
+    case 2: launch_mvt_m<2>(a, s); break;
+    case 3: launch_mvt_m<3>(a, s); break;
+    case 4: launch_mvt_m<4>(a, s); break;
+    case 5: launch_mvt_m<5>(a, s); break;
+    case 6: launch_mvt_m<6>(a, s); break;
+    case 7: launch_mvt_m<7>(a, s); break;
+    case 8: launch_mvt_m<8>(a, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace cfust

@@ -1,0 +1,87 @@
+// cfust_kernels.h -- kernel argument blocks and launchers (private).
+#pragma once
+#include "cfust_common.h"
+
+namespace cfust {
+
+struct LatticeArgs {
+    int N, S, log2N;            // log2N < 0 when N is not a power of two
+    const int32_t *z;           // [LATD]
+    const double *shifts;       // [S][LATD]
+};
+
+struct EstepQmcArgs {
+    const double *y;            // [p][n]
+    const double *mu;           // [g][p]
+    const CompPre *pre;         // [g]
+    const float *tabs;          // [g][NDOF][TAB_FLOATS] (mixed)
+    LatticeArgs lat;
+    int n, p, q, g;
+    int J;                      // integrals stored per pair in est
+    int idx0;                   // first integral index of this launch
+    int mixed;
+    double *est;                // [g][J][n]
+    double *lnA;                // [g][n]  ln of integral 0 (A)
+    double *se;                 // [g][n]  optional stderr of A
+    int32_t *flag;              // [g][J][n] mixed: 1 where the FP32 estimate underflowed
+};
+
+struct EstepAsmArgs {
+    const double *y, *mu;
+    const CompPre *pre;
+    int n, p, q, g, J;
+    int mixed, density_only;
+    const double *est, *lnA;
+    double *logf_comp;
+    void *w, *e1, *e2, *e3;
+};
+
+struct EstepLseArgs {
+    const double *pi;
+    const double *logf_comp;
+    int n, g, q, mixed;
+    double *tau, *logf_obs;
+    void *w, *e1, *e2, *e3;
+    double *partial;            // [ceil(n/256)]
+};
+
+struct MvtArgs {
+    int m, batch, mixed, nmat;
+    const double *b, *L, *nu;
+    const int32_t *mat_idx;
+    LatticeArgs lat;
+    double *p, *logp, *se;
+    int32_t *flag;              // [batch] mixed: FP32 underflow -> redo in FP64
+};
+
+struct MstepArgs {
+    const double *y;            // [p][n]
+    const double *tau;          // [g][n]
+    const void *w, *e1, *e2, *e3;
+    const double *mu0;          // [g][p] shift (Psi^(k) means)
+    int n, p, q, g, mixed;
+    int nblk;                   // blocks per component
+    double *partial;            // [g][nblk][nstat]
+};
+
+struct MsolveArgs {
+    const double *partial;
+    int n, p, q, g, nblk;
+    const double *mu0, *Sigma0, *Delta0, *nu0;
+    double *pi1, *mu1, *Sigma1, *Delta1, *nu1;
+    int32_t *status;            // optional
+};
+
+hipError_t launch_precompute(const cfust_params &P, int p, int q, int g, CompPre *pre, hipStream_t s);
+hipError_t launch_status_fold(const CompPre *pre, int g, int32_t *status, hipStream_t s);
+hipError_t launch_tables(const CompPre *pre, int p, int g, int ndof, float *tabs, hipStream_t s);
+// Lattice integrals idx0 .. idx0+nidx-1 of every pair; all must share the
+// same dimension m >= 2.  In mixed mode the FP32 kernel runs first and an
+// FP64 pass then redoes only the flagged (underflowed) items.
+hipError_t launch_estep_qmc(const EstepQmcArgs &a, int m, int nidx, hipStream_t s);
+hipError_t launch_assemble(const EstepAsmArgs &a, hipStream_t s);
+hipError_t launch_lse(const EstepLseArgs &a, double *loglik, hipStream_t s);
+hipError_t launch_mvt(const MvtArgs &a, hipStream_t s);
+hipError_t launch_mstep(const MstepArgs &r, const MsolveArgs &s, hipStream_t st);
+
+}  // namespace cfust

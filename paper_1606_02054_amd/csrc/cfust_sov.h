@@ -1,0 +1,263 @@
+// cfust_sov.h -- the lattice estimate of a multivariate t probability
+//     T_m(b; 0, L L^T, nu) = P(Z <= b),  Z ~ t_m(0, L L^T, nu),
+// by Genz's separation of variables for the t law: with Z = L Y, the
+// coordinates of Y are sampled one after another from their conditional laws
+//     Y_i | y_0..y_{i-1} ~ sqrt((nu + S_i)/(nu + i)) t_{nu+i},  S_i = sum_{j<i} y_j^2,
+// each truncated to the region that keeps Z_i <= b_i; the integrand is the
+// product of the truncation probabilities e_1 ... e_{m-1} (e_0 is the same for
+// every point and is factored out).  Coordinate i uses lattice coordinate i.
+//
+// Both precisions track Q_i = sqrt(nu + S_i), for which the algebra of the
+// conditional t collapses to
+//     s_i   = num_i / sqrt(L_ii^2 Q_i^2 + num_i^2),  num_i = b_i - sum_{j<i} L_ij y_j,
+//     tau_i = 1 - |s_i|  (the argument of the lower-tail probability),
+//     y_i   = s'_i Q_{i+1},   Q_{i+1} = Q_i / sqrt(tau'_i (2 - tau'_i)),
+// where s'_i, tau'_i belong to the quantile drawn at p = x_i e_i.
+// The complement 1 - p = (1 - x_i) e_i + (1 - e_i) is formed from accurate
+// complements, so neither tail loses relative accuracy.
+#pragma once
+#include "cfust_devmath.h"
+#include "cfust_kernels.h"
+
+namespace cfust {
+
+// ------------------------------------------------------------ wave helpers --
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+using Lattice = LatticeArgs;
+
+// ------------------------------------------------------------- FP64 path ---
+
+// Lattice coordinate (FP64), the same arithmetic as the definition:
+// t = frac(r/N + shift), x = 1 - |2t - 1|, clamped to [2^-24, 1 - 2^-24].
+__device__ __forceinline__ void point64(const Lattice &Lt, int s, int k, int j, double &x, double &xb) {
+    const unsigned long long r = ((unsigned long long)k * (unsigned long long)Lt.z[j]) % (unsigned long long)Lt.N;
+    double t = (double)r / (double)Lt.N + Lt.shifts[s * LATD + j];
+    if (t >= 1.0) t -= 1.0;
+    double xbv = fabs(2.0 * t - 1.0);
+    double xv = 1.0 - xbv;
+    const double lo = 1.0 / 16777216.0;
+    if (xv < lo) { xv = lo; xbv = 1.0 - lo; }
+    if (xv > 1.0 - lo) { xv = 1.0 - lo; xbv = lo; }
+    x = xv;
+    xb = xbv;
+}
+
+// Quantile step shared by all coordinates: given the truncation probability
+// (e, eb = 1-e, lne valid when lowt) and the point (x, xb), draw y and update Q.
+__device__ __forceinline__ double quantile_step64(double x, double xb, double e, double eb, double lne,
+                                                  bool lowt, double a, double lb, double &Q) {
+    const double p = x * e;
+    const double pb = xb * e + eb;
+    const bool lower = lowt || p <= 0.5;
+    const double lnq = lowt ? log(x) + lne : log(lower ? p : pb);
+    const double tq = dm_tau_of_lnq(lnq, a, lb);
+    const double sabs = 1.0 - tq;
+    Q *= 1.0 / sqrt(tq * (2.0 - tq));
+    return (lower ? -sabs : sabs) * Q;
+}
+
+// Per-lane sum over this lane's points of one shift, FP64 arithmetic.
+template <int M>
+__device__ double sov_lane_sum64(const double *b, const double *L, double nu, const Lattice &Lt, int s,
+                                 double e0, double eb0, double lne0, bool low0, int lane) {
+    double a[M], lb[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) { a[i] = 0.5 * (nu + i); lb[i] = dm_lbeta_half(a[i]); }
+    double acc = 0.0;
+    for (int k = lane; k < Lt.N; k += 64) {
+        double y[M];
+        double Q = sqrt(nu);
+        double x, xb;
+        point64(Lt, s, k, 0, x, xb);
+        y[0] = quantile_step64(x, xb, e0, eb0, lne0, low0, a[0], lb[0], Q);
+        double f = 1.0;
+#pragma unroll
+        for (int i = 1; i < M; ++i) {
+            double num = b[i];
+#pragma unroll
+            for (int j = 0; j < i; ++j) num -= L[i * M + j] * y[j];
+            const double LQ = L[i * M + i] * Q;
+            const double K = LQ * LQ;
+            const double R = 1.0 / sqrt(K + num * num);
+            const double tau = K * R * R / (1.0 + fabs(num) * R);
+            const double sr = num * R;
+            const double lt = dm_lnT_lower(tau * (2.0 - tau), sr * sr, a[i], lb[i]);
+            const double small = exp(lt);
+            const bool lowt = num <= 0.0;
+            const double e = lowt ? small : 1.0 - small;
+            const double eb = lowt ? 1.0 - small : small;
+            f *= e;
+            if (f == 0.0) break;
+            if (i < M - 1) {
+                point64(Lt, s, k, i, x, xb);
+                y[i] = quantile_step64(x, xb, e, eb, lt, lowt, a[i], lb[i], Q);
+            }
+        }
+        acc += f;
+    }
+    return acc;
+}
+
+// ------------------------------------------------------------- FP32 path ---
+
+// Lattice coordinate (FP32): t in 32-bit fixed point so that both x = 2 min(t, 1-t)
+// and xb = 1 - x keep full relative accuracy near 0.  Needs N a power of two.
+__device__ __forceinline__ void point32(uint32_t k, uint32_t zj, uint32_t mask, int sh, uint32_t shfix,
+                                        float &x, float &xb) {
+    const uint32_t r = (k * zj) & mask;
+    const uint32_t t = (r << sh) + shfix;
+    uint32_t u = min(t, 0u - t);                      // 2^32 min(t, 1-t), in [0, 2^31]
+    u = min(max(u, 128u), 2147483520u);               // [2^-24, 1 - 2^-24] after scaling
+    x = (float)u * 4.656612873077393e-10f;            // 2^-31
+    xb = (float)(2147483648u - u) * 4.656612873077393e-10f;
+}
+
+__device__ __forceinline__ float quantile_step32(float x, float xb, float e, float eb, float l2e, bool lowt,
+                                                 const float *tab, float &Q) {
+    const float p = x * e;
+    const float pb = fmaf(xb, e, eb);
+    const bool lower = lowt || p <= 0.5f;
+    const float arg = lowt ? x : (lower ? p : pb);
+    const float l2q = flog2(arg) + (lowt ? l2e : 0.0f);
+    const float G = fmaxf(tab_inv_G(tab, -1.0f - l2q), -100.0f);
+    const float tq = fexp2(G);
+    const float sabs = 1.0f - tq;
+    Q = fminf(Q * frsq(tq * (2.0f - tq)), 1e15f);
+    return (lower ? -sabs : sabs) * Q;
+}
+
+struct Sov32Setup {
+    float b[MAXQ];
+    float L[MAXQ * MAXQ];      // row-major, stride M
+    float a[MAXQ];             // (nu + i)/2
+    float e0, eb0, l2e0, sqrtnu;
+    bool low0;
+};
+
+template <int M>
+__device__ float sov_lane_sum32(const Sov32Setup &P, const float *tabs, uint32_t z0, const uint32_t *zz,
+                                uint32_t mask, int sh, const uint32_t *shfix, int N, int lane) {
+    float acc = 0.0f;
+    for (int k = lane; k < N; k += 64) {
+        float y[M];
+        float Q = P.sqrtnu;
+        float x, xb;
+        point32((uint32_t)k, z0, mask, sh, shfix[0], x, xb);
+        y[0] = quantile_step32(x, xb, P.e0, P.eb0, P.l2e0, P.low0, tabs, Q);
+        float f = 1.0f;
+#pragma unroll
+        for (int i = 1; i < M; ++i) {
+            float num = P.b[i];
+#pragma unroll
+            for (int j = 0; j < i; ++j) num = fmaf(-P.L[i * M + j], y[j], num);
+            const float LQ = P.L[i * M + i] * Q;
+            const float K = LQ * LQ;
+            const float R = frsq(fmaf(num, num, K));
+            const float tau = K * R * R * frcp(fmaf(fabsf(num), R, 1.0f));
+            const float *tab = tabs + i * TAB_FLOATS;
+            const float l2 = fmaf(P.a[i], flog2(tau), tab_cdf_F(tab, tau));
+            const float small = fexp2(l2);
+            const bool lowt = num <= 0.0f;
+            const float e = lowt ? small : 1.0f - small;
+            const float eb = lowt ? 1.0f - small : small;
+            f *= e;
+            if (i < M - 1) {
+                point32((uint32_t)k, zz[i], mask, sh, shfix[i], x, xb);
+                y[i] = quantile_step32(x, xb, e, eb, l2, lowt, tab, Q);
+            }
+        }
+        acc += f;
+    }
+    return acc;
+}
+
+// ------------------------------------------------------------- driver -------
+
+// The first factor e_0 = T_nu(b_0 / L_00) of the SOV product, FP64, with its
+// complement and logarithm (finite even when e_0 underflows).
+struct SovHead {
+    double e0, eb0, lne0;
+    bool low0;
+};
+
+__device__ inline SovHead sov_head(const double *b, const double *L, double nu) {
+    const double a0 = 0.5 * nu, lb0 = dm_lbeta_half(a0);
+    const double u = b[0] / L[0];
+    const double au = fabs(u);
+    double z0, zc0;
+    if (au > 1.0) { const double r = (nu / au) / au; z0 = r / (1.0 + r); zc0 = 1.0 / (1.0 + r); }
+    else { const double den = nu + u * u; z0 = nu / den; zc0 = u * u / den; }
+    const double lt0 = dm_lnT_lower(z0, zc0, a0, lb0);
+    const double small0 = exp(lt0);
+    SovHead H;
+    H.low0 = u <= 0.0;
+    H.e0 = H.low0 ? small0 : 1.0 - small0;
+    H.eb0 = H.low0 ? 1.0 - small0 : small0;
+    H.lne0 = H.low0 ? lt0 : log(H.e0);
+    return H;
+}
+
+// Mean over shifts, its standard error and ln(e_0 * mean) from the per-shift
+// means in this wave's LDS slice (written by lane 0).
+__device__ inline void sov_finish(const SovHead &H, const double *smean, int S,
+                                  double *est, double *se, double *lnest) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double mean = 0.0;
+    for (int s = 0; s < S; ++s) mean += smean[s];
+    mean /= S;
+    double var = 0.0;
+    for (int s = 0; s < S; ++s) var += (smean[s] - mean) * (smean[s] - mean);
+    const double sem = S > 1 ? sqrt(var / ((double)S * (S - 1))) : 0.0;
+    *est = H.e0 * mean;
+    *se = H.e0 * sem;
+    *lnest = mean > 0.0 ? H.lne0 + log(mean) : -INFINITY;
+}
+
+// FP32 lattice sums (mixed precision).  Returns false when the FP32 product
+// underflowed for the whole item (mean below 1e-30): the caller then redoes
+// the item in FP64.  tabs: LDS tables of dofs nu .. nu+M-1.
+template <int M>
+__device__ bool sov_mixed(const SovHead &H, const double *b, const double *L, double nu, const Lattice &Lt,
+                          const float *tabs, double *smean, int lane) {
+    Sov32Setup P;
+#pragma unroll
+    for (int i = 0; i < M; ++i) { P.b[i] = (float)b[i]; P.a[i] = (float)(0.5 * (nu + i)); }
+#pragma unroll
+    for (int i = 0; i < M * M; ++i) P.L[i] = (float)L[i];
+    P.e0 = (float)H.e0; P.eb0 = (float)H.eb0; P.l2e0 = (float)(H.lne0 / LN2); P.low0 = H.low0;
+    P.sqrtnu = (float)sqrt(nu);
+    uint32_t zz[M], shfix[M];
+    const uint32_t mask = (uint32_t)Lt.N - 1u;
+    const int sh = 32 - Lt.log2N;
+#pragma unroll
+    for (int i = 0; i < M - 1; ++i) zz[i] = (uint32_t)Lt.z[i];
+    double tot = 0.0;
+    for (int s = 0; s < Lt.S; ++s) {
+#pragma unroll
+        for (int i = 0; i < M - 1; ++i) shfix[i] = (uint32_t)(Lt.shifts[s * LATD + i] * 4294967296.0);
+        const float ls = sov_lane_sum32<M>(P, tabs, zz[0], zz, mask, sh, shfix, Lt.N, lane);
+        const double ms = wave_sum((double)ls) / (double)Lt.N;
+        if (lane == 0) smean[s] = ms;
+        tot += ms;
+    }
+    return tot / Lt.S > 1e-30;
+}
+
+template <int M>
+__device__ void sov_fp64(const SovHead &H, const double *b, const double *L, double nu, const Lattice &Lt,
+                         double *smean, int lane) {
+    for (int s = 0; s < Lt.S; ++s) {
+        const double ls = sov_lane_sum64<M>(b, L, nu, Lt, s, H.e0, H.eb0, H.lne0, H.low0, lane);
+        const double ms = wave_sum(ls) / (double)Lt.N;
+        if (lane == 0) smean[s] = ms;
+    }
+}
+
+}  // namespace cfust
