@@ -158,6 +158,16 @@ cfust_status mvt_cdf_batch(cfust_handle handle, int32_t m, int32_t batch, const 
                            const double *nu, const cfust_qmc *qmc,
                            double *p, double *logp, double *stderr_, void *stream);
 
+/* Timing of the lattice-integrand kernels.  While enabled, HIP events
+ * bracket the main lattice kernel of each integral dimension launched by
+ * cfust_estep / cfust_loglik, on the call's stream (creating events: do not
+ * enable during stream capture). */
+cfust_status cfust_profile_enable(cfust_handle handle, int enable);
+/* Waits for the recorded events, adds up their durations per integral
+ * dimension m (0..CFUST_MAX_Q) into host arrays ms[CFUST_MAX_Q+1] and
+ * launches[CFUST_MAX_Q+1], and clears the record. */
+cfust_status cfust_profile_read(cfust_handle handle, double *ms, int32_t *launches);
+
 /* Size the workspace for calls up to these dims and lattice sizes, so that
  * later calls allocate nothing (e.g. under stream capture). */
 cfust_status cfust_reserve(cfust_handle handle, cfust_dims dims, const cfust_qmc *qmc);

@@ -431,11 +431,12 @@ int or_estep(int n, int p, int q, int g, const double *y,
     }
     if (status) { free(LO); free(BB); free(LAM); free(LLAM); free(logdet); return status; }
 
-    #pragma omp parallel for schedule(dynamic, 1)
+    double *LF = malloc(sizeof(double) * (size_t)g * (nr > 0 ? nr : 1));
+    /* every (observation, component) pair is independent (Sec. 4.1) */
+    #pragma omp parallel for schedule(dynamic, 1) collapse(2)
     for (int r = 0; r < nr; ++r) {
-        int j = rows ? rows[r] : r;
-        double lf[64];
         for (int h = 0; h < g; ++h) {
+            int j = rows ? rows[r] : r;
             const double *Lo = LO + (size_t)h * p * p;
             const double *Bh = BB + (size_t)h * p * q;
             const double *Lam = LAM + (size_t)h * q * q;
@@ -468,7 +469,7 @@ int or_estep(int n, int p, int q, int g, const double *y,
             or_tmoments(q, c, Rm, nus, &Q, &M0, M1, M2, &T2);
             double Bv = M0;          /* T_q(c sqrt(nu_s/(nu+d)); Lambda, nu_s), nu_s = nu+p+2 */
             double lfh = q * M_LN2 + logt + log(A);
-            lf[h] = lfh;
+            LF[(size_t)h * nr + r] = lfh;
             size_t o = (size_t)h * nr + r;
             if (logf_comp) logf_comp[o] = lfh;
             if (intA) intA[o] = A;
@@ -494,6 +495,11 @@ int or_estep(int n, int p, int q, int g, const double *y,
                 for (int k = i; k < q; ++k, ++t)
                     e3[((size_t)h * nq2 + t) * nr + r] = wv * EUU[i * q + k];
         }
+    }
+    #pragma omp parallel for schedule(static)
+    for (int r = 0; r < nr; ++r) {
+        double lf[64];
+        for (int h = 0; h < g; ++h) lf[h] = LF[(size_t)h * nr + r];
         /* eq. (12) and (27): tau_hj = pi_h f_h / sum_l pi_l f_l, via log-sum-exp */
         double mx = -INFINITY;
         for (int h = 0; h < g; ++h) {
@@ -515,7 +521,7 @@ int or_estep(int n, int p, int q, int g, const double *y,
             }
         }
     }
-    free(LO); free(BB); free(LAM); free(LLAM); free(logdet);
+    free(LO); free(BB); free(LAM); free(LLAM); free(logdet); free(LF);
     return 0;
 }
 

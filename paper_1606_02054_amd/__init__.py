@@ -59,6 +59,17 @@ class Handle:
         st = self.lib.cfust_reserve(self.h, B.Dims(n, p, q, g), C.byref(qmc.c) if qmc else None)
         B.check(st, self.h, "cfust_reserve")
 
+    def profile(self, enable: bool = True):
+        """Bracket the lattice kernels with HIP events (see cfust_profile_enable)."""
+        B.check(self.lib.cfust_profile_enable(self.h, int(bool(enable))), self.h, "cfust_profile_enable")
+
+    def profile_read(self):
+        """{m: (total_ms, launches)} for the lattice kernels recorded since the last read."""
+        ms = (C.c_double * (B.MAX_Q + 1))()
+        cnt = (C.c_int32 * (B.MAX_Q + 1))()
+        B.check(self.lib.cfust_profile_read(self.h, ms, cnt), self.h, "cfust_profile_read")
+        return {m: (ms[m], cnt[m]) for m in range(B.MAX_Q + 1) if cnt[m] > 0}
+
     def close(self):
         if getattr(self, "h", None):
             self.lib.cfust_destroy(self.h)

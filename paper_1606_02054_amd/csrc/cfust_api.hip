@@ -6,14 +6,23 @@
 
 #include <new>
 #include <string>
+#include <vector>
 
 #include "cfust_kernels.h"
+
+struct ProfRec {
+    int m;
+    hipEvent_t e0, e1;
+};
 
 struct cfust_ctx {
     int device = 0;
     std::string err;
     void *ws = nullptr;
     size_t ws_size = 0;
+    bool prof = false;
+    std::vector<ProfRec> rec;        // recorded (pending) event pairs
+    std::vector<hipEvent_t> pool;    // free events
 };
 
 namespace {
@@ -141,6 +150,25 @@ size_t mstep_bytes(const cfust_dims &d) {
     return align256((size_t)d.g * mstep_nblk(d) * nstat(d.p, d.q) * sizeof(double) + (size_t)d.g * sizeof(int32_t));
 }
 
+hipEvent_t pool_event(cfust_handle h) {
+    if (!h->pool.empty()) {
+        hipEvent_t e = h->pool.back();
+        h->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+hipError_t timed_qmc(cfust_handle h, const EstepQmcArgs &a, int m, int nidx, hipStream_t s) {
+    if (!h->prof || a.n == 0 || nidx == 0) return launch_estep_qmc(a, m, nidx, s);
+    ProfRec r{m, pool_event(h), pool_event(h)};
+    const hipError_t e = launch_estep_qmc(a, m, nidx, s, r.e0, r.e1);
+    if (r.e0 && r.e1) h->rec.push_back(r);
+    return e;
+}
+
 // Shared launch sequence of cfust_estep / cfust_loglik.
 cfust_status run_estep(cfust_handle h, const double *y, const cfust_dims &d, const cfust_params *P,
                        const cfust_qmc *Q, bool density_only, double *tau, double *logf_obs, double *loglik,
@@ -173,14 +201,14 @@ cfust_status run_estep(cfust_handle h, const double *y, const cfust_dims &d, con
         a.flag = at<int32_t>(h, L.flag);
         // integrals of equal dimension share a launch: (A, B) m = q, C_i m = q-1, D_ik m = q-2
         a.idx0 = 0;
-        e = launch_estep_qmc(a, d.q, density_only ? 1 : 2, s);
+        e = timed_qmc(h, a, d.q, density_only ? 1 : 2, s);
         if (e == hipSuccess && !density_only && d.q - 1 >= 2) {
             a.idx0 = 2;
-            e = launch_estep_qmc(a, d.q - 1, d.q, s);
+            e = timed_qmc(h, a, d.q - 1, d.q, s);
         }
         if (e == hipSuccess && !density_only && d.q - 2 >= 2) {
             a.idx0 = 2 + d.q;
-            e = launch_estep_qmc(a, d.q - 2, npairs(d.q), s);
+            e = timed_qmc(h, a, d.q - 2, npairs(d.q), s);
         }
     }
     if (e == hipSuccess) {
@@ -229,10 +257,10 @@ cfust_status cfust_create(cfust_handle *handle, int device) {
 
 cfust_status cfust_destroy(cfust_handle h) {
     if (!h) return CFUST_EINVAL;
-    if (h->ws) {
-        hipSetDevice(h->device);
-        hipFree(h->ws);
-    }
+    hipSetDevice(h->device);
+    for (auto &r : h->rec) { hipEventSynchronize(r.e1); hipEventDestroy(r.e0); hipEventDestroy(r.e1); }
+    for (auto e : h->pool) hipEventDestroy(e);
+    if (h->ws) hipFree(h->ws);
     delete h;
     return CFUST_OK;
 }
@@ -311,6 +339,29 @@ cfust_status mvt_cdf_batch(cfust_handle h, int32_t m, int32_t batch, const doubl
     a.p = p; a.logp = logp; a.se = stderr_;
     a.flag = at<int32_t>(h, 0);
     return hip_check(h, launch_mvt(a, (hipStream_t)stream), "mvt_cdf_batch launch");
+}
+
+cfust_status cfust_profile_enable(cfust_handle h, int enable) {
+    if (!h) return CFUST_EINVAL;
+    h->prof = enable != 0;
+    return CFUST_OK;
+}
+
+cfust_status cfust_profile_read(cfust_handle h, double *ms, int32_t *launches) {
+    if (!h || !ms || !launches) return CFUST_EINVAL;
+    for (int m = 0; m <= MAXQ; ++m) { ms[m] = 0.0; launches[m] = 0; }
+    cfust_status st = CFUST_OK;
+    for (auto &r : h->rec) {
+        float t = 0.0f;
+        hipError_t e = hipEventSynchronize(r.e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, r.e0, r.e1);
+        if (e != hipSuccess) st = hip_check(h, e, "cfust_profile_read");
+        else if (r.m >= 0 && r.m <= MAXQ) { ms[r.m] += t; launches[r.m] += 1; }
+        h->pool.push_back(r.e0);
+        h->pool.push_back(r.e1);
+    }
+    h->rec.clear();
+    return st;
 }
 
 cfust_status cfust_reserve(cfust_handle h, cfust_dims d, const cfust_qmc *qmc) {

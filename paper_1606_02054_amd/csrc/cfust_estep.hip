@@ -619,26 +619,30 @@ hipError_t launch_tables(const CompPre *pre, int p, int g, int ndof, float *tabs
 }
 
 template <int M>
-static void launch_qmc_m(const EstepQmcArgs &a, int nidx, hipStream_t s) {
+static void launch_qmc_m(const EstepQmcArgs &a, int nidx, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     dim3 grid((a.n + 3) / 4, nidx, a.g);
+    if (ev0) hipEventRecord(ev0, s);
     if (a.mixed) {
         hipLaunchKernelGGL((k_estep_qmc<M, true, false>), grid, dim3(256), 0, s, a);
+        if (ev1) hipEventRecord(ev1, s);
         hipLaunchKernelGGL((k_estep_qmc<M, false, true>), grid, dim3(256), 0, s, a);
     } else {
         hipLaunchKernelGGL((k_estep_qmc<M, false, false>), grid, dim3(256), 0, s, a);
+        if (ev1) hipEventRecord(ev1, s);
     }
 }
 
-hipError_t launch_estep_qmc(const EstepQmcArgs &a, int m, int nidx, hipStream_t s) {
+hipError_t launch_estep_qmc(const EstepQmcArgs &a, int m, int nidx, hipStream_t s, hipEvent_t ev0,
+                            hipEvent_t ev1) {
     if (a.n == 0 || nidx == 0) return hipSuccess;
     switch (m) {
-    case 2: launch_qmc_m<2>(a, nidx, s); break;
-    case 3: launch_qmc_m<3>(a, nidx, s); break;
-    case 4: launch_qmc_m<4>(a, nidx, s); break;
-    case 5: launch_qmc_m<5>(a, nidx, s); break;
-    case 6: launch_qmc_m<6>(a, nidx, s); break;
-    case 7: launch_qmc_m<7>(a, nidx, s); break;
-    case 8: launch_qmc_m<8>(a, nidx, s); break;
+    case 2: launch_qmc_m<2>(a, nidx, s, ev0, ev1); break;
+    case 3: launch_qmc_m<3>(a, nidx, s, ev0, ev1); break;
+    case 4: launch_qmc_m<4>(a, nidx, s, ev0, ev1); break;
+    case 5: launch_qmc_m<5>(a, nidx, s, ev0, ev1); break;
+    case 6: launch_qmc_m<6>(a, nidx, s, ev0, ev1); break;
+    case 7: launch_qmc_m<7>(a, nidx, s, ev0, ev1); break;
+    case 8: launch_qmc_m<8>(a, nidx, s, ev0, ev1); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

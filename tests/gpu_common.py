@@ -1,8 +1,9 @@
 """Helpers shared by the GPU parity tests (not collected by pytest)."""
 import numpy as np
 
-# Tolerances (the reading of the design notes): log-density per observation,
-# tau (absolute), e-terms (relative, on pairs with tau > 1e-8).
+# Tolerances: log-density per observation (absolute), tau (absolute), e-terms
+# relative to each entry's natural scale (see compare_estep), on pairs with
+# tau > 1e-8.
 TOL = {
     "fp64": dict(logf=1e-6, tau=1e-9, eterm=1e-8),
     "mixed": dict(logf=1e-4, tau=1e-5, eterm=1e-3),
@@ -26,13 +27,24 @@ def compare_estep(gpu, ora, mode, rows=None, label=""):
     tau_g = sel(gpu.tau.cpu().numpy())
     assert np.abs(tau_g - ora.tau).max() <= t["tau"], f"{label} tau err {np.abs(tau_g - ora.tau).max():.3e}"
     mask = ora.tau > 1e-8
+    q = ora.e2.shape[1]
+    iu = np.triu_indices(q)
+    diag = np.array([k for k, (i, j) in enumerate(zip(*iu)) if i == j])
+    e3d = np.abs(ora.e3[:, diag, :])                    # [g][q][n] = w E[U_i^2]
+    # natural scale of each entry: |e1| floored at 1, w; for e2_i the RMS
+    # sqrt(w e3_ii); for e3_ik (Cauchy-Schwarz) sqrt(e3_ii e3_kk)
+    scales = {
+        "w": np.abs(ora.w),
+        "e1": np.maximum(np.abs(ora.e1), 1.0),
+        "e2": np.maximum(np.abs(ora.e2), np.sqrt(np.abs(ora.w)[:, None, :] * e3d)),
+        "e3": np.sqrt(e3d[:, iu[0], :] * e3d[:, iu[1], :]),
+    }
     for name in ("w", "e1", "e2", "e3"):
         g = sel(getattr(gpu, name).cpu().numpy().astype(np.float64))
         o = getattr(ora, name)
         m = mask if g.ndim == 2 else mask[:, None, :]
         m = np.broadcast_to(m, o.shape)
-        floor = 1.0 if name == "e1" else 1e-6
-        err = rel_err(g, o, floor)[m]
+        err = (np.abs(g - o) / np.maximum(scales[name], 1e-300))[m]
         if err.size:
-            assert err.max() <= t["eterm"], f"{label} {name} max rel err {err.max():.3e}"
+            assert err.max() <= t["eterm"], f"{label} {name} max scaled err {err.max():.3e}"
     return d_lf.max()

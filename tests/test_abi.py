@@ -1,0 +1,76 @@
+"""Host-side checks of the C-ABI library (no GPU): it loads, it exports every
+entry point include/cfust.h declares, and the binding refuses to run without
+it.  Also checks host logic that needs no device: the lattice design inputs
+and the integral bookkeeping of the bench."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cfust.h")
+LIB = os.path.join(ROOT, "paper_1606_02054_amd", "libcfust.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:cfust_status|const char \*)\s*(\w+)\s*\(", text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def built():
+    if not os.path.exists(LIB):
+        from paper_1606_02054_amd import build
+        build.build()
+    return LIB
+
+
+def test_header_declares_the_four_calls():
+    names = declared_functions()
+    for f in ("cfust_estep", "cfust_mstep", "cfust_loglik", "mvt_cdf_batch"):
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol(built):
+    lib = ctypes.CDLL(built)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    from paper_1606_02054_amd import _binding
+    assert sorted(_binding.EXPORTS) == declared_functions()
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    from paper_1606_02054_amd import _binding
+    with pytest.raises(RuntimeError, match="not found"):
+        _binding._lib = None
+        _binding.load(str(tmp_path / "missing.so"))
+    _binding._lib = None
+
+
+def test_status_codes_match_header():
+    text = open(HEADER).read()
+    from paper_1606_02054_amd import _binding
+    for code, name in _binding.STATUS.items():
+        assert re.search(rf"{name}\s*=\s*{code}\b", text), name
+    for bit, name in _binding.DEV_BITS.items():
+        m = re.search(rf"CFUST_DEV_{name}\s*\(1 << (\d+)\)", text)
+        assert m and (1 << int(m.group(1))) == bit, name
+
+
+def test_lattice_design_inputs():
+    from cfust_inputs import make_design
+    d = make_design(4096, 8, seed=3)
+    assert d.z.shape == (7,) and d.z.dtype == np.int32
+    assert d.z[0] == 1 and np.all(d.z % 2 == 1) and np.all(d.z < 4096)
+    assert d.shifts.shape == (8, 7) and np.all((d.shifts >= 0) & (d.shifts < 1))
+    assert np.array_equal(make_design(4096, 8, seed=3).shifts, d.shifts)
+
+
+def test_bench_flop_bookkeeping():
+    import bench
+    assert bench.integral_dims(4) == [4, 4, 3, 3, 3, 3, 2, 2, 2, 2, 2, 2]
+    assert bench.integral_dims(2) == [2, 2]
+    assert len(bench.integral_dims(8)) == 38
+    assert bench.lattice_flops_per_point(2) == bench.FLOPS_CDF + bench.FLOPS_QUANTILE + 2
