@@ -56,6 +56,9 @@ def main():
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--cpu-rows", type=int, default=0, help="oracle sample rows (0: one per thread)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="first run one device-to-device copy of this many MiB (a known-size "
+                         "reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part of it",
@@ -67,6 +70,14 @@ def main():
 
     import paper_1606_02054_amd as cf
     from cfust_inputs import make_design, workload
+
+    if args.calibrate_copy_mib:
+        src = torch.ones(args.calibrate_copy_mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     ds = workload(args.workload)
     n, p = ds.y.shape
@@ -89,6 +100,7 @@ def main():
         cf.cfust_estep(y, cur, qmc, out=es)
         cf.cfust_mstep(y, es, cur, out=nxt)
 
+    tuned = h.autotune(y, start, qmc)
     for k in range(args.warmup):
         step(k)
     torch.cuda.synchronize()
@@ -129,6 +141,7 @@ def main():
            "data": "synthetic (drawn from the CFUST hierarchy, seeded)",
            "config": {"workload": args.workload, "n": n, "p": p, "q": q, "g": g, "N": N, "S": S,
                       "precision": args.precision, "step": "E-step + M-step (one EM iteration)",
+                      "autotuned_points_per_lane": {f"m{m}": v for m, v in tuned.items()},
                       "loglik_last": ll},
            "roofline": roofline}
 

@@ -158,6 +158,17 @@ cfust_status mvt_cdf_batch(cfust_handle handle, int32_t m, int32_t batch, const 
                            const double *nu, const cfust_qmc *qmc,
                            double *p, double *logp, double *stderr_, void *stream);
 
+/* Autotuner: times the variants of the lattice kernel (lattice points per
+ * lane per loop trip) for every integral dimension these dims use, at this
+ * lattice size and precision, on `stream`, and caches the fastest in the
+ * handle (key: device architecture, m, N, S, precision).  Later calls with
+ * the same key use the cached choice.  Synchronises the stream; call it
+ * outside stream capture.  chosen (optional, host int32[CFUST_MAX_Q+1])
+ * receives the choice per m (0 = not applicable). */
+cfust_status cfust_autotune(cfust_handle handle, const double *y, cfust_dims dims,
+                            const cfust_params *params, const cfust_qmc *qmc, int32_t *chosen,
+                            void *stream);
+
 /* Timing of the lattice-integrand kernels.  While enabled, HIP events
  * bracket the main lattice kernel of each integral dimension launched by
  * cfust_estep / cfust_loglik, on the call's stream (creating events: do not

@@ -59,6 +59,17 @@ class Handle:
         st = self.lib.cfust_reserve(self.h, B.Dims(n, p, q, g), C.byref(qmc.c) if qmc else None)
         B.check(st, self.h, "cfust_reserve")
 
+    def autotune(self, y: torch.Tensor, params: "DeviceParams", qmc: "DeviceQmc", stream=None):
+        """Time the lattice-kernel variants for these shapes and cache the fastest.
+        Returns {m: points_per_lane}."""
+        n = _check_y(y, params.p)
+        ch = (C.c_int32 * (B.MAX_Q + 1))()
+        pc = params.c()
+        st = self.lib.cfust_autotune(self.h, _ptr(y), B.Dims(n, params.p, params.q, params.g), C.byref(pc),
+                                     C.byref(qmc.c), ch, _stream(stream))
+        B.check(st, self.h, "cfust_autotune")
+        return {m: ch[m] for m in range(B.MAX_Q + 1) if ch[m]}
+
     def profile(self, enable: bool = True):
         """Bracket the lattice kernels with HIP events (see cfust_profile_enable)."""
         B.check(self.lib.cfust_profile_enable(self.h, int(bool(enable))), self.h, "cfust_profile_enable")

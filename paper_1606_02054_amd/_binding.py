@@ -25,7 +25,8 @@ DEV_BITS = {1: "NOTSPD_OMEGA", 2: "NOTSPD_LAMBDA", 4: "BADPARAM", 8: "NOTSPD_E3"
             16: "NOTSPD_SIGMA", 32: "FROZEN", 64: "NU_CLAMPED"}
 
 EXPORTS = ["cfust_create", "cfust_destroy", "cfust_last_error", "cfust_estep", "cfust_mstep",
-           "cfust_loglik", "mvt_cdf_batch", "cfust_reserve", "cfust_profile_enable", "cfust_profile_read"]
+           "cfust_loglik", "mvt_cdf_batch", "cfust_reserve", "cfust_profile_enable", "cfust_profile_read",
+           "cfust_autotune"]
 
 
 class Dims(C.Structure):
@@ -75,6 +76,8 @@ def load(path: str = LIB_PATH):
     lib.mvt_cdf_batch.argtypes = [vp, i32, i32, vp, vp, vp, i32, vp, C.POINTER(QmcC), vp, vp, vp, vp]
     lib.cfust_reserve.restype = C.c_int
     lib.cfust_reserve.argtypes = [vp, Dims, C.POINTER(QmcC)]
+    lib.cfust_autotune.restype = C.c_int
+    lib.cfust_autotune.argtypes = [vp, vp, Dims, C.POINTER(ParamsC), C.POINTER(QmcC), C.POINTER(C.c_int32), vp]
     lib.cfust_profile_enable.restype = C.c_int
     lib.cfust_profile_enable.argtypes = [vp, C.c_int]
     lib.cfust_profile_read.restype = C.c_int

@@ -4,8 +4,10 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <map>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "cfust_kernels.h"
@@ -23,6 +25,9 @@ struct cfust_ctx {
     bool prof = false;
     std::vector<ProfRec> rec;        // recorded (pending) event pairs
     std::vector<hipEvent_t> pool;    // free events
+    std::string arch;                // gcnArchName of the device
+    // autotuner cache: (m, N, S, precision) -> lattice points per lane
+    std::map<std::tuple<int, int, int, int>, int> tuned;
 };
 
 namespace {
@@ -161,10 +166,17 @@ hipEvent_t pool_event(cfust_handle h) {
     return e;
 }
 
+int choose_ppl(cfust_handle h, int m, const LatticeArgs &L, bool mixed) {
+    auto it = h->tuned.find(std::make_tuple(m, L.N, L.S, mixed ? 1 : 0));
+    if (it != h->tuned.end()) return it->second;
+    return 1;
+}
+
 hipError_t timed_qmc(cfust_handle h, const EstepQmcArgs &a, int m, int nidx, hipStream_t s) {
-    if (!h->prof || a.n == 0 || nidx == 0) return launch_estep_qmc(a, m, nidx, s);
+    const int ppl = choose_ppl(h, m, a.lat, a.mixed != 0);
+    if (!h->prof || a.n == 0 || nidx == 0) return launch_estep_qmc(a, m, nidx, s, nullptr, nullptr, ppl);
     ProfRec r{m, pool_event(h), pool_event(h)};
-    const hipError_t e = launch_estep_qmc(a, m, nidx, s, r.e0, r.e1);
+    const hipError_t e = launch_estep_qmc(a, m, nidx, s, r.e0, r.e1, ppl);
     if (r.e0 && r.e1) h->rec.push_back(r);
     return e;
 }
@@ -251,6 +263,7 @@ cfust_status cfust_create(cfust_handle *handle, int device) {
     cfust_ctx *c = new (std::nothrow) cfust_ctx;
     if (!c) return CFUST_ENOMEM;
     c->device = device;
+    c->arch = prop.gcnArchName;
     *handle = c;
     return CFUST_OK;
 }
@@ -339,6 +352,60 @@ cfust_status mvt_cdf_batch(cfust_handle h, int32_t m, int32_t batch, const doubl
     a.p = p; a.logp = logp; a.se = stderr_;
     a.flag = at<int32_t>(h, 0);
     return hip_check(h, launch_mvt(a, (hipStream_t)stream), "mvt_cdf_batch launch");
+}
+
+cfust_status cfust_autotune(cfust_handle h, const double *y, cfust_dims d, const cfust_params *P,
+                            const cfust_qmc *Q, int32_t *chosen, void *stream) {
+    if (!h) return CFUST_EINVAL;
+    cfust_status st;
+    if ((st = check_dims(h, d)) != CFUST_OK) return st;
+    if ((st = check_params(h, P)) != CFUST_OK) return st;
+    if ((st = check_qmc(h, Q, d.q >= 2)) != CFUST_OK) return st;
+    if (chosen) for (int m = 0; m <= MAXQ; ++m) chosen[m] = 0;
+    if (d.q < 2 || d.n == 0) return CFUST_OK;
+    if (!y) return fail(h, CFUST_EINVAL, "y is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const bool mixed = Q->precision == CFUST_MIXED;
+    const int J = nint_qmc(d.q);
+    const EstepWs L = estep_layout(d, J, true);
+    if ((st = ensure_ws(h, L.total)) != CFUST_OK) return st;
+    if ((st = hip_check(h, hipSetDevice(h->device), "hipSetDevice")) != CFUST_OK) return st;
+    CompPre *pre = at<CompPre>(h, L.pre);
+    hipError_t e = launch_precompute(*P, d.p, d.q, d.g, pre, s);
+    if (e == hipSuccess && mixed) e = launch_tables(pre, d.p, d.g, d.q + 2, at<float>(h, L.tabs), s);
+    if (e != hipSuccess) return hip_check(h, e, "cfust_autotune");
+    EstepQmcArgs a;
+    a.y = y; a.mu = P->mu; a.pre = pre; a.tabs = at<float>(h, L.tabs);
+    a.lat = lattice_of(Q);
+    a.n = d.n; a.p = d.p; a.q = d.q; a.g = d.g; a.J = J; a.mixed = mixed ? 1 : 0;
+    a.est = at<double>(h, L.est); a.lnA = at<double>(h, L.lnA); a.se = nullptr;
+    a.flag = at<int32_t>(h, L.flag);
+    struct Group { int idx0, m, nidx; };
+    Group groups[3] = {{0, d.q, 2}, {2, d.q - 1, d.q}, {2 + d.q, d.q - 2, npairs(d.q)}};
+    hipEvent_t e0 = pool_event(h), e1 = pool_event(h);
+    if (!e0 || !e1) return fail(h, CFUST_EDEVICE, "cfust_autotune: event creation failed");
+    for (const Group &gr : groups) {
+        if (gr.m < 2) continue;
+        a.idx0 = gr.idx0;
+        int best = 1;
+        float best_ms = 1e30f;
+        const int maxp = (mixed && a.lat.N % 128 == 0) ? 2 : 1;
+        for (int ppl = 1; ppl <= maxp; ++ppl) {
+            float t = 0.0f;
+            e = launch_estep_qmc(a, gr.m, gr.nidx, s, nullptr, nullptr, ppl);          // warm
+            if (e == hipSuccess) e = launch_estep_qmc(a, gr.m, gr.nidx, s, e0, e1, ppl);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+            if (e != hipSuccess) break;
+            if (t < best_ms) { best_ms = t; best = ppl; }
+        }
+        if (e != hipSuccess) break;
+        h->tuned[std::make_tuple(gr.m, a.lat.N, a.lat.S, mixed ? 1 : 0)] = best;
+        if (chosen) chosen[gr.m] = best;
+    }
+    h->pool.push_back(e0);
+    h->pool.push_back(e1);
+    return hip_check(h, e, "cfust_autotune");
 }
 
 cfust_status cfust_profile_enable(cfust_handle h, int enable) {

@@ -312,7 +312,7 @@ __device__ inline const double *integral_limits(const IntDesc &D, const CompPre 
 // block share the integral's tables.  MIXED: FP32 integrand, items whose FP32
 // product underflows are flagged for the FP64 pass.  !MIXED: FP64 integrand;
 // with FLAGGED_ONLY it processes only the flagged items.
-template <int M, bool MIXED, bool FLAGGED_ONLY>
+template <int M, bool MIXED, bool FLAGGED_ONLY, int PPL>
 __global__ __launch_bounds__(256) void k_estep_qmc(EstepQmcArgs a) {
     __shared__ __align__(16) float tab[MIXED ? M * TAB_FLOATS : 4];
     __shared__ double smean[4][MAXS];
@@ -337,7 +337,7 @@ __global__ __launch_bounds__(256) void k_estep_qmc(EstepQmcArgs a) {
     double est = 0.0, se = 0.0, lnest = -INFINITY;
     if (H.e0 > 0.0 || H.lne0 > -INFINITY) {
         if (MIXED) {
-            const bool ok = sov_mixed<M>(H, b, L, nu0, a.lat, tab, smean[wave], lane);
+            const bool ok = sov_mixed<M, PPL>(H, b, L, nu0, a.lat, tab, smean[wave], lane);
             if (lane == 0) a.flag[o] = ok ? 0 : 1;
             if (!ok) return;
         } else {
@@ -569,7 +569,8 @@ __global__ __launch_bounds__(256) void k_mvt(MvtArgs a) {
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
-            const bool ok = sov_mixed<M>(H, b, L, nu, a.lat, tab[wave], smean[wave], lane);
+            const bool ok = (a.lat.N % 128 == 0) ? sov_mixed<M, 2>(H, b, L, nu, a.lat, tab[wave], smean[wave], lane)
+                                                 : sov_mixed<M, 1>(H, b, L, nu, a.lat, tab[wave], smean[wave], lane);
             if (lane == 0) a.flag[it] = ok ? 0 : 1;
             if (!ok) return;
         } else {
@@ -619,30 +620,32 @@ hipError_t launch_tables(const CompPre *pre, int p, int g, int ndof, float *tabs
 }
 
 template <int M>
-static void launch_qmc_m(const EstepQmcArgs &a, int nidx, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+static void launch_qmc_m(const EstepQmcArgs &a, int nidx, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, int ppl) {
     dim3 grid((a.n + 3) / 4, nidx, a.g);
-    if (ev0) hipEventRecord(ev0, s);
+    if (ev0) (void)hipEventRecord(ev0, s);
     if (a.mixed) {
-        hipLaunchKernelGGL((k_estep_qmc<M, true, false>), grid, dim3(256), 0, s, a);
-        if (ev1) hipEventRecord(ev1, s);
-        hipLaunchKernelGGL((k_estep_qmc<M, false, true>), grid, dim3(256), 0, s, a);
+        if (ppl == 2) hipLaunchKernelGGL((k_estep_qmc<M, true, false, 2>), grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_estep_qmc<M, true, false, 1>), grid, dim3(256), 0, s, a);
+        if (ev1) (void)hipEventRecord(ev1, s);
+        hipLaunchKernelGGL((k_estep_qmc<M, false, true, 1>), grid, dim3(256), 0, s, a);
     } else {
-        hipLaunchKernelGGL((k_estep_qmc<M, false, false>), grid, dim3(256), 0, s, a);
-        if (ev1) hipEventRecord(ev1, s);
+        hipLaunchKernelGGL((k_estep_qmc<M, false, false, 1>), grid, dim3(256), 0, s, a);
+        if (ev1) (void)hipEventRecord(ev1, s);
     }
 }
 
 hipError_t launch_estep_qmc(const EstepQmcArgs &a, int m, int nidx, hipStream_t s, hipEvent_t ev0,
-                            hipEvent_t ev1) {
+                            hipEvent_t ev1, int ppl) {
     if (a.n == 0 || nidx == 0) return hipSuccess;
+    if (a.lat.N % 128 != 0) ppl = 1;
     switch (m) {
-    case 2: launch_qmc_m<2>(a, nidx, s, ev0, ev1); break;
-    case 3: launch_qmc_m<3>(a, nidx, s, ev0, ev1); break;
-    case 4: launch_qmc_m<4>(a, nidx, s, ev0, ev1); break;
-    case 5: launch_qmc_m<5>(a, nidx, s, ev0, ev1); break;
-    case 6: launch_qmc_m<6>(a, nidx, s, ev0, ev1); break;
-    case 7: launch_qmc_m<7>(a, nidx, s, ev0, ev1); break;
-    case 8: launch_qmc_m<8>(a, nidx, s, ev0, ev1); break;
+    case 2: launch_qmc_m<2>(a, nidx, s, ev0, ev1, ppl); break;
+    case 3: launch_qmc_m<3>(a, nidx, s, ev0, ev1, ppl); break;
+    case 4: launch_qmc_m<4>(a, nidx, s, ev0, ev1, ppl); break;
+    case 5: launch_qmc_m<5>(a, nidx, s, ev0, ev1, ppl); break;
+    case 6: launch_qmc_m<6>(a, nidx, s, ev0, ev1, ppl); break;
+    case 7: launch_qmc_m<7>(a, nidx, s, ev0, ev1, ppl); break;
+    case 8: launch_qmc_m<8>(a, nidx, s, ev0, ev1, ppl); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

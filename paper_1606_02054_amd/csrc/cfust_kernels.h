@@ -78,9 +78,10 @@ hipError_t launch_tables(const CompPre *pre, int p, int g, int ndof, float *tabs
 // Lattice integrals idx0 .. idx0+nidx-1 of every pair; all must share the
 // same dimension m >= 2.  In mixed mode the FP32 kernel runs first and an
 // FP64 pass then redoes only the flagged (underflowed) items.
-// ev0/ev1 (optional) bracket the main kernel of the launch.
+// ev0/ev1 (optional) bracket the main kernel of the launch; ppl = lattice
+// points per lane per loop trip of the FP32 kernel (1 or 2).
 hipError_t launch_estep_qmc(const EstepQmcArgs &a, int m, int nidx, hipStream_t s,
-                            hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                            hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, int ppl = 1);
 hipError_t launch_assemble(const EstepAsmArgs &a, hipStream_t s);
 hipError_t launch_lse(const EstepLseArgs &a, double *loglik, hipStream_t s);
 hipError_t launch_mvt(const MvtArgs &a, hipStream_t s);

@@ -105,16 +105,17 @@ __device__ double sov_lane_sum64(const double *b, const double *L, double nu, co
 
 // ------------------------------------------------------------- FP32 path ---
 
-// Lattice coordinate (FP32): t in 32-bit fixed point so that both x = 2 min(t, 1-t)
-// and xb = 1 - x keep full relative accuracy near 0.  Needs N a power of two.
+// Lattice coordinate (FP32): t in 32-bit fixed point so that x = 2 min(t, 1-t)
+// keeps full relative accuracy near 0 (it enters log2 x in the lower tail);
+// xb = 1 - x only enters the upper-tail complement.  Needs N a power of two.
 __device__ __forceinline__ void point32(uint32_t k, uint32_t zj, uint32_t mask, int sh, uint32_t shfix,
                                         float &x, float &xb) {
     const uint32_t r = (k * zj) & mask;
     const uint32_t t = (r << sh) + shfix;
     uint32_t u = min(t, 0u - t);                      // 2^32 min(t, 1-t), in [0, 2^31]
     u = min(max(u, 128u), 2147483520u);               // [2^-24, 1 - 2^-24] after scaling
-    x = (float)u * 4.656612873077393e-10f;            // 2^-31
-    xb = (float)(2147483648u - u) * 4.656612873077393e-10f;
+    x = (float)u * 4.656612873077393e-10f;            // 2^-31, relative accuracy near 0
+    xb = 1.0f - x;                                    // absolute accuracy suffices for 1 - x
 }
 
 __device__ __forceinline__ float quantile_step32(float x, float xb, float e, float eb, float l2e, bool lowt,
@@ -139,39 +140,54 @@ struct Sov32Setup {
     bool low0;
 };
 
+// Integrand value of lattice point k (FP32), product e_1 ... e_{M-1}.
 template <int M>
-__device__ float sov_lane_sum32(const Sov32Setup &P, const float *tabs, uint32_t z0, const uint32_t *zz,
+__device__ __forceinline__ float sov_point32(const Sov32Setup &P, const float *tabs, uint32_t k,
+                                             const uint32_t *zz, uint32_t mask, int sh,
+                                             const uint32_t *shfix) {
+    float y[M];
+    float Q = P.sqrtnu;
+    float x, xb;
+    point32(k, zz[0], mask, sh, shfix[0], x, xb);
+    y[0] = quantile_step32(x, xb, P.e0, P.eb0, P.l2e0, P.low0, tabs, Q);
+    float f = 1.0f;
+#pragma unroll
+    for (int i = 1; i < M; ++i) {
+        float num = P.b[i];
+#pragma unroll
+        for (int j = 0; j < i; ++j) num = fmaf(-P.L[i * M + j], y[j], num);
+        const float LQ = P.L[i * M + i] * Q;
+        const float K = LQ * LQ;
+        const float R = frsq(fmaf(num, num, K));
+        const float tau = K * R * R * frcp(fmaf(fabsf(num), R, 1.0f));
+        const float *tab = tabs + i * TAB_FLOATS;
+        const float l2 = fmaf(P.a[i], flog2(tau), tab_cdf_F(tab, tau));
+        const float small = fexp2(l2);
+        const bool lowt = num <= 0.0f;
+        const float e = lowt ? small : 1.0f - small;
+        const float eb = lowt ? 1.0f - small : small;
+        f *= e;
+        if (i < M - 1) {
+            point32(k, zz[i], mask, sh, shfix[i], x, xb);
+            y[i] = quantile_step32(x, xb, e, eb, l2, lowt, tab, Q);
+        }
+    }
+    return f;
+}
+
+// Per-lane FP32 sum over this lane's points of one shift.  PPL independent
+// points are evaluated per loop trip (instruction-level parallelism across
+// the dependency chains); needs N to be a multiple of 64 PPL when PPL > 1.
+template <int M, int PPL>
+__device__ float sov_lane_sum32(const Sov32Setup &P, const float *tabs, const uint32_t *zz,
                                 uint32_t mask, int sh, const uint32_t *shfix, int N, int lane) {
     float acc = 0.0f;
-    for (int k = lane; k < N; k += 64) {
-        float y[M];
-        float Q = P.sqrtnu;
-        float x, xb;
-        point32((uint32_t)k, z0, mask, sh, shfix[0], x, xb);
-        y[0] = quantile_step32(x, xb, P.e0, P.eb0, P.l2e0, P.low0, tabs, Q);
-        float f = 1.0f;
+    for (int k = lane; k < N; k += 64 * PPL) {
+        float f[PPL];
 #pragma unroll
-        for (int i = 1; i < M; ++i) {
-            float num = P.b[i];
+        for (int u = 0; u < PPL; ++u) f[u] = sov_point32<M>(P, tabs, (uint32_t)(k + 64 * u), zz, mask, sh, shfix);
 #pragma unroll
-            for (int j = 0; j < i; ++j) num = fmaf(-P.L[i * M + j], y[j], num);
-            const float LQ = P.L[i * M + i] * Q;
-            const float K = LQ * LQ;
-            const float R = frsq(fmaf(num, num, K));
-            const float tau = K * R * R * frcp(fmaf(fabsf(num), R, 1.0f));
-            const float *tab = tabs + i * TAB_FLOATS;
-            const float l2 = fmaf(P.a[i], flog2(tau), tab_cdf_F(tab, tau));
-            const float small = fexp2(l2);
-            const bool lowt = num <= 0.0f;
-            const float e = lowt ? small : 1.0f - small;
-            const float eb = lowt ? 1.0f - small : small;
-            f *= e;
-            if (i < M - 1) {
-                point32((uint32_t)k, zz[i], mask, sh, shfix[i], x, xb);
-                y[i] = quantile_step32(x, xb, e, eb, l2, lowt, tab, Q);
-            }
-        }
-        acc += f;
+        for (int u = 0; u < PPL; ++u) acc += f[u];
     }
     return acc;
 }
@@ -223,7 +239,7 @@ __device__ inline void sov_finish(const SovHead &H, const double *smean, int S,
 // FP32 lattice sums (mixed precision).  Returns false when the FP32 product
 // underflowed for the whole item (mean below 1e-30): the caller then redoes
 // the item in FP64.  tabs: LDS tables of dofs nu .. nu+M-1.
-template <int M>
+template <int M, int PPL>
 __device__ bool sov_mixed(const SovHead &H, const double *b, const double *L, double nu, const Lattice &Lt,
                           const float *tabs, double *smean, int lane) {
     Sov32Setup P;
@@ -242,7 +258,7 @@ __device__ bool sov_mixed(const SovHead &H, const double *b, const double *L, do
     for (int s = 0; s < Lt.S; ++s) {
 #pragma unroll
         for (int i = 0; i < M - 1; ++i) shfix[i] = (uint32_t)(Lt.shifts[s * LATD + i] * 4294967296.0);
-        const float ls = sov_lane_sum32<M>(P, tabs, zz[0], zz, mask, sh, shfix, Lt.N, lane);
+        const float ls = sov_lane_sum32<M, PPL>(P, tabs, zz, mask, sh, shfix, Lt.N, lane);
         const double ms = wave_sum((double)ls) / (double)Lt.N;
         if (lane == 0) smean[s] = ms;
         tot += ms;
