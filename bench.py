@@ -35,6 +35,25 @@ FLOPS_CDF = 32               # conditional truncation probability e_i
 FLOPS_QUANTILE = 29          # quantile draw y_i
 
 
+# HBM bytes of the FP32 lattice kernels per E-step of the default workload,
+# from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a 1 GiB copy
+# (profiles/k_estep_qmc_cfust_n20000_p4_q4_g3_counters.md), valid for the
+# kernel sources with this digest only; otherwise the figure is reported null.
+TRAFFIC_SOURCES = ["paper_1606_02054_amd/csrc/cfust_sov.h", "paper_1606_02054_amd/csrc/cfust_devmath.h",
+                   "paper_1606_02054_amd/csrc/cfust_estep.hip"]
+TRAFFIC_DIGEST = "29ac73d40971f146"
+TRAFFIC_MIB = {"read": 3.38 + 2.97 + 2.97, "write": 2.44 + 3.66 + 5.49}
+
+
+def kernel_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def lattice_flops_per_point(m: int) -> int:
     """Flops of one lattice point of an m-variate T_m: quantiles for
     coordinates 0..m-2, probabilities for 1..m-1, plus the Cholesky rows
@@ -130,8 +149,12 @@ def main():
     per_kernel = {f"m{m}": {"avg_ms": prof[m][0] / prof[m][1],
                             "tflops": flops_by_m[m] / (prof[m][0] / prof[m][1] / 1e3) / 1e12}
                   for m in sorted(prof) if m in flops_by_m}
+    traffic = None
+    if args.workload == "cfust_n20000_p4_q4_g3" and prec == cf.CFUST_MIXED and kernel_digest() == TRAFFIC_DIGEST:
+        traffic = {"bytes_per_estep": (TRAFFIC_MIB["read"] + TRAFFIC_MIB["write"]) * (1 << 20),
+                   "read_MiB": TRAFFIC_MIB["read"], "write_MiB": TRAFFIC_MIB["write"]}
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": (achieved / PEAK_FP32_TFLOPS) if achieved else None, "traffic": None,
+                "frac": (achieved / PEAK_FP32_TFLOPS) if achieved else None, "traffic": traffic,
                 "kernel": "k_estep_qmc (FP32 lattice integrand, all dimensions of one E-step)",
                 "lattice_ms_per_step": lat_ms, "per_kernel": per_kernel}
 
