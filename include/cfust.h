@@ -158,6 +158,96 @@ cfust_status mvt_cdf_batch(cfust_handle handle, int32_t m, int32_t batch, const 
                            const double *nu, const cfust_qmc *qmc,
                            double *p, double *logp, double *stderr_, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Surrogate network (learned replacement of the lattice estimate of T_m,
+ * m = 2..4, with the lattice as fallback).  A 16 -> 256 -> 256 -> 256 -> 256
+ * -> 16 perceptron, tanh-form GELU, BF16 weights/activations, FP32
+ * accumulation on the matrix cores, FP32 master weights and Adam.  Input
+ * features (FP32 before rounding to BF16): the m standardised limits b_i/6,
+ * the m(m-1)/2 correlations, (ln nu - ln 2)/(ln 30 - ln 2), zero padding;
+ * output 0 is ln T_m / 10, output 1 the predicted log10 of its absolute
+ * error.  All buffers are device memory owned by the caller; B (rows) must
+ * be a positive multiple of 64; rows are independent.
+ * ---------------------------------------------------------------------- */
+#define CFUST_MLP_IN 16
+#define CFUST_MLP_HIDDEN 256
+#define CFUST_MLP_OUT 16
+#define CFUST_MLP_LAYERS 5
+
+/* Layer l maps K_l -> N_l (K = 16, 256, 256, 256, 256; N = 256, 256, 256, 256, 16).
+ * W[l]: BF16 [N_l][K_l]; Wt[l]: the same matrix transposed, BF16 [K_l][N_l];
+ * b[l]: FP32 [N_l]. */
+typedef struct {
+    void *W[CFUST_MLP_LAYERS];
+    void *Wt[CFUST_MLP_LAYERS];
+    float *b[CFUST_MLP_LAYERS];
+} cfust_mlp_weights;
+
+/* Saved activations for the backward pass: X[l] = input of layer l, BF16
+ * [B][K_l] (X[0] is written as a copy of the input); XT[l] its transpose
+ * [K_l][B]; Z[l] = pre-activation of hidden layer l, FP32 [B][N_l], l < 4. */
+typedef struct {
+    uint16_t *X[CFUST_MLP_LAYERS];
+    uint16_t *XT[CFUST_MLP_LAYERS];
+    float *Z[CFUST_MLP_LAYERS - 1];
+} cfust_mlp_acts;
+
+/* Gradients: dW[l] FP32 [N_l][K_l], db[l] FP32 [N_l] (overwritten). */
+typedef struct {
+    float *dW[CFUST_MLP_LAYERS];
+    float *db[CFUST_MLP_LAYERS];
+} cfust_mlp_grads;
+
+/* FP32 master weights and Adam moments, same shapes as the gradients. */
+typedef struct {
+    float *W[CFUST_MLP_LAYERS], *mW[CFUST_MLP_LAYERS], *vW[CFUST_MLP_LAYERS];
+    float *b[CFUST_MLP_LAYERS], *mb[CFUST_MLP_LAYERS], *vb[CFUST_MLP_LAYERS];
+} cfust_mlp_master;
+
+/* Forward pass: out FP32 [B][CFUST_MLP_OUT].  X0: BF16 [B][CFUST_MLP_IN].
+ * acts (optional) receives what cfust_mlp_backward needs. */
+cfust_status cfust_mlp_forward(cfust_handle handle, const cfust_mlp_weights *w, const uint16_t *X0,
+                               int32_t B, float *out, const cfust_mlp_acts *acts, void *stream);
+/* Backward pass from dout = dLoss/dout (FP32 [B][CFUST_MLP_OUT]) through the
+ * activations saved by the forward pass; writes grads. */
+cfust_status cfust_mlp_backward(cfust_handle handle, const cfust_mlp_weights *w, const cfust_mlp_acts *acts,
+                                const float *dout, int32_t B, const cfust_mlp_grads *grads, void *stream);
+/* Adam step `step` (1-based) on the master weights; refreshes the BF16 W, Wt. */
+cfust_status cfust_mlp_adam(cfust_handle handle, const cfust_mlp_master *master, const cfust_mlp_grads *grads,
+                            const cfust_mlp_weights *w, float lr, float beta1, float beta2, float eps,
+                            int32_t step, void *stream);
+/* Training loss: sum over the first nvalid rows of (out0 - label)^2 +
+ * lam (out1 - log10(|out0 - label| + 1e-6))^2 into loss_sum[1], and its
+ * gradient divided by nvalid into dout (padding rows get 0). */
+cfust_status cfust_mlp_loss(cfust_handle handle, const float *out, const float *label, int32_t B,
+                            int32_t nvalid, float lam, float *dout, float *loss_sum, void *stream);
+
+/* Surrogate configuration for cfust_estep_surrogate.  model[m] (m = 2..4)
+ * holds the trained weights of the network for T_m, or NULL to use the
+ * lattice for that dimension.  A lattice integral is answered by the network
+ * when its inputs lie in the training domain and the predicted absolute
+ * error of ln T_m is at most tol; otherwise the lattice estimate is used.
+ * tol = 0 therefore reproduces cfust_estep exactly. */
+typedef struct {
+    const cfust_mlp_weights *model[CFUST_MAX_Q + 1];
+    float tol;
+    int32_t *n_fallback;   /* optional device int32[1]: integrals sent to the lattice */
+} cfust_surrogate;
+
+/* E-step with the surrogate for the T_m of dimension 2..4 (same outputs as
+ * cfust_estep; cdf_stderr is left unwritten for network-answered items). */
+cfust_status cfust_estep_surrogate(cfust_handle handle, const double *y, cfust_dims dims,
+                                   const cfust_params *params, const cfust_qmc *qmc,
+                                   const cfust_surrogate *sur, const cfust_estep_out *out, void *stream);
+
+/* Network features of a batch of T_m problems (same arguments as
+ * mvt_cdf_batch): X0 BF16 [rows_pad][CFUST_MLP_IN] (rows >= batch zeroed),
+ * inrange (optional) int32 [batch]: 1 inside the training domain
+ * (|b_i / sqrt(R_ii)| <= 6, 2 <= nu <= 30). */
+cfust_status cfust_mlp_features(cfust_handle handle, int32_t m, int32_t batch, int32_t rows_pad,
+                                const double *b, const double *L, const int32_t *mat_idx, int32_t nmat,
+                                const double *nu, uint16_t *X0, int32_t *inrange, void *stream);
+
 /* Autotuner: times the variants of the lattice kernel (lattice points per
  * lane per loop trip) for every integral dimension these dims use, at this
  * lattice size and precision, on `stream`, and caches the fastest in the

@@ -17,6 +17,9 @@ CFUST_FP64 = 0
 CFUST_MIXED = 1
 LATTICE_DIM = 7
 MAX_P, MAX_Q, MAX_G, MAX_SHIFTS = 16, 8, 64, 64
+MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_LAYERS = 16, 256, 16, 5
+MLP_K = [MLP_IN, MLP_HIDDEN, MLP_HIDDEN, MLP_HIDDEN, MLP_HIDDEN]
+MLP_N = [MLP_HIDDEN, MLP_HIDDEN, MLP_HIDDEN, MLP_HIDDEN, MLP_OUT]
 
 STATUS = {0: "CFUST_OK", -1: "CFUST_EINVAL", -2: "CFUST_ENOTSPD", -3: "CFUST_ENUMERIC",
           -4: "CFUST_EDEVICE", -5: "CFUST_ENOMEM", -6: "CFUST_EUNSUPPORTED"}
@@ -26,7 +29,8 @@ DEV_BITS = {1: "NOTSPD_OMEGA", 2: "NOTSPD_LAMBDA", 4: "BADPARAM", 8: "NOTSPD_E3"
 
 EXPORTS = ["cfust_create", "cfust_destroy", "cfust_last_error", "cfust_estep", "cfust_mstep",
            "cfust_loglik", "mvt_cdf_batch", "cfust_reserve", "cfust_profile_enable", "cfust_profile_read",
-           "cfust_autotune"]
+           "cfust_autotune", "cfust_mlp_forward", "cfust_mlp_backward", "cfust_mlp_adam",
+           "cfust_mlp_loss", "cfust_mlp_features", "cfust_estep_surrogate"]
 
 
 class Dims(C.Structure):
@@ -47,6 +51,26 @@ class EstepOutC(C.Structure):
     _fields_ = [("tau", C.c_void_p), ("logf_obs", C.c_void_p), ("loglik", C.c_void_p),
                 ("w", C.c_void_p), ("e1", C.c_void_p), ("e2", C.c_void_p), ("e3", C.c_void_p),
                 ("logf_comp", C.c_void_p), ("cdf_stderr", C.c_void_p), ("status", C.c_void_p)]
+
+
+class MlpWeightsC(C.Structure):
+    _fields_ = [("W", C.c_void_p * MLP_LAYERS), ("Wt", C.c_void_p * MLP_LAYERS), ("b", C.c_void_p * MLP_LAYERS)]
+
+
+class MlpActsC(C.Structure):
+    _fields_ = [("X", C.c_void_p * MLP_LAYERS), ("XT", C.c_void_p * MLP_LAYERS), ("Z", C.c_void_p * (MLP_LAYERS - 1))]
+
+
+class MlpGradsC(C.Structure):
+    _fields_ = [("dW", C.c_void_p * MLP_LAYERS), ("db", C.c_void_p * MLP_LAYERS)]
+
+
+class MlpMasterC(C.Structure):
+    _fields_ = [(k, C.c_void_p * MLP_LAYERS) for k in ("W", "mW", "vW", "b", "mb", "vb")]
+
+
+class SurrogateC(C.Structure):
+    _fields_ = [("model", C.c_void_p * (MAX_Q + 1)), ("tol", C.c_float), ("n_fallback", C.c_void_p)]
 
 
 _lib = None
@@ -76,6 +100,22 @@ def load(path: str = LIB_PATH):
     lib.mvt_cdf_batch.argtypes = [vp, i32, i32, vp, vp, vp, i32, vp, C.POINTER(QmcC), vp, vp, vp, vp]
     lib.cfust_reserve.restype = C.c_int
     lib.cfust_reserve.argtypes = [vp, Dims, C.POINTER(QmcC)]
+    f = C.c_float
+    lib.cfust_mlp_forward.restype = C.c_int
+    lib.cfust_mlp_forward.argtypes = [vp, C.POINTER(MlpWeightsC), vp, i32, vp, C.POINTER(MlpActsC), vp]
+    lib.cfust_mlp_backward.restype = C.c_int
+    lib.cfust_mlp_backward.argtypes = [vp, C.POINTER(MlpWeightsC), C.POINTER(MlpActsC), vp, i32,
+                                       C.POINTER(MlpGradsC), vp]
+    lib.cfust_mlp_adam.restype = C.c_int
+    lib.cfust_mlp_adam.argtypes = [vp, C.POINTER(MlpMasterC), C.POINTER(MlpGradsC), C.POINTER(MlpWeightsC),
+                                   f, f, f, f, i32, vp]
+    lib.cfust_mlp_loss.restype = C.c_int
+    lib.cfust_mlp_loss.argtypes = [vp, vp, vp, i32, i32, f, vp, vp, vp]
+    lib.cfust_mlp_features.restype = C.c_int
+    lib.cfust_mlp_features.argtypes = [vp, i32, i32, i32, vp, vp, vp, i32, vp, vp, vp, vp]
+    lib.cfust_estep_surrogate.restype = C.c_int
+    lib.cfust_estep_surrogate.argtypes = [vp, vp, Dims, C.POINTER(ParamsC), C.POINTER(QmcC), C.POINTER(SurrogateC),
+                                          C.POINTER(EstepOutC), vp]
     lib.cfust_autotune.restype = C.c_int
     lib.cfust_autotune.argtypes = [vp, vp, Dims, C.POINTER(ParamsC), C.POINTER(QmcC), C.POINTER(C.c_int32), vp]
     lib.cfust_profile_enable.restype = C.c_int

@@ -124,6 +124,18 @@ cfust_status check_params(cfust_handle h, const cfust_params *P) {
     return CFUST_OK;
 }
 
+cfust_status check_mlp_b(cfust_handle h, int32_t B) {
+    if (B <= 0 || B % 64) return fail(h, CFUST_EINVAL, "B = %d is not a positive multiple of 64", B);
+    return CFUST_OK;
+}
+
+bool weights_ok(const cfust_mlp_weights *w) {
+    if (!w) return false;
+    for (int l = 0; l < CFUST_MLP_LAYERS; ++l)
+        if (!w->W[l] || !w->Wt[l] || !w->b[l]) return false;
+    return true;
+}
+
 // Workspace layout of an E-step (or log-likelihood) call.
 struct EstepWs {
     size_t pre, tabs, est, lnA, flag, logf, partial, total;
@@ -182,10 +194,12 @@ hipError_t timed_qmc(cfust_handle h, const EstepQmcArgs &a, int m, int nidx, hip
 }
 
 // Shared launch sequence of cfust_estep / cfust_loglik.
+constexpr int SUR_CHUNK = 65536;   // network rows per forward launch
+
 cfust_status run_estep(cfust_handle h, const double *y, const cfust_dims &d, const cfust_params *P,
                        const cfust_qmc *Q, bool density_only, double *tau, double *logf_obs, double *loglik,
                        void *w, void *e1, void *e2, void *e3, double *logf_comp, double *se,
-                       int32_t *status, hipStream_t s) {
+                       int32_t *status, hipStream_t s, const cfust_surrogate *sur = nullptr) {
     cfust_status st;
     if ((st = check_dims(h, d)) != CFUST_OK) return st;
     if ((st = check_params(h, P)) != CFUST_OK) return st;
@@ -198,14 +212,72 @@ cfust_status run_estep(cfust_handle h, const double *y, const cfust_dims &d, con
     const bool mixed = Q->precision == CFUST_MIXED;
     const int J = density_only ? (lattice ? 1 : 0) : nint_qmc(d.q);
     const EstepWs L = estep_layout(d, J, logf_comp == nullptr);
-    if ((st = ensure_ws(h, L.total)) != CFUST_OK) return st;
+    // surrogate workspace: need flags, and per dimension group features/outputs
+    struct SurGroup { int m, idx0, cnt; long rows, rows_pad; size_t x0, out, inr; };
+    SurGroup sg[3];
+    int nsg = 0;
+    size_t need_off = 0, sa_off = 0, sb_off = 0, total = L.total;
+    if (sur && J > 0) {
+        Carve c;
+        c.off = L.total;
+        need_off = c.take<int32_t>((size_t)d.g * J * (d.n > 0 ? d.n : 1));
+        const int gm[3][3] = {{d.q, 0, 2}, {d.q - 1, 2, d.q}, {d.q - 2, 2 + d.q, npairs(d.q)}};
+        for (int k = 0; k < 3; ++k) {
+            const int m = gm[k][0];
+            if (m < 2 || m > MAXQ || !sur->model[m] || gm[k][1] + gm[k][2] > J) continue;
+            if (!weights_ok(sur->model[m])) return fail(h, CFUST_EINVAL, "surrogate model for m = %d is incomplete", m);
+            SurGroup G;
+            G.m = m; G.idx0 = gm[k][1]; G.cnt = gm[k][2];
+            G.rows = (long)d.g * G.cnt * d.n;
+            G.rows_pad = (G.rows + 63) / 64 * 64;
+            G.x0 = c.take<uint16_t>((size_t)(G.rows_pad > 0 ? G.rows_pad : 64) * CFUST_MLP_IN);
+            G.out = c.take<float>((size_t)(G.rows_pad > 0 ? G.rows_pad : 64) * CFUST_MLP_OUT);
+            G.inr = c.take<int32_t>((size_t)(G.rows > 0 ? G.rows : 1));
+            sg[nsg++] = G;
+        }
+        sa_off = c.take<uint16_t>((size_t)SUR_CHUNK * CFUST_MLP_HIDDEN);
+        sb_off = c.take<uint16_t>((size_t)SUR_CHUNK * CFUST_MLP_HIDDEN);
+        total = c.off;
+    }
+    if ((st = ensure_ws(h, total)) != CFUST_OK) return st;
     if ((st = hip_check(h, hipSetDevice(h->device), "hipSetDevice")) != CFUST_OK) return st;
     CompPre *pre = at<CompPre>(h, L.pre);
     double *lfc = logf_comp ? logf_comp : at<double>(h, L.logf);
     hipError_t e = launch_precompute(*P, d.p, d.q, d.g, pre, s);
     if (e == hipSuccess && mixed && J > 0) e = launch_tables(pre, d.p, d.g, d.q + 2, at<float>(h, L.tabs), s);
+    int32_t *need = nullptr;
+    if (e == hipSuccess && sur && J > 0) {
+        need = at<int32_t>(h, need_off);
+        e = launch_fill_i32(need, (size_t)d.g * J * d.n, 1, s);
+        for (int k = 0; k < nsg && e == hipSuccess; ++k) {
+            const SurGroup &G = sg[k];
+            if (G.rows == 0) continue;
+            SurFeatArgs fa;
+            fa.y = y; fa.mu = P->mu; fa.pre = pre;
+            fa.n = d.n; fa.p = d.p; fa.q = d.q; fa.g = d.g; fa.J = J;
+            fa.m = G.m; fa.idx0 = G.idx0; fa.cnt = G.cnt;
+            fa.X0 = at<uint16_t>(h, G.x0); fa.inrange = at<int32_t>(h, G.inr);
+            e = launch_sur_features(fa, s);
+            if (e == hipSuccess && G.rows_pad > G.rows)
+                e = launch_fill_i32((int32_t *)(fa.X0 + (size_t)G.rows * CFUST_MLP_IN),
+                                    (size_t)(G.rows_pad - G.rows) * CFUST_MLP_IN / 2, 0, s);
+            for (long r = 0; r < G.rows_pad && e == hipSuccess; r += SUR_CHUNK) {
+                const int B = (int)(G.rows_pad - r < SUR_CHUNK ? G.rows_pad - r : SUR_CHUNK);
+                e = launch_mlp_forward(*sur->model[G.m], fa.X0 + (size_t)r * CFUST_MLP_IN, B,
+                                       at<float>(h, G.out) + (size_t)r * CFUST_MLP_OUT, nullptr,
+                                       at<uint16_t>(h, sa_off), at<uint16_t>(h, sb_off), s);
+            }
+            if (e != hipSuccess) break;
+            SurSelArgs sa;
+            sa.n = d.n; sa.g = d.g; sa.J = J; sa.m = G.m; sa.idx0 = G.idx0; sa.cnt = G.cnt;
+            sa.out = at<float>(h, G.out); sa.inrange = at<int32_t>(h, G.inr); sa.tol = sur->tol;
+            sa.est = at<double>(h, L.est); sa.lnA = at<double>(h, L.lnA); sa.need = need;
+            e = launch_sur_select(sa, s);
+        }
+    }
     if (e == hipSuccess && J > 0) {
         EstepQmcArgs a;
+        a.need = need;
         a.y = y; a.mu = P->mu; a.pre = pre; a.tabs = at<float>(h, L.tabs);
         a.lat = lattice_of(Q);
         a.n = d.n; a.p = d.p; a.q = d.q; a.g = d.g; a.J = J; a.mixed = mixed ? 1 : 0;
@@ -244,6 +316,10 @@ cfust_status run_estep(cfust_handle h, const double *y, const cfust_dims &d, con
         e = launch_lse(a, loglik, s);
     }
     if (e == hipSuccess && status) e = launch_status_fold(pre, d.g, status, s);
+    if (e == hipSuccess && sur && sur->n_fallback) {
+        if (need) e = launch_count_i32(need, (size_t)d.g * J * d.n, sur->n_fallback, s);
+        else e = launch_fill_i32(sur->n_fallback, 1, 0, s);
+    }
     return hip_check(h, e, density_only ? "cfust_loglik launch" : "cfust_estep launch");
 }
 
@@ -288,6 +364,31 @@ cfust_status cfust_estep(cfust_handle h, const double *y, cfust_dims dims, const
     if (!out) return fail(h, CFUST_EINVAL, "out is NULL");
     return run_estep(h, y, dims, params, qmc, false, out->tau, out->logf_obs, out->loglik, out->w, out->e1,
                      out->e2, out->e3, out->logf_comp, out->cdf_stderr, out->status, (hipStream_t)stream);
+}
+
+cfust_status cfust_estep_surrogate(cfust_handle h, const double *y, cfust_dims dims, const cfust_params *params,
+                                   const cfust_qmc *qmc, const cfust_surrogate *sur, const cfust_estep_out *out,
+                                   void *stream) {
+    if (!h) return CFUST_EINVAL;
+    if (!out) return fail(h, CFUST_EINVAL, "out is NULL");
+    if (!sur) return fail(h, CFUST_EINVAL, "sur is NULL");
+    return run_estep(h, y, dims, params, qmc, false, out->tau, out->logf_obs, out->loglik, out->w, out->e1,
+                     out->e2, out->e3, out->logf_comp, out->cdf_stderr, out->status, (hipStream_t)stream, sur);
+}
+
+cfust_status cfust_mlp_features(cfust_handle h, int32_t m, int32_t batch, int32_t rows_pad, const double *b,
+                                const double *L, const int32_t *mat_idx, int32_t nmat, const double *nu,
+                                uint16_t *X0, int32_t *inrange, void *stream) {
+    if (!h) return CFUST_EINVAL;
+    if (m < 2 || m > MAXQ) return fail(h, CFUST_EINVAL, "m = %d outside [2, %d]", m, MAXQ);
+    if (batch < 0 || rows_pad < batch) return fail(h, CFUST_EINVAL, "rows_pad < batch");
+    if (nmat < 1) return fail(h, CFUST_EINVAL, "nmat < 1");
+    if (!X0 || (batch > 0 && (!b || !L || !mat_idx || !nu))) return fail(h, CFUST_EINVAL, "a buffer is NULL");
+    cfust_status st;
+    if ((st = hip_check(h, hipSetDevice(h->device), "hipSetDevice")) != CFUST_OK) return st;
+    return hip_check(h, launch_mvt_features(m, batch, rows_pad, b, L, mat_idx, nmat, nu, X0, inrange,
+                                            (hipStream_t)stream),
+                     "cfust_mlp_features");
 }
 
 cfust_status cfust_loglik(cfust_handle h, const double *y, cfust_dims dims, const cfust_params *params,
@@ -380,6 +481,7 @@ cfust_status cfust_autotune(cfust_handle h, const double *y, cfust_dims d, const
     a.n = d.n; a.p = d.p; a.q = d.q; a.g = d.g; a.J = J; a.mixed = mixed ? 1 : 0;
     a.est = at<double>(h, L.est); a.lnA = at<double>(h, L.lnA); a.se = nullptr;
     a.flag = at<int32_t>(h, L.flag);
+    a.need = nullptr;
     struct Group { int idx0, m, nidx; };
     Group groups[3] = {{0, d.q, 2}, {2, d.q - 1, d.q}, {2 + d.q, d.q - 2, npairs(d.q)}};
     hipEvent_t e0 = pool_event(h), e1 = pool_event(h);
@@ -406,6 +508,81 @@ cfust_status cfust_autotune(cfust_handle h, const double *y, cfust_dims d, const
     h->pool.push_back(e0);
     h->pool.push_back(e1);
     return hip_check(h, e, "cfust_autotune");
+}
+
+// ------------------------------------------------------------- surrogate MLP
+
+
+cfust_status cfust_mlp_forward(cfust_handle h, const cfust_mlp_weights *w, const uint16_t *X0, int32_t B,
+                               float *out, const cfust_mlp_acts *acts, void *stream) {
+    if (!h) return CFUST_EINVAL;
+    cfust_status st;
+    if ((st = check_mlp_b(h, B)) != CFUST_OK) return st;
+    if (!weights_ok(w) || !X0 || !out) return fail(h, CFUST_EINVAL, "a network buffer is NULL");
+    if (acts) {
+        for (int l = 0; l < CFUST_MLP_LAYERS; ++l)
+            if (!acts->X[l] || !acts->XT[l] || (l < CFUST_MLP_LAYERS - 1 && !acts->Z[l]))
+                return fail(h, CFUST_EINVAL, "an activation buffer is NULL");
+    }
+    Carve c;
+    const size_t sa = c.take<uint16_t>((size_t)B * CFUST_MLP_HIDDEN);
+    const size_t sb = c.take<uint16_t>((size_t)B * CFUST_MLP_HIDDEN);
+    if (!acts && (st = ensure_ws(h, c.off)) != CFUST_OK) return st;
+    if ((st = hip_check(h, hipSetDevice(h->device), "hipSetDevice")) != CFUST_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    const uint16_t *x0 = X0;
+    if (acts) {
+        e = launch_transpose_in(X0, B, acts->X[0], acts->XT[0], s);
+        x0 = acts->X[0];
+    }
+    if (e == hipSuccess)
+        e = launch_mlp_forward(*w, x0, B, out, acts, acts ? nullptr : at<uint16_t>(h, sa),
+                               acts ? nullptr : at<uint16_t>(h, sb), s);
+    return hip_check(h, e, "cfust_mlp_forward");
+}
+
+cfust_status cfust_mlp_backward(cfust_handle h, const cfust_mlp_weights *w, const cfust_mlp_acts *acts,
+                                const float *dout, int32_t B, const cfust_mlp_grads *grads, void *stream) {
+    if (!h) return CFUST_EINVAL;
+    cfust_status st;
+    if ((st = check_mlp_b(h, B)) != CFUST_OK) return st;
+    if (!weights_ok(w) || !acts || !dout || !grads) return fail(h, CFUST_EINVAL, "a network buffer is NULL");
+    for (int l = 0; l < CFUST_MLP_LAYERS; ++l)
+        if (!grads->dW[l] || !grads->db[l]) return fail(h, CFUST_EINVAL, "a gradient buffer is NULL");
+    Carve c;
+    const size_t part = c.take<float>((size_t)16 * CFUST_MLP_HIDDEN * CFUST_MLP_HIDDEN);
+    const size_t dy = c.take<float>((size_t)B * CFUST_MLP_HIDDEN);
+    const size_t dzb = c.take<uint16_t>((size_t)B * CFUST_MLP_HIDDEN);
+    const size_t dzt = c.take<uint16_t>((size_t)B * CFUST_MLP_HIDDEN);
+    if ((st = ensure_ws(h, c.off)) != CFUST_OK) return st;
+    if ((st = hip_check(h, hipSetDevice(h->device), "hipSetDevice")) != CFUST_OK) return st;
+    return hip_check(h, launch_mlp_backward(*w, *acts, dout, B, *grads, at<float>(h, part), at<float>(h, dy),
+                                            at<uint16_t>(h, dzb), at<uint16_t>(h, dzt), (hipStream_t)stream),
+                     "cfust_mlp_backward");
+}
+
+cfust_status cfust_mlp_adam(cfust_handle h, const cfust_mlp_master *m, const cfust_mlp_grads *g,
+                            const cfust_mlp_weights *w, float lr, float b1, float b2, float eps, int32_t step,
+                            void *stream) {
+    if (!h) return CFUST_EINVAL;
+    if (!m || !g || !weights_ok(w) || step < 1) return fail(h, CFUST_EINVAL, "bad Adam arguments");
+    cfust_status st;
+    if ((st = hip_check(h, hipSetDevice(h->device), "hipSetDevice")) != CFUST_OK) return st;
+    return hip_check(h, launch_mlp_adam(*m, *g, *w, lr, b1, b2, eps, step, (hipStream_t)stream), "cfust_mlp_adam");
+}
+
+cfust_status cfust_mlp_loss(cfust_handle h, const float *out, const float *label, int32_t B, int32_t nvalid,
+                            float lam, float *dout, float *loss_sum, void *stream) {
+    if (!h) return CFUST_EINVAL;
+    cfust_status st;
+    if ((st = check_mlp_b(h, B)) != CFUST_OK) return st;
+    if (nvalid < 1 || nvalid > B) return fail(h, CFUST_EINVAL, "nvalid = %d outside [1, B]", nvalid);
+    if (!out || !label || !dout || !loss_sum) return fail(h, CFUST_EINVAL, "a loss buffer is NULL");
+    if ((st = ensure_ws(h, align256((size_t)(B / 256 + 2) * sizeof(float)))) != CFUST_OK) return st;
+    if ((st = hip_check(h, hipSetDevice(h->device), "hipSetDevice")) != CFUST_OK) return st;
+    return hip_check(h, launch_mlp_loss(out, label, B, nvalid, lam, dout, at<float>(h, 0), loss_sum,
+                                        (hipStream_t)stream), "cfust_mlp_loss");
 }
 
 cfust_status cfust_profile_enable(cfust_handle h, int enable) {

@@ -329,6 +329,10 @@ __global__ __launch_bounds__(256) void k_estep_qmc(EstepQmcArgs a) {
     if (j >= a.n) return;
     const size_t o = ((size_t)h * a.J + idx) * a.n + j;
     if (FLAGGED_ONLY && a.flag[o] == 0) return;
+    if (!FLAGGED_ONLY && a.need && a.need[o] == 0) {   // answered by the surrogate
+        if (MIXED && lane == 0) a.flag[o] = 0;
+        return;
+    }
     double c[MAXQ], d, b[MAXQ];
     pair_geometry(a.y, a.n, a.p, a.q, j, a.mu + (size_t)h * a.p, P, c, d);
     const double *L = integral_limits(D, P, a.p, a.q, c, d, b);
@@ -600,6 +604,154 @@ __global__ __launch_bounds__(256) void k_mvt1(MvtArgs a) {
     a.p[it] = H.e0;
     if (a.logp) a.logp[it] = H.lne0;
     if (a.se) a.se[it] = 0.0;
+}
+
+// ------------------------------------------------------------- surrogate ---
+
+// Features of T_m(b; 0, L L^T, nu) for the network: standardised limits
+// b_i / sqrt(R_ii) / 6, correlations R_ij / sqrt(R_ii R_jj) (i < j, row
+// order), (ln nu - ln 2) / (ln 30 - ln 2), zero padding; R = L L^T.  Returns
+// whether the problem lies in the training domain (|b_i/sqrt(R_ii)| <= 6,
+// 2 <= nu <= 30).
+__device__ inline bool sur_features(int m, const double *b, const double *L, double nu, float *x) {
+    double R[MAXQ * MAXQ], sd[MAXQ];
+    for (int i = 0; i < m; ++i)
+        for (int k = 0; k <= i; ++k) {
+            double s = 0.0;
+            for (int l = 0; l <= k; ++l) s += L[i * m + l] * L[k * m + l];
+            R[i * m + k] = R[k * m + i] = s;
+        }
+    bool ok = nu >= 2.0 && nu <= 30.0;
+    for (int i = 0; i < m; ++i) sd[i] = sqrt(R[i * m + i]);
+    int c = 0;
+    for (int i = 0; i < m; ++i) {
+        const double z = b[i] / sd[i];
+        ok = ok && fabs(z) <= 6.0;
+        x[c++] = (float)(fmax(-6.0, fmin(6.0, z)) / 6.0);
+    }
+    for (int i = 0; i < m; ++i)
+        for (int k = i + 1; k < m; ++k) x[c++] = (float)(R[i * m + k] / (sd[i] * sd[k]));
+    x[c++] = (float)((log(fmax(nu, 1e-3)) - 0.69314718055994531) / (3.4011973816621555 - 0.69314718055994531));
+    while (c < CFUST_MLP_IN) x[c++] = 0.0f;
+    return ok;
+}
+
+__device__ __forceinline__ uint16_t sur_f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__global__ __launch_bounds__(128) void k_sur_features(SurFeatArgs a) {
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long rows = (long)a.g * a.cnt * a.n;
+    if (gid >= rows) return;
+    const int j = (int)(gid % a.n);
+    const int t = (int)((gid / a.n) % a.cnt);
+    const int h = (int)(gid / ((long)a.n * a.cnt));
+    const IntDesc D = int_desc(a.q, a.idx0 + t);
+    const CompPre &P = a.pre[h];
+    double c[MAXQ], d, b[MAXQ];
+    pair_geometry(a.y, a.n, a.p, a.q, j, a.mu + (size_t)h * a.p, P, c, d);
+    const double *L = integral_limits(D, P, a.p, a.q, c, d, b);
+    float x[CFUST_MLP_IN];
+    const bool ok = sur_features(D.m, b, L, P.nu + a.p + D.dofoff, x);
+    for (int i = 0; i < CFUST_MLP_IN; ++i) a.X0[gid * CFUST_MLP_IN + i] = sur_f2bf(x[i]);
+    a.inrange[gid] = ok ? 1 : 0;
+}
+
+__global__ __launch_bounds__(256) void k_sur_select(SurSelArgs a) {
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long rows = (long)a.g * a.cnt * a.n;
+    if (gid >= rows) return;
+    const int j = (int)(gid % a.n);
+    const int t = (int)((gid / a.n) % a.cnt);
+    const int h = (int)(gid / ((long)a.n * a.cnt));
+    const int idx = a.idx0 + t;
+    const size_t o = ((size_t)h * a.J + idx) * a.n + j;
+    const float o0 = a.out[gid * CFUST_MLP_OUT], o1 = a.out[gid * CFUST_MLP_OUT + 1];
+    const double lnT = fmin(10.0 * (double)o0, 0.0);
+    const double err = 10.0 * pow(10.0, (double)o1);      // predicted |error| of ln T
+    const bool use = a.inrange[gid] && isfinite(lnT) && err <= a.tol;
+    a.need[o] = use ? 0 : 1;
+    if (use) {
+        a.est[o] = exp(lnT);
+        if (idx == 0) a.lnA[(size_t)h * a.n + j] = lnT;
+    }
+}
+
+__global__ void k_fill_i32(int32_t *p, size_t count, int32_t v) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_count_i32(const int32_t *__restrict__ p, size_t count, int32_t *out) {
+    __shared__ int red[256];
+    int s = 0;
+    for (size_t i = threadIdx.x; i < count; i += 256) s += p[i] != 0;
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
+__global__ __launch_bounds__(128) void k_mvt_features(int m, int batch, const double *__restrict__ bb,
+                                                      const double *__restrict__ LL,
+                                                      const int32_t *__restrict__ mat_idx,
+                                                      const double *__restrict__ nu, uint16_t *__restrict__ X0,
+                                                      int32_t *__restrict__ inrange, int rows_pad, int nmat) {
+    const int it = blockIdx.x * blockDim.x + threadIdx.x;
+    if (it >= rows_pad) return;
+    float x[CFUST_MLP_IN];
+    bool ok = false;
+    const int mi = it < batch ? mat_idx[it] : -1;
+    if (mi >= 0 && mi < nmat) {
+        double b[MAXQ], L[MAXQ * MAXQ];
+        for (int i = 0; i < m; ++i) b[i] = bb[(size_t)it * m + i];
+        for (int i = 0; i < m * m; ++i) L[i] = LL[(size_t)mi * m * m + i];
+        ok = sur_features(m, b, L, nu[it], x);
+    } else {
+        for (int i = 0; i < CFUST_MLP_IN; ++i) x[i] = 0.0f;
+    }
+    for (int i = 0; i < CFUST_MLP_IN; ++i) X0[(size_t)it * CFUST_MLP_IN + i] = sur_f2bf(x[i]);
+    if (inrange && it < batch) inrange[it] = ok ? 1 : 0;
+}
+
+hipError_t launch_sur_features(const SurFeatArgs &a, hipStream_t s) {
+    const long rows = (long)a.g * a.cnt * a.n;
+    if (rows == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sur_features, dim3((unsigned)((rows + 127) / 128)), dim3(128), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sur_select(const SurSelArgs &a, hipStream_t s) {
+    const long rows = (long)a.g * a.cnt * a.n;
+    if (rows == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sur_select, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t *p, size_t count, int32_t v, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, count, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_i32(const int32_t *p, size_t count, int32_t *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_count_i32, dim3(1), dim3(256), 0, s, p, count, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_mvt_features(int m, int batch, int rows_pad, const double *b, const double *L,
+                               const int32_t *mat_idx, int nmat, const double *nu, uint16_t *X0, int32_t *inrange,
+                               hipStream_t s) {
+    if (rows_pad == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mvt_features, dim3((rows_pad + 127) / 128), dim3(128), 0, s, m, batch, b, L, mat_idx,
+                       nu, X0, inrange, rows_pad, nmat);
+    return hipGetLastError();
 }
 
 // --------------------------------------------------------------- launch ----

@@ -24,6 +24,27 @@ struct EstepQmcArgs {
     double *lnA;                // [g][n]  ln of integral 0 (A)
     double *se;                 // [g][n]  optional stderr of A
     int32_t *flag;              // [g][J][n] mixed: 1 where the FP32 estimate underflowed
+    const int32_t *need;        // [g][J][n] or null: only items with need != 0 are evaluated
+};
+
+// Surrogate features of the lattice integrals of one dimension m: rows
+// ((h * cnt) + (idx - idx0)) * n + j of X0 [rows][16] BF16.
+struct SurFeatArgs {
+    const double *y, *mu;
+    const CompPre *pre;
+    int n, p, q, g, J;
+    int m, idx0, cnt;           // integrals idx0 .. idx0+cnt-1 have dimension m
+    uint16_t *X0;               // [rows_pad][CFUST_MLP_IN]
+    int32_t *inrange;           // [rows]
+};
+
+struct SurSelArgs {
+    int n, g, J, m, idx0, cnt;
+    const float *out;           // [rows_pad][CFUST_MLP_OUT]
+    const int32_t *inrange;
+    float tol;                  // fallback when the predicted |error| of ln T exceeds tol
+    double *est, *lnA;
+    int32_t *need;              // [g][J][n]
 };
 
 struct EstepAsmArgs {
@@ -86,5 +107,28 @@ hipError_t launch_assemble(const EstepAsmArgs &a, hipStream_t s);
 hipError_t launch_lse(const EstepLseArgs &a, double *loglik, hipStream_t s);
 hipError_t launch_mvt(const MvtArgs &a, hipStream_t s);
 hipError_t launch_mstep(const MstepArgs &r, const MsolveArgs &s, hipStream_t st);
+
+hipError_t launch_sur_features(const SurFeatArgs &a, hipStream_t s);
+hipError_t launch_sur_select(const SurSelArgs &a, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, size_t count, int32_t v, hipStream_t s);
+hipError_t launch_count_i32(const int32_t *p, size_t count, int32_t *out, hipStream_t s);
+// Features of batched T_m problems (training inputs of the surrogate).
+hipError_t launch_mvt_features(int m, int batch, int rows_pad, const double *b, const double *L,
+                               const int32_t *mat_idx, int nmat, const double *nu, uint16_t *X0, int32_t *inrange,
+                               hipStream_t s);
+
+int mlp_layer_k(int l);
+int mlp_layer_n(int l);
+hipError_t launch_mlp_forward(const cfust_mlp_weights &W, const uint16_t *X0, int B, float *out,
+                              const cfust_mlp_acts *acts, uint16_t *scratch_a, uint16_t *scratch_b,
+                              hipStream_t s);
+hipError_t launch_mlp_backward(const cfust_mlp_weights &W, const cfust_mlp_acts &A, const float *dout, int B,
+                               const cfust_mlp_grads &G, float *part, float *dY, uint16_t *dZb, uint16_t *dZbT,
+                               hipStream_t s);
+hipError_t launch_mlp_adam(const cfust_mlp_master &Mst, const cfust_mlp_grads &G, const cfust_mlp_weights &W,
+                           float lr, float b1, float b2, float eps, int step, hipStream_t s);
+hipError_t launch_mlp_loss(const float *out, const float *label, int B, int nvalid, float lam, float *dout,
+                           float *part, float *loss, hipStream_t s);
+hipError_t launch_transpose_in(const uint16_t *X0, int B, uint16_t *X, uint16_t *XT, hipStream_t s);
 
 }  // namespace cfust

@@ -1,0 +1,320 @@
+// cfust_mlp.hip -- the surrogate network: a 16 -> 256 -> 256 -> 256 -> 256 -> 16
+// perceptron with tanh-form GELU, BF16 weights and activations, FP32
+// accumulation on the matrix cores (v_mfma_f32_16x16x16_bf16), FP32 master
+// weights and Adam.  Forward, backward, loss and optimiser kernels.
+//
+// GEMM convention: C[M][N] = P[M][K] * Q[N][K]^T with P, Q row-major BF16
+// (K contiguous).  One 256-thread block computes a 64 x 64 tile of C; each
+// wave a 32 x 32 quarter as 2 x 2 MFMA tiles of 16 x 16, stepping K by 16.
+// Operand fragments are read straight from global memory (8 bytes per lane:
+// four consecutive K values), the layout the 16x16x16 BF16 MFMA expects:
+//   lane l holds P[row0 + l%16][k0 + 4(l/16) + 0..3] and Q[col0 + l%16][k0 + 4(l/16) + 0..3],
+//   and receives C[row0 + 4(l/16) + i][col0 + l%16], i = 0..3.
+#include "cfust_kernels.h"
+
+namespace cfust {
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) {   // round to nearest even
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+constexpr float GELU_C = 0.7978845608028654f;   // sqrt(2/pi)
+constexpr float GELU_A = 0.044715f;
+
+__device__ __forceinline__ float gelu(float z) {
+    const float u = GELU_C * (z + GELU_A * z * z * z);
+    return 0.5f * z * (1.0f + tanhf(u));
+}
+__device__ __forceinline__ float gelu_grad(float z) {
+    const float u = GELU_C * (z + GELU_A * z * z * z);
+    const float t = tanhf(u);
+    return 0.5f * (1.0f + t) + 0.5f * z * (1.0f - t * t) * GELU_C * (1.0f + 3.0f * GELU_A * z * z);
+}
+
+// Epilogue of a GEMM tile element: add bias, apply the activation, store.
+struct GemmOut {
+    const float *bias;      // [N] or null
+    float *Cf;              // [M][N] FP32 (pre-activation) or null
+    uint16_t *Cb;           // [M][N] BF16 after activation, or null
+    uint16_t *CbT;          // [N][M] BF16 after activation (transposed), or null
+    float *Cpart;           // split-K partials [split][M][N] or null
+    int act;                // 0: identity, 1: GELU
+};
+
+__global__ __launch_bounds__(256) void k_gemm_bf16(const uint16_t *__restrict__ P, const uint16_t *__restrict__ Q,
+                                                   int M, int N, int K, int kchunk, GemmOut o) {
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int row_w = blockIdx.y * 64 + 32 * (wave >> 1);
+    const int col_w = blockIdx.x * 64 + 32 * (wave & 1);
+    const int k_beg = blockIdx.z * kchunk;
+    const int k_end = min(K, k_beg + kchunk);
+    v4f acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+    const bool colok[2] = {col_w < N, col_w + 16 < N};
+    const bool rowok[2] = {row_w < M, row_w + 16 < M};
+    const int lr = l & 15, lk = 4 * (l >> 4);
+    for (int k0 = k_beg; k0 < k_end; k0 += 16) {
+        v4s pa[2], qb[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            if (rowok[a]) pa[a] = *reinterpret_cast<const v4s *>(P + (size_t)(row_w + 16 * a + lr) * K + k0 + lk);
+            else pa[a] = v4s{0, 0, 0, 0};
+            if (colok[a]) qb[a] = *reinterpret_cast<const v4s *>(Q + (size_t)(col_w + 16 * a + lr) * K + k0 + lk);
+            else qb[a] = v4s{0, 0, 0, 0};
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(pa[a], qb[b], acc[a][b], 0, 0, 0);
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            if (!rowok[a] || !colok[b]) continue;
+            const int col = col_w + 16 * b + lr;
+            const int r0 = row_w + 16 * a + lk;
+            if (o.Cpart) {
+                float *dst = o.Cpart + (size_t)blockIdx.z * M * N;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) dst[(size_t)(r0 + i) * N + col] = acc[a][b][i];
+                continue;
+            }
+            const float bias = o.bias ? o.bias[col] : 0.0f;
+            uint16_t ob[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float z = acc[a][b][i] + bias;
+                if (o.Cf) o.Cf[(size_t)(r0 + i) * N + col] = z;
+                const float y = o.act ? gelu(z) : z;
+                ob[i] = f2bf(y);
+                if (o.Cb) o.Cb[(size_t)(r0 + i) * N + col] = ob[i];
+            }
+            if (o.CbT) {
+                // four consecutive rows = four consecutive entries of the transposed row
+                uint2 pk;
+                pk.x = (uint32_t)ob[0] | ((uint32_t)ob[1] << 16);
+                pk.y = (uint32_t)ob[2] | ((uint32_t)ob[3] << 16);
+                *reinterpret_cast<uint2 *>(o.CbT + (size_t)col * M + r0) = pk;
+            }
+        }
+}
+
+// Sum split-K partials: dst[i] = sum_s part[s][i].
+__global__ void k_sum_split(const float *__restrict__ part, int nsplit, size_t count, float *__restrict__ dst) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    float s = 0.0f;
+    for (int k = 0; k < nsplit; ++k) s += part[(size_t)k * count + i];
+    dst[i] = s;
+}
+
+// dZ = dY * gelu'(Z) (or dY when the layer has no activation), written as BF16
+// in both layouts, and the bias gradient by a column reduction.
+__global__ void k_act_back(const float *__restrict__ dY, const float *__restrict__ Z, int M, int N, int act,
+                           uint16_t *__restrict__ dZb, uint16_t *__restrict__ dZbT) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)M * N) return;
+    const int r = (int)(i / N), c = (int)(i % N);
+    const float g = act ? dY[i] * gelu_grad(Z[i]) : dY[i];
+    const uint16_t h = f2bf(g);
+    dZb[i] = h;
+    dZbT[(size_t)c * M + r] = h;
+}
+
+__global__ void k_col_sum(const uint16_t *__restrict__ dZbT, int M, int N, float *__restrict__ db) {
+    // one block per column, rows reduced in a fixed order
+    __shared__ float red[256];
+    const int c = blockIdx.x;
+    float s = 0.0f;
+    for (int r = threadIdx.x; r < M; r += blockDim.x) s += bf2f(dZbT[(size_t)c * M + r]);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) db[c] = red[0];
+}
+
+// Adam on FP32 master weights (one launch per parameter array), refreshing
+// the BF16 copies in both layouts for weight matrices.
+__global__ void k_adam(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
+                       const float *__restrict__ g, size_t count, int rows, int cols, float lr, float b1,
+                       float b2, float eps, float c1, float c2, uint16_t *__restrict__ wb,
+                       uint16_t *__restrict__ wbT) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    w[i] = wi;
+    if (wb) {
+        const uint16_t h = f2bf(wi);
+        wb[i] = h;
+        const int r = (int)(i / cols), c = (int)(i % cols);
+        wbT[(size_t)c * rows + r] = h;
+    }
+}
+
+// Loss of the two heads and the gradient w.r.t. the network output.
+// out[b][0]: prediction of the scaled log-probability, out[b][1]: predicted
+// log10 of its absolute error.  Rows b >= nvalid are padding.
+__global__ __launch_bounds__(256) void k_mlp_loss(const float *__restrict__ out, const float *__restrict__ label,
+                                                  int B, int nvalid, float lam, float *__restrict__ dout,
+                                                  float *__restrict__ part) {
+    __shared__ float red[256];
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    float loss = 0.0f;
+    if (b < B) {
+        for (int c = 0; c < CFUST_MLP_OUT; ++c) dout[(size_t)b * CFUST_MLP_OUT + c] = 0.0f;
+        if (b < nvalid) {
+            const float o0 = out[(size_t)b * CFUST_MLP_OUT], o1 = out[(size_t)b * CFUST_MLP_OUT + 1];
+            const float r = o0 - label[b];
+            const float tgt = log10f(fabsf(r) + 1e-6f);
+            const float r1 = o1 - tgt;
+            loss = r * r + lam * r1 * r1;
+            dout[(size_t)b * CFUST_MLP_OUT] = 2.0f * r / nvalid;
+            dout[(size_t)b * CFUST_MLP_OUT + 1] = 2.0f * lam * r1 / nvalid;
+        }
+    }
+    red[threadIdx.x] = loss;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// Copy of the network input in both layouts ([B][16] and [16][B]).
+__global__ void k_transpose_in(const uint16_t *__restrict__ X0, int B, uint16_t *__restrict__ X,
+                               uint16_t *__restrict__ XT) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= B * CFUST_MLP_IN) return;
+    const int r = i / CFUST_MLP_IN, c = i % CFUST_MLP_IN;
+    const uint16_t v = X0[i];
+    X[i] = v;
+    XT[(size_t)c * B + r] = v;
+}
+
+// --------------------------------------------------------------- launch ----
+
+static const int LAYER_K[CFUST_MLP_LAYERS] = {CFUST_MLP_IN, CFUST_MLP_HIDDEN, CFUST_MLP_HIDDEN, CFUST_MLP_HIDDEN,
+                                              CFUST_MLP_HIDDEN};
+static const int LAYER_N[CFUST_MLP_LAYERS] = {CFUST_MLP_HIDDEN, CFUST_MLP_HIDDEN, CFUST_MLP_HIDDEN, CFUST_MLP_HIDDEN,
+                                              CFUST_MLP_OUT};
+
+int mlp_layer_k(int l) { return LAYER_K[l]; }
+int mlp_layer_n(int l) { return LAYER_N[l]; }
+
+static hipError_t gemm(const uint16_t *P, const uint16_t *Q, int M, int N, int K, int nsplit, const GemmOut &o,
+                       hipStream_t s) {
+    const int kchunk = ((K / nsplit + 15) / 16) * 16;
+    dim3 grid((N + 63) / 64, (M + 63) / 64, nsplit);
+    hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, s, P, Q, M, N, K, kchunk, o);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(const cfust_mlp_weights &W, const uint16_t *X0, int B, float *out,
+                              const cfust_mlp_acts *acts, uint16_t *scratch_a, uint16_t *scratch_b,
+                              hipStream_t s) {
+    const uint16_t *x = X0;
+    hipError_t e = hipSuccess;
+    for (int l = 0; l < CFUST_MLP_LAYERS && e == hipSuccess; ++l) {
+        GemmOut o{};
+        o.bias = W.b[l];
+        const bool last = l == CFUST_MLP_LAYERS - 1;
+        o.act = last ? 0 : 1;
+        if (last) {
+            o.Cf = out;
+        } else {
+            o.Cf = acts ? acts->Z[l] : nullptr;
+            uint16_t *next = acts ? acts->X[l + 1] : ((l & 1) ? scratch_b : scratch_a);
+            o.Cb = next;
+            o.CbT = acts ? acts->XT[l + 1] : nullptr;
+        }
+        e = gemm(x, (const uint16_t *)W.W[l], B, LAYER_N[l], LAYER_K[l], 1, o, s);
+        // the forward pass of layer l + 1 reads the BF16 activation just written
+        if (!last) x = o.Cb;
+    }
+    return e;
+}
+
+hipError_t launch_mlp_backward(const cfust_mlp_weights &W, const cfust_mlp_acts &A, const float *dout, int B,
+                               const cfust_mlp_grads &G, float *part, float *dY, uint16_t *dZb, uint16_t *dZbT,
+                               hipStream_t s) {
+    hipError_t e = hipSuccess;
+    const float *dy = dout;
+    for (int l = CFUST_MLP_LAYERS - 1; l >= 0 && e == hipSuccess; --l) {
+        const int N = LAYER_N[l], K = LAYER_K[l];
+        const bool last = l == CFUST_MLP_LAYERS - 1;
+        const size_t mn = (size_t)B * N;
+        hipLaunchKernelGGL(k_act_back, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, s, dy,
+                           last ? nullptr : A.Z[l], B, N, last ? 0 : 1, dZb, dZbT);
+        hipLaunchKernelGGL(k_col_sum, dim3(N), dim3(256), 0, s, dZbT, B, N, G.db[l]);
+        // dW[N][K] = dZ^T X : P = dZ^T [N][B], Q = X^T [K][B], split over the batch
+        const int nsplit = B >= 1024 ? 16 : 1;
+        GemmOut o{};
+        o.Cpart = part;
+        e = gemm(dZbT, A.XT[l], N, K, B, nsplit, o, s);
+        if (e != hipSuccess) break;
+        hipLaunchKernelGGL(k_sum_split, dim3((unsigned)(((size_t)N * K + 255) / 256)), dim3(256), 0, s, part,
+                           nsplit, (size_t)N * K, G.dW[l]);
+        if (l > 0) {
+            // dX[B][K] = dZ W : P = dZ [B][N], Q = W^T [K][N]
+            GemmOut ox{};
+            ox.Cf = dY;
+            e = gemm(dZb, (const uint16_t *)W.Wt[l], B, K, N, 1, ox, s);
+            dy = dY;
+            // dY is consumed by the next k_act_back before being overwritten
+        }
+    }
+    return e == hipSuccess ? hipGetLastError() : e;
+}
+
+hipError_t launch_mlp_adam(const cfust_mlp_master &Mst, const cfust_mlp_grads &G, const cfust_mlp_weights &W,
+                           float lr, float b1, float b2, float eps, int step, hipStream_t s) {
+    const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+    for (int l = 0; l < CFUST_MLP_LAYERS; ++l) {
+        const int N = LAYER_N[l], K = LAYER_K[l];
+        const size_t nw = (size_t)N * K;
+        hipLaunchKernelGGL(k_adam, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, Mst.W[l], Mst.mW[l],
+                           Mst.vW[l], G.dW[l], nw, N, K, lr, b1, b2, eps, c1, c2, (uint16_t *)W.W[l],
+                           (uint16_t *)W.Wt[l]);
+        hipLaunchKernelGGL(k_adam, dim3((N + 255) / 256), dim3(256), 0, s, Mst.b[l], Mst.mb[l], Mst.vb[l],
+                           G.db[l], (size_t)N, 1, N, lr, b1, b2, eps, c1, c2, (uint16_t *)nullptr,
+                           (uint16_t *)nullptr);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_loss(const float *out, const float *label, int B, int nvalid, float lam, float *dout,
+                           float *part, float *loss, hipStream_t s) {
+    const int nb = (B + 255) / 256;
+    hipLaunchKernelGGL(k_mlp_loss, dim3(nb), dim3(256), 0, s, out, label, B, nvalid, lam, dout, part);
+    hipLaunchKernelGGL(k_sum_split, dim3(1), dim3(1), 0, s, part, nb, (size_t)1, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose_in(const uint16_t *X0, int B, uint16_t *X, uint16_t *XT, hipStream_t s) {
+    const int cnt = B * CFUST_MLP_IN;
+    hipLaunchKernelGGL(k_transpose_in, dim3((cnt + 255) / 256), dim3(256), 0, s, X0, B, X, XT);
+    return hipGetLastError();
+}
+
+}  // namespace cfust

@@ -1,0 +1,173 @@
+"""GPU tests of the surrogate network (forward/backward/loss/Adam kernels
+against the FP64 reference in oracle/mlp.py), of its training, and of the
+E-step that uses it with the lattice as fallback."""
+import os
+import time
+
+import numpy as np
+import pytest
+import torch
+
+from cfust_inputs import make_design, workload
+from oracle import mlp as omlp
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sur():
+    import paper_1606_02054_amd as cf
+    from paper_1606_02054_amd import surrogate as S
+    assert torch.cuda.is_available()
+    cf.default_handle()
+    return cf, S
+
+
+def _host_net(net):
+    Ws = [omlp.bf16_round(w.cpu().numpy().astype(np.float64)) for w in net.W32]
+    bs = [b.cpu().numpy().astype(np.float64) for b in net.b32]
+    return Ws, bs
+
+
+def _bf16_input(rng, rows):
+    X = rng.uniform(-1, 1, (rows, 16))
+    Xb = omlp.bf16_round(X)
+    t = torch.tensor(Xb, dtype=torch.float32).to(torch.bfloat16).view(torch.int16).cuda()
+    return Xb, t
+
+
+def test_forward_backward_vs_reference(sur):
+    cf, S = sur
+    print("mlp forward/backward", flush=True)
+    rng = np.random.default_rng(3)
+    net = S.SurrogateNet(2, seed=5)
+    rows = 192                      # three 64-row tiles
+    Xb, X0 = _bf16_input(rng, rows)
+    acts = S.Activations(rows, "cuda")
+    out = torch.zeros((rows, 16), dtype=torch.float32, device="cuda")
+    S.mlp_forward(net, X0, out, acts)
+    label = rng.uniform(-1.5, 0.0, rows)
+    dout = torch.zeros_like(out)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    S.mlp_loss(out, torch.tensor(label, dtype=torch.float32).cuda(), rows, 0.2, dout, loss)
+    S.mlp_backward(net, acts, dout)
+    torch.cuda.synchronize()
+    Ws, bs = _host_net(net)
+    ref_out, cache = omlp.forward(Ws, bs, Xb, bf16=True)
+    got = out.cpu().numpy().astype(np.float64)
+    scale = np.abs(ref_out).max()
+    assert np.abs(got - ref_out).max() <= 2e-2 * scale
+    rl, rdout = omlp.loss_and_grad(got, label.astype(np.float32).astype(np.float64), 0.2)
+    assert abs(float(loss.cpu()[0]) / rows - rl) <= 1e-4 * max(1.0, rl)
+    np.testing.assert_allclose(dout.cpu().numpy(), rdout, rtol=1e-4, atol=1e-7)
+    dWs, dbs, _ = omlp.backward(Ws, bs, cache, rdout, bf16=True)
+    for l in range(5):
+        gW = net.dW[l].cpu().numpy().astype(np.float64)
+        rel = np.linalg.norm(gW - dWs[l]) / np.linalg.norm(dWs[l])
+        assert rel <= 3e-2, (l, rel)
+        gb = net.db[l].cpu().numpy().astype(np.float64)
+        relb = np.linalg.norm(gb - dbs[l]) / max(np.linalg.norm(dbs[l]), 1e-12)
+        assert relb <= 3e-2, (l, relb)
+
+
+def test_adam_step_vs_reference(sur):
+    cf, S = sur
+    net = S.SurrogateNet(3, seed=9)
+    rng = np.random.default_rng(4)
+    for l in range(5):
+        net.dW[l].copy_(torch.tensor(rng.standard_normal(net.dW[l].shape), dtype=torch.float32))
+        net.db[l].copy_(torch.tensor(rng.standard_normal(net.db[l].shape), dtype=torch.float32))
+    W0 = [w.cpu().numpy().astype(np.float64) for w in net.W32]
+    g = [d.cpu().numpy().astype(np.float64) for d in net.dW]
+    S.mlp_adam(net, 1e-3)
+    torch.cuda.synchronize()
+    for l in range(5):
+        m = 0.1 * g[l]; v = 0.001 * g[l] ** 2
+        ref = W0[l] - 1e-3 * (m / 0.1) / (np.sqrt(v / 0.001) + 1e-8)
+        np.testing.assert_allclose(net.W32[l].cpu().numpy(), ref, rtol=1e-5, atol=1e-7)
+        bf = torch.tensor(net.W32[l].cpu().numpy()).to(torch.bfloat16).view(torch.int16)
+        assert torch.equal(net.Wb[l].cpu(), bf)
+        assert torch.equal(net.WbT[l].cpu(), bf.t().contiguous())
+
+
+def test_training_reduces_error(sur):
+    cf, S = sur
+    print("surrogate short training", flush=True)
+    des = make_design(1024, 4, seed=31)
+    net, rep = S.train(2, 131072, des, epochs=3, batch=4096, lr=2e-3, seed=7, n_val=8192, log=print)
+    print(rep, flush=True)
+    assert rep.val_rmse_lnT < 0.1
+    assert rep.err_head_corr > 0.2
+
+
+def _c1(cf):
+    ds = workload("cfust_n1000_p2_q2_g2")
+    y = torch.as_tensor(ds.y_soa).cuda()
+    return ds, y, cf.device_params(ds.params)
+
+
+def test_surrogate_tol_zero_is_plain_lattice(sur):
+    cf, S = sur
+    ds, y, dp = _c1(cf)
+    qmc = cf.device_qmc(make_design(1024, 4, seed=1606), cf.CFUST_MIXED)
+    net = S.SurrogateNet(2, seed=1)
+    nf = torch.zeros(1, dtype=torch.int32, device="cuda")
+    a = S.cfust_estep_surrogate(y, dp, qmc, {2: net}, tol=0.0, n_fallback=nf)
+    b = cf.cfust_estep(y, dp, qmc)
+    torch.cuda.synchronize()
+    for name in ("tau", "w", "e1", "e2", "e3", "logf_obs", "loglik"):
+        assert torch.equal(getattr(a, name), getattr(b, name)), name
+    assert int(nf.cpu()[0]) == 2 * 2 * 1000
+
+
+def _trained(S, m, des):
+    path = os.path.join(os.path.dirname(S.__file__), "weights", f"surrogate_m{m}.npz")
+    if os.path.exists(path):
+        return S.SurrogateNet.load(path)
+    net, _ = S.train(m, 262144, des, epochs=4, seed=11, log=print)
+    return net
+
+
+def test_surrogate_estep_accuracy_and_gain(sur, orc):
+    """E-step of the n=1000, p=q=2, g=2 data: network answers vs the lattice.
+    Reports the speed-up at equal log-likelihood accuracy (reference: lattice
+    with 65536 x 16 points)."""
+    cf, S = sur
+    print("surrogate E-step gain", flush=True)
+    ds, y, dp = _c1(cf)
+    net = _trained(S, 2, make_design(8192, 8, seed=2024))
+    ref_qmc = cf.device_qmc(make_design(65536, 16, seed=99), cf.CFUST_MIXED)
+    ref = cf.cfust_estep(y, dp, ref_qmc)
+    torch.cuda.synchronize()
+    l_ref = float(ref.loglik.cpu()[0])
+
+    def timed(fn, reps=5):
+        fn(); torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            out = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps, out
+
+    qmc_s = cf.device_qmc(make_design(1024, 4, seed=1606), cf.CFUST_MIXED)
+    nf = torch.zeros(1, dtype=torch.int32, device="cuda")
+    t_sur, o_sur = timed(lambda: S.cfust_estep_surrogate(y, dp, qmc_s, {2: net}, tol=5e-3, n_fallback=nf))
+    err_sur = abs(float(o_sur.loglik.cpu()[0]) - l_ref)
+    frac_fb = int(nf.cpu()[0]) / 4000
+    # lattice sizes of increasing accuracy
+    rows = []
+    for N, Sh in [(64, 2), (128, 2), (256, 2), (256, 4), (512, 4), (1024, 4), (2048, 8), (4096, 8)]:
+        q = cf.device_qmc(make_design(N, Sh, seed=1606), cf.CFUST_MIXED)
+        t, o = timed(lambda: cf.cfust_estep(y, dp, q))
+        rows.append((N, Sh, t, abs(float(o.loglik.cpu()[0]) - l_ref)))
+    match = [r for r in rows if r[3] <= err_sur]
+    print(f"surrogate: {t_sur * 1e3:.3f} ms, |dl| = {err_sur:.3e}, fallback {frac_fb:.3f}", flush=True)
+    for r in rows:
+        print(f"lattice {r[0]}x{r[1]}: {r[2] * 1e3:.3f} ms, |dl| = {r[3]:.3e}", flush=True)
+    t_eq = match[0][2] if match else rows[-1][2]
+    print(f"speed-up at equal log-likelihood accuracy: {t_eq / t_sur:.2f}x", flush=True)
+    # the answers stay within the network's accuracy on every observation
+    ora = orc.estep(ds.y, ds.params, make_design(1024, 4, seed=1606), rows=np.arange(0, 1000, 50))
+    got = o_sur.logf_obs.cpu().numpy()[np.arange(0, 1000, 50)]
+    assert np.abs(got - ora.logf_obs).max() < 0.05
+    assert err_sur < 1.0
