@@ -66,6 +66,56 @@ def integral_dims(q: int):
     return [m for m in dims if m >= 2]
 
 
+def surrogate_vs_lattice(cf, ds, y, params, design, pairs):
+    """E-step with the trained networks (T_m, m = 2..4, lattice fallback) against
+    the plain lattice E-step at several lattice sizes, both measured by their
+    log-likelihood error against a 4x larger lattice; speed-up at equal accuracy."""
+    import torch
+    from paper_1606_02054_amd import surrogate as S
+    from cfust_inputs import make_design
+    wdir = os.path.join(ROOT, "paper_1606_02054_amd", "weights")
+    models = {}
+    for m in (2, 3, 4):
+        f = os.path.join(wdir, f"surrogate_m{m}.npz")
+        if os.path.exists(f):
+            models[m] = S.SurrogateNet.load(f)
+    if not models:
+        return {"skipped": "no trained weights under paper_1606_02054_amd/weights"}
+
+    def timed(fn, reps=3):
+        o = fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            o = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps * 1e3, float(o.loglik.cpu()[0])
+
+    ref_q = cf.device_qmc(make_design(4 * design.N, 2 * design.S, seed=4242), cf.CFUST_MIXED)
+    ref = cf.cfust_estep(y, params, ref_q)
+    torch.cuda.synchronize()
+    l_ref = float(ref.loglik.cpu()[0])
+    lat = []
+    for N, Sh in [(128, 2), (256, 4), (512, 4), (1024, 4), (2048, 8), (design.N, design.S)]:
+        q = cf.device_qmc(make_design(N, Sh, seed=1606), cf.CFUST_MIXED)
+        ms, ll = timed(lambda: cf.cfust_estep(y, params, q))
+        lat.append({"N": N, "S": Sh, "ms": ms, "abs_dloglik": abs(ll - l_ref)})
+    q0 = cf.device_qmc(design, cf.CFUST_MIXED)
+    sur = []
+    for tol in (0.02, 0.05, 0.1):
+        nf = torch.zeros(1, dtype=torch.int32, device="cuda")
+        ms, ll = timed(lambda: S.cfust_estep_surrogate(y, params, q0, models, tol, n_fallback=nf))
+        J = len(integral_dims(params.q))
+        err = abs(ll - l_ref)
+        ok = [r for r in lat if r["abs_dloglik"] <= err]
+        eq = min(ok, key=lambda r: r["ms"]) if ok else None
+        sur.append({"tol": tol, "ms": ms, "abs_dloglik": err, "fallback_frac": int(nf.cpu()[0]) / (pairs * J),
+                    "lattice_at_equal_accuracy": eq and {"N": eq["N"], "S": eq["S"], "ms": eq["ms"]},
+                    "speedup_at_equal_accuracy": (eq["ms"] / ms) if eq else None})
+    return {"reference": {"N": 4 * design.N, "S": 2 * design.S, "loglik": l_ref}, "lattice": lat,
+            "surrogate": sur, "models": sorted(models)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +125,7 @@ def main():
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--cpu-rows", type=int, default=0, help="oracle sample rows (0: one per thread)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate-vs-lattice comparison")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a known-size "
                          "reference for the HBM byte counters)")
@@ -167,6 +218,9 @@ def main():
                       "autotuned_points_per_lane": {f"m{m}": v for m, v in tuned.items()},
                       "loglik_last": ll},
            "roofline": roofline}
+
+    if not args.no_surrogate and prec == cf.CFUST_MIXED:
+        out["surrogate"] = surrogate_vs_lattice(cf, ds, y, start, design, n * g)
 
     if not args.no_cpu:
         import oracle

@@ -163,9 +163,11 @@ cfust_status mvt_cdf_batch(cfust_handle handle, int32_t m, int32_t batch, const 
  * m = 2..4, with the lattice as fallback).  A 16 -> 256 -> 256 -> 256 -> 256
  * -> 16 perceptron, tanh-form GELU, BF16 weights/activations, FP32
  * accumulation on the matrix cores, FP32 master weights and Adam.  Input
- * features (FP32 before rounding to BF16): the m standardised limits b_i/6,
- * the m(m-1)/2 correlations, (ln nu - ln 2)/(ln 30 - ln 2), zero padding;
- * output 0 is ln T_m / 10, output 1 the predicted log10 of its absolute
+ * features (FP32 before rounding to BF16): the m standardised limits
+ * z_i = b_i/sqrt(R_ii) as z_i/6, the m(m-1)/2 correlations,
+ * (ln nu - ln 2)/(ln 30 - ln 2), the marginal log-CDFs ln T_nu(z_i)/10, zero
+ * padding.  Output 0 is (ln T_m - sum_i ln T_nu(z_i)) / 5 (the correction to
+ * the independence value), output 1 the predicted log10 of its absolute
  * error.  All buffers are device memory owned by the caller; B (rows) must
  * be a positive multiple of 64; rows are independent.
  * ---------------------------------------------------------------------- */
@@ -243,10 +245,11 @@ cfust_status cfust_estep_surrogate(cfust_handle handle, const double *y, cfust_d
 /* Network features of a batch of T_m problems (same arguments as
  * mvt_cdf_batch): X0 BF16 [rows_pad][CFUST_MLP_IN] (rows >= batch zeroed),
  * inrange (optional) int32 [batch]: 1 inside the training domain
- * (|b_i / sqrt(R_ii)| <= 6, 2 <= nu <= 30). */
+ * (|b_i / sqrt(R_ii)| <= 6, 2 <= nu <= 30); base (optional) FP64 [batch]:
+ * sum_i ln T_nu(z_i), the value output 0 corrects. */
 cfust_status cfust_mlp_features(cfust_handle handle, int32_t m, int32_t batch, int32_t rows_pad,
                                 const double *b, const double *L, const int32_t *mat_idx, int32_t nmat,
-                                const double *nu, uint16_t *X0, int32_t *inrange, void *stream);
+                                const double *nu, uint16_t *X0, int32_t *inrange, double *base, void *stream);
 
 /* Autotuner: times the variants of the lattice kernel (lattice points per
  * lane per loop trip) for every integral dimension these dims use, at this

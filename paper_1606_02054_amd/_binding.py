@@ -112,7 +112,7 @@ def load(path: str = LIB_PATH):
     lib.cfust_mlp_loss.restype = C.c_int
     lib.cfust_mlp_loss.argtypes = [vp, vp, vp, i32, i32, f, vp, vp, vp]
     lib.cfust_mlp_features.restype = C.c_int
-    lib.cfust_mlp_features.argtypes = [vp, i32, i32, i32, vp, vp, vp, i32, vp, vp, vp, vp]
+    lib.cfust_mlp_features.argtypes = [vp, i32, i32, i32, vp, vp, vp, i32, vp, vp, vp, vp, vp]
     lib.cfust_estep_surrogate.restype = C.c_int
     lib.cfust_estep_surrogate.argtypes = [vp, vp, Dims, C.POINTER(ParamsC), C.POINTER(QmcC), C.POINTER(SurrogateC),
                                           C.POINTER(EstepOutC), vp]

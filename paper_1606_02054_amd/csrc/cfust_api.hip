@@ -213,7 +213,7 @@ cfust_status run_estep(cfust_handle h, const double *y, const cfust_dims &d, con
     const int J = density_only ? (lattice ? 1 : 0) : nint_qmc(d.q);
     const EstepWs L = estep_layout(d, J, logf_comp == nullptr);
     // surrogate workspace: need flags, and per dimension group features/outputs
-    struct SurGroup { int m, idx0, cnt; long rows, rows_pad; size_t x0, out, inr; };
+    struct SurGroup { int m, idx0, cnt; long rows, rows_pad; size_t x0, out, inr, base; };
     SurGroup sg[3];
     int nsg = 0;
     size_t need_off = 0, sa_off = 0, sb_off = 0, total = L.total;
@@ -233,6 +233,7 @@ cfust_status run_estep(cfust_handle h, const double *y, const cfust_dims &d, con
             G.x0 = c.take<uint16_t>((size_t)(G.rows_pad > 0 ? G.rows_pad : 64) * CFUST_MLP_IN);
             G.out = c.take<float>((size_t)(G.rows_pad > 0 ? G.rows_pad : 64) * CFUST_MLP_OUT);
             G.inr = c.take<int32_t>((size_t)(G.rows > 0 ? G.rows : 1));
+            G.base = c.take<double>((size_t)(G.rows > 0 ? G.rows : 1));
             sg[nsg++] = G;
         }
         sa_off = c.take<uint16_t>((size_t)SUR_CHUNK * CFUST_MLP_HIDDEN);
@@ -256,7 +257,7 @@ cfust_status run_estep(cfust_handle h, const double *y, const cfust_dims &d, con
             fa.y = y; fa.mu = P->mu; fa.pre = pre;
             fa.n = d.n; fa.p = d.p; fa.q = d.q; fa.g = d.g; fa.J = J;
             fa.m = G.m; fa.idx0 = G.idx0; fa.cnt = G.cnt;
-            fa.X0 = at<uint16_t>(h, G.x0); fa.inrange = at<int32_t>(h, G.inr);
+            fa.X0 = at<uint16_t>(h, G.x0); fa.inrange = at<int32_t>(h, G.inr); fa.base = at<double>(h, G.base);
             e = launch_sur_features(fa, s);
             if (e == hipSuccess && G.rows_pad > G.rows)
                 e = launch_fill_i32((int32_t *)(fa.X0 + (size_t)G.rows * CFUST_MLP_IN),
@@ -271,6 +272,7 @@ cfust_status run_estep(cfust_handle h, const double *y, const cfust_dims &d, con
             SurSelArgs sa;
             sa.n = d.n; sa.g = d.g; sa.J = J; sa.m = G.m; sa.idx0 = G.idx0; sa.cnt = G.cnt;
             sa.out = at<float>(h, G.out); sa.inrange = at<int32_t>(h, G.inr); sa.tol = sur->tol;
+            sa.base = at<double>(h, G.base);
             sa.est = at<double>(h, L.est); sa.lnA = at<double>(h, L.lnA); sa.need = need;
             e = launch_sur_select(sa, s);
         }
@@ -378,7 +380,7 @@ cfust_status cfust_estep_surrogate(cfust_handle h, const double *y, cfust_dims d
 
 cfust_status cfust_mlp_features(cfust_handle h, int32_t m, int32_t batch, int32_t rows_pad, const double *b,
                                 const double *L, const int32_t *mat_idx, int32_t nmat, const double *nu,
-                                uint16_t *X0, int32_t *inrange, void *stream) {
+                                uint16_t *X0, int32_t *inrange, double *base, void *stream) {
     if (!h) return CFUST_EINVAL;
     if (m < 2 || m > MAXQ) return fail(h, CFUST_EINVAL, "m = %d outside [2, %d]", m, MAXQ);
     if (batch < 0 || rows_pad < batch) return fail(h, CFUST_EINVAL, "rows_pad < batch");
@@ -386,7 +388,7 @@ cfust_status cfust_mlp_features(cfust_handle h, int32_t m, int32_t batch, int32_
     if (!X0 || (batch > 0 && (!b || !L || !mat_idx || !nu))) return fail(h, CFUST_EINVAL, "a buffer is NULL");
     cfust_status st;
     if ((st = hip_check(h, hipSetDevice(h->device), "hipSetDevice")) != CFUST_OK) return st;
-    return hip_check(h, launch_mvt_features(m, batch, rows_pad, b, L, mat_idx, nmat, nu, X0, inrange,
+    return hip_check(h, launch_mvt_features(m, batch, rows_pad, b, L, mat_idx, nmat, nu, X0, inrange, base,
                                             (hipStream_t)stream),
                      "cfust_mlp_features");
 }

@@ -609,11 +609,13 @@ __global__ __launch_bounds__(256) void k_mvt1(MvtArgs a) {
 // ------------------------------------------------------------- surrogate ---
 
 // Features of T_m(b; 0, L L^T, nu) for the network: standardised limits
-// b_i / sqrt(R_ii) / 6, correlations R_ij / sqrt(R_ii R_jj) (i < j, row
-// order), (ln nu - ln 2) / (ln 30 - ln 2), zero padding; R = L L^T.  Returns
-// whether the problem lies in the training domain (|b_i/sqrt(R_ii)| <= 6,
-// 2 <= nu <= 30).
-__device__ inline bool sur_features(int m, const double *b, const double *L, double nu, float *x) {
+// z_i = b_i / sqrt(R_ii), as z_i / 6; correlations R_ij / sqrt(R_ii R_jj)
+// (i < j, row order); (ln nu - ln 2) / (ln 30 - ln 2); the marginal log-CDFs
+// ln T_nu(z_i) / 10; zero padding; R = L L^T.  *base receives
+// sum_i ln T_nu(z_i) (the log-probability under independence), which the
+// network corrects.  Returns whether the problem lies in the training domain
+// (|z_i| <= 6, 2 <= nu <= 30).
+__device__ inline bool sur_features(int m, const double *b, const double *L, double nu, float *x, double *base) {
     double R[MAXQ * MAXQ], sd[MAXQ];
     for (int i = 0; i < m; ++i)
         for (int k = 0; k <= i; ++k) {
@@ -622,19 +624,35 @@ __device__ inline bool sur_features(int m, const double *b, const double *L, dou
             R[i * m + k] = R[k * m + i] = s;
         }
     bool ok = nu >= 2.0 && nu <= 30.0;
+    const double nuc = fmin(fmax(nu, 0.5), 1e4);
+    const double a = 0.5 * nuc, lb = dm_lbeta_half(a);
     for (int i = 0; i < m; ++i) sd[i] = sqrt(R[i * m + i]);
     int c = 0;
+    double lm[MAXQ], sum = 0.0;
     for (int i = 0; i < m; ++i) {
         const double z = b[i] / sd[i];
         ok = ok && fabs(z) <= 6.0;
-        x[c++] = (float)(fmax(-6.0, fmin(6.0, z)) / 6.0);
+        const double zc = fmax(-6.0, fmin(6.0, z));
+        x[c++] = (float)(zc / 6.0);
+        // ln T_nu(z): lower-tail form, complement for z > 0
+        const double az = fabs(z);
+        double zz, zzc;
+        if (az > 1.0) { const double r = (nuc / az) / az; zz = r / (1.0 + r); zzc = 1.0 / (1.0 + r); }
+        else { const double den = nuc + z * z; zz = nuc / den; zzc = z * z / den; }
+        const double lt = dm_lnT_lower(zz, zzc, a, lb);
+        lm[i] = z <= 0.0 ? lt : log1p(-exp(lt));
+        sum += lm[i];
     }
     for (int i = 0; i < m; ++i)
         for (int k = i + 1; k < m; ++k) x[c++] = (float)(R[i * m + k] / (sd[i] * sd[k]));
-    x[c++] = (float)((log(fmax(nu, 1e-3)) - 0.69314718055994531) / (3.4011973816621555 - 0.69314718055994531));
+    x[c++] = (float)((log(nuc) - 0.69314718055994531) / (3.4011973816621555 - 0.69314718055994531));
+    for (int i = 0; i < m; ++i) x[c++] = (float)fmax(lm[i] / 10.0, -10.0);
     while (c < CFUST_MLP_IN) x[c++] = 0.0f;
+    *base = sum;
     return ok;
 }
+
+constexpr double SUR_RESID_SCALE = 5.0;   // network output 0 = (ln T - base) / 5
 
 __device__ __forceinline__ uint16_t sur_f2bf(float f) {
     uint32_t u = __float_as_uint(f);
@@ -655,9 +673,11 @@ __global__ __launch_bounds__(128) void k_sur_features(SurFeatArgs a) {
     pair_geometry(a.y, a.n, a.p, a.q, j, a.mu + (size_t)h * a.p, P, c, d);
     const double *L = integral_limits(D, P, a.p, a.q, c, d, b);
     float x[CFUST_MLP_IN];
-    const bool ok = sur_features(D.m, b, L, P.nu + a.p + D.dofoff, x);
+    double base;
+    const bool ok = sur_features(D.m, b, L, P.nu + a.p + D.dofoff, x, &base);
     for (int i = 0; i < CFUST_MLP_IN; ++i) a.X0[gid * CFUST_MLP_IN + i] = sur_f2bf(x[i]);
     a.inrange[gid] = ok ? 1 : 0;
+    a.base[gid] = base;
 }
 
 __global__ __launch_bounds__(256) void k_sur_select(SurSelArgs a) {
@@ -670,8 +690,8 @@ __global__ __launch_bounds__(256) void k_sur_select(SurSelArgs a) {
     const int idx = a.idx0 + t;
     const size_t o = ((size_t)h * a.J + idx) * a.n + j;
     const float o0 = a.out[gid * CFUST_MLP_OUT], o1 = a.out[gid * CFUST_MLP_OUT + 1];
-    const double lnT = fmin(10.0 * (double)o0, 0.0);
-    const double err = 10.0 * pow(10.0, (double)o1);      // predicted |error| of ln T
+    const double lnT = fmin(a.base[gid] + SUR_RESID_SCALE * (double)o0, 0.0);
+    const double err = SUR_RESID_SCALE * pow(10.0, (double)o1);   // predicted |error| of ln T
     const bool use = a.inrange[gid] && isfinite(lnT) && err <= a.tol;
     a.need[o] = use ? 0 : 1;
     if (use) {
@@ -702,7 +722,8 @@ __global__ __launch_bounds__(128) void k_mvt_features(int m, int batch, const do
                                                       const double *__restrict__ LL,
                                                       const int32_t *__restrict__ mat_idx,
                                                       const double *__restrict__ nu, uint16_t *__restrict__ X0,
-                                                      int32_t *__restrict__ inrange, int rows_pad, int nmat) {
+                                                      int32_t *__restrict__ inrange, int rows_pad, int nmat,
+                                                      double *__restrict__ basev) {
     const int it = blockIdx.x * blockDim.x + threadIdx.x;
     if (it >= rows_pad) return;
     float x[CFUST_MLP_IN];
@@ -712,9 +733,12 @@ __global__ __launch_bounds__(128) void k_mvt_features(int m, int batch, const do
         double b[MAXQ], L[MAXQ * MAXQ];
         for (int i = 0; i < m; ++i) b[i] = bb[(size_t)it * m + i];
         for (int i = 0; i < m * m; ++i) L[i] = LL[(size_t)mi * m * m + i];
-        ok = sur_features(m, b, L, nu[it], x);
+        double base;
+        ok = sur_features(m, b, L, nu[it], x, &base);
+        if (basev) basev[it] = base;
     } else {
         for (int i = 0; i < CFUST_MLP_IN; ++i) x[i] = 0.0f;
+        if (basev && it < batch) basev[it] = 0.0;
     }
     for (int i = 0; i < CFUST_MLP_IN; ++i) X0[(size_t)it * CFUST_MLP_IN + i] = sur_f2bf(x[i]);
     if (inrange && it < batch) inrange[it] = ok ? 1 : 0;
@@ -747,10 +771,10 @@ hipError_t launch_count_i32(const int32_t *p, size_t count, int32_t *out, hipStr
 
 hipError_t launch_mvt_features(int m, int batch, int rows_pad, const double *b, const double *L,
                                const int32_t *mat_idx, int nmat, const double *nu, uint16_t *X0, int32_t *inrange,
-                               hipStream_t s) {
+                               double *base, hipStream_t s) {
     if (rows_pad == 0) return hipSuccess;
     hipLaunchKernelGGL(k_mvt_features, dim3((rows_pad + 127) / 128), dim3(128), 0, s, m, batch, b, L, mat_idx,
-                       nu, X0, inrange, rows_pad, nmat);
+                       nu, X0, inrange, rows_pad, nmat, base);
     return hipGetLastError();
 }
 

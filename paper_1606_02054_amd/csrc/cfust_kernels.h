@@ -36,12 +36,14 @@ struct SurFeatArgs {
     int m, idx0, cnt;           // integrals idx0 .. idx0+cnt-1 have dimension m
     uint16_t *X0;               // [rows_pad][CFUST_MLP_IN]
     int32_t *inrange;           // [rows]
+    double *base;               // [rows] sum of marginal log-CDFs
 };
 
 struct SurSelArgs {
     int n, g, J, m, idx0, cnt;
     const float *out;           // [rows_pad][CFUST_MLP_OUT]
     const int32_t *inrange;
+    const double *base;
     float tol;                  // fallback when the predicted |error| of ln T exceeds tol
     double *est, *lnA;
     int32_t *need;              // [g][J][n]
@@ -115,7 +117,7 @@ hipError_t launch_count_i32(const int32_t *p, size_t count, int32_t *out, hipStr
 // Features of batched T_m problems (training inputs of the surrogate).
 hipError_t launch_mvt_features(int m, int batch, int rows_pad, const double *b, const double *L,
                                const int32_t *mat_idx, int nmat, const double *nu, uint16_t *X0, int32_t *inrange,
-                               hipStream_t s);
+                               double *base, hipStream_t s);
 
 int mlp_layer_k(int l);
 int mlp_layer_n(int l);

@@ -29,7 +29,7 @@ from . import _binding as B
 from . import (DeviceQmc, EStepResult, Handle, _check_y, _ptr, _stream, alloc_estep, default_handle,
                mvt_cdf_batch)
 
-LN_T_SCALE = 10.0          # network output 0 = ln T / LN_T_SCALE
+RESID_SCALE = 5.0          # network output 0 = (ln T - sum of marginal ln T_nu) / RESID_SCALE
 
 
 def _arr(ptrs):
@@ -155,15 +155,17 @@ def mlp_loss(out, label, nvalid, lam, dout, loss_sum, handle: Optional[Handle] =
 
 
 def mvt_features(m, b, L, mat_idx, nu, rows_pad, handle: Optional[Handle] = None, stream=None):
-    """Network inputs (BF16 as int16 [rows_pad][16]) and training-domain flags of T_m problems."""
+    """Network inputs (BF16 as int16 [rows_pad][16]), training-domain flags and
+    the independence log-probability sum_i ln T_nu(z_i) of T_m problems."""
     h = handle or default_handle()
     batch = int(b.shape[0])
     X0 = torch.zeros((rows_pad, B.MLP_IN), dtype=torch.int16, device=b.device)
     inr = torch.zeros(max(batch, 1), dtype=torch.int32, device=b.device)
+    base = torch.zeros(max(batch, 1), dtype=torch.float64, device=b.device)
     st = h.lib.cfust_mlp_features(h.h, int(m), batch, int(rows_pad), _ptr(b), _ptr(L), _ptr(mat_idx),
-                                  int(L.shape[0]), _ptr(nu), _ptr(X0), _ptr(inr), _stream(stream))
+                                  int(L.shape[0]), _ptr(nu), _ptr(X0), _ptr(inr), _ptr(base), _stream(stream))
     B.check(st, h.h, "cfust_mlp_features")
-    return X0, inr[:batch]
+    return X0, inr[:batch], base[:batch]
 
 
 # ------------------------------------------------------------------ training --
@@ -179,6 +181,11 @@ class TrainReport:
     val_rmse_lnT: float          # RMSE of ln T on held-out problems
     val_max_abs_lnT: float
     err_head_corr: float         # correlation of predicted vs actual log10 |error|
+    val_p50_abs_lnT: float = float("nan")
+    val_p90_abs_lnT: float = float("nan")
+    val_p99_abs_lnT: float = float("nan")
+    accepted_frac_at_0p05: float = float("nan")    # share whose predicted error is <= 0.05
+    accepted_p99_abs_lnT: float = float("nan")     # actual error of those, 99th percentile
 
 
 def draw_training_problems(m: int, n: int, seed: int, nmat: int = 16384):
@@ -205,7 +212,7 @@ def label_problems(m, b, L, idx, nu, design, handle=None, chunk=1 << 18):
     return out
 
 
-def train(m: int, n_train: int, design, epochs: int = 4, batch: int = 4096, lr: float = 2e-3, lam: float = 0.1,
+def train(m: int, n_train: int, design, epochs: int = 4, batch: int = 4096, lr: float = 2e-3, lam: float = 0.05,
           seed: int = 0, n_val: int = 16384, handle=None, log=print) -> (SurrogateNet, TrainReport):
     h = handle or default_handle()
     dev = "cuda"
@@ -216,9 +223,10 @@ def train(m: int, n_train: int, design, epochs: int = 4, batch: int = 4096, lr: 
     t1 = time.perf_counter()
     rows = n_train + n_val
     rows_pad = (rows + 63) // 64 * 64
-    X0, inr = mvt_features(m, torch.as_tensor(b, device=dev), torch.as_tensor(L, device=dev),
-                           torch.as_tensor(idx, device=dev), torch.as_tensor(nu, device=dev), rows_pad, handle=h)
-    label = (lnT / LN_T_SCALE).to(torch.float32)
+    X0, inr, base = mvt_features(m, torch.as_tensor(b, device=dev), torch.as_tensor(L, device=dev),
+                                 torch.as_tensor(idx, device=dev), torch.as_tensor(nu, device=dev), rows_pad,
+                                 handle=h)
+    label = ((lnT - base) / RESID_SCALE).to(torch.float32)
     net = SurrogateNet(m, seed=seed + 1, device=dev)
     acts = Activations(batch, dev)
     out = torch.zeros((batch, B.MLP_OUT), dtype=torch.float32, device=dev)
@@ -256,14 +264,19 @@ def train(m: int, n_train: int, design, epochs: int = 4, batch: int = 4096, lr: 
     xv[:n_val] = X0[n_train:n_train + n_val]
     ov = torch.zeros((vpad, B.MLP_OUT), dtype=torch.float32, device=dev)
     mlp_forward(net, xv, ov, None, handle=h)
-    pred = ov[:n_val, 0].double() * LN_T_SCALE
+    pred = torch.clamp(base[n_train:n_train + n_val] + ov[:n_val, 0].double() * RESID_SCALE, max=0.0)
     truth = lnT[n_train:n_train + n_val]
     err = (pred - truth).abs()
     pe = ov[:n_val, 1].double()
-    ae = torch.log10(err / LN_T_SCALE + 1e-6)
+    ae = torch.log10(err / RESID_SCALE + 1e-6)
     corr = float(torch.corrcoef(torch.stack([pe, ae]))[0, 1].item())
+    qs = torch.quantile(err.float(), torch.tensor([0.5, 0.9, 0.99], device=dev)).tolist()
+    pred_err = RESID_SCALE * torch.pow(10.0, pe)
+    acc_mask = (pred_err <= 0.05) & (inr[n_train:n_train + n_val] > 0)
+    acc_frac = float(acc_mask.double().mean().item())
+    acc_p99 = float(torch.quantile(err[acc_mask].float(), 0.99).item()) if acc_mask.any() else float("nan")
     rep = TrainReport(m, n_train, epochs, t1 - t0, t2 - t1, last, float(err.pow(2).mean().sqrt().item()),
-                      float(err.max().item()), corr)
+                      float(err.max().item()), corr, qs[0], qs[1], qs[2], acc_frac, acc_p99)
     return net, rep
 
 
