@@ -28,11 +28,12 @@ def main():
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--seed", type=int, default=2024)
+    ap.add_argument("--out", default=None, help="output directory (default: the package's weights/)")
     args = ap.parse_args()
     from cfust_inputs import make_design
     from paper_1606_02054_amd import surrogate as S
     design = make_design(8192, 8, seed=args.seed)
-    out_dir = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights")
+    out_dir = args.out or os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights")
     os.makedirs(out_dir, exist_ok=True)
     for m in args.m:
         net, rep = S.train(m, args.n, design, epochs=args.epochs, batch=args.batch, lr=args.lr,
