@@ -276,6 +276,75 @@ cfust_status cfust_profile_read(cfust_handle handle, double *ms, int32_t *launch
  * later calls allocate nothing (e.g. under stream capture). */
 cfust_status cfust_reserve(cfust_handle handle, cfust_dims dims, const cfust_qmc *qmc);
 
+/* ------------------------------------------------------------------------
+ * Batches of independent fits (e.g. the starts of the initialisation of
+ * Sec. 3.3, Algorithm 1, or fits of several data sets, each with its own n,
+ * p, q, g).  A batch runs
+ * the E-step (Sec. 3.1) and M-step (Sec. 3.2) of all its fits with one launch
+ * per kernel kind: the lattice integrals of every fit form one work queue per
+ * integral dimension m, drained by a persistent kernel in
+ * longest-processing-time order (tiles of observations x component x
+ * integral).  Each fit's results equal those of cfust_estep / cfust_mstep on
+ * that fit alone, bit for bit.
+ * ---------------------------------------------------------------------- */
+#define CFUST_MAX_FITS 1024
+
+/* One fit.  All pointers are device memory owned by the caller and must stay
+ * valid for the life of the batch.  params is read by the E-step and
+ * overwritten in place by the M-step (Psi^(k) -> Psi^(k+1)).  out: tau,
+ * logf_obs, loglik, w, e1, e2, e3 are required (FP32 e-terms in mixed
+ * precision, as for cfust_estep); logf_comp and cdf_stderr are optional;
+ * out.status is ignored (use status). */
+typedef struct {
+    cfust_dims dims;
+    const double *y;             /* [p][n] */
+    cfust_params_out params;
+    cfust_estep_out out;
+    int32_t *status;             /* optional [1]: device status bits of this fit, OR-ed in */
+} cfust_fit;
+
+typedef struct cfust_batch_ctx *cfust_batch;
+
+/* Plan a batch of 1 <= nfits <= CFUST_MAX_FITS fits (host array `fits`,
+ * copied) with one lattice rule for all of them.  Allocates the batch's own
+ * device workspace; later batch calls allocate nothing. */
+cfust_status cfust_batch_create(cfust_handle handle, int32_t nfits, const cfust_fit *fits, const cfust_qmc *qmc,
+                                cfust_batch *batch);
+cfust_status cfust_batch_destroy(cfust_batch batch);
+
+/* E-step of every fit (cfust_estep semantics per fit). */
+cfust_status cfust_batch_estep(cfust_batch batch, void *stream);
+/* M-step of every fit (cfust_mstep semantics per fit, in place). */
+cfust_status cfust_batch_mstep(cfust_batch batch, void *stream);
+
+/* `iters` EM iterations of every fit: E-step, convergence check, M-step.
+ * The log-likelihood (eq. 27) of iteration k of fit f goes to trace[k][f]
+ * (optional device FP64 [iters][nfits]).  Convergence is Aitken's criterion
+ * of Sec. 3.4 (eqs. 24-26): from the third iteration on, a fit stops when
+ * |l_inf^(k+1) - l^(k+1)| < tol, with a^(k) = (l^(k+1) - l^(k)) / (l^(k) -
+ * l^(k-1)) and l_inf^(k+1) = l^(k) + (l^(k+1) - l^(k)) / (1 - a^(k)); an
+ * unchanged log-likelihood also stops it, and so does a non-finite one.
+ * tol <= 0 runs all iterations.  A stopped fit is retired on the device: its
+ * M-step and all later work are skipped, so its parameters and E-step
+ * outputs stay those of its last E-step.  A fit that is never retired ends
+ * after its last M-step (parameters one step ahead of the outputs, as in a
+ * plain loop of cfust_estep, cfust_mstep).  iters_done (optional device int32
+ * [nfits]) receives the E-steps run per fit.  use_graph != 0 captures one
+ * iteration in a HIP graph (on first use, or when trace, iters, tol or
+ * iters_done change) and replays it; 0 launches the kernels directly.  Do
+ * not call while `stream` is being captured. */
+cfust_status cfust_fit_batch(cfust_batch batch, int32_t iters, double tol, int32_t use_graph, double *trace,
+                             int32_t *iters_done, void *stream);
+
+/* Autotuner of the batch's lattice queues: times, for each integral
+ * dimension, tiles of 4, 8 or 16 observations, one or two persistent blocks
+ * per resident slot and (mixed, N a multiple of 128) 1 or 2 lattice points
+ * per lane per trip, on a prefix of the queue, and keeps the fastest.
+ * Synchronises the stream.  chosen (optional, host int32
+ * [(CFUST_MAX_Q+1) * 3]) receives (rows per tile, blocks per slot, points per
+ * lane) per m (zeros where no queue). */
+cfust_status cfust_batch_tune(cfust_batch batch, int32_t *chosen, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

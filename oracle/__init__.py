@@ -197,3 +197,37 @@ def mstep(y, es: EStepOut, params):
 
 def loglik(y, params, design) -> float:
     return estep(y, params, design).loglik
+
+
+def aitken_iterations(trace, tol: float) -> int:
+    """Number of EM iterations (E-steps) after which Aitken's criterion of
+    Sec. 3.4 stops a fit whose log-likelihoods are trace[0], trace[1], ...
+
+    With l^(k+1) the newest value: a^(k) = (l^(k+1) - l^(k)) / (l^(k) -
+    l^(k-1)) (eq. 26), l_inf^(k+1) = l^(k) + (l^(k+1) - l^(k)) / (1 - a^(k))
+    (eq. 25), stop when |l_inf^(k+1) - l^(k+1)| < tol (eq. 24), which needs
+    three values.  Readings where the formulas are undefined: an unchanged
+    log-likelihood stops (a is 0/0; the iteration has reached a fixed point);
+    l^(k) = l^(k-1) with a change after it gives a = +-inf and l_inf = l^(k);
+    a = 1 gives an infinite l_inf (no stop); a non-finite value stops.
+    tol <= 0 never stops on the criterion."""
+    t = np.asarray(trace, dtype=np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        for k in range(len(t)):
+            l1 = t[k]
+            if not np.isfinite(l1):
+                return k + 1
+            if k >= 1 and l1 == t[k - 1]:
+                return k + 1
+            if k >= 2 and tol > 0:
+                l0, lm = t[k - 1], t[k - 2]
+                d1, d0 = l1 - l0, l0 - lm
+                if d0 == 0.0:
+                    gap = abs(d1)
+                else:
+                    a = np.float64(d1) / np.float64(d0)
+                    linf = l0 + np.float64(d1) / (np.float64(1.0) - a)
+                    gap = abs(linf - l1)
+                if gap < tol:
+                    return k + 1
+    return len(t)

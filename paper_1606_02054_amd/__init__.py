@@ -258,5 +258,74 @@ def mvt_cdf_batch(b: torch.Tensor, L: torch.Tensor, mat_idx: torch.Tensor, nu: t
     return p, logp, se
 
 
+class Batch:
+    """Many independent fits run together (include/cfust.h, "Batches of
+    independent fits").  ``fits`` is a list of (y [p][n] float64, DeviceParams,
+    EStepResult) on one device; the parameters are updated in place by the
+    M-step.  All fits share one lattice rule and precision."""
+
+    def __init__(self, fits, qmc: DeviceQmc, handle: Optional[Handle] = None):
+        self.handle = handle or default_handle()
+        self.qmc = qmc
+        self.fits = list(fits)
+        if not 1 <= len(self.fits) <= B.MAX_FITS:
+            raise ValueError(f"1 <= number of fits <= {B.MAX_FITS}")
+        arr = (B.FitC * len(self.fits))()
+        for k, (y, P, es) in enumerate(self.fits):
+            n = _check_y(y, P.p)
+            if es.precision != qmc.precision:
+                raise ValueError(f"fit {k}: E-step outputs of another precision")
+            arr[k] = B.FitC(B.Dims(n, P.p, P.q, P.g), _ptr(y), P.c(), es.c(), _ptr(es.status))
+        self._arr = arr
+        b = C.c_void_p()
+        B.check(self.handle.lib.cfust_batch_create(self.handle.h, len(self.fits), arr, C.byref(qmc.c), C.byref(b)),
+                self.handle.h, "cfust_batch_create")
+        self.b = b
+
+    @property
+    def nfits(self) -> int:
+        return len(self.fits)
+
+    def estep(self, stream=None):
+        B.check(self.handle.lib.cfust_batch_estep(self.b, _stream(stream)), self.handle.h, "cfust_batch_estep")
+
+    def mstep(self, stream=None):
+        B.check(self.handle.lib.cfust_batch_mstep(self.b, _stream(stream)), self.handle.h, "cfust_batch_mstep")
+
+    def fit(self, iters: int, tol: float = 0.0, use_graph: bool = True, trace: Optional[torch.Tensor] = None,
+            iters_done: Optional[torch.Tensor] = None, stream=None):
+        """``iters`` EM iterations with Aitken's stopping rule (Sec. 3.4) at
+        tolerance ``tol`` (<= 0: all iterations).  Returns (trace [iters][nfits]
+        float64, NaN where a fit had stopped; iters_done [nfits] int32)."""
+        dev = self.fits[0][0].device
+        if trace is None:
+            trace = torch.full((max(iters, 1), self.nfits), float("nan"), dtype=torch.float64, device=dev)
+        if iters_done is None:
+            iters_done = torch.zeros(self.nfits, dtype=torch.int32, device=dev)
+        _need(trace, torch.float64, "trace", (max(iters, 1), self.nfits))
+        _need(iters_done, torch.int32, "iters_done", (self.nfits,))
+        st = self.handle.lib.cfust_fit_batch(self.b, int(iters), float(tol), 1 if use_graph else 0,
+                                             _ptr(trace), _ptr(iters_done), _stream(stream))
+        B.check(st, self.handle.h, "cfust_fit_batch")
+        return trace, iters_done
+
+    def tune(self, stream=None):
+        """Autotune the lattice queues; returns {m: (rows per tile, blocks per slot, points per lane)}."""
+        arr = (C.c_int32 * ((B.MAX_Q + 1) * 3))()
+        B.check(self.handle.lib.cfust_batch_tune(self.b, arr, _stream(stream)), self.handle.h, "cfust_batch_tune")
+        return {m: tuple(arr[3 * m:3 * m + 3]) for m in range(B.MAX_Q + 1) if arr[3 * m] > 0}
+
+    def close(self):
+        if getattr(self, "b", None):
+            self.handle.lib.cfust_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def decode_status(word: int):
     return [name for bit, name in B.DEV_BITS.items() if word & bit]

@@ -30,7 +30,9 @@ DEV_BITS = {1: "NOTSPD_OMEGA", 2: "NOTSPD_LAMBDA", 4: "BADPARAM", 8: "NOTSPD_E3"
 EXPORTS = ["cfust_create", "cfust_destroy", "cfust_last_error", "cfust_estep", "cfust_mstep",
            "cfust_loglik", "mvt_cdf_batch", "cfust_reserve", "cfust_profile_enable", "cfust_profile_read",
            "cfust_autotune", "cfust_mlp_forward", "cfust_mlp_backward", "cfust_mlp_adam",
-           "cfust_mlp_loss", "cfust_mlp_features", "cfust_estep_surrogate"]
+           "cfust_mlp_loss", "cfust_mlp_features", "cfust_estep_surrogate", "cfust_batch_create",
+           "cfust_batch_destroy", "cfust_batch_estep", "cfust_batch_mstep", "cfust_fit_batch", "cfust_batch_tune"]
+MAX_FITS = 1024
 
 
 class Dims(C.Structure):
@@ -51,6 +53,10 @@ class EstepOutC(C.Structure):
     _fields_ = [("tau", C.c_void_p), ("logf_obs", C.c_void_p), ("loglik", C.c_void_p),
                 ("w", C.c_void_p), ("e1", C.c_void_p), ("e2", C.c_void_p), ("e3", C.c_void_p),
                 ("logf_comp", C.c_void_p), ("cdf_stderr", C.c_void_p), ("status", C.c_void_p)]
+
+
+class FitC(C.Structure):
+    _fields_ = [("dims", Dims), ("y", C.c_void_p), ("params", ParamsC), ("out", EstepOutC), ("status", C.c_void_p)]
 
 
 class MlpWeightsC(C.Structure):
@@ -118,6 +124,15 @@ def load(path: str = LIB_PATH):
                                           C.POINTER(EstepOutC), vp]
     lib.cfust_autotune.restype = C.c_int
     lib.cfust_autotune.argtypes = [vp, vp, Dims, C.POINTER(ParamsC), C.POINTER(QmcC), C.POINTER(C.c_int32), vp]
+    lib.cfust_batch_create.restype = C.c_int
+    lib.cfust_batch_create.argtypes = [vp, i32, C.POINTER(FitC), C.POINTER(QmcC), C.POINTER(vp)]
+    lib.cfust_batch_destroy.restype = C.c_int; lib.cfust_batch_destroy.argtypes = [vp]
+    lib.cfust_batch_estep.restype = C.c_int; lib.cfust_batch_estep.argtypes = [vp, vp]
+    lib.cfust_batch_mstep.restype = C.c_int; lib.cfust_batch_mstep.argtypes = [vp, vp]
+    lib.cfust_fit_batch.restype = C.c_int
+    lib.cfust_fit_batch.argtypes = [vp, i32, C.c_double, i32, vp, vp, vp]
+    lib.cfust_batch_tune.restype = C.c_int
+    lib.cfust_batch_tune.argtypes = [vp, C.POINTER(C.c_int32), vp]
     lib.cfust_profile_enable.restype = C.c_int
     lib.cfust_profile_enable.argtypes = [vp, C.c_int]
     lib.cfust_profile_read.restype = C.c_int

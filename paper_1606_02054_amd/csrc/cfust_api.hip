@@ -1,128 +1,15 @@
 // cfust_api.hip -- host side of the C ABI declared in include/cfust.h:
 // argument checks, workspace, and the launch sequence of each call.
-#include <stdarg.h>
-#include <stdio.h>
 #include <string.h>
 
-#include <map>
 #include <new>
-#include <string>
-#include <tuple>
-#include <vector>
 
-#include "cfust_kernels.h"
-
-struct ProfRec {
-    int m;
-    hipEvent_t e0, e1;
-};
-
-struct cfust_ctx {
-    int device = 0;
-    std::string err;
-    void *ws = nullptr;
-    size_t ws_size = 0;
-    bool prof = false;
-    std::vector<ProfRec> rec;        // recorded (pending) event pairs
-    std::vector<hipEvent_t> pool;    // free events
-    std::string arch;                // gcnArchName of the device
-    // autotuner cache: (m, N, S, precision) -> lattice points per lane
-    std::map<std::tuple<int, int, int, int>, int> tuned;
-};
+#include "cfust_host.h"
 
 namespace {
 
 using namespace cfust;
-
-cfust_status fail(cfust_handle h, cfust_status st, const char *fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    if (h) h->err = buf;
-    return st;
-}
-
-cfust_status hip_check(cfust_handle h, hipError_t e, const char *what) {
-    if (e == hipSuccess) return CFUST_OK;
-    return fail(h, CFUST_EDEVICE, "%s: %s", what, hipGetErrorString(e));
-}
-
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-// Bump allocator over the handle's workspace.
-struct Carve {
-    size_t off = 0;
-    template <class T> size_t take(size_t count) {
-        const size_t o = off;
-        off = align256(off + count * sizeof(T));
-        return o;
-    }
-};
-
-cfust_status ensure_ws(cfust_handle h, size_t bytes) {
-    if (bytes <= h->ws_size) return CFUST_OK;
-    if (h->ws) {
-        hipError_t e = hipFree(h->ws);   // synchronises the device
-        h->ws = nullptr;
-        h->ws_size = 0;
-        if (e != hipSuccess) return hip_check(h, e, "hipFree(workspace)");
-    }
-    const size_t sz = align256(bytes + bytes / 4);
-    if (hipMalloc(&h->ws, sz) != hipSuccess) {
-        h->ws = nullptr;
-        return fail(h, CFUST_ENOMEM, "workspace allocation of %zu bytes failed", sz);
-    }
-    h->ws_size = sz;
-    return CFUST_OK;
-}
-
-template <class T> T *at(cfust_handle h, size_t off) { return (T *)((char *)h->ws + off); }
-
-cfust_status check_dims(cfust_handle h, const cfust_dims &d) {
-    if (d.n < 0) return fail(h, CFUST_EINVAL, "n = %d < 0", d.n);
-    if (d.p < 1 || d.p > MAXP) return fail(h, CFUST_EINVAL, "p = %d outside [1, %d]", d.p, MAXP);
-    if (d.q < 1 || d.q > MAXQ) return fail(h, CFUST_EINVAL, "q = %d outside [1, %d]", d.q, MAXQ);
-    if (d.g < 1 || d.g > MAXG) return fail(h, CFUST_EINVAL, "g = %d outside [1, %d]", d.g, MAXG);
-    return CFUST_OK;
-}
-
-int ilog2_exact(int N) {
-    if (N <= 0 || (N & (N - 1))) return -1;
-    int k = 0;
-    while ((1 << k) < N) ++k;
-    return k;
-}
-
-cfust_status check_qmc(cfust_handle h, const cfust_qmc *Q, bool lattice_needed) {
-    if (!Q) return fail(h, CFUST_EINVAL, "qmc is NULL");
-    if (Q->precision != CFUST_FP64 && Q->precision != CFUST_MIXED)
-        return fail(h, CFUST_EINVAL, "precision %d is neither CFUST_FP64 nor CFUST_MIXED", Q->precision);
-    if (!lattice_needed) return CFUST_OK;
-    if (Q->N < 2 || Q->N > 65536) return fail(h, CFUST_EINVAL, "lattice size N = %d outside [2, 65536]", Q->N);
-    if (Q->S < 1 || Q->S > MAXS) return fail(h, CFUST_EINVAL, "shift count S = %d outside [1, %d]", Q->S, MAXS);
-    if (!Q->z || !Q->shifts) return fail(h, CFUST_EINVAL, "lattice vector or shifts are NULL");
-    if (Q->precision == CFUST_MIXED && ilog2_exact(Q->N) < 0)
-        return fail(h, CFUST_EINVAL, "mixed precision needs N a power of two (N = %d)", Q->N);
-    return CFUST_OK;
-}
-
-LatticeArgs lattice_of(const cfust_qmc *Q) {
-    LatticeArgs L;
-    L.N = Q->N;
-    L.S = Q->S;
-    L.log2N = ilog2_exact(Q->N);
-    L.z = Q->z;
-    L.shifts = Q->shifts;
-    return L;
-}
-
-cfust_status check_params(cfust_handle h, const cfust_params *P) {
-    if (!P || !P->pi || !P->mu || !P->Sigma || !P->Delta || !P->nu)
-        return fail(h, CFUST_EINVAL, "a parameter array is NULL");
-    return CFUST_OK;
-}
+using namespace cfust_host;
 
 cfust_status check_mlp_b(cfust_handle h, int32_t B) {
     if (B <= 0 || B % 64) return fail(h, CFUST_EINVAL, "B = %d is not a positive multiple of 64", B);
@@ -155,18 +42,6 @@ EstepWs estep_layout(const cfust_dims &d, int J, bool own_logf) {
     return w;
 }
 
-int mstep_nblk(const cfust_dims &d) {
-    const int ntiles = (d.n + 63) / 64;
-    int nb = (ntiles + 3) / 4;
-    if (nb < 1) nb = 1;
-    if (nb > 256) nb = 256;
-    return nb;
-}
-
-size_t mstep_bytes(const cfust_dims &d) {
-    return align256((size_t)d.g * mstep_nblk(d) * nstat(d.p, d.q) * sizeof(double) + (size_t)d.g * sizeof(int32_t));
-}
-
 hipEvent_t pool_event(cfust_handle h) {
     if (!h->pool.empty()) {
         hipEvent_t e = h->pool.back();
@@ -178,14 +53,9 @@ hipEvent_t pool_event(cfust_handle h) {
     return e;
 }
 
-int choose_ppl(cfust_handle h, int m, const LatticeArgs &L, bool mixed) {
-    auto it = h->tuned.find(std::make_tuple(m, L.N, L.S, mixed ? 1 : 0));
-    if (it != h->tuned.end()) return it->second;
-    return 1;
-}
 
 hipError_t timed_qmc(cfust_handle h, const EstepQmcArgs &a, int m, int nidx, hipStream_t s) {
-    const int ppl = choose_ppl(h, m, a.lat, a.mixed != 0);
+    const int ppl = tuned_ppl(h, m, a.lat, a.mixed != 0);
     if (!h->prof || a.n == 0 || nidx == 0) return launch_estep_qmc(a, m, nidx, s, nullptr, nullptr, ppl);
     ProfRec r{m, pool_event(h), pool_event(h)};
     const hipError_t e = launch_estep_qmc(a, m, nidx, s, r.e0, r.e1, ppl);
@@ -341,6 +211,7 @@ cfust_status cfust_create(cfust_handle *handle, int device) {
     cfust_ctx *c = new (std::nothrow) cfust_ctx;
     if (!c) return CFUST_ENOMEM;
     c->device = device;
+    c->ncu = prop.multiProcessorCount;
     c->arch = prop.gcnArchName;
     *handle = c;
     return CFUST_OK;

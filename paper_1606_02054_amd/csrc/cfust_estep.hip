@@ -52,12 +52,10 @@ __device__ inline int pair_index(int q, int i, int k) {  // i < k
 
 // ------------------------------------------------------------ precompute ---
 
-__global__ __launch_bounds__(64) void k_precompute(const double *__restrict__ pi, const double *__restrict__ mu,
-                                                   const double *__restrict__ Sigma,
-                                                   const double *__restrict__ Delta,
-                                                   const double *__restrict__ nu, int p, int q,
-                                                   CompPre *__restrict__ pre) {
-    const int h = blockIdx.x;
+// Component h of one parameter set; a block of 64 threads.
+__device__ inline void precompute_body(const double *__restrict__ pi, const double *__restrict__ Sigma,
+                                       const double *__restrict__ Delta, const double *__restrict__ nu, int p,
+                                       int q, CompPre *__restrict__ pre, int h) {
     CompPre &P = pre[h];
     __shared__ double Lam[MAXQ * MAXQ];
     __shared__ int st;
@@ -183,6 +181,13 @@ __global__ __launch_bounds__(64) void k_precompute(const double *__restrict__ pi
     }
 }
 
+__global__ __launch_bounds__(64) void k_precompute(const double *__restrict__ pi, const double *__restrict__ Sigma,
+                                                   const double *__restrict__ Delta,
+                                                   const double *__restrict__ nu, int p, int q,
+                                                   CompPre *__restrict__ pre) {
+    precompute_body(pi, Sigma, Delta, nu, p, q, pre, blockIdx.x);
+}
+
 // Fold the per-component status words into the caller's status word.
 __global__ void k_status_fold(const CompPre *__restrict__ pre, int g, int32_t *__restrict__ status) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -232,9 +237,10 @@ __device__ inline void table_fit_row(const double *f, float *dst) {
 
 constexpr int TAB_NODES = (TAB_CDF_ROWS + TAB_INV_ROWS) * 7;   // 133
 
-__global__ __launch_bounds__(192) void k_tables(const CompPre *__restrict__ pre, int p, int ndof,
-                                                float *__restrict__ tabs) {
-    const int h = blockIdx.x / ndof, off = blockIdx.x % ndof;
+// Block `bid` = (component, dof offset) of one parameter set; 192 threads.
+__device__ inline void tables_body(const CompPre *__restrict__ pre, int p, int ndof, float *__restrict__ tabs,
+                                   int bid) {
+    const int h = bid / ndof, off = bid % ndof;
     const double nu = pre[h].nu + p + off;
     __shared__ double fv[TAB_NODES];
     const int t = threadIdx.x;
@@ -245,6 +251,11 @@ __global__ __launch_bounds__(192) void k_tables(const CompPre *__restrict__ pre,
     if (t >= TAB_CDF_ROWS + TAB_INV_ROWS && t < TAB_ROWS) {   // pad row
         for (int i = 0; i < 8; ++i) dst[8 * t + i] = 0.0f;
     }
+}
+
+__global__ __launch_bounds__(192) void k_tables(const CompPre *__restrict__ pre, int p, int ndof,
+                                                float *__restrict__ tabs) {
+    tables_body(pre, p, ndof, tabs, blockIdx.x);
 }
 
 // ------------------------------------------------------------- geometry ----
@@ -308,6 +319,69 @@ __device__ inline const double *integral_limits(const IntDesc &D, const CompPre 
 
 // --------------------------------------------------------------- lattice ---
 
+// FP64 prologue and epilogue of one integral.  They are kept out of line:
+// inlined into a loop over items (the persistent kernel), their FP64
+// constants would be hoisted out of the loop and stay live in vector
+// registers through the lattice loop, halving the occupancy.
+struct ItemHead {
+    SovHead H;
+    double b[MAXQ];
+    const double *L;
+    double nu0;
+};
+
+__device__ __attribute__((noinline)) void item_head(const EstepQmcArgs &a, int h, int idx, int j, ItemHead &o) {
+    const IntDesc D = int_desc(a.q, idx);
+    const CompPre &P = a.pre[h];
+    double c[MAXQ], d;
+    pair_geometry(a.y, a.n, a.p, a.q, j, a.mu + (size_t)h * a.p, P, c, d);
+    o.L = integral_limits(D, P, a.p, a.q, c, d, o.b);
+    o.nu0 = P.nu + a.p + D.dofoff;
+    o.H = sov_head(o.b, o.L, o.nu0);
+}
+
+__device__ __attribute__((noinline)) void item_finish(const SovHead &H, const double *smean, int S, double *est,
+                                                      double *se, double *lnest) {
+    sov_finish(H, smean, S, est, se, lnest);
+}
+
+// Integral idx of pair (observation j, component h), evaluated by one wave.
+// MIXED: FP32 integrand with the dof tables in `tab` (LDS); returns false,
+// writing nothing, when the FP32 product underflowed (the item then needs the
+// FP64 integrand).  Lane 0 writes the estimate (and, for idx 0, ln A and its
+// standard error).
+template <int M, bool MIXED, int PPL>
+__device__ inline bool qmc_item(const EstepQmcArgs &a, int h, int idx, int j, const float *tab, double *smean,
+                                int lane) {
+    ItemHead I;
+    item_head(a, h, idx, j, I);
+    double est = 0.0, se = 0.0, lnest = -INFINITY;
+    if (I.H.e0 > 0.0 || I.H.lne0 > -INFINITY) {
+        if (MIXED) {
+            if (!sov_mixed<M, PPL>(I.H, I.b, I.L, I.nu0, a.lat, tab, smean, lane)) return false;
+        } else {
+            sov_fp64<M>(I.H, I.b, I.L, I.nu0, a.lat, smean, lane);
+        }
+        item_finish(I.H, smean, a.lat.S, &est, &se, &lnest);
+    }
+    if (lane == 0) {
+        const size_t o = ((size_t)h * a.J + idx) * a.n + j;
+        a.est[o] = est;
+        if (idx == 0) {
+            a.lnA[(size_t)h * a.n + j] = lnest;
+            if (a.se) a.se[(size_t)h * a.n + j] = se;
+        }
+    }
+    return true;
+}
+
+// Stage the FP32 tables of the dofs an integral of dimension M uses.
+template <int M>
+__device__ inline void load_tables(const float *__restrict__ tabs, int h, int dofoff, float *tab) {
+    const float *src = tabs + ((size_t)h * NDOF + dofoff) * TAB_FLOATS;
+    for (int t = threadIdx.x; t < M * TAB_FLOATS; t += blockDim.x) tab[t] = src[t];
+}
+
 // One wave per (observation j, integral idx, component h); 4 observations per
 // block share the integral's tables.  MIXED: FP32 integrand, items whose FP32
 // product underflows are flagged for the FP64 pass.  !MIXED: FP64 integrand;
@@ -317,11 +391,8 @@ __global__ __launch_bounds__(256) void k_estep_qmc(EstepQmcArgs a) {
     __shared__ __align__(16) float tab[MIXED ? M * TAB_FLOATS : 4];
     __shared__ double smean[4][MAXS];
     const int h = blockIdx.z, idx = a.idx0 + blockIdx.y;
-    const IntDesc D = int_desc(a.q, idx);
-    const CompPre &P = a.pre[h];
     if (MIXED) {
-        const float *src = a.tabs + ((size_t)h * NDOF + D.dofoff) * TAB_FLOATS;
-        for (int t = threadIdx.x; t < M * TAB_FLOATS; t += blockDim.x) tab[t] = src[t];
+        load_tables<M>(a.tabs, h, int_desc(a.q, idx).dofoff, tab);
         __syncthreads();
     }
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -333,29 +404,8 @@ __global__ __launch_bounds__(256) void k_estep_qmc(EstepQmcArgs a) {
         if (MIXED && lane == 0) a.flag[o] = 0;
         return;
     }
-    double c[MAXQ], d, b[MAXQ];
-    pair_geometry(a.y, a.n, a.p, a.q, j, a.mu + (size_t)h * a.p, P, c, d);
-    const double *L = integral_limits(D, P, a.p, a.q, c, d, b);
-    const double nu0 = P.nu + a.p + D.dofoff;
-    const SovHead H = sov_head(b, L, nu0);
-    double est = 0.0, se = 0.0, lnest = -INFINITY;
-    if (H.e0 > 0.0 || H.lne0 > -INFINITY) {
-        if (MIXED) {
-            const bool ok = sov_mixed<M, PPL>(H, b, L, nu0, a.lat, tab, smean[wave], lane);
-            if (lane == 0) a.flag[o] = ok ? 0 : 1;
-            if (!ok) return;
-        } else {
-            sov_fp64<M>(H, b, L, nu0, a.lat, smean[wave], lane);
-        }
-        sov_finish(H, smean[wave], a.lat.S, &est, &se, &lnest);
-    }
-    if (lane == 0) {
-        a.est[o] = est;
-        if (idx == 0) {
-            a.lnA[(size_t)h * a.n + j] = lnest;
-            if (a.se) a.se[(size_t)h * a.n + j] = se;
-        }
-    }
+    const bool ok = qmc_item<M, MIXED, PPL>(a, h, idx, j, tab, smean[wave], lane);
+    if (MIXED && lane == 0) a.flag[o] = ok ? 0 : 1;
 }
 
 // ------------------------------------------------------------- assembly ----
@@ -371,8 +421,8 @@ __device__ inline double integral_value(const EstepAsmArgs &a, const CompPre &P,
     return dm_tcdf(b[0] / L[0], P.nu + a.p + D.dofoff);
 }
 
-__global__ __launch_bounds__(128) void k_assemble(EstepAsmArgs a) {
-    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+// Pair gid = h * n + j of one parameter set.
+__device__ inline void assemble_body(const EstepAsmArgs &a, int gid) {
     if (gid >= a.n * a.g) return;
     const int h = gid / a.n, j = gid % a.n;
     const CompPre &P = a.pre[h];
@@ -469,11 +519,16 @@ __global__ __launch_bounds__(128) void k_assemble(EstepAsmArgs a) {
     }
 }
 
+__global__ __launch_bounds__(128) void k_assemble(EstepAsmArgs a) {
+    assemble_body(a, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 // ------------------------------------------------------------------ LSE ----
 
-__global__ __launch_bounds__(256) void k_lse(EstepLseArgs a) {
+// Block bid (256 observations) of one parameter set; writes partial[bid].
+__device__ inline void lse_body(const EstepLseArgs &a, int bid) {
     __shared__ double red[256];
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = bid * 256 + threadIdx.x;
     double lj = 0.0;
     if (j < a.n) {
         double mx = -INFINITY;
@@ -515,12 +570,15 @@ __global__ __launch_bounds__(256) void k_lse(EstepLseArgs a) {
         if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) a.partial[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) a.partial[bid] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_lse(EstepLseArgs a) {
+    lse_body(a, blockIdx.x);
 }
 
 // Sum of per-block partials in a fixed order (deterministic).
-__global__ __launch_bounds__(256) void k_sum_partials(const double *__restrict__ part, int np,
-                                                      double *__restrict__ out) {
+__device__ inline void sum_partials_body(const double *__restrict__ part, int np, double *__restrict__ out) {
     __shared__ double red[256];
     double s = 0.0;
     for (int i = threadIdx.x; i < np; i += 256) s += part[i];
@@ -531,6 +589,11 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double *__restrict__
         __syncthreads();
     }
     if (threadIdx.x == 0) out[0] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_sum_partials(const double *__restrict__ part, int np,
+                                                      double *__restrict__ out) {
+    sum_partials_body(part, np, out);
 }
 
 // ------------------------------------------------------------ mvt batch ----
@@ -781,7 +844,7 @@ hipError_t launch_mvt_features(int m, int batch, int rows_pad, const double *b, 
 // --------------------------------------------------------------- launch ----
 
 hipError_t launch_precompute(const cfust_params &P, int p, int q, int g, CompPre *pre, hipStream_t s) {
-    hipLaunchKernelGGL(k_precompute, dim3(g), dim3(64), 0, s, P.pi, P.mu, P.Sigma, P.Delta, P.nu, p, q, pre);
+    hipLaunchKernelGGL(k_precompute, dim3(g), dim3(64), 0, s, P.pi, P.Sigma, P.Delta, P.nu, p, q, pre);
     return hipGetLastError();
 }
 
@@ -866,6 +929,270 @@ hipError_t launch_mvt(const MvtArgs &a, hipStream_t s) {
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+// ------------------------------------------------------------ batches ----
+
+// Fit owning block b: the largest f with prefix[f] <= b.
+__device__ inline int batch_fit(const int *__restrict__ prefix, int nfits, int b) {
+    int lo = 0, hi = nfits - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(64) void k_batch_precompute(BatchArgs B) {
+    const int *pf = B.prefix + BK_PRE * (B.nfits + 1);
+    const int f = batch_fit(pf, B.nfits, blockIdx.x);
+    if (!B.active[f]) return;
+    const PrecompArgs &a = B.fits[f].pc;
+    precompute_body(a.pi, a.Sigma, a.Delta, a.nu, a.p, a.q, a.pre, blockIdx.x - pf[f]);
+}
+
+__global__ __launch_bounds__(192) void k_batch_tables(BatchArgs B) {
+    const int *pf = B.prefix + BK_TAB * (B.nfits + 1);
+    const int f = batch_fit(pf, B.nfits, blockIdx.x);
+    if (!B.active[f]) return;
+    const FitDesc &F = B.fits[f];
+    tables_body(F.pc.pre, F.pc.p, F.ndof, F.tabs, blockIdx.x - pf[f]);
+}
+
+__global__ __launch_bounds__(128) void k_batch_assemble(BatchArgs B) {
+    const int *pf = B.prefix + BK_ASM * (B.nfits + 1);
+    const int f = batch_fit(pf, B.nfits, blockIdx.x);
+    if (!B.active[f]) return;
+    const EstepAsmArgs a = B.fits[f].aa;
+    assemble_body(a, (blockIdx.x - pf[f]) * 128 + threadIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_batch_lse(BatchArgs B) {
+    const int *pf = B.prefix + BK_LSE * (B.nfits + 1);
+    const int f = batch_fit(pf, B.nfits, blockIdx.x);
+    if (!B.active[f]) return;
+    const EstepLseArgs a = B.fits[f].la;
+    lse_body(a, blockIdx.x - pf[f]);
+}
+
+// One block per fit: log-likelihood from the LSE partials, status fold.
+__global__ __launch_bounds__(256) void k_batch_sum(BatchArgs B) {
+    const int f = blockIdx.x;
+    if (!B.active[f]) return;
+    const FitDesc &F = B.fits[f];
+    sum_partials_body(F.la.partial, F.nlse, F.loglik);
+    if (threadIdx.x == 0 && F.status) {
+        int s = F.status[0];
+        for (int h = 0; h < F.g; ++h) s |= F.pc.pre[h].status;
+        F.status[0] = s;
+    }
+}
+
+// Persistent lattice kernel: each block draws tiles from the queue until it
+// is empty; the 4 waves of a block share the tile's component and integral,
+// hence its LDS tables, and take its observations in turn.
+template <int M, bool MIXED, int PPL>
+__global__ __launch_bounds__(256) void k_queue_qmc(QueueArgs Q) {
+    __shared__ __align__(16) float tab[MIXED ? M * TAB_FLOATS : 4];
+    __shared__ double smean[4][MAXS];
+    __shared__ long long s_tile;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int cur_f = -1, cur_h = -1, cur_dof = -1;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = (long long)atomicAdd(Q.counter, 1ULL);
+        __syncthreads();              // also: every wave is done with the previous tile
+        // the tile number is block-uniform: keep it (and all that derives from
+        // it, including the fit's argument block) in scalar registers
+        const unsigned long long tv = (unsigned long long)s_tile;
+        const long long t = (long long)(((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(tv >> 32)) << 32) |
+                                        (unsigned)__builtin_amdgcn_readfirstlane((unsigned)tv));
+        __syncthreads();
+        if (t >= Q.ntiles) break;
+        int lo = 0, hi = Q.nseg - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (Q.seg[mid].t0 <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const QSeg S = Q.seg[lo];
+        if (!Q.active[S.fit]) continue;
+        const long long local = t - S.t0;
+        const int rt = (int)(local % S.rtiles);
+        const long long rest = local / S.rtiles;
+        const int idx = S.idx0 + (int)(rest % S.nidx);
+        const int h = (int)(rest / S.nidx);
+        EstepQmcArgs a = Q.fits[S.fit].qa;
+        a.lat = Q.lat;
+        if (MIXED) {
+            const int dof = int_desc(a.q, idx).dofoff;
+            if (S.fit != cur_f || h != cur_h || dof != cur_dof) {
+                load_tables<M>(a.tabs, h, dof, tab);
+                __syncthreads();
+                cur_f = S.fit; cur_h = h; cur_dof = dof;
+            }
+        }
+        const int jb = S.j0 + rt * S.rows;
+        for (int r = wave; r < S.rows; r += 4) {
+            const int j = jb + r;
+            const bool ok = qmc_item<M, MIXED, PPL>(a, h, idx, j, tab, smean[wave], lane);
+            if (MIXED && !ok && lane == 0) {
+                const unsigned slot = atomicAdd(Q.redo_count, 1u);
+                Q.redo[slot] = ((unsigned long long)S.fit << 43) | ((unsigned long long)h << 37) |
+                               ((unsigned long long)idx << 31) | (unsigned long long)j;
+            }
+        }
+    }
+}
+
+// FP64 integrand for the items of the redo list; one wave per entry.
+template <int M>
+__global__ __launch_bounds__(256) void k_queue_redo(QueueArgs Q) {
+    __shared__ double smean[4][MAXS];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const unsigned cnt = Q.redo_count[0];
+    for (unsigned e = blockIdx.x * 4 + wave; e < cnt; e += gridDim.x * 4) {
+        const unsigned long long v0 = Q.redo[e];
+        const unsigned long long v = ((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(v0 >> 32)) << 32) |
+                                     (unsigned)__builtin_amdgcn_readfirstlane((unsigned)v0);
+        const int f = (int)(v >> 43), h = (int)((v >> 37) & 63), idx = (int)((v >> 31) & 63);
+        const int j = (int)(v & 0x7fffffffULL);
+        EstepQmcArgs a = Q.fits[f].qa;
+        a.lat = Q.lat;
+        qmc_item<M, false, 1>(a, h, idx, j, nullptr, smean[wave], lane);
+    }
+}
+
+// Between the E-step and the M-step of a batched EM iteration: records the
+// log-likelihood of every active fit in trace[iter][fit] and retires a fit by
+// Aitken's criterion (Sec. 3.4, eqs. 24-26) with tolerance tol, or when its
+// log-likelihood is unchanged or not finite.  A retired fit's M-step and
+// later E-steps are skipped, so its parameters stay those of its last E-step.
+// hist[f] = (l^(k-1), l^(k)) of the fit's two previous iterations.  One block.
+__global__ __launch_bounds__(256) void k_batch_check(const FitDesc *__restrict__ fits, int nfits,
+                                                     int32_t *__restrict__ active, int32_t *__restrict__ iter,
+                                                     double *__restrict__ hist, double tol,
+                                                     double *__restrict__ trace, int max_trace,
+                                                     int32_t *__restrict__ iters_done) {
+    const int it = iter[0];
+    for (int f = threadIdx.x; f < nfits; f += blockDim.x) {
+        if (!active[f]) continue;
+        const double l1 = fits[f].loglik[0];            // l^(k+1), this iteration
+        if (trace && it < max_trace) trace[(size_t)it * nfits + f] = l1;
+        if (iters_done) iters_done[f] = it + 1;
+        const double lm = hist[2 * f], l0 = hist[2 * f + 1];   // l^(k-1), l^(k)
+        bool stop = !isfinite(l1);
+        if (!stop && it >= 1 && l1 == l0) stop = true;
+        if (!stop && it >= 2 && tol > 0.0) {
+            const double d1 = l1 - l0, d0 = l0 - lm;
+            double gap;                                   // |l_inf^(k+1) - l^(k+1)|
+            if (d0 == 0.0) {
+                gap = fabs(d1);                           // a = +-inf: l_inf = l^(k)
+            } else {
+                const double a = d1 / d0;                 // eq. (26)
+                const double linf = l0 + d1 / (1.0 - a);  // eq. (25)
+                gap = fabs(linf - l1);
+            }
+            stop = gap < tol;                             // eq. (24)
+        }
+        hist[2 * f] = l0;
+        hist[2 * f + 1] = l1;
+        if (stop) active[f] = 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) iter[0] = it + 1;
+}
+
+hipError_t launch_batch_precompute(const BatchArgs &b, int nblocks, hipStream_t s) {
+    if (nblocks > 0) hipLaunchKernelGGL(k_batch_precompute, dim3(nblocks), dim3(64), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_tables(const BatchArgs &b, int nblocks, hipStream_t s) {
+    if (nblocks > 0) hipLaunchKernelGGL(k_batch_tables, dim3(nblocks), dim3(192), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_assemble(const BatchArgs &b, int nblocks, hipStream_t s) {
+    if (nblocks > 0) hipLaunchKernelGGL(k_batch_assemble, dim3(nblocks), dim3(128), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_lse(const BatchArgs &b, int nblocks, hipStream_t s) {
+    if (nblocks > 0) hipLaunchKernelGGL(k_batch_lse, dim3(nblocks), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_sum(const BatchArgs &b, hipStream_t s) {
+    if (b.nfits > 0) hipLaunchKernelGGL(k_batch_sum, dim3(b.nfits), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_check(const FitDesc *fits, int nfits, int32_t *active, int32_t *iter, double *hist,
+                              double tol, double *trace, int max_trace, int32_t *iters_done, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_check, dim3(1), dim3(256), 0, s, fits, nfits, active, iter, hist, tol, trace,
+                       max_trace, iters_done);
+    return hipGetLastError();
+}
+
+template <int M>
+static const void *queue_kernel(bool mixed, int ppl) {
+    if (!mixed) return (const void *)k_queue_qmc<M, false, 1>;
+    return ppl == 2 ? (const void *)k_queue_qmc<M, true, 2> : (const void *)k_queue_qmc<M, true, 1>;
+}
+
+static const void *queue_kernel_m(int m, bool mixed, int ppl) {
+    switch (m) {
+    case 2: return queue_kernel<2>(mixed, ppl);
+    case 3: return queue_kernel<3>(mixed, ppl);
+    case 4: return queue_kernel<4>(mixed, ppl);
+    case 5: return queue_kernel<5>(mixed, ppl);
+    case 6: return queue_kernel<6>(mixed, ppl);
+    case 7: return queue_kernel<7>(mixed, ppl);
+    case 8: return queue_kernel<8>(mixed, ppl);
+    default: return nullptr;
+    }
+}
+
+static const void *redo_kernel_m(int m) {
+    switch (m) {
+    case 2: return (const void *)k_queue_redo<2>;
+    case 3: return (const void *)k_queue_redo<3>;
+    case 4: return (const void *)k_queue_redo<4>;
+    case 5: return (const void *)k_queue_redo<5>;
+    case 6: return (const void *)k_queue_redo<6>;
+    case 7: return (const void *)k_queue_redo<7>;
+    case 8: return (const void *)k_queue_redo<8>;
+    default: return nullptr;
+    }
+}
+
+hipError_t launch_queue_qmc(const QueueArgs &q, int m, bool mixed, int ppl, int grid, hipStream_t s) {
+    const void *k = queue_kernel_m(m, mixed, ppl);
+    if (!k || grid < 1) return hipErrorInvalidValue;
+    void *args[] = {(void *)&q};
+    return hipLaunchKernel(k, dim3(grid), dim3(256), args, 0, s);
+}
+
+hipError_t launch_queue_redo(const QueueArgs &q, int m, int grid, hipStream_t s) {
+    const void *k = redo_kernel_m(m);
+    if (!k || grid < 1) return hipErrorInvalidValue;
+    void *args[] = {(void *)&q};
+    return hipLaunchKernel(k, dim3(grid), dim3(256), args, 0, s);
+}
+
+int queue_qmc_occupancy(int m, bool mixed, int ppl) {
+    const void *k = queue_kernel_m(m, mixed, ppl);
+    int nb = 0;
+    if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 256, 0) != hipSuccess) return 1;
+    return nb > 0 ? nb : 1;
+}
+
+int queue_redo_occupancy(int m) {
+    const void *k = redo_kernel_m(m);
+    int nb = 0;
+    if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 256, 0) != hipSuccess) return 1;
+    return nb > 0 ? nb : 1;
 }
 
 }  // namespace cfust

@@ -1,0 +1,148 @@
+// cfust_host.h -- host-side state of a handle and the argument checks shared
+// by the entry points (private).
+#pragma once
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "cfust_kernels.h"
+
+struct ProfRec {
+    int m;
+    hipEvent_t e0, e1;
+};
+
+struct cfust_ctx {
+    int device = 0;
+    int ncu = 0;                     // compute units of the device
+    std::string err;
+    void *ws = nullptr;
+    size_t ws_size = 0;
+    bool prof = false;
+    std::vector<ProfRec> rec;        // recorded (pending) event pairs
+    std::vector<hipEvent_t> pool;    // free events
+    std::string arch;                // gcnArchName of the device
+    // autotuner cache: (m, N, S, precision) -> lattice points per lane
+    std::map<std::tuple<int, int, int, int>, int> tuned;
+};
+
+namespace cfust_host {
+
+using namespace cfust;
+
+inline cfust_status fail(cfust_handle h, cfust_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (h) h->err = buf;
+    return st;
+}
+
+inline cfust_status hip_check(cfust_handle h, hipError_t e, const char *what) {
+    if (e == hipSuccess) return CFUST_OK;
+    return fail(h, CFUST_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Bump allocator over a workspace.
+struct Carve {
+    size_t off = 0;
+    template <class T> size_t take(size_t count) {
+        const size_t o = off;
+        off = align256(off + count * sizeof(T));
+        return o;
+    }
+};
+
+inline cfust_status ensure_ws(cfust_handle h, size_t bytes) {
+    if (bytes <= h->ws_size) return CFUST_OK;
+    if (h->ws) {
+        hipError_t e = hipFree(h->ws);   // synchronises the device
+        h->ws = nullptr;
+        h->ws_size = 0;
+        if (e != hipSuccess) return hip_check(h, e, "hipFree(workspace)");
+    }
+    const size_t sz = align256(bytes + bytes / 4);
+    if (hipMalloc(&h->ws, sz) != hipSuccess) {
+        h->ws = nullptr;
+        return fail(h, CFUST_ENOMEM, "workspace allocation of %zu bytes failed", sz);
+    }
+    h->ws_size = sz;
+    return CFUST_OK;
+}
+
+template <class T> T *at(cfust_handle h, size_t off) { return (T *)((char *)h->ws + off); }
+
+inline cfust_status check_dims(cfust_handle h, const cfust_dims &d) {
+    if (d.n < 0) return fail(h, CFUST_EINVAL, "n = %d < 0", d.n);
+    if (d.p < 1 || d.p > MAXP) return fail(h, CFUST_EINVAL, "p = %d outside [1, %d]", d.p, MAXP);
+    if (d.q < 1 || d.q > MAXQ) return fail(h, CFUST_EINVAL, "q = %d outside [1, %d]", d.q, MAXQ);
+    if (d.g < 1 || d.g > MAXG) return fail(h, CFUST_EINVAL, "g = %d outside [1, %d]", d.g, MAXG);
+    return CFUST_OK;
+}
+
+inline int ilog2_exact(int N) {
+    if (N <= 0 || (N & (N - 1))) return -1;
+    int k = 0;
+    while ((1 << k) < N) ++k;
+    return k;
+}
+
+inline cfust_status check_qmc(cfust_handle h, const cfust_qmc *Q, bool lattice_needed) {
+    if (!Q) return fail(h, CFUST_EINVAL, "qmc is NULL");
+    if (Q->precision != CFUST_FP64 && Q->precision != CFUST_MIXED)
+        return fail(h, CFUST_EINVAL, "precision %d is neither CFUST_FP64 nor CFUST_MIXED", Q->precision);
+    if (!lattice_needed) return CFUST_OK;
+    if (Q->N < 2 || Q->N > 65536) return fail(h, CFUST_EINVAL, "lattice size N = %d outside [2, 65536]", Q->N);
+    if (Q->S < 1 || Q->S > MAXS) return fail(h, CFUST_EINVAL, "shift count S = %d outside [1, %d]", Q->S, MAXS);
+    if (!Q->z || !Q->shifts) return fail(h, CFUST_EINVAL, "lattice vector or shifts are NULL");
+    if (Q->precision == CFUST_MIXED && ilog2_exact(Q->N) < 0)
+        return fail(h, CFUST_EINVAL, "mixed precision needs N a power of two (N = %d)", Q->N);
+    return CFUST_OK;
+}
+
+inline LatticeArgs lattice_of(const cfust_qmc *Q) {
+    LatticeArgs L;
+    L.N = Q->N;
+    L.S = Q->S;
+    L.log2N = ilog2_exact(Q->N);
+    L.z = Q->z;
+    L.shifts = Q->shifts;
+    return L;
+}
+
+inline cfust_status check_params(cfust_handle h, const cfust_params *P) {
+    if (!P || !P->pi || !P->mu || !P->Sigma || !P->Delta || !P->nu)
+        return fail(h, CFUST_EINVAL, "a parameter array is NULL");
+    return CFUST_OK;
+}
+
+// M-step reduction blocks per component (the partition fixes the summation
+// order, so it depends on n only).
+inline int mstep_nblk(const cfust_dims &d) {
+    const int ntiles = (d.n + 63) / 64;
+    int nb = (ntiles + 3) / 4;
+    if (nb < 1) nb = 1;
+    if (nb > 256) nb = 256;
+    return nb;
+}
+
+inline size_t mstep_bytes(const cfust_dims &d) {
+    return align256((size_t)d.g * mstep_nblk(d) * nstat(d.p, d.q) * sizeof(double) + (size_t)d.g * sizeof(int32_t));
+}
+
+// Lattice points per lane chosen by the autotuner for (m, N, S, precision).
+inline int tuned_ppl(cfust_handle h, int m, const LatticeArgs &L, bool mixed) {
+    auto it = h->tuned.find(std::make_tuple(m, L.N, L.S, mixed ? 1 : 0));
+    if (it != h->tuned.end()) return it->second;
+    return 1;
+}
+
+}  // namespace cfust_host

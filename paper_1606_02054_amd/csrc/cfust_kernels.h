@@ -95,6 +95,84 @@ struct MsolveArgs {
     int32_t *status;            // optional
 };
 
+// ------------------------------------------------------------ batches ----
+// Many independent fits share one launch per kernel kind: each fit keeps the
+// argument blocks of its single-fit kernels in a FitDesc (device memory), and a
+// block finds its fit from a per-kind prefix table of block counts.
+
+struct PrecompArgs {
+    const double *pi, *Sigma, *Delta, *nu;
+    int p, q;
+    CompPre *pre;               // [g]
+};
+
+struct FitDesc {
+    int g;
+    PrecompArgs pc;
+    int ndof;                   // dof tables per component (mixed)
+    float *tabs;                // [g][NDOF][TAB_FLOATS]
+    EstepQmcArgs qa;
+    EstepAsmArgs aa;
+    EstepLseArgs la;
+    int nlse;                   // LSE blocks = partials
+    double *loglik;             // [1]
+    int32_t *status;            // optional [1]
+    MstepArgs ma;
+    MsolveArgs sa;
+    int32_t *cstat;             // [g] per-component M-step status
+};
+
+enum BatchKind { BK_PRE = 0, BK_TAB, BK_ASM, BK_LSE, BK_MRED, BK_MSOL, BK_NKIND };
+
+struct BatchArgs {
+    const FitDesc *fits;
+    int nfits;
+    const int32_t *active;      // [nfits]: 0 = fit skipped
+    const int *prefix;          // [BK_NKIND][nfits + 1] block prefix per kernel kind
+};
+
+// A run of tiles of one fit in a lattice work queue: tiles of `rows`
+// observations starting at j0 + rt * rows (rt < rtiles), for every component
+// h < g and integral idx0 .. idx0 + nidx - 1 (all of one dimension m).
+// Tile number t0 + (h * nidx + (idx - idx0)) * rtiles + rt.
+struct QSeg {
+    int fit, idx0, nidx, j0, rows, rtiles;
+    long long t0;
+};
+
+struct QueueArgs {
+    const FitDesc *fits;
+    const int32_t *active;
+    const QSeg *seg;            // [nseg], t0 ascending
+    int nseg;
+    long long ntiles;           // tiles handed out (all of them, or a prefix while tuning)
+    unsigned long long *counter;        // next tile
+    unsigned long long *redo;           // mixed: packed (fit, h, idx, j) of underflowed items
+    unsigned int *redo_count;
+    LatticeArgs lat;
+};
+
+constexpr int BATCH_MAX_FITS = 1024;   // fit index packs into 10 bits of a redo entry
+
+hipError_t launch_batch_precompute(const BatchArgs &b, int nblocks, hipStream_t s);
+hipError_t launch_batch_tables(const BatchArgs &b, int nblocks, hipStream_t s);
+hipError_t launch_batch_assemble(const BatchArgs &b, int nblocks, hipStream_t s);
+hipError_t launch_batch_lse(const BatchArgs &b, int nblocks, hipStream_t s);
+hipError_t launch_batch_sum(const BatchArgs &b, hipStream_t s);
+hipError_t launch_batch_mstep(const BatchArgs &b, int nred, int nsol, hipStream_t s);
+// Persistent lattice kernel of dimension m over a queue: `grid` blocks draw
+// tiles until the queue is empty; mixed mode appends underflowed items to the
+// redo list and launch_queue_redo evaluates them with the FP64 integrand.
+hipError_t launch_queue_qmc(const QueueArgs &q, int m, bool mixed, int ppl, int grid, hipStream_t s);
+hipError_t launch_queue_redo(const QueueArgs &q, int m, int grid, hipStream_t s);
+// Resident blocks per compute unit of the queue kernels.
+int queue_qmc_occupancy(int m, bool mixed, int ppl);
+int queue_redo_occupancy(int m);
+// Convergence check between the E-step and the M-step of a batched EM
+// iteration (see k_batch_check).
+hipError_t launch_batch_check(const FitDesc *fits, int nfits, int32_t *active, int32_t *iter, double *hist,
+                              double tol, double *trace, int max_trace, int32_t *iters_done, hipStream_t s);
+
 hipError_t launch_precompute(const cfust_params &P, int p, int q, int g, CompPre *pre, hipStream_t s);
 hipError_t launch_status_fold(const CompPre *pre, int g, int32_t *status, hipStream_t s);
 hipError_t launch_tables(const CompPre *pre, int p, int g, int ndof, float *tabs, hipStream_t s);

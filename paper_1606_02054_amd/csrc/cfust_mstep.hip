@@ -62,9 +62,9 @@ __device__ inline void ms_stat_rows(int s, int p, int q, const MsRows &R, int *f
     f[1] = R.e30 + s;
 }
 
-__global__ __launch_bounds__(256) void k_mstep_reduce(MstepArgs a) {
+// Block bx of component h of one fit.
+__device__ inline void mstep_reduce_body(const MstepArgs &a, int bx, int h) {
     __shared__ double tile[MS_MAXROWS * MS_STRIDE];
-    const int h = blockIdx.y;
     const int p = a.p, q = a.q, n = a.n;
     const int nq2 = q * (q + 1) / 2;
     const MsRows R = ms_rows(p, q);
@@ -76,7 +76,7 @@ __global__ __launch_bounds__(256) void k_mstep_reduce(MstepArgs a) {
     double acc0 = 0.0, acc1 = 0.0;
     const double *mu0 = a.mu0 + (size_t)h * p;
     const int ntiles = (n + MS_TILE - 1) / MS_TILE;
-    for (int tl = blockIdx.x; tl < ntiles; tl += a.nblk) {
+    for (int tl = bx; tl < ntiles; tl += a.nblk) {
         const int base = tl * MS_TILE;
         // stage: each (row, obs) element once, coalesced along observations
         for (int e = threadIdx.x; e < R.nrows * MS_TILE; e += blockDim.x) {
@@ -118,9 +118,13 @@ __global__ __launch_bounds__(256) void k_mstep_reduce(MstepArgs a) {
         }
         __syncthreads();
     }
-    double *out = a.partial + ((size_t)h * a.nblk + blockIdx.x) * NS;
+    double *out = a.partial + ((size_t)h * a.nblk + bx) * NS;
     if (s0 < NS) out[s0] = acc0;
     if (s1 < NS) out[s1] = acc1;
+}
+
+__global__ __launch_bounds__(256) void k_mstep_reduce(MstepArgs a) {
+    mstep_reduce_body(a, blockIdx.x, blockIdx.y);
 }
 
 __device__ inline bool ms_chol(double *A, int n) {
@@ -144,9 +148,9 @@ __device__ inline double ms_nu_eq(double v, double m) {
     return log(0.5 * v) - dm_digamma(0.5 * v) + 1.0 + m;
 }
 
-__global__ __launch_bounds__(256) void k_mstep_solve(MsolveArgs a, int32_t *cstat) {
+// Component h of one fit.
+__device__ inline void mstep_solve_body(const MsolveArgs &a, int32_t *cstat, int h) {
     __shared__ double st[512];
-    const int h = blockIdx.x;
     const int p = a.p, q = a.q;
     const int NS = nstat(p, q);
     for (int s = threadIdx.x; s < NS; s += blockDim.x) {
@@ -247,6 +251,10 @@ __global__ __launch_bounds__(256) void k_mstep_solve(MsolveArgs a, int32_t *csta
     cstat[h] = status;
 }
 
+__global__ __launch_bounds__(256) void k_mstep_solve(MsolveArgs a, int32_t *cstat) {
+    mstep_solve_body(a, cstat, blockIdx.x);
+}
+
 __global__ void k_mstep_status(const int32_t *__restrict__ cstat, int g, int32_t *__restrict__ status) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         int s = status[0];
@@ -261,6 +269,53 @@ hipError_t launch_mstep(const MstepArgs &r, const MsolveArgs &s, hipStream_t st)
     int32_t *cstat = (int32_t *)(r.partial + (size_t)r.g * r.nblk * nstat(r.p, r.q));
     hipLaunchKernelGGL(k_mstep_solve, dim3(s.g), dim3(256), 0, st, s, cstat);
     if (s.status) hipLaunchKernelGGL(k_mstep_status, dim3(1), dim3(64), 0, st, cstat, s.g, s.status);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ batches ----
+
+__device__ inline int mbatch_fit(const int *__restrict__ prefix, int nfits, int b) {
+    int lo = 0, hi = nfits - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_batch_mreduce(BatchArgs B) {
+    const int *pf = B.prefix + BK_MRED * (B.nfits + 1);
+    const int f = mbatch_fit(pf, B.nfits, blockIdx.x);
+    if (!B.active[f]) return;
+    const MstepArgs a = B.fits[f].ma;
+    const int local = blockIdx.x - pf[f];
+    mstep_reduce_body(a, local % a.nblk, local / a.nblk);
+}
+
+__global__ __launch_bounds__(256) void k_batch_msolve(BatchArgs B) {
+    const int *pf = B.prefix + BK_MSOL * (B.nfits + 1);
+    const int f = mbatch_fit(pf, B.nfits, blockIdx.x);
+    if (!B.active[f]) return;
+    const FitDesc &F = B.fits[f];
+    const MsolveArgs a = F.sa;
+    mstep_solve_body(a, F.cstat, blockIdx.x - pf[f]);
+}
+
+__global__ void k_batch_mstatus(BatchArgs B) {
+    const int f = blockIdx.x;
+    if (threadIdx.x != 0 || !B.active[f]) return;
+    const FitDesc &F = B.fits[f];
+    if (!F.status) return;
+    int s = F.status[0];
+    for (int h = 0; h < F.g; ++h) s |= F.cstat[h];
+    F.status[0] = s;
+}
+
+hipError_t launch_batch_mstep(const BatchArgs &b, int nred, int nsol, hipStream_t s) {
+    if (nred > 0) hipLaunchKernelGGL(k_batch_mreduce, dim3(nred), dim3(256), 0, s, b);
+    if (nsol > 0) hipLaunchKernelGGL(k_batch_msolve, dim3(nsol), dim3(256), 0, s, b);
+    if (b.nfits > 0) hipLaunchKernelGGL(k_batch_mstatus, dim3(b.nfits), dim3(64), 0, s, b);
     return hipGetLastError();
 }
 
