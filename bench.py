@@ -116,6 +116,147 @@ def surrogate_vs_lattice(cf, ds, y, params, design, pairs):
             "surrogate": sur, "models": sorted(models)}
 
 
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def batched_main(args) -> dict:
+    """The restart workload: 64 independent fits (n ~ logU[5e3, 2e5], p = q in
+    3..8, g in 2..6) run as one batch, one step = one EM iteration of every fit
+    (a replay of the captured graph), against the same fits run one after the
+    other through the single-fit calls.  Both produce the same log-likelihoods
+    bit for bit (checked), i.e. they are compared at equal accuracy."""
+    import numpy as np
+    import torch
+
+    import paper_1606_02054_amd as cf
+    from cfust_inputs import make_design, workload
+
+    prec = cf.CFUST_MIXED if args.precision == "mixed" else cf.CFUST_FP64
+    log("batched: drawing 64 fits")
+    sets = workload("batched_fit")
+    N, S = sets[0].meta["N"], sets[0].meta["S"]
+    design = make_design(N, S, seed=1606)
+    dev = torch.device("cuda:0")
+    h = cf.default_handle(0)
+    qmc = cf.device_qmc(design, prec, device=dev)
+
+    def make():
+        fits = []
+        for ds in sets:
+            n, p = ds.y.shape
+            fits.append((torch.as_tensor(ds.y_soa, device=dev), cf.device_params(ds.params, device=dev),
+                         cf.alloc_estep(n, p, ds.params.q, ds.params.g, prec, device=dev, stderr=False)))
+        return fits
+
+    fb, fs = make(), make()
+    pairs = sum(int(ds.y.shape[0]) * ds.params.g for ds in sets)
+    rows = sum(int(ds.y.shape[0]) for ds in sets)
+    B = cf.Batch(fb, qmc, handle=h)
+    log("batched: tuning queues")
+    tuned = B.tune()
+    iters = args.warmup + args.steps
+    # batched: warm-up iterations, then the timed ones (graph replays)
+    log("batched: warm-up")
+    B.fit(args.warmup, tol=0.0, use_graph=True)
+    torch.cuda.synchronize()
+    for (_, dp, _), ds in zip(fb, sets):          # restart from the initial parameters
+        src = cf.device_params(ds.params, device=dev)
+        for f in ("pi", "mu", "Sigma", "Delta", "nu"):
+            getattr(dp, f).copy_(getattr(src, f))
+    torch.cuda.synchronize()
+    log("batched: timed")
+    t0 = time.perf_counter()
+    trace, done = B.fit(args.steps, tol=0.0, use_graph=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_batched = (t1 - t0) * 1e3 / args.steps
+
+    # sequential: the same fits one after the other, same number of iterations
+    for ds in {ds.params.q: ds for ds in sets}.values():
+        h.autotune(torch.as_tensor(ds.y_soa, device=dev), cf.device_params(ds.params, device=dev), qmc)
+    log("sequential: warm-up")
+    for (y, P, es) in fs[:4]:
+        cf.cfust_estep(y, P.clone(), qmc, out=es)
+    torch.cuda.synchronize()
+    log("sequential: timed")
+    seq_trace = torch.zeros((args.steps, len(fs)), dtype=torch.float64, device=dev)
+    t0 = time.perf_counter()
+    for it in range(args.steps):
+        for k, (y, P, es) in enumerate(fs):
+            cf.cfust_estep(y, P, qmc, out=es)
+            seq_trace[it, k].copy_(es.loglik[0])
+            cf.cfust_mstep(y, es, P, out=P)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_seq = (t1 - t0) * 1e3 / args.steps
+    equal = bool(torch.equal(seq_trace, trace))
+
+    # lattice kernel time of one batched E-step (events around the queue kernels)
+    log("batched: profiled E-step")
+    h.profile(True)
+    h.profile_read()
+    B.estep()
+    torch.cuda.synchronize()
+    prof = h.profile_read()
+    h.profile(False)
+    flops_by_m = {}
+    for ds in sets:
+        n = int(ds.y.shape[0])
+        for m in integral_dims(ds.params.q):
+            flops_by_m[m] = flops_by_m.get(m, 0) + lattice_flops_per_point(m) * N * S * n * ds.params.g
+    lat_ms = sum(v[0] for v in prof.values())
+    achieved = sum(flops_by_m.values()) / (lat_ms / 1e3) / 1e12 if lat_ms > 0 else None
+    per_kernel = {f"m{m}": {"ms": prof[m][0], "tflops": flops_by_m[m] / (prof[m][0] / 1e3) / 1e12}
+                  for m in sorted(prof) if m in flops_by_m}
+    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": (achieved / PEAK_FP32_TFLOPS) if achieved else None, "traffic": None,
+                "kernel": "k_queue_qmc (persistent lattice kernels, all dimensions of one batched E-step)",
+                "lattice_ms_per_estep": lat_ms, "per_kernel": per_kernel}
+    out = {"metric": METRIC, "value": pairs / (ms_batched / 1e3), "unit": "(obs*comp)/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_batched, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32" if prec == cf.CFUST_MIXED else "f64",
+           "data": "synthetic (drawn from the CFUST hierarchy, seeded)",
+           "config": {"workload": "batched_fit", "fits": len(sets), "rows": rows, "pairs": pairs,
+                      "N": N, "S": S, "precision": args.precision,
+                      "step": "one EM iteration of every fit (graph replay)",
+                      "tuned_queues": {f"m{m}": {"rows": v[0], "blocks_per_slot": v[1], "points_per_lane": v[2]}
+                                       for m, v in tuned.items()}},
+           "roofline": roofline,
+           "batched_vs_sequential": {"sequential_ms_per_step": ms_seq, "batched_ms_per_step": ms_batched,
+                                     "speedup": ms_seq / ms_batched,
+                                     "sequential_value": pairs / (ms_seq / 1e3),
+                                     "loglik_traces_bit_equal": equal}}
+    if not args.no_cpu:
+        # one fit per q (the cost of a row depends on q and grows with g):
+        # max(1, threads // g) rows of it, per-row time scaled by g to every
+        # fit of that q and multiplied by its n
+        import oracle
+        oracle.build(force=False)
+        threads = oracle.get_threads()
+        per_row_comp, c_tot, sample_rows = {}, 0.0, 0
+        for ds in sets:
+            q, g = ds.params.q, ds.params.g
+            if q in per_row_comp:
+                continue
+            r = max(1, threads // g)
+            c0 = time.perf_counter()
+            oracle.estep(ds.y, ds.params, design, rows=np.arange(r, dtype=np.int32))
+            dt = time.perf_counter() - c0
+            log(f"cpu baseline: q = {q}, g = {g}, {r} rows: {dt:.1f} s")
+            per_row_comp[q] = dt / (r * g)
+            c_tot += dt
+            sample_rows += r
+        est_s = sum(per_row_comp[ds.params.q] * ds.params.g * ds.y.shape[0] for ds in sets)
+        out["cpu_baseline"] = {"value": pairs / est_s, "unit": "(obs*comp)/s", "cores": threads, "kind": "oracle",
+                               "sample": f"E-step of max(1, {threads}//g) observations of the first fit of each q "
+                                         f"({sample_rows} rows, {c_tot:.1f} s), per (row, component) time "
+                                         f"extrapolated to all pairs of the fits of that q; same lattice "
+                                         f"(N={N}, S={S}), FP64"}
+    B.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,6 +267,7 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=0, help="oracle sample rows (0: one per thread)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate-vs-lattice comparison")
+    ap.add_argument("--n", type=int, default=0, help="observations (0: the workload's own n)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a known-size "
                          "reference for the HBM byte counters)")
@@ -149,7 +291,11 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    ds = workload(args.workload)
+    if args.workload == "batched_fit":
+        print(json.dumps(batched_main(args)), flush=True)
+        return
+
+    ds = workload(args.workload, **({"n": args.n} if args.n else {}))
     n, p = ds.y.shape
     q, g = ds.params.q, ds.params.g
     N, S = ds.meta["N"], ds.meta["S"]

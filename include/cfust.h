@@ -264,8 +264,9 @@ cfust_status cfust_autotune(cfust_handle handle, const double *y, cfust_dims dim
 
 /* Timing of the lattice-integrand kernels.  While enabled, HIP events
  * bracket the main lattice kernel of each integral dimension launched by
- * cfust_estep / cfust_loglik, on the call's stream (creating events: do not
- * enable during stream capture). */
+ * cfust_estep / cfust_loglik and the persistent queue kernels of the batch
+ * calls (not inside a captured graph), on the call's stream (creating
+ * events: do not enable during stream capture). */
 cfust_status cfust_profile_enable(cfust_handle handle, int enable);
 /* Waits for the recorded events, adds up their durations per integral
  * dimension m (0..CFUST_MAX_Q) into host arrays ms[CFUST_MAX_Q+1] and
@@ -330,9 +331,9 @@ cfust_status cfust_batch_mstep(cfust_batch batch, void *stream);
  * after its last M-step (parameters one step ahead of the outputs, as in a
  * plain loop of cfust_estep, cfust_mstep).  iters_done (optional device int32
  * [nfits]) receives the E-steps run per fit.  use_graph != 0 captures one
- * iteration in a HIP graph (on first use, or when trace, iters, tol or
- * iters_done change) and replays it; 0 launches the kernels directly.  Do
- * not call while `stream` is being captured. */
+ * iteration in a HIP graph (on first use, and again after cfust_batch_tune)
+ * and replays it; 0 launches the kernels directly.  Do not call while
+ * `stream` is being captured. */
 cfust_status cfust_fit_batch(cfust_batch batch, int32_t iters, double tol, int32_t use_graph, double *trace,
                              int32_t *iters_done, void *stream);
 

@@ -42,18 +42,6 @@ EstepWs estep_layout(const cfust_dims &d, int J, bool own_logf) {
     return w;
 }
 
-hipEvent_t pool_event(cfust_handle h) {
-    if (!h->pool.empty()) {
-        hipEvent_t e = h->pool.back();
-        h->pool.pop_back();
-        return e;
-    }
-    hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    return e;
-}
-
-
 hipError_t timed_qmc(cfust_handle h, const EstepQmcArgs &a, int m, int nidx, hipStream_t s) {
     const int ppl = tuned_ppl(h, m, a.lat, a.mixed != 0);
     if (!h->prof || a.n == 0 || nidx == 0) return launch_estep_qmc(a, m, nidx, s, nullptr, nullptr, ppl);

@@ -71,10 +71,8 @@ struct cfust_batch_ctx {
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    double g_tol = 0.0;
-    double *g_trace = nullptr;
-    int g_iters = -1;
-    int32_t *g_done = nullptr;
+    BatchCtl *ctl = nullptr;         // device copy of the run's arguments
+    BatchCtl hctl{};                 // host staging of *ctl
 };
 
 namespace {
@@ -151,7 +149,6 @@ void drop_graph(cfust_batch b) {
     if (b->graph) hipGraphDestroy(b->graph);
     b->exec = nullptr;
     b->graph = nullptr;
-    b->g_iters = -1;
 }
 
 hipError_t enqueue_estep(cfust_batch b, hipStream_t s) {
@@ -159,10 +156,17 @@ hipError_t enqueue_estep(cfust_batch b, hipStream_t s) {
     hipError_t e = launch_fill_i32(b->counters, 4 * b->queues.size(), 0, s);
     if (e == hipSuccess) e = launch_batch_precompute(A, b->nblocks[BK_PRE], s);
     if (e == hipSuccess) e = launch_batch_tables(A, b->nblocks[BK_TAB], s);
+    // timing events (cfust_profile_enable) only outside stream capture
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    const bool prof = b->h->prof && hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone;
     for (const Queue &Q : b->queues) {
         if (e != hipSuccess || Q.ntiles == 0) continue;
         const QueueArgs qa = queue_args(b, Q, Q.ntiles);
-        e = launch_queue_qmc(qa, Q.m, b->mixed, Q.ppl, Q.grid, s);
+        ProfRec r{Q.m, prof ? pool_event(b->h) : nullptr, prof ? pool_event(b->h) : nullptr};
+        if (r.e0) e = hipEventRecord(r.e0, s);
+        if (e == hipSuccess) e = launch_queue_qmc(qa, Q.m, b->mixed, Q.ppl, Q.grid, s);
+        if (e == hipSuccess && r.e1) e = hipEventRecord(r.e1, s);
+        if (r.e0 && r.e1) b->h->rec.push_back(r);
         if (e == hipSuccess && b->mixed) e = launch_queue_redo(qa, Q.m, Q.redo_grid, s);
     }
     if (e == hipSuccess) e = launch_batch_assemble(A, b->nblocks[BK_ASM], s);
@@ -175,11 +179,9 @@ hipError_t enqueue_mstep(cfust_batch b, hipStream_t s) {
     return launch_batch_mstep(batch_args(b), b->nblocks[BK_MRED], b->nblocks[BK_MSOL], s);
 }
 
-hipError_t enqueue_iteration(cfust_batch b, double tol, double *trace, int max_trace, int32_t *done,
-                             hipStream_t s) {
+hipError_t enqueue_iteration(cfust_batch b, hipStream_t s) {
     hipError_t e = enqueue_estep(b, s);
-    if (e == hipSuccess)
-        e = launch_batch_check(b->dfits, b->nfits, b->active, b->iter, b->hist, tol, trace, max_trace, done, s);
+    if (e == hipSuccess) e = launch_batch_check(b->dfits, b->nfits, b->active, b->iter, b->hist, b->ctl, s);
     if (e == hipSuccess) e = enqueue_mstep(b, s);
     return e;
 }
@@ -265,6 +267,7 @@ cfust_status cfust_batch_create(cfust_handle h, int32_t nfits, const cfust_fit *
     const size_t o_iter = c.take<int32_t>(1);
     const size_t o_hist = c.take<double>((size_t)2 * nfits);
     const size_t o_counters = c.take<int32_t>(4 * (b->queues.size() > 0 ? b->queues.size() : 1));
+    const size_t o_ctl = c.take<BatchCtl>(1);
     std::vector<size_t> o_seg(b->queues.size()), o_redo(b->queues.size());
     for (size_t k = 0; k < b->queues.size(); ++k) {
         o_seg[k] = c.take<QSeg>(b->queues[k].seg_cap);
@@ -282,6 +285,7 @@ cfust_status cfust_batch_create(cfust_handle h, int32_t nfits, const cfust_fit *
     b->iter = bat<int32_t>(b, o_iter);
     b->hist = bat<double>(b, o_hist);
     b->counters = bat<int32_t>(b, o_counters);
+    b->ctl = bat<BatchCtl>(b, o_ctl);
     for (size_t k = 0; k < b->queues.size(); ++k) {
         Queue &Q = b->queues[k];
         Q.counter = (unsigned long long *)(b->counters + 4 * k);
@@ -411,21 +415,25 @@ cfust_status cfust_fit_batch(cfust_batch b, int32_t iters, double tol, int32_t u
     cfust_status st;
     if ((st = hip_check(h, hipSetDevice(h->device), "hipSetDevice")) != CFUST_OK) return st;
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = launch_fill_i32(b->active, b->nfits, 1, s);
+    // the run's arguments go to device memory: the captured iteration reads them there
+    b->hctl.tol = tol;
+    b->hctl.trace = trace;
+    b->hctl.iters_done = iters_done;
+    b->hctl.max_trace = iters;
+    hipError_t e = hipMemcpyAsync(b->ctl, &b->hctl, sizeof(BatchCtl), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_fill_i32(b->active, b->nfits, 1, s);
     if (e == hipSuccess) e = launch_fill_i32(b->iter, 1, 0, s);
     if (e == hipSuccess) e = launch_fill_i32((int32_t *)b->hist, (size_t)4 * b->nfits, 0, s);
     if (e == hipSuccess && iters_done) e = launch_fill_i32(iters_done, b->nfits, 0, s);
     if (e != hipSuccess || iters == 0) return hip_check(h, e, "cfust_fit_batch launch");
     if (!use_graph) {
-        for (int it = 0; it < iters && e == hipSuccess; ++it)
-            e = enqueue_iteration(b, tol, trace, iters, iters_done, s);
+        for (int it = 0; it < iters && e == hipSuccess; ++it) e = enqueue_iteration(b, s);
         return hip_check(h, e, "cfust_fit_batch launch");
     }
-    if (!b->exec || b->g_tol != tol || b->g_trace != trace || b->g_iters != iters || b->g_done != iters_done) {
-        drop_graph(b);
+    if (!b->exec) {
         e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            const hipError_t el = enqueue_iteration(b, tol, trace, iters, iters_done, b->cap);
+            const hipError_t el = enqueue_iteration(b, b->cap);
             hipGraph_t g = nullptr;
             e = hipStreamEndCapture(b->cap, &g);
             if (el != hipSuccess) e = el;
@@ -437,7 +445,6 @@ cfust_status cfust_fit_batch(cfust_batch b, int32_t iters, double tol, int32_t u
             drop_graph(b);
             return hip_check(h, e, "cfust_fit_batch graph capture");
         }
-        b->g_tol = tol; b->g_trace = trace; b->g_iters = iters; b->g_done = iters_done;
     }
     for (int it = 0; it < iters && e == hipSuccess; ++it) e = hipGraphLaunch(b->exec, s);
     return hip_check(h, e, "cfust_fit_batch graph launch");

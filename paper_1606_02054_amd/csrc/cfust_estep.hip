@@ -330,14 +330,21 @@ struct ItemHead {
     double nu0;
 };
 
-__device__ __attribute__((noinline)) void item_head(const EstepQmcArgs &a, int h, int idx, int j, ItemHead &o) {
+// Limits of the integral; with fp64_head also the first SOV factor in FP64
+// (otherwise the caller takes it from the FP32 tables).
+__device__ __attribute__((noinline)) void item_head(const EstepQmcArgs &a, int h, int idx, int j, ItemHead &o,
+                                                    bool fp64_head) {
     const IntDesc D = int_desc(a.q, idx);
     const CompPre &P = a.pre[h];
     double c[MAXQ], d;
     pair_geometry(a.y, a.n, a.p, a.q, j, a.mu + (size_t)h * a.p, P, c, d);
     o.L = integral_limits(D, P, a.p, a.q, c, d, o.b);
     o.nu0 = P.nu + a.p + D.dofoff;
-    o.H = sov_head(o.b, o.L, o.nu0);
+    if (fp64_head) o.H = sov_head(o.b, o.L, o.nu0);
+}
+
+__device__ __attribute__((noinline)) void item_head_tab(ItemHead &o, const float *tab) {
+    o.H = sov_head_tab(o.b, o.L, o.nu0, tab);
 }
 
 __device__ __attribute__((noinline)) void item_finish(const SovHead &H, const double *smean, int S, double *est,
@@ -346,15 +353,16 @@ __device__ __attribute__((noinline)) void item_finish(const SovHead &H, const do
 }
 
 // Integral idx of pair (observation j, component h), evaluated by one wave.
-// MIXED: FP32 integrand with the dof tables in `tab` (LDS); returns false,
-// writing nothing, when the FP32 product underflowed (the item then needs the
-// FP64 integrand).  Lane 0 writes the estimate (and, for idx 0, ln A and its
+// MIXED: FP32 integrand with the dof tables in `tab` (LDS), the first factor
+// included (log domain, from the table); returns false, writing nothing,
+// when the FP32 product underflowed (the item then needs the FP64 integrand).  Lane 0 writes the estimate (and, for idx 0, ln A and its
 // standard error).
 template <int M, bool MIXED, int PPL>
 __device__ inline bool qmc_item(const EstepQmcArgs &a, int h, int idx, int j, const float *tab, double *smean,
                                 int lane) {
     ItemHead I;
-    item_head(a, h, idx, j, I);
+    item_head(a, h, idx, j, I, !MIXED);
+    if (MIXED) item_head_tab(I, tab);
     double est = 0.0, se = 0.0, lnest = -INFINITY;
     if (I.H.e0 > 0.0 || I.H.lne0 > -INFINITY) {
         if (MIXED) {
@@ -1022,8 +1030,7 @@ __global__ __launch_bounds__(256) void k_queue_qmc(QueueArgs Q) {
         const long long rest = local / S.rtiles;
         const int idx = S.idx0 + (int)(rest % S.nidx);
         const int h = (int)(rest / S.nidx);
-        EstepQmcArgs a = Q.fits[S.fit].qa;
-        a.lat = Q.lat;
+        const EstepQmcArgs &a = Q.fits[S.fit].qa;     // in device memory (its lattice is Q.lat)
         if (MIXED) {
             const int dof = int_desc(a.q, idx).dofoff;
             if (S.fit != cur_f || h != cur_h || dof != cur_dof) {
@@ -1057,9 +1064,7 @@ __global__ __launch_bounds__(256) void k_queue_redo(QueueArgs Q) {
                                      (unsigned)__builtin_amdgcn_readfirstlane((unsigned)v0);
         const int f = (int)(v >> 43), h = (int)((v >> 37) & 63), idx = (int)((v >> 31) & 63);
         const int j = (int)(v & 0x7fffffffULL);
-        EstepQmcArgs a = Q.fits[f].qa;
-        a.lat = Q.lat;
-        qmc_item<M, false, 1>(a, h, idx, j, nullptr, smean[wave], lane);
+        qmc_item<M, false, 1>(Q.fits[f].qa, h, idx, j, nullptr, smean[wave], lane);
     }
 }
 
@@ -1071,10 +1076,12 @@ __global__ __launch_bounds__(256) void k_queue_redo(QueueArgs Q) {
 // hist[f] = (l^(k-1), l^(k)) of the fit's two previous iterations.  One block.
 __global__ __launch_bounds__(256) void k_batch_check(const FitDesc *__restrict__ fits, int nfits,
                                                      int32_t *__restrict__ active, int32_t *__restrict__ iter,
-                                                     double *__restrict__ hist, double tol,
-                                                     double *__restrict__ trace, int max_trace,
-                                                     int32_t *__restrict__ iters_done) {
+                                                     double *__restrict__ hist, const BatchCtl *__restrict__ ctl) {
     const int it = iter[0];
+    const double tol = ctl->tol;
+    double *trace = ctl->trace;
+    int32_t *iters_done = ctl->iters_done;
+    const int max_trace = ctl->max_trace;
     for (int f = threadIdx.x; f < nfits; f += blockDim.x) {
         if (!active[f]) continue;
         const double l1 = fits[f].loglik[0];            // l^(k+1), this iteration
@@ -1129,9 +1136,8 @@ hipError_t launch_batch_sum(const BatchArgs &b, hipStream_t s) {
 }
 
 hipError_t launch_batch_check(const FitDesc *fits, int nfits, int32_t *active, int32_t *iter, double *hist,
-                              double tol, double *trace, int max_trace, int32_t *iters_done, hipStream_t s) {
-    hipLaunchKernelGGL(k_batch_check, dim3(1), dim3(256), 0, s, fits, nfits, active, iter, hist, tol, trace,
-                       max_trace, iters_done);
+                              const BatchCtl *ctl, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_check, dim3(1), dim3(256), 0, s, fits, nfits, active, iter, hist, ctl);
     return hipGetLastError();
 }
 

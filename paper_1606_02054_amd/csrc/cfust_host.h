@@ -145,4 +145,16 @@ inline int tuned_ppl(cfust_handle h, int m, const LatticeArgs &L, bool mixed) {
     return 1;
 }
 
+// An event from the handle's pool (created when the pool is empty).
+inline hipEvent_t pool_event(cfust_handle h) {
+    if (!h->pool.empty()) {
+        hipEvent_t e = h->pool.back();
+        h->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
 }  // namespace cfust_host

@@ -149,7 +149,7 @@ struct QueueArgs {
     unsigned long long *counter;        // next tile
     unsigned long long *redo;           // mixed: packed (fit, h, idx, j) of underflowed items
     unsigned int *redo_count;
-    LatticeArgs lat;
+    LatticeArgs lat;            // the batch's lattice (also in every fit's argument block)
 };
 
 constexpr int BATCH_MAX_FITS = 1024;   // fit index packs into 10 bits of a redo entry
@@ -168,10 +168,19 @@ hipError_t launch_queue_redo(const QueueArgs &q, int m, int grid, hipStream_t s)
 // Resident blocks per compute unit of the queue kernels.
 int queue_qmc_occupancy(int m, bool mixed, int ppl);
 int queue_redo_occupancy(int m);
+// Arguments of a batched EM run that the captured iteration reads from
+// device memory, so that one graph serves every call.
+struct BatchCtl {
+    double tol;                 // Aitken tolerance (<= 0: no stop on it)
+    double *trace;              // optional [max_trace][nfits]
+    int32_t *iters_done;        // optional [nfits]
+    int max_trace;
+};
+
 // Convergence check between the E-step and the M-step of a batched EM
 // iteration (see k_batch_check).
 hipError_t launch_batch_check(const FitDesc *fits, int nfits, int32_t *active, int32_t *iter, double *hist,
-                              double tol, double *trace, int max_trace, int32_t *iters_done, hipStream_t s);
+                              const BatchCtl *ctl, hipStream_t s);
 
 hipError_t launch_precompute(const cfust_params &P, int p, int q, int g, CompPre *pre, hipStream_t s);
 hipError_t launch_status_fold(const CompPre *pre, int g, int32_t *status, hipStream_t s);

@@ -218,6 +218,26 @@ __device__ inline SovHead sov_head(const double *b, const double *L, double nu) 
     return H;
 }
 
+// The same first factor from the FP32 table of dof nu (mixed precision): the
+// table gives F(tau) = log2 T_lower - (nu/2) log2 tau with tau = 1 - |s|,
+// s = u / sqrt(nu + u^2), u = b_0 / L_00.  tau and log2 tau are formed in
+// FP64, so no range is lost; only F carries the table's FP32 accuracy.
+__device__ inline SovHead sov_head_tab(const double *b, const double *L, double nu, const float *tab) {
+    const double u = b[0] / L[0];
+    const double au = fabs(u);
+    const double r = au > 1.0 ? au * sqrt(1.0 + (nu / au) / au) : sqrt(nu + u * u);
+    const double tau = nu / (r * (r + au));
+    const double l2 = 0.5 * nu * log2(tau) + (double)tab_cdf_F(tab, (float)tau);
+    const double lt0 = l2 * LN2;
+    const double small0 = exp(lt0);
+    SovHead H;
+    H.low0 = u <= 0.0;
+    H.e0 = H.low0 ? small0 : 1.0 - small0;
+    H.eb0 = H.low0 ? 1.0 - small0 : small0;
+    H.lne0 = H.low0 ? lt0 : log1p(-small0);
+    return H;
+}
+
 // Mean over shifts, its standard error and ln(e_0 * mean) from the per-shift
 // means in this wave's LDS slice (written by lane 0).
 __device__ inline void sov_finish(const SovHead &H, const double *smean, int S,
