@@ -187,6 +187,14 @@ def _wl_batch(seed: int, nfits: int = 64, n_lo: float = 5e3, n_hi: float = 2e5):
     return sets
 
 
+def restart_params(seed: int, nstarts: int = 64):
+    """Starting parameter sets for restarts on the n = 1000, p = q = 2, g = 2
+    data: each drawn like that workload's own parameters (weights 0.4/0.6,
+    nu = 4, 8, mu ~ U[-5, 5]^2, Sigma = A A^T + I, Delta ~ U[-3, 3])."""
+    rng = np.random.default_rng(seed)
+    return [draw_params(rng, 2, 2, 2, pi=[0.4, 0.6], nu=[4.0, 8.0], sigma="aat") for _ in range(nstarts)]
+
+
 WORKLOADS = {
     "cfust_n1000_p2_q2_g2": _wl_small,
     "cfust_n20000_p4_q4_g3": _wl_p4,

@@ -338,12 +338,13 @@ cfust_status cfust_fit_batch(cfust_batch batch, int32_t iters, double tol, int32
                              int32_t *iters_done, void *stream);
 
 /* Autotuner of the batch's lattice queues: times, for each integral
- * dimension, tiles of 4, 8 or 16 observations, one or two persistent blocks
- * per resident slot and (mixed, N a multiple of 128) 1 or 2 lattice points
- * per lane per trip, on a prefix of the queue, and keeps the fastest.
- * Synchronises the stream.  chosen (optional, host int32
- * [(CFUST_MAX_Q+1) * 3]) receives (rows per tile, blocks per slot, points per
- * lane) per m (zeros where no queue). */
+ * dimension, the persistent kernel with tiles of 4, 8 or 16 observations and
+ * one or two blocks per resident slot, and the one-block-per-tile form of
+ * the same queue (tiles of 4), each with (mixed, N a multiple of 128) 1 or 2
+ * lattice points per lane per trip, on a prefix of the queue, and keeps the
+ * fastest.  Synchronises the stream.  chosen (optional, host int32
+ * [(CFUST_MAX_Q+1) * 3]) receives (rows per tile, blocks per slot -- 0 for
+ * one block per tile --, points per lane) per m (zeros where no queue). */
 cfust_status cfust_batch_tune(cfust_batch batch, int32_t *chosen, void *stream);
 
 #ifdef __cplusplus

@@ -310,7 +310,8 @@ class Batch:
         return trace, iters_done
 
     def tune(self, stream=None):
-        """Autotune the lattice queues; returns {m: (rows per tile, blocks per slot, points per lane)}."""
+        """Autotune the lattice queues; returns {m: (rows per tile, persistent blocks per
+        resident slot (0: one block per tile), points per lane)}."""
         arr = (C.c_int32 * ((B.MAX_Q + 1) * 3))()
         B.check(self.handle.lib.cfust_batch_tune(self.b, arr, _stream(stream)), self.handle.h, "cfust_batch_tune")
         return {m: tuple(arr[3 * m:3 * m + 3]) for m in range(B.MAX_Q + 1) if arr[3 * m] > 0}

@@ -35,6 +35,7 @@ struct Queue {
     unsigned long long *redo = nullptr;     // [items]
     unsigned int *redo_count = nullptr;
     int rows = 4, mult = 1, ppl = 1;
+    bool persist = true;                    // persistent blocks, or one block per tile
     int grid = 0, redo_grid = 0;
 };
 
@@ -124,9 +125,10 @@ cfust_status upload_segments(cfust_batch b, Queue &Q) {
                      "batch segments upload");
 }
 
+// grid = 0 selects one block per tile (launch_queue_qmc).
 void set_grid(cfust_batch b, Queue &Q) {
     const int ncu = b->h->ncu > 0 ? b->h->ncu : 256;
-    Q.grid = ncu * queue_qmc_occupancy(Q.m, b->mixed, Q.ppl) * Q.mult;
+    Q.grid = Q.persist ? ncu * queue_qmc_occupancy(Q.m, b->mixed, Q.ppl) * Q.mult : 0;
     Q.redo_grid = ncu * queue_redo_occupancy(Q.m);
 }
 
@@ -465,44 +467,52 @@ cfust_status cfust_batch_tune(cfust_batch b, int32_t *chosen, void *stream) {
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     const bool ppl2 = b->mixed && b->lat.N % 128 == 0;
+    // candidates: persistent (rows per tile, blocks per resident slot) or one
+    // block per tile (rows 4, written as 0 blocks per slot), each with 1 or 2
+    // lattice points per lane per trip
+    struct Cand { bool persist; int rows, mult; };
+    const Cand cands[7] = {{true, 4, 1}, {true, 4, 2}, {true, 8, 1}, {true, 8, 2},
+                           {true, 16, 1}, {true, 16, 2}, {false, 4, 0}};
+    const int ncu = h->ncu > 0 ? h->ncu : 256;
     for (Queue &Q : b->queues) {
         if (e != hipSuccess) break;
         double best = 1e300;
-        int brow = Q.rows, bmult = Q.mult, bppl = Q.ppl;
-        const int rows_c[3] = {4, 8, 16};
-        for (int ri = 0; ri < 3 && e == hipSuccess; ++ri)
-            for (int mult = 1; mult <= 2 && e == hipSuccess; ++mult)
-                for (int ppl = 1; ppl <= (ppl2 ? 2 : 1) && e == hipSuccess; ++ppl) {
-                    Q.mult = mult; Q.ppl = ppl;
-                    set_grid(b, Q);
-                    build_segments(b, Q, rows_c[ri]);
-                    if ((st = upload_segments(b, Q)) != CFUST_OK) { e = hipErrorUnknown; break; }
-                    // a prefix of the queue: about 16 items per resident wave
-                    const long long want = std::min(Q.items, (long long)Q.grid * 4 * 16);
-                    const long long tiles = std::min(Q.ntiles, (want + Q.rows - 1) / Q.rows);
-                    if (tiles == 0) continue;
-                    const QueueArgs qa = queue_args(b, Q, tiles);
-                    float ms = 0.0f;
-                    for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
-                        e = launch_fill_i32(b->counters, 4 * b->queues.size(), 0, s);
-                        if (e == hipSuccess) e = hipEventRecord(e0, s);
-                        if (e == hipSuccess) e = launch_queue_qmc(qa, Q.m, b->mixed, Q.ppl, Q.grid, s);
-                        if (e == hipSuccess) e = hipEventRecord(e1, s);
-                        if (e == hipSuccess) e = hipEventSynchronize(e1);
-                        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-                    }
-                    const double per_item = ms / (double)std::min(tiles * Q.rows, Q.items);
-                    if (e == hipSuccess && per_item < best) {
-                        best = per_item; brow = Q.rows; bmult = mult; bppl = ppl;
-                    }
+        Cand bc{Q.persist, Q.rows, Q.mult};
+        int bppl = Q.ppl;
+        // the same prefix of the queue for every candidate: about 16 items
+        // per wave the chip holds at 8 waves per SIMD
+        const long long want = std::min(Q.items, (long long)ncu * 4 * 8 * 16);
+        for (int ci = 0; ci < 7 && e == hipSuccess; ++ci)
+            for (int ppl = 1; ppl <= (ppl2 ? 2 : 1) && e == hipSuccess; ++ppl) {
+                const Cand &C = cands[ci];
+                Q.persist = C.persist; Q.mult = C.mult; Q.ppl = ppl;
+                set_grid(b, Q);
+                build_segments(b, Q, C.rows);
+                if ((st = upload_segments(b, Q)) != CFUST_OK) { e = hipErrorUnknown; break; }
+                const long long tiles = std::min(Q.ntiles, (want + Q.rows - 1) / Q.rows);
+                if (tiles == 0) continue;
+                const QueueArgs qa = queue_args(b, Q, tiles);
+                float ms = 0.0f;
+                for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+                    e = launch_fill_i32(b->counters, 4 * b->queues.size(), 0, s);
+                    if (e == hipSuccess) e = hipEventRecord(e0, s);
+                    if (e == hipSuccess) e = launch_queue_qmc(qa, Q.m, b->mixed, Q.ppl, Q.grid, s);
+                    if (e == hipSuccess) e = hipEventRecord(e1, s);
+                    if (e == hipSuccess) e = hipEventSynchronize(e1);
+                    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
                 }
-        Q.mult = bmult; Q.ppl = bppl;
+                const double per_item = ms / (double)std::min(tiles * Q.rows, Q.items);
+                if (e == hipSuccess && per_item < best) {
+                    best = per_item; bc = C; bppl = ppl;
+                }
+            }
+        Q.persist = bc.persist; Q.mult = bc.mult; Q.ppl = bppl;
         set_grid(b, Q);
-        build_segments(b, Q, brow);
+        build_segments(b, Q, bc.rows);
         if (e == hipSuccess && (st = upload_segments(b, Q)) != CFUST_OK) e = hipErrorUnknown;
         if (chosen) {
             chosen[Q.m * 3 + 0] = Q.rows;
-            chosen[Q.m * 3 + 1] = Q.mult;
+            chosen[Q.m * 3 + 1] = Q.persist ? Q.mult : 0;
             chosen[Q.m * 3 + 2] = Q.ppl;
         }
     }

@@ -279,6 +279,26 @@ __device__ inline void pair_geometry(const double *__restrict__ y, int n, int p,
     }
 }
 
+// The same with caller-provided storage v[p] (the forward-substitution
+// vector) and r recomputed where needed: no private arrays, so an
+// out-of-line caller keeps no stack frame (v and c may live in LDS).
+__device__ inline void pair_geometry_ws(const double *__restrict__ y, int n, int p, int q, int j,
+                                        const double *__restrict__ mu, const CompPre &P, double *c, double &d,
+                                        double *v) {
+    d = 0.0;
+    for (int i = 0; i < p; ++i) {
+        double s = y[(size_t)i * n + j] - mu[i];
+        for (int k = 0; k < i; ++k) s -= P.LO[i * p + k] * v[k];
+        v[i] = s / P.LO[i * p + i];
+        d += v[i] * v[i];
+    }
+    for (int l = 0; l < q; ++l) {
+        double s = 0.0;
+        for (int k = 0; k < p; ++k) s += P.B[k * q + l] * (y[(size_t)k * n + j] - mu[k]);
+        c[l] = s;
+    }
+}
+
 // Standardised limits of integral D of the pair: T_m(b; 0, L L^T, nu0) with L
 // a per-component Cholesky factor (stride m) and the per-observation scale
 // folded into b.  Returns L (FP64).
@@ -322,62 +342,72 @@ __device__ inline const double *integral_limits(const IntDesc &D, const CompPre 
 // FP64 prologue and epilogue of one integral.  They are kept out of line:
 // inlined into a loop over items (the persistent kernel), their FP64
 // constants would be hoisted out of the loop and stay live in vector
-// registers through the lattice loop, halving the occupancy.
-struct ItemHead {
-    SovHead H;
-    double b[MAXQ];
-    const double *L;
-    double nu0;
+// registers through the lattice loop, halving the occupancy.  Their work
+// arrays are a per-wave LDS slot (the values are the same in every lane of
+// the wave) and their arguments are scalars, so they need no stack frame.
+struct WaveItem {
+    double v[MAXP];      // forward-substitution vector of the pair's geometry
+    double c[MAXQ];      // Delta^T Omega^-1 (y - mu)
+    double b[MAXQ];      // standardised limits of the integral
+    SovHead H;           // first SOV factor
+    const double *L;     // Cholesky factor of the integral (FP64, stride m)
+    double nu0;          // dof of the integral
 };
 
-// Limits of the integral; with fp64_head also the first SOV factor in FP64
-// (otherwise the caller takes it from the FP32 tables).
-__device__ __attribute__((noinline)) void item_head(const EstepQmcArgs &a, int h, int idx, int j, ItemHead &o,
+// Limits of integral idx of pair (j, h); with fp64_head also the first SOV
+// factor in FP64 (otherwise the caller takes it from the FP32 tables).
+__device__ __attribute__((noinline)) void item_head(const double *y, const double *mu, const CompPre *pre, int n,
+                                                    int p, int q, int h, int idx, int j, WaveItem *w,
                                                     bool fp64_head) {
-    const IntDesc D = int_desc(a.q, idx);
-    const CompPre &P = a.pre[h];
-    double c[MAXQ], d;
-    pair_geometry(a.y, a.n, a.p, a.q, j, a.mu + (size_t)h * a.p, P, c, d);
-    o.L = integral_limits(D, P, a.p, a.q, c, d, o.b);
-    o.nu0 = P.nu + a.p + D.dofoff;
-    if (fp64_head) o.H = sov_head(o.b, o.L, o.nu0);
+    const IntDesc D = int_desc(q, idx);
+    const CompPre &P = pre[h];
+    double d;
+    pair_geometry_ws(y, n, p, q, j, mu + (size_t)h * p, P, w->c, d, w->v);
+    w->L = integral_limits(D, P, p, q, w->c, d, w->b);
+    w->nu0 = P.nu + p + D.dofoff;
+    if (fp64_head) w->H = sov_head(w->b, w->L, w->nu0);
 }
 
-__device__ __attribute__((noinline)) void item_head_tab(ItemHead &o, const float *tab) {
-    o.H = sov_head_tab(o.b, o.L, o.nu0, tab);
+__device__ __attribute__((noinline)) void item_head_tab(WaveItem *w, const float *tab) {
+    w->H = sov_head_tab(w->b, w->L, w->nu0, tab);
 }
 
-__device__ __attribute__((noinline)) void item_finish(const SovHead &H, const double *smean, int S, double *est,
-                                                      double *se, double *lnest) {
-    sov_finish(H, smean, S, est, se, lnest);
+struct ItemResult {
+    double est, se, lnest;
+};
+
+__device__ __attribute__((noinline)) ItemResult item_finish(const WaveItem *w, const double *smean, int S) {
+    ItemResult r;
+    sov_finish(w->H, smean, S, &r.est, &r.se, &r.lnest);
+    return r;
 }
 
 // Integral idx of pair (observation j, component h), evaluated by one wave.
 // MIXED: FP32 integrand with the dof tables in `tab` (LDS), the first factor
 // included (log domain, from the table); returns false, writing nothing,
-// when the FP32 product underflowed (the item then needs the FP64 integrand).  Lane 0 writes the estimate (and, for idx 0, ln A and its
-// standard error).
+// when the FP32 product underflowed (the item then needs the FP64 integrand).
+// w: this wave's LDS work slot.  Lane 0 writes the estimate (and, for idx 0,
+// ln A and its standard error).
 template <int M, bool MIXED, int PPL>
 __device__ inline bool qmc_item(const EstepQmcArgs &a, int h, int idx, int j, const float *tab, double *smean,
-                                int lane) {
-    ItemHead I;
-    item_head(a, h, idx, j, I, !MIXED);
-    if (MIXED) item_head_tab(I, tab);
-    double est = 0.0, se = 0.0, lnest = -INFINITY;
-    if (I.H.e0 > 0.0 || I.H.lne0 > -INFINITY) {
+                                WaveItem *w, int lane) {
+    item_head(a.y, a.mu, a.pre, a.n, a.p, a.q, h, idx, j, w, !MIXED);
+    if (MIXED) item_head_tab(w, tab);
+    ItemResult r{0.0, 0.0, -INFINITY};
+    if (w->H.e0 > 0.0 || w->H.lne0 > -INFINITY) {
         if (MIXED) {
-            if (!sov_mixed<M, PPL>(I.H, I.b, I.L, I.nu0, a.lat, tab, smean, lane)) return false;
+            if (!sov_mixed<M, PPL>(w->H, w->b, w->L, w->nu0, a.lat, tab, smean, lane)) return false;
         } else {
-            sov_fp64<M>(I.H, I.b, I.L, I.nu0, a.lat, smean, lane);
+            sov_fp64<M>(w->H, w->b, w->L, w->nu0, a.lat, smean, lane);
         }
-        item_finish(I.H, smean, a.lat.S, &est, &se, &lnest);
+        r = item_finish(w, smean, a.lat.S);
     }
     if (lane == 0) {
         const size_t o = ((size_t)h * a.J + idx) * a.n + j;
-        a.est[o] = est;
+        a.est[o] = r.est;
         if (idx == 0) {
-            a.lnA[(size_t)h * a.n + j] = lnest;
-            if (a.se) a.se[(size_t)h * a.n + j] = se;
+            a.lnA[(size_t)h * a.n + j] = r.lnest;
+            if (a.se) a.se[(size_t)h * a.n + j] = r.se;
         }
     }
     return true;
@@ -398,6 +428,7 @@ template <int M, bool MIXED, bool FLAGGED_ONLY, int PPL>
 __global__ __launch_bounds__(256) void k_estep_qmc(EstepQmcArgs a) {
     __shared__ __align__(16) float tab[MIXED ? M * TAB_FLOATS : 4];
     __shared__ double smean[4][MAXS];
+    __shared__ WaveItem witem[4];
     const int h = blockIdx.z, idx = a.idx0 + blockIdx.y;
     if (MIXED) {
         load_tables<M>(a.tabs, h, int_desc(a.q, idx).dofoff, tab);
@@ -412,7 +443,7 @@ __global__ __launch_bounds__(256) void k_estep_qmc(EstepQmcArgs a) {
         if (MIXED && lane == 0) a.flag[o] = 0;
         return;
     }
-    const bool ok = qmc_item<M, MIXED, PPL>(a, h, idx, j, tab, smean[wave], lane);
+    const bool ok = qmc_item<M, MIXED, PPL>(a, h, idx, j, tab, smean[wave], &witem[wave], lane);
     if (MIXED && lane == 0) a.flag[o] = ok ? 0 : 1;
 }
 
@@ -1004,6 +1035,7 @@ template <int M, bool MIXED, int PPL>
 __global__ __launch_bounds__(256) void k_queue_qmc(QueueArgs Q) {
     __shared__ __align__(16) float tab[MIXED ? M * TAB_FLOATS : 4];
     __shared__ double smean[4][MAXS];
+    __shared__ WaveItem witem[4];
     __shared__ long long s_tile;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int cur_f = -1, cur_h = -1, cur_dof = -1;
@@ -1042,7 +1074,7 @@ __global__ __launch_bounds__(256) void k_queue_qmc(QueueArgs Q) {
         const int jb = S.j0 + rt * S.rows;
         for (int r = wave; r < S.rows; r += 4) {
             const int j = jb + r;
-            const bool ok = qmc_item<M, MIXED, PPL>(a, h, idx, j, tab, smean[wave], lane);
+            const bool ok = qmc_item<M, MIXED, PPL>(a, h, idx, j, tab, smean[wave], &witem[wave], lane);
             if (MIXED && !ok && lane == 0) {
                 const unsigned slot = atomicAdd(Q.redo_count, 1u);
                 Q.redo[slot] = ((unsigned long long)S.fit << 43) | ((unsigned long long)h << 37) |
@@ -1052,10 +1084,52 @@ __global__ __launch_bounds__(256) void k_queue_qmc(QueueArgs Q) {
     }
 }
 
+// The same queue with one block per tile, in queue order (blocks are handed
+// out in increasing index, so the longest-first order of the queue holds):
+// tiles of at most 4 observations, one per wave.  With no loop around the
+// item its registers are not held across items, which the persistent form
+// pays for; the autotuner picks between the two.  Block t = y * gridDim.x + x.
+template <int M, bool MIXED, int PPL>
+__global__ __launch_bounds__(256) void k_queue_grid(QueueArgs Q) {
+    __shared__ __align__(16) float tab[MIXED ? M * TAB_FLOATS : 4];
+    __shared__ double smean[4][MAXS];
+    __shared__ WaveItem witem[4];
+    const long long t = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+    if (t >= Q.ntiles) return;
+    int lo = 0, hi = Q.nseg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (Q.seg[mid].t0 <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    const QSeg S = Q.seg[lo];
+    if (!Q.active[S.fit]) return;
+    const long long local = t - S.t0;
+    const int rt = (int)(local % S.rtiles);
+    const long long rest = local / S.rtiles;
+    const int idx = S.idx0 + (int)(rest % S.nidx);
+    const int h = (int)(rest / S.nidx);
+    const EstepQmcArgs &a = Q.fits[S.fit].qa;
+    if (MIXED) {
+        load_tables<M>(a.tabs, h, int_desc(a.q, idx).dofoff, tab);
+        __syncthreads();
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (wave >= S.rows) return;
+    const int j = S.j0 + rt * S.rows + wave;
+    const bool ok = qmc_item<M, MIXED, PPL>(a, h, idx, j, tab, smean[wave], &witem[wave], lane);
+    if (MIXED && !ok && lane == 0) {
+        const unsigned slot = atomicAdd(Q.redo_count, 1u);
+        Q.redo[slot] = ((unsigned long long)S.fit << 43) | ((unsigned long long)h << 37) |
+                       ((unsigned long long)idx << 31) | (unsigned long long)j;
+    }
+}
+
 // FP64 integrand for the items of the redo list; one wave per entry.
 template <int M>
 __global__ __launch_bounds__(256) void k_queue_redo(QueueArgs Q) {
     __shared__ double smean[4][MAXS];
+    __shared__ WaveItem witem[4];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const unsigned cnt = Q.redo_count[0];
     for (unsigned e = blockIdx.x * 4 + wave; e < cnt; e += gridDim.x * 4) {
@@ -1064,7 +1138,7 @@ __global__ __launch_bounds__(256) void k_queue_redo(QueueArgs Q) {
                                      (unsigned)__builtin_amdgcn_readfirstlane((unsigned)v0);
         const int f = (int)(v >> 43), h = (int)((v >> 37) & 63), idx = (int)((v >> 31) & 63);
         const int j = (int)(v & 0x7fffffffULL);
-        qmc_item<M, false, 1>(Q.fits[f].qa, h, idx, j, nullptr, smean[wave], lane);
+        qmc_item<M, false, 1>(Q.fits[f].qa, h, idx, j, nullptr, smean[wave], &witem[wave], lane);
     }
 }
 
@@ -1142,20 +1216,24 @@ hipError_t launch_batch_check(const FitDesc *fits, int nfits, int32_t *active, i
 }
 
 template <int M>
-static const void *queue_kernel(bool mixed, int ppl) {
-    if (!mixed) return (const void *)k_queue_qmc<M, false, 1>;
-    return ppl == 2 ? (const void *)k_queue_qmc<M, true, 2> : (const void *)k_queue_qmc<M, true, 1>;
+static const void *queue_kernel(bool mixed, int ppl, bool persist) {
+    if (persist) {
+        if (!mixed) return (const void *)k_queue_qmc<M, false, 1>;
+        return ppl == 2 ? (const void *)k_queue_qmc<M, true, 2> : (const void *)k_queue_qmc<M, true, 1>;
+    }
+    if (!mixed) return (const void *)k_queue_grid<M, false, 1>;
+    return ppl == 2 ? (const void *)k_queue_grid<M, true, 2> : (const void *)k_queue_grid<M, true, 1>;
 }
 
-static const void *queue_kernel_m(int m, bool mixed, int ppl) {
+static const void *queue_kernel_m(int m, bool mixed, int ppl, bool persist) {
     switch (m) {
-    case 2: return queue_kernel<2>(mixed, ppl);
-    case 3: return queue_kernel<3>(mixed, ppl);
-    case 4: return queue_kernel<4>(mixed, ppl);
-    case 5: return queue_kernel<5>(mixed, ppl);
-    case 6: return queue_kernel<6>(mixed, ppl);
-    case 7: return queue_kernel<7>(mixed, ppl);
-    case 8: return queue_kernel<8>(mixed, ppl);
+    case 2: return queue_kernel<2>(mixed, ppl, persist);
+    case 3: return queue_kernel<3>(mixed, ppl, persist);
+    case 4: return queue_kernel<4>(mixed, ppl, persist);
+    case 5: return queue_kernel<5>(mixed, ppl, persist);
+    case 6: return queue_kernel<6>(mixed, ppl, persist);
+    case 7: return queue_kernel<7>(mixed, ppl, persist);
+    case 8: return queue_kernel<8>(mixed, ppl, persist);
     default: return nullptr;
     }
 }
@@ -1174,10 +1252,16 @@ static const void *redo_kernel_m(int m) {
 }
 
 hipError_t launch_queue_qmc(const QueueArgs &q, int m, bool mixed, int ppl, int grid, hipStream_t s) {
-    const void *k = queue_kernel_m(m, mixed, ppl);
-    if (!k || grid < 1) return hipErrorInvalidValue;
+    const bool persist = grid > 0;
+    const void *k = queue_kernel_m(m, mixed, ppl, persist);
+    if (!k) return hipErrorInvalidValue;
     void *args[] = {(void *)&q};
-    return hipLaunchKernel(k, dim3(grid), dim3(256), args, 0, s);
+    if (persist) return hipLaunchKernel(k, dim3(grid), dim3(256), args, 0, s);
+    if (q.ntiles <= 0) return hipSuccess;
+    const long long gx = q.ntiles < 32768 ? q.ntiles : 32768;
+    const long long gy = (q.ntiles + gx - 1) / gx;
+    if (gy > 0x7fffffffLL) return hipErrorInvalidValue;
+    return hipLaunchKernel(k, dim3((unsigned)gx, (unsigned)gy), dim3(256), args, 0, s);
 }
 
 hipError_t launch_queue_redo(const QueueArgs &q, int m, int grid, hipStream_t s) {
@@ -1188,7 +1272,7 @@ hipError_t launch_queue_redo(const QueueArgs &q, int m, int grid, hipStream_t s)
 }
 
 int queue_qmc_occupancy(int m, bool mixed, int ppl) {
-    const void *k = queue_kernel_m(m, mixed, ppl);
+    const void *k = queue_kernel_m(m, mixed, ppl, true);
     int nb = 0;
     if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 256, 0) != hipSuccess) return 1;
     return nb > 0 ? nb : 1;

@@ -160,9 +160,11 @@ hipError_t launch_batch_assemble(const BatchArgs &b, int nblocks, hipStream_t s)
 hipError_t launch_batch_lse(const BatchArgs &b, int nblocks, hipStream_t s);
 hipError_t launch_batch_sum(const BatchArgs &b, hipStream_t s);
 hipError_t launch_batch_mstep(const BatchArgs &b, int nred, int nsol, hipStream_t s);
-// Persistent lattice kernel of dimension m over a queue: `grid` blocks draw
-// tiles until the queue is empty; mixed mode appends underflowed items to the
-// redo list and launch_queue_redo evaluates them with the FP64 integrand.
+// Lattice kernel of dimension m over a queue.  grid > 0: persistent, `grid`
+// blocks draw tiles until the queue is empty; grid == 0: one block per tile
+// in queue order (tiles of at most 4 observations).  Mixed mode appends
+// underflowed items to the redo list and launch_queue_redo evaluates them
+// with the FP64 integrand.
 hipError_t launch_queue_qmc(const QueueArgs &q, int m, bool mixed, int ppl, int grid, hipStream_t s);
 hipError_t launch_queue_redo(const QueueArgs &q, int m, int grid, hipStream_t s);
 // Resident blocks per compute unit of the queue kernels.

@@ -287,7 +287,7 @@ __device__ bool sov_mixed(const SovHead &H, const double *b, const double *L, do
 }
 
 template <int M>
-__device__ void sov_fp64(const SovHead &H, const double *b, const double *L, double nu, const Lattice &Lt,
+__device__ __forceinline__ void sov_fp64(const SovHead &H, const double *b, const double *L, double nu, const Lattice &Lt,
                          double *smean, int lane) {
     for (int s = 0; s < Lt.S; ++s) {
         const double ls = sov_lane_sum64<M>(b, L, nu, Lt, s, H.e0, H.eb0, H.lne0, H.low0, lane);

@@ -204,7 +204,8 @@ def test_batch_tune_keeps_results(cf):
     print("tuned", chosen, flush=True)
     assert set(chosen) == {2, 3, 4, 5, 6, 7, 8}
     for m, (rows, mult, ppl) in chosen.items():
-        assert rows in (4, 8, 16) and mult in (1, 2) and ppl in (1, 2)
+        assert rows in (4, 8, 16) and mult in (0, 1, 2) and ppl in (1, 2)
+        assert mult > 0 or rows == 4
     B.estep()
     for (y, P, es) in fs:
         cf.cfust_estep(y, P, qmc, out=es)
