@@ -19,7 +19,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-MAX_LATTICE_DIM = 7  # an m-variate integral uses m-1 lattice coordinates; m <= 8
+MAX_LATTICE_DIM = 8  # an m-variate integral uses m-1 lattice coordinates (m with its moments); m <= 8
 
 
 @dataclass(frozen=True)

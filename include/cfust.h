@@ -39,7 +39,8 @@ extern "C" {
 #define CFUST_MAX_P 16      /* data dimension p */
 #define CFUST_MAX_Q 8       /* skewing dimension q; also the largest T_m dimension */
 #define CFUST_MAX_G 64      /* mixture components */
-#define CFUST_LATTICE_DIM 7 /* lattice coordinates; an m-variate T_m uses the first m-1 */
+#define CFUST_LATTICE_DIM 8 /* lattice coordinates: an m-variate T_m uses the first m-1, the moment
+                              integrals of the direct estimator the first m */
 #define CFUST_MAX_SHIFTS 64
 
 typedef enum {

@@ -50,8 +50,10 @@ def _load():
         lib.or_tmoments_c.restype = None
         lib.or_tmoments_c.argtypes = [i, pd, pd, d, i, i, pi, pd, pd, pd, pd, pd]
         lib.or_estep.restype = i
-        lib.or_estep.argtypes = [i, i, i, i, pd, pd, pd, pd, pd, pd, i, i, pi, pd, pi, i,
+        lib.or_estep.argtypes = [i, i, i, i, pd, pd, pd, pd, pd, pd, i, i, pi, pd, pi, i, i,
                                  pd, pd, pd, pd, pd, pd, pd, pd, pd]
+        lib.or_mvt_mom_c.restype = None
+        lib.or_mvt_mom_c.argtypes = [i, pd, pd, d, i, i, pi, pd, pd, pd, pd]
         lib.or_mstep.restype = i
         lib.or_mstep.argtypes = [i, i, i, i, pd, pd, pd, pd, pd, pd, pd, pd, pd, pd, pd,
                                  pd, pd, pd, pd, pd, pi]
@@ -135,6 +137,17 @@ def tmoments(a, R, nu, design):
     return float(M0[0]), M1, M2, float(T2[0])
 
 
+def mvt_moments(b, L, nu, design):
+    """Direct SOV moments of Z ~ t_m(0, L L^T, nu) on {Z <= b}: (P, M1 [m],
+    M2 [m][m]) = lattice means of f, f z, f z z^T with every coordinate drawn."""
+    b = _f64(b); L = _f64(L)
+    m = b.shape[0]
+    N, S, z, sh = _design(design)
+    P = np.zeros(1); M1 = np.zeros(m); M2 = np.zeros((m, m))
+    _load().or_mvt_mom_c(m, _pd(b), _pd(L), float(nu), N, S, _pi(z), _pd(sh), _pd(P), _pd(M1), _pd(M2))
+    return float(P[0]), M1, M2
+
+
 # -- E-step / M-step ------------------------------------------------------------
 @dataclass
 class EStepOut:
@@ -153,8 +166,13 @@ class EStepOut:
         return float(self.logf_obs.sum())
 
 
-def estep(y, params, design, rows=None) -> EStepOut:
-    """Oracle E-step.  y: [n][p] float64.  rows: optional subset of observations."""
+def estep(y, params, design, rows=None, moments: str = "identity") -> EStepOut:
+    """Oracle E-step.  y: [n][p] float64.  rows: optional subset of observations.
+    moments: "identity" (truncated-t moments from the gradient identity, with
+    the lower-dimensional T_{q-1}, T_{q-2}) or "direct" (lattice means of f z,
+    f z z^T inside the B integral; q >= 2, q = 1 keeps the closed forms)."""
+    if moments not in ("identity", "direct"):
+        raise ValueError(f"moments = {moments!r}")
     y = _f64(y)
     n, p = y.shape
     g, q = params.g, params.q
@@ -169,7 +187,7 @@ def estep(y, params, design, rows=None) -> EStepOut:
                                            (g, nq2, r), (g, r), (g, r)]))
     st = _load().or_estep(n, p, q, g, _pd(y), _pd(_f64(params.pi)), _pd(_f64(params.mu)),
                           _pd(_f64(params.Sigma)), _pd(_f64(params.Delta)), _pd(_f64(params.nu)),
-                          N, S, _pi(z), _pd(sh), _pi(rows), r,
+                          N, S, _pi(z), _pd(sh), _pi(rows), r, 1 if moments == "direct" else 0,
                           _pd(out.tau), _pd(out.logf_obs), _pd(out.logf_comp), _pd(out.w),
                           _pd(out.e1), _pd(out.e2), _pd(out.e3), _pd(out.A), _pd(out.B))
     if st != 0:

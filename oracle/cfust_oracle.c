@@ -211,11 +211,11 @@ static int or_spd_solve(int n, int r, const double *A, double *B)
 
 typedef struct {
     int N, S;
-    const int32_t *z;        /* [7] */
-    const double *shifts;    /* [S][7] */
+    const int32_t *z;        /* [8] */
+    const double *shifts;    /* [S][8] */
 } or_qmc;
 
-#define OR_LATDIM 7
+#define OR_LATDIM 8
 #define OR_XCLAMP (1.0 / 16777216.0)   /* 2^-24 */
 
 /* Lattice coordinate j of point k under shift s, after the tent transform. */
@@ -274,6 +274,60 @@ double or_mvt(int m, const double *b, const double *L, double nu, const or_qmc *
         *se = sqrt(v / ((double)S * (S - 1)));
     }
     return est;
+}
+
+/* Direct SOV moments: the same points and weights f = e_0 e_1 ... e_{m-1} as
+ * or_mvt, but every coordinate of the point is drawn (the last one with
+ * lattice coordinate m-1), z = L y, and
+ *     P = E[1{Z<=b}],  M1 = E[Z 1{Z<=b}],  M2 = E[Z Z^T 1{Z<=b}]
+ * (Z ~ t_m(0, L L^T, nu)) are the lattice means of f, f z, f z z^T.
+ * M2 is dense m x m.  m >= 1. */
+void or_mvt_mom(int m, const double *b, const double *L, double nu, const or_qmc *Q,
+                double *P, double *M1, double *M2)
+{
+    double e0 = or_tcdf(b[0] / L[0], nu);
+    double sP = 0.0, s1[OR_MAXM], s2m[OR_MAXM * OR_MAXM];
+    for (int i = 0; i < m; ++i) s1[i] = 0.0;
+    for (int i = 0; i < m * m; ++i) s2m[i] = 0.0;
+    for (int s = 0; s < Q->S; ++s) {
+        double a0 = 0.0, a1[OR_MAXM], a2[OR_MAXM * OR_MAXM];
+        for (int i = 0; i < m; ++i) a1[i] = 0.0;
+        for (int i = 0; i < m * m; ++i) a2[i] = 0.0;
+        for (long k = 0; k < Q->N; ++k) {
+            if (e0 == 0.0) break;
+            double y[OR_MAXM], zz[OR_MAXM];
+            double f = e0;
+            y[0] = or_tinv(or_point(Q, s, k, 0) * e0, nu);
+            double s2 = y[0] * y[0];
+            for (int i = 1; i < m && f > 0.0; ++i) {
+                double sc = sqrt((nu + s2) / (nu + i));
+                double num = b[i];
+                for (int j = 0; j < i; ++j) num -= L[i * m + j] * y[j];
+                double e = or_tcdf(num / (L[i * m + i] * sc), nu + i);
+                f *= e;
+                if (f == 0.0) break;
+                y[i] = sc * or_tinv(or_point(Q, s, k, i) * e, nu + i);
+                s2 += y[i] * y[i];
+            }
+            if (f == 0.0) continue;
+            for (int i = 0; i < m; ++i) {
+                double v = 0.0;
+                for (int j = 0; j <= i; ++j) v += L[i * m + j] * y[j];
+                zz[i] = v;
+            }
+            a0 += f;
+            for (int i = 0; i < m; ++i) {
+                a1[i] += f * zz[i];
+                for (int k2 = 0; k2 < m; ++k2) a2[i * m + k2] += f * zz[i] * zz[k2];
+            }
+        }
+        sP += a0 / Q->N;
+        for (int i = 0; i < m; ++i) s1[i] += a1[i] / Q->N;
+        for (int i = 0; i < m * m; ++i) s2m[i] += a2[i] / Q->N;
+    }
+    *P = sP / Q->S;
+    for (int i = 0; i < m; ++i) M1[i] = s1[i] / Q->S;
+    for (int i = 0; i < m * m; ++i) M2[i] = s2m[i] / Q->S;
 }
 
 /* T_m(b; 0, R, nu) for a dense SPD R. */
@@ -387,7 +441,7 @@ void or_tmoments(int m, const double *a, const double *R, double nu, const or_qm
 int or_estep(int n, int p, int q, int g, const double *y,
              const double *pi, const double *mu, const double *Sigma, const double *Delta,
              const double *nu, int N, int S, const int32_t *z, const double *shifts,
-             const int32_t *rows, int nrows,
+             const int32_t *rows, int nrows, int direct,
              double *tau, double *logf_obs, double *logf_comp,
              double *w, double *e1, double *e2, double *e3, double *intA, double *intB)
 {
@@ -465,8 +519,18 @@ int or_estep(int n, int p, int q, int g, const double *y,
             /* U | y ~ tt_q(c, s Lambda, nu*; R+) with s = (nu+d)/nu*, nu* = nu+p+2 */
             double nus = nuh + p + 2.0, sc = (nuh + d) / nus;
             double Rm[OR_MAXM * OR_MAXM], M0, M1[OR_MAXM], M2[OR_MAXM * OR_MAXM], T2;
-            for (int k = 0; k < q * q; ++k) Rm[k] = sc * Lam[k];
-            or_tmoments(q, c, Rm, nus, &Q, &M0, M1, M2, &T2);
+            if (direct && q >= 2) {
+                /* Z = sqrt(sc) Zs, Zs ~ t_q(0, Lambda, nu*) truncated to Zs <= c / sqrt(sc) */
+                double cb[OR_MAXM], Ms1[OR_MAXM], Ms2[OR_MAXM * OR_MAXM];
+                double rs = sqrt(sc);
+                for (int i = 0; i < q; ++i) cb[i] = c[i] / rs;
+                or_mvt_mom(q, cb, LLAM + (size_t)h * q * q, nus, &Q, &M0, Ms1, Ms2);
+                for (int i = 0; i < q; ++i) M1[i] = rs * Ms1[i];
+                for (int k = 0; k < q * q; ++k) M2[k] = sc * Ms2[k];
+            } else {
+                for (int k = 0; k < q * q; ++k) Rm[k] = sc * Lam[k];
+                or_tmoments(q, c, Rm, nus, &Q, &M0, M1, M2, &T2);
+            }
             double Bv = M0;          /* T_q(c sqrt(nu_s/(nu+d)); Lambda, nu_s), nu_s = nu+p+2 */
             double lfh = q * M_LN2 + logt + log(A);
             LF[(size_t)h * nr + r] = lfh;
@@ -671,6 +735,13 @@ double or_mvt_c(int m, const double *b, const double *L, double nu, int N, int S
 {
     or_qmc Q = {N, S, z, shifts};
     return or_mvt(m, b, L, nu, &Q, se);
+}
+
+void or_mvt_mom_c(int m, const double *b, const double *L, double nu, int N, int S,
+                  const int32_t *z, const double *shifts, double *P, double *M1, double *M2)
+{
+    or_qmc Q = {N, S, z, shifts};
+    or_mvt_mom(m, b, L, nu, &Q, P, M1, M2);
 }
 
 void or_tmoments_c(int m, const double *a, const double *R, double nu, int N, int S,

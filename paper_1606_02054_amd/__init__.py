@@ -141,7 +141,7 @@ def device_params(P, device="cuda") -> DeviceParams:
 
 
 class DeviceQmc:
-    """Lattice rule on the device: N points, S shifts, generating vector z[7], shifts[S][7]."""
+    """Lattice rule on the device: N points, S shifts, generating vector z[8], shifts[S][8]."""
 
     def __init__(self, N: int, S: int, z: torch.Tensor, shifts: torch.Tensor, precision: int):
         self.N, self.S, self.precision = int(N), int(S), int(precision)

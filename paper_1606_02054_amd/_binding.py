@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libcfust.so")
 
 CFUST_FP64 = 0
 CFUST_MIXED = 1
-LATTICE_DIM = 7
+LATTICE_DIM = 8
 MAX_P, MAX_Q, MAX_G, MAX_SHIFTS = 16, 8, 64, 64
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_LAYERS = 16, 256, 16, 5
 MLP_K = [MLP_IN, MLP_HIDDEN, MLP_HIDDEN, MLP_HIDDEN, MLP_HIDDEN]

@@ -62,9 +62,9 @@ def test_status_codes_match_header():
 def test_lattice_design_inputs():
     from cfust_inputs import make_design
     d = make_design(4096, 8, seed=3)
-    assert d.z.shape == (7,) and d.z.dtype == np.int32
+    assert d.z.shape == (8,) and d.z.dtype == np.int32
     assert d.z[0] == 1 and np.all(d.z % 2 == 1) and np.all(d.z < 4096)
-    assert d.shifts.shape == (8, 7) and np.all((d.shifts >= 0) & (d.shifts < 1))
+    assert d.shifts.shape == (8, 8) and np.all((d.shifts >= 0) & (d.shifts < 1))
     assert np.array_equal(make_design(4096, 8, seed=3).shifts, d.shifts)
 
 
