@@ -296,7 +296,10 @@ cfust_status cfust_reserve(cfust_handle handle, cfust_dims dims, const cfust_qmc
  * overwritten in place by the M-step (Psi^(k) -> Psi^(k+1)).  out: tau,
  * logf_obs, loglik, w, e1, e2, e3 are required (FP32 e-terms in mixed
  * precision, as for cfust_estep); logf_comp and cdf_stderr are optional;
- * out.status is ignored (use status). */
+ * out.status is ignored (use status).  A fit with n > 0 whose tau, w, e1,
+ * e2, e3 are all NULL is log-likelihood only: its E-step computes log f and the
+ * log-likelihood (eq. 27) as cfust_loglik does, and a batch holding one
+ * cannot run cfust_batch_mstep or cfust_fit_batch. */
 typedef struct {
     cfust_dims dims;
     const double *y;             /* [p][n] */
@@ -347,6 +350,33 @@ cfust_status cfust_fit_batch(cfust_batch batch, int32_t iters, double tol, int32
  * [(CFUST_MAX_Q+1) * 3]) receives (rows per tile, blocks per slot -- 0 for
  * one block per tile --, points per lane) per m (zeros where no queue). */
 cfust_status cfust_batch_tune(cfust_batch batch, int32_t *chosen, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Starting values, Sec. 3.3 (eq. 23, Algorithm 1).  For every starting
+ * partition s (labels[s][j] in [0, g): the component of observation j) and
+ * every alpha[a] in (0, 1), each cluster h gives, from its sample mean ybar,
+ * sample covariance S (divisor n_h - 1), s* = diag(S) and third central
+ * moments m3:
+ *     delta_i = sign(m3_i) sqrt(pi (1 - alpha) s*_i / (pi - 2))   (sign 0: +),
+ *     Sigma_h = S - (1 - alpha) diag(s*)   on the skewed coordinates,
+ *     mu_h = ybar - sqrt(2/pi) delta,   Delta_h[:, l] = delta_l e_l (l < q),
+ *     nu_h = nu0,   pi_h = n_h / n
+ * (the square root covers s*_i; with q < p the first q coordinates are
+ * skewed).  A candidate (s, a) is invalid when a cluster has n_h < p + 1 or a
+ * Sigma_h that is not positive definite.  The log-likelihood (eq. 27) of
+ * every valid candidate is evaluated in one density-only batch with the
+ * lattice rule qmc; the first candidate with the largest value is written to
+ * `best` (device arrays of the sizes of cfust_params).  loglik (optional,
+ * device FP64 [nstarts][nalpha]) receives every candidate's value (-inf when
+ * invalid); best_index (optional, device int32 [1]) the flat index
+ * s * nalpha + a, or -1 when no candidate is valid (best is then unwritten).
+ * 1 <= nstarts * nalpha <= CFUST_MAX_FITS; q <= p.  y: device [p][n];
+ * labels: device int32 [nstarts][n]; alpha: host [nalpha].  Allocates its
+ * own scratch and synchronises the device before returning. */
+cfust_status cfust_init(cfust_handle handle, const double *y, cfust_dims dims, int32_t nstarts,
+                        const int32_t *labels, int32_t nalpha, const double *alpha, double nu0,
+                        const cfust_qmc *qmc, const cfust_params_out *best, double *loglik,
+                        int32_t *best_index, void *stream);
 
 #ifdef __cplusplus
 }

@@ -328,5 +328,35 @@ class Batch:
             pass
 
 
+def initialise(y: torch.Tensor, g: int, q: int, labels: torch.Tensor, qmc: DeviceQmc,
+               alphas=(0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9), nu0: float = 10.0, stream=None,
+               handle: Optional[Handle] = None):
+    """Starting values of Sec. 3.3 (eq. 23, Algorithm 1) over the partitions
+    labels [nstarts][n] (int32, device) and the alpha grid.  Returns
+    (DeviceParams of the best candidate, loglik [nstarts][nalpha] with -inf
+    for invalid candidates, best flat index or -1)."""
+    h = handle or default_handle()
+    p = int(y.shape[0])
+    n = _check_y(y, p)
+    _need(labels, torch.int32, "labels")
+    nstarts = int(labels.shape[0])
+    if labels.dim() != 2 or labels.shape[1] != n:
+        raise ValueError("labels must be [nstarts][n]")
+    dev = y.device
+    best = DeviceParams(torch.zeros(g, dtype=torch.float64, device=dev),
+                        torch.zeros((g, p), dtype=torch.float64, device=dev),
+                        torch.zeros((g, p, p), dtype=torch.float64, device=dev),
+                        torch.zeros((g, p, q), dtype=torch.float64, device=dev),
+                        torch.zeros(g, dtype=torch.float64, device=dev))
+    al = (C.c_double * len(alphas))(*[float(a) for a in alphas])
+    ll = torch.zeros((nstarts, len(alphas)), dtype=torch.float64, device=dev)
+    bi = torch.zeros(1, dtype=torch.int32, device=dev)
+    bc = best.c()
+    st = h.lib.cfust_init(h.h, _ptr(y), B.Dims(n, p, q, g), nstarts, _ptr(labels), len(alphas), al, float(nu0),
+                          C.byref(qmc.c), C.byref(bc), _ptr(ll), _ptr(bi), _stream(stream))
+    B.check(st, h.h, "cfust_init")
+    return best, ll, int(bi.cpu()[0])
+
+
 def decode_status(word: int):
     return [name for bit, name in B.DEV_BITS.items() if word & bit]

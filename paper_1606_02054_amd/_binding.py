@@ -31,7 +31,8 @@ EXPORTS = ["cfust_create", "cfust_destroy", "cfust_last_error", "cfust_estep", "
            "cfust_loglik", "mvt_cdf_batch", "cfust_reserve", "cfust_profile_enable", "cfust_profile_read",
            "cfust_autotune", "cfust_mlp_forward", "cfust_mlp_backward", "cfust_mlp_adam",
            "cfust_mlp_loss", "cfust_mlp_features", "cfust_estep_surrogate", "cfust_batch_create",
-           "cfust_batch_destroy", "cfust_batch_estep", "cfust_batch_mstep", "cfust_fit_batch", "cfust_batch_tune"]
+           "cfust_batch_destroy", "cfust_batch_estep", "cfust_batch_mstep", "cfust_fit_batch", "cfust_batch_tune",
+           "cfust_init"]
 MAX_FITS = 1024
 
 
@@ -133,6 +134,9 @@ def load(path: str = LIB_PATH):
     lib.cfust_fit_batch.argtypes = [vp, i32, C.c_double, i32, vp, vp, vp]
     lib.cfust_batch_tune.restype = C.c_int
     lib.cfust_batch_tune.argtypes = [vp, C.POINTER(C.c_int32), vp]
+    lib.cfust_init.restype = C.c_int
+    lib.cfust_init.argtypes = [vp, vp, Dims, i32, vp, i32, C.POINTER(C.c_double), C.c_double, C.POINTER(QmcC),
+                               C.POINTER(ParamsC), vp, vp, vp]
     lib.cfust_profile_enable.restype = C.c_int
     lib.cfust_profile_enable.argtypes = [vp, C.c_int]
     lib.cfust_profile_read.restype = C.c_int

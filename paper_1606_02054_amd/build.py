@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcfust.so")
-SOURCES = ["cfust_api.hip", "cfust_batch.hip", "cfust_estep.hip", "cfust_mstep.hip", "cfust_mlp.hip"]
+SOURCES = ["cfust_api.hip", "cfust_batch.hip", "cfust_estep.hip", "cfust_init.hip", "cfust_mstep.hip", "cfust_mlp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

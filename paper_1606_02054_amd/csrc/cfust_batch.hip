@@ -35,7 +35,7 @@ struct Queue {
     unsigned long long *redo = nullptr;     // [items]
     unsigned int *redo_count = nullptr;
     int rows = 4, mult = 1, ppl = 1;
-    bool persist = true;                    // persistent blocks, or one block per tile
+    bool persist = false;                   // persistent blocks, or one block per tile (default)
     int grid = 0, redo_grid = 0;
 };
 
@@ -43,12 +43,20 @@ struct Group {
     int m, idx0, nidx;
 };
 
-int fit_groups(int q, Group *gr) {
+// Lattice integrals of a fit by dimension; a density-only fit needs A only.
+int fit_groups(int q, bool density, Group *gr) {
     int ng = 0;
-    if (q >= 2) gr[ng++] = {q, 0, 2};
+    if (q >= 2) gr[ng++] = {q, 0, density ? 1 : 2};
+    if (density) return ng;
     if (q - 1 >= 2) gr[ng++] = {q - 1, 2, q};
     if (q - 2 >= 2) gr[ng++] = {q - 2, 2 + q, npairs(q)};
     return ng;
+}
+
+// A fit with observations and no E-step output arrays asks for its
+// log-likelihood only (an empty fit's arrays may be NULL either way).
+bool density_only(const cfust_fit &F) {
+    return F.dims.n > 0 && !F.out.tau && !F.out.w && !F.out.e1 && !F.out.e2 && !F.out.e3;
 }
 
 }  // namespace
@@ -59,6 +67,8 @@ struct cfust_batch_ctx {
     bool mixed = false;
     LatticeArgs lat{};
     std::vector<cfust_fit> fits;
+    std::vector<char> dens;          // per fit: log-likelihood only
+    bool any_density = false;
     void *ws = nullptr;
     size_t ws_size = 0;
     FitDesc *dfits = nullptr;
@@ -99,7 +109,7 @@ void build_segments(cfust_batch b, Queue &Q, int rows) {
         for (int f = 0; f < b->nfits; ++f) {
             const cfust_dims &d = b->fits[f].dims;
             Group gr[3];
-            const int ng = fit_groups(d.q, gr);
+            const int ng = fit_groups(d.q, b->dens[f] != 0, gr);
             for (int k = 0; k < ng; ++k) {
                 if (gr[k].m != Q.m || d.n == 0) continue;
                 QSeg s;
@@ -195,8 +205,9 @@ cfust_status check_fit(cfust_handle h, int f, const cfust_fit &F) {
     if (!P.pi || !P.mu || !P.Sigma || !P.Delta || !P.nu) return fail(h, CFUST_EINVAL, "fit %d: a parameter array is NULL", f);
     const cfust_estep_out &O = F.out;
     if (!O.loglik) return fail(h, CFUST_EINVAL, "fit %d: loglik is NULL", f);
-    if (F.dims.n > 0 && (!F.y || !O.tau || !O.logf_obs || !O.w || !O.e1 || !O.e2 || !O.e3))
-        return fail(h, CFUST_EINVAL, "fit %d: y or an E-step output array is NULL", f);
+    if (F.dims.n > 0 && !F.y) return fail(h, CFUST_EINVAL, "fit %d: y is NULL", f);
+    if (F.dims.n > 0 && !density_only(F) && (!O.tau || !O.logf_obs || !O.w || !O.e1 || !O.e2 || !O.e3))
+        return fail(h, CFUST_EINVAL, "fit %d: an E-step output array is NULL", f);
     return CFUST_OK;
 }
 
@@ -228,6 +239,11 @@ cfust_status cfust_batch_create(cfust_handle h, int32_t nfits, const cfust_fit *
     b->mixed = qmc->precision == CFUST_MIXED;
     b->lat = lattice ? lattice_of(qmc) : LatticeArgs{};
     b->fits.assign(fits, fits + nfits);
+    b->dens.resize(nfits);
+    for (int f = 0; f < nfits; ++f) {
+        b->dens[f] = density_only(fits[f]) ? 1 : 0;
+        b->any_density = b->any_density || b->dens[f];
+    }
 
     // queues: one per lattice dimension present, largest first
     for (int m = MAXQ; m >= 2; --m) {
@@ -236,7 +252,7 @@ cfust_status cfust_batch_create(cfust_handle h, int32_t nfits, const cfust_fit *
         for (int f = 0; f < nfits; ++f) {
             const cfust_dims &d = fits[f].dims;
             Group gr[3];
-            const int ng = fit_groups(d.q, gr);
+            const int ng = fit_groups(d.q, b->dens[f] != 0, gr);
             for (int k = 0; k < ng; ++k)
                 if (gr[k].m == m) {
                     Q.items += (long long)d.g * gr[k].nidx * d.n;
@@ -253,14 +269,15 @@ cfust_status cfust_batch_create(cfust_handle h, int32_t nfits, const cfust_fit *
     for (int f = 0; f < nfits; ++f) {
         const cfust_dims &d = fits[f].dims;
         const size_t n1 = d.n > 0 ? d.n : 1;
-        const int J = nint_qmc(d.q);
+        const bool dn = b->dens[f] != 0;
+        const int J = dn ? (d.q >= 2 ? 1 : 0) : nint_qmc(d.q);
         fo[f].pre = c.take<CompPre>(d.g);
         fo[f].tabs = c.take<float>(b->mixed && J > 0 ? (size_t)d.g * NDOF * TAB_FLOATS : 1);
         fo[f].est = c.take<double>((size_t)d.g * (J > 0 ? J : 1) * n1);
         fo[f].lnA = c.take<double>((size_t)d.g * n1);
         fo[f].logf = c.take<double>(fits[f].out.logf_comp ? 1 : (size_t)d.g * n1);
         fo[f].lse = c.take<double>((size_t)(d.n + 255) / 256 + 1);
-        fo[f].mpart = c.take<double>((size_t)d.g * mstep_nblk(d) * nstat(d.p, d.q));
+        fo[f].mpart = c.take<double>(dn ? 1 : (size_t)d.g * mstep_nblk(d) * nstat(d.p, d.q));
         fo[f].cstat = c.take<int32_t>(d.g);
     }
     const size_t o_fits = c.take<FitDesc>(nfits);
@@ -302,7 +319,8 @@ cfust_status cfust_batch_create(cfust_handle h, int32_t nfits, const cfust_fit *
     for (int f = 0; f < nfits; ++f) {
         const cfust_fit &F = fits[f];
         const cfust_dims &d = F.dims;
-        const int J = nint_qmc(d.q);
+        const bool dn = b->dens[f] != 0;
+        const int J = dn ? (d.q >= 2 ? 1 : 0) : nint_qmc(d.q);
         FitDesc &D = hd[f];
         memset(&D, 0, sizeof D);
         CompPre *pre = bat<CompPre>(b, fo[f].pre);
@@ -322,13 +340,13 @@ cfust_status cfust_batch_create(cfust_handle h, int32_t nfits, const cfust_fit *
         EstepAsmArgs &a = D.aa;
         a.y = F.y; a.mu = F.params.mu; a.pre = pre;
         a.n = d.n; a.p = d.p; a.q = d.q; a.g = d.g; a.J = J > 0 ? J : 1;
-        a.mixed = b->mixed; a.density_only = 0;
+        a.mixed = b->mixed; a.density_only = dn ? 1 : 0;
         a.est = est; a.lnA = lnA; a.logf_comp = lfc;
         a.w = F.out.w; a.e1 = F.out.e1; a.e2 = F.out.e2; a.e3 = F.out.e3;
         EstepLseArgs &l = D.la;
         l.pi = F.params.pi; l.logf_comp = lfc;
         l.n = d.n; l.g = d.g; l.q = d.q; l.mixed = b->mixed;
-        l.tau = F.out.tau; l.logf_obs = F.out.logf_obs;
+        l.tau = dn ? nullptr : F.out.tau; l.logf_obs = F.out.logf_obs;
         l.w = F.out.w; l.e1 = F.out.e1; l.e2 = F.out.e2; l.e3 = F.out.e3;
         l.partial = bat<double>(b, fo[f].lse);
         D.nlse = (d.n + 255) / 256;
@@ -351,8 +369,8 @@ cfust_status cfust_batch_create(cfust_handle h, int32_t nfits, const cfust_fit *
                                    b->mixed && J > 0 ? d.g * D.ndof : 0,
                                    (d.n * d.g + 127) / 128,
                                    (d.n + 255) / 256,
-                                   nblk * d.g,
-                                   d.g};
+                                   dn ? 0 : nblk * d.g,
+                                   dn ? 0 : d.g};
         for (int k = 0; k < BK_NKIND; ++k) pref[(size_t)k * (nfits + 1) + f + 1] = pref[(size_t)k * (nfits + 1) + f] + cnt[k];
     }
     for (int k = 0; k < BK_NKIND; ++k) b->nblocks[k] = pref[(size_t)k * (nfits + 1) + nfits];
@@ -401,6 +419,7 @@ cfust_status cfust_batch_estep(cfust_batch b, void *stream) {
 
 cfust_status cfust_batch_mstep(cfust_batch b, void *stream) {
     if (!b) return CFUST_EINVAL;
+    if (b->any_density) return fail(b->h, CFUST_EINVAL, "the batch has log-likelihood-only fits");
     cfust_status st;
     if ((st = hip_check(b->h, hipSetDevice(b->h->device), "hipSetDevice")) != CFUST_OK) return st;
     hipStream_t s = (hipStream_t)stream;
@@ -414,6 +433,7 @@ cfust_status cfust_fit_batch(cfust_batch b, int32_t iters, double tol, int32_t u
     if (!b) return CFUST_EINVAL;
     cfust_handle h = b->h;
     if (iters < 0) return fail(h, CFUST_EINVAL, "iters = %d < 0", iters);
+    if (b->any_density) return fail(h, CFUST_EINVAL, "the batch has log-likelihood-only fits");
     cfust_status st;
     if ((st = hip_check(h, hipSetDevice(h->device), "hipSetDevice")) != CFUST_OK) return st;
     hipStream_t s = (hipStream_t)stream;
@@ -521,6 +541,86 @@ cfust_status cfust_batch_tune(cfust_batch b, int32_t *chosen, void *stream) {
     drop_graph(b);
     if (e == hipSuccess) e = launch_fill_i32(b->counters, 4 * b->queues.size(), 0, s);
     return hip_check(h, e, "cfust_batch_tune");
+}
+
+cfust_status cfust_init(cfust_handle h, const double *y, cfust_dims d, int32_t nstarts, const int32_t *labels,
+                        int32_t nalpha, const double *alpha, double nu0, const cfust_qmc *qmc,
+                        const cfust_params_out *best, double *loglik, int32_t *best_index, void *stream) {
+    if (!h) return CFUST_EINVAL;
+    cfust_status st;
+    if ((st = check_dims(h, d)) != CFUST_OK) return st;
+    if (d.q > d.p) return fail(h, CFUST_EINVAL, "q = %d > p = %d", d.q, d.p);
+    if (d.n < 1 || !y || !labels) return fail(h, CFUST_EINVAL, "y or labels is NULL, or n = 0");
+    if (nstarts < 1 || nalpha < 1 || (long)nstarts * nalpha > BATCH_MAX_FITS)
+        return fail(h, CFUST_EINVAL, "nstarts * nalpha outside [1, %d]", BATCH_MAX_FITS);
+    if (!alpha) return fail(h, CFUST_EINVAL, "alpha is NULL");
+    for (int a = 0; a < nalpha; ++a)
+        if (!(alpha[a] > 0.0 && alpha[a] < 1.0)) return fail(h, CFUST_EINVAL, "alpha[%d] outside (0, 1)", a);
+    if (!(nu0 > 0.0) || !(nu0 < 1e300)) return fail(h, CFUST_EINVAL, "nu0 must be positive and finite");
+    if (!best || !best->pi || !best->mu || !best->Sigma || !best->Delta || !best->nu)
+        return fail(h, CFUST_EINVAL, "an output parameter array is NULL");
+    if ((st = check_qmc(h, qmc, d.q >= 2)) != CFUST_OK) return st;
+    if ((st = hip_check(h, hipSetDevice(h->device), "hipSetDevice")) != CFUST_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const int C = nstarts * nalpha, g = d.g, p = d.p, q = d.q;
+    const int ntiles = (d.n + 63) / 64;
+    int nblk = (ntiles + 3) / 4;
+    nblk = nblk < 1 ? 1 : (nblk > 256 ? 256 : nblk);
+    const int ns0 = 1 + p, ns1 = p * (p + 1) / 2 + p;
+    Carve c;
+    const size_t o_p0 = c.take<double>((size_t)nstarts * g * nblk * ns0);
+    const size_t o_p1 = c.take<double>((size_t)nstarts * g * nblk * ns1);
+    const size_t o_cnt = c.take<double>((size_t)nstarts * g);
+    const size_t o_mean = c.take<double>((size_t)nstarts * g * p);
+    const size_t o_S = c.take<double>((size_t)nstarts * g * p * p);
+    const size_t o_m3 = c.take<double>((size_t)nstarts * g * p);
+    const size_t o_pi = c.take<double>((size_t)C * g);
+    const size_t o_mu = c.take<double>((size_t)C * g * p);
+    const size_t o_Sg = c.take<double>((size_t)C * g * p * p);
+    const size_t o_Dl = c.take<double>((size_t)C * g * p * q);
+    const size_t o_nu = c.take<double>((size_t)C * g);
+    const size_t o_vch = c.take<int32_t>((size_t)C * g);
+    const size_t o_ll = c.take<double>((size_t)C);
+    const size_t o_al = c.take<double>((size_t)nalpha);
+    void *ws = nullptr;
+    if (hipMalloc(&ws, c.off) != hipSuccess) return fail(h, CFUST_ENOMEM, "initialiser scratch of %zu bytes", c.off);
+    auto P = [&](size_t off) { return (double *)((char *)ws + off); };
+    InitArgs A;
+    A.y = y; A.n = d.n; A.p = p; A.q = q; A.g = g;
+    A.nstarts = nstarts; A.nalpha = nalpha; A.labels = labels; A.alpha = P(o_al); A.nu0 = nu0; A.nblk = nblk;
+    A.part0 = P(o_p0); A.part1 = P(o_p1); A.cnt = P(o_cnt); A.mean = P(o_mean); A.S = P(o_S); A.m3 = P(o_m3);
+    A.pi = P(o_pi); A.mu = P(o_mu); A.Sigma = P(o_Sg); A.Delta = P(o_Dl); A.nu = P(o_nu);
+    A.valid_ch = (int32_t *)((char *)ws + o_vch);
+    double *llc = P(o_ll);
+    // one density-only fit per candidate, on the shared data
+    std::vector<cfust_fit> fits(C);
+    for (int k = 0; k < C; ++k) {
+        cfust_fit &F = fits[k];
+        memset(&F, 0, sizeof F);
+        F.dims = d;
+        F.y = y;
+        F.params.pi = A.pi + (size_t)k * g;
+        F.params.mu = A.mu + (size_t)k * g * p;
+        F.params.Sigma = A.Sigma + (size_t)k * g * p * p;
+        F.params.Delta = A.Delta + (size_t)k * g * p * q;
+        F.params.nu = A.nu + (size_t)k * g;
+        F.out.loglik = llc + k;
+    }
+    cfust_batch b = nullptr;
+    hipError_t e = hipMemcpy((void *)A.alpha, alpha, sizeof(double) * nalpha, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        st = cfust_batch_create(h, C, fits.data(), qmc, &b);
+        if (st != CFUST_OK) { hipFree(ws); return st; }
+    }
+    // statistics, candidates, and their validity as the batch's active mask
+    if (e == hipSuccess) e = launch_init_stats(A, s);
+    if (e == hipSuccess) e = launch_init_candidates(A, b->active, s);
+    if (e == hipSuccess) e = enqueue_estep(b, s);
+    if (e == hipSuccess) e = launch_init_select(A, b->active, llc, loglik, best_index, *best, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (b) cfust_batch_destroy(b);
+    hipFree(ws);
+    return hip_check(h, e, "cfust_init");
 }
 
 }  // extern "C"

@@ -161,9 +161,10 @@ __device__ __forceinline__ float tab_poly(const float *row, float x) {
     return r;
 }
 
-// F(tau) from the CDF rows of one dof's table; tau in [0, 1].
+// F(tau) from the CDF rows of one dof's table; tau in [0, 1] (anything else,
+// NaN included, is clamped into the table so the index stays in range).
 __device__ __forceinline__ float tab_cdf_F(const float *tab, float tau) {
-    const float pos = tau * 8.0f;
+    const float pos = fminf(fmaxf(tau * 8.0f, 0.0f), 8.0f);
     const int k = min((int)pos, TAB_CDF_ROWS - 1);
     const float x = fmaf(2.0f, pos - (float)k, -1.0f);
     return tab_poly(tab + 8 * k, x);

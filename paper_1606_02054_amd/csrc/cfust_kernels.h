@@ -184,6 +184,26 @@ struct BatchCtl {
 hipError_t launch_batch_check(const FitDesc *fits, int nfits, int32_t *active, int32_t *iter, double *hist,
                               const BatchCtl *ctl, hipStream_t s);
 
+// ------------------------------------------------------ initialisation ----
+struct InitArgs {
+    const double *y;            // [p][n]
+    int n, p, q, g;
+    int nstarts, nalpha;
+    const int32_t *labels;      // [nstarts][n]
+    const double *alpha;        // [nalpha]
+    double nu0;
+    int nblk;                   // reduction blocks per (start, component)
+    double *part0, *part1;      // block partials of the two passes
+    double *cnt, *mean, *S, *m3;                // [nstarts][g] (x p, x p x p, x p)
+    double *pi, *mu, *Sigma, *Delta, *nu;       // candidates [C][g] ...
+    int32_t *valid_ch;          // [C][g]
+};
+
+hipError_t launch_init_stats(const InitArgs &a, hipStream_t s);
+hipError_t launch_init_candidates(const InitArgs &a, int32_t *active, hipStream_t s);
+hipError_t launch_init_select(const InitArgs &a, const int32_t *active, const double *llc, double *ll_out,
+                              int32_t *best_index, const cfust_params_out &best, hipStream_t s);
+
 hipError_t launch_precompute(const cfust_params &P, int p, int q, int g, CompPre *pre, hipStream_t s);
 hipError_t launch_status_fold(const CompPre *pre, int g, int32_t *status, hipStream_t s);
 hipError_t launch_tables(const CompPre *pre, int p, int g, int ndof, float *tabs, hipStream_t s);
