@@ -120,6 +120,96 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
+PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
+PEAK_BF16_TFLOPS = 2500.0    # MI355X dense BF16 matrix
+
+
+def _event_ms(fn, reps: int) -> float:
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def component_rooflines(cf, dev) -> dict:
+    """The other bound kernels of the path, each against its own roofline:
+    the M-step reduction (HBM) at the cytometry shape n = 1e6, p = q = 8,
+    g = 5 with mixed-precision E-step arrays (values synthetic: the reduction
+    reads every input once whatever it holds), and the surrogate network's
+    BF16 matrix kernels (forward, and forward + backward of a training step)."""
+    import numpy as np
+    import torch
+    from cfust_inputs.synth import draw_params
+    from paper_1606_02054_amd import surrogate as S
+    from paper_1606_02054_amd._binding import MLP_K, MLP_N
+
+    out = {}
+    n, p, q, g = 1_000_000, 8, 8, 5
+    gen = torch.Generator(device=dev).manual_seed(5)
+    y = torch.rand((p, n), dtype=torch.float64, device=dev, generator=gen) * 1024.0
+    es = cf.alloc_estep(n, p, q, g, cf.CFUST_MIXED, device=dev, logf_comp=False, stderr=False)
+    es.tau.copy_(torch.rand((g, n), dtype=torch.float64, device=dev, generator=gen))
+    for t in (es.w, es.e1, es.e2, es.e3):
+        t.copy_(torch.rand(t.shape, dtype=torch.float32, device=dev, generator=gen))
+    P = cf.device_params(draw_params(np.random.default_rng(3), p, q, g, sigma="wishart"), device=dev)
+    nxt = P.clone()
+    ms = _event_ms(lambda: cf.cfust_mstep(y, es, P, out=nxt), 5)
+    byts = n * (g * (8 + 4 * (2 + q + q * (q + 1) // 2)) + 8 * p)
+    out["mstep"] = {"bound": "hbm", "kernel": "k_mstep_reduce + k_mstep_solve (cfust_mstep)",
+                    "config": {"n": n, "p": p, "q": q, "g": g, "precision": "mixed"},
+                    "ms": ms, "algorithmic_bytes": byts, "achieved": byts / (ms / 1e3) / 1e9,
+                    "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": byts / (ms / 1e3) / 1e9 / PEAK_HBM_GBS}
+    del y, es
+    net = S.SurrogateNet(3, seed=1, device=dev)
+    B = 65536
+    X0 = torch.zeros((B, 16), dtype=torch.int16, device=dev)
+    o = torch.zeros((B, 16), dtype=torch.float32, device=dev)
+    acts = S.Activations(B, dev)
+    kn = sum(k * nn for k, nn in zip(MLP_K, MLP_N))
+    f_fwd = 2.0 * B * kn
+    ms_f = _event_ms(lambda: S.mlp_forward(net, X0, o, acts), 10)
+    dout = torch.zeros_like(o)
+    ms_fb = _event_ms(lambda: (S.mlp_forward(net, X0, o, acts), S.mlp_backward(net, acts, dout)), 10)
+    f_bwd = 2.0 * B * kn + 2.0 * B * (kn - MLP_K[0] * MLP_N[0])
+    out["surrogate_forward"] = {"bound": "mfma", "kernel": "k_gemm_bf16 (forward, 16-4x256-16, B=65536)",
+                                "ms": ms_f, "achieved": f_fwd / (ms_f / 1e3) / 1e12, "peak": PEAK_BF16_TFLOPS,
+                                "unit": "TFLOP/s", "frac": f_fwd / (ms_f / 1e3) / 1e12 / PEAK_BF16_TFLOPS}
+    out["surrogate_train_step"] = {"bound": "mfma", "kernel": "k_gemm_bf16 (forward + backward, B=65536)",
+                                   "ms": ms_fb, "achieved": (f_fwd + f_bwd) / (ms_fb / 1e3) / 1e12,
+                                   "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                                   "frac": (f_fwd + f_bwd) / (ms_fb / 1e3) / 1e12 / PEAK_BF16_TFLOPS}
+    return out
+
+
+def initialisation(cf, ds, y, qmc, dev, nstarts: int = 8) -> dict:
+    """Algorithm 1 on the bench data: nstarts k-means partitions (seeded
+    input, computed on the host and not timed) x 9 values of alpha, every
+    candidate's log-likelihood in one density-only batch."""
+    import numpy as np
+    import torch
+    from cfust_inputs import kmeans_partitions
+
+    g, q = ds.params.g, ds.params.q
+    labels = torch.as_tensor(kmeans_partitions(ds.y, g, nstarts, seed=5), device=dev)
+    cf.initialise(y, g, q, labels, qmc)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, ll, k = cf.initialise(y, g, q, labels, qmc)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    llv = ll.cpu().numpy()
+    n = int(y.shape[1])
+    return {"starts": nstarts, "alphas": 9, "candidates": nstarts * 9, "valid": int(np.isfinite(llv).sum()),
+            "ms": ms, "candidate_pairs_per_s": nstarts * 9 * n * g / (ms / 1e3), "best_index": k,
+            "best_loglik": float(llv.ravel()[k]) if k >= 0 else None}
+
+
 def small_restarts(cf, h, prec, dev, nstarts: int = 64, iters: int = 5) -> dict:
     """64 restarts of EM on the same n = 1000, p = q = 2, g = 2 data (the
     starts of Algorithm 1), lattice 1024 x 4: one batched EM iteration of all
@@ -315,6 +405,8 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=0, help="oracle sample rows (0: one per thread)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate-vs-lattice comparison")
+    ap.add_argument("--no-components", action="store_true",
+                    help="skip the M-step and network roofline figures")
     ap.add_argument("--n", type=int, default=0, help="observations (0: the workload's own n)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a known-size "
@@ -415,6 +507,9 @@ def main():
 
     if not args.no_surrogate and prec == cf.CFUST_MIXED:
         out["surrogate"] = surrogate_vs_lattice(cf, ds, y, start, design, n * g)
+    if not args.no_components and args.workload == "cfust_n20000_p4_q4_g3":
+        out["component_rooflines"] = component_rooflines(cf, dev)
+        out["initialisation"] = initialisation(cf, ds, y, qmc, dev)
 
     if not args.no_cpu:
         import oracle

@@ -74,6 +74,7 @@ struct cfust_batch_ctx {
     FitDesc *dfits = nullptr;
     int *dprefix = nullptr;
     int nblocks[BK_NKIND] = {};
+    size_t mred_lds = 0;             // dynamic LDS of the batched M-step reduction
     int32_t *active = nullptr;       // [nfits]
     int32_t *iter = nullptr;         // [1]
     double *hist = nullptr;          // [nfits][2]
@@ -188,7 +189,7 @@ hipError_t enqueue_estep(cfust_batch b, hipStream_t s) {
 }
 
 hipError_t enqueue_mstep(cfust_batch b, hipStream_t s) {
-    return launch_batch_mstep(batch_args(b), b->nblocks[BK_MRED], b->nblocks[BK_MSOL], s);
+    return launch_batch_mstep(batch_args(b), b->nblocks[BK_MRED], b->nblocks[BK_MSOL], b->mred_lds, s);
 }
 
 hipError_t enqueue_iteration(cfust_batch b, hipStream_t s) {
@@ -328,6 +329,7 @@ cfust_status cfust_batch_create(cfust_handle h, int32_t nfits, const cfust_fit *
         double *est = bat<double>(b, fo[f].est), *lnA = bat<double>(b, fo[f].lnA);
         double *lfc = F.out.logf_comp ? F.out.logf_comp : bat<double>(b, fo[f].logf);
         const int nblk = mstep_nblk(d);
+        if (!dn) b->mred_lds = std::max(b->mred_lds, mstep_lds_bytes(d.p, d.q));
         D.g = d.g;
         D.pc.pi = F.params.pi; D.pc.Sigma = F.params.Sigma; D.pc.Delta = F.params.Delta; D.pc.nu = F.params.nu;
         D.pc.p = d.p; D.pc.q = d.q; D.pc.pre = pre;

@@ -124,13 +124,14 @@ inline cfust_status check_params(cfust_handle h, const cfust_params *P) {
     return CFUST_OK;
 }
 
-// M-step reduction blocks per component (the partition fixes the summation
-// order, so it depends on n only).
+// M-step reduction blocks per component: about 16 tiles of 64 observations
+// each, at most 1024 (the partition fixes the summation order, so it depends
+// on n only).
 inline int mstep_nblk(const cfust_dims &d) {
     const int ntiles = (d.n + 63) / 64;
-    int nb = (ntiles + 3) / 4;
+    int nb = (ntiles + 15) / 16;
     if (nb < 1) nb = 1;
-    if (nb > 256) nb = 256;
+    if (nb > 1024) nb = 1024;
     return nb;
 }
 

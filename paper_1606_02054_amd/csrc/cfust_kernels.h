@@ -159,7 +159,9 @@ hipError_t launch_batch_tables(const BatchArgs &b, int nblocks, hipStream_t s);
 hipError_t launch_batch_assemble(const BatchArgs &b, int nblocks, hipStream_t s);
 hipError_t launch_batch_lse(const BatchArgs &b, int nblocks, hipStream_t s);
 hipError_t launch_batch_sum(const BatchArgs &b, hipStream_t s);
-hipError_t launch_batch_mstep(const BatchArgs &b, int nred, int nsol, hipStream_t s);
+// lds: dynamic LDS of the reduction, the largest mstep_lds_bytes of the fits.
+hipError_t launch_batch_mstep(const BatchArgs &b, int nred, int nsol, size_t lds, hipStream_t s);
+size_t mstep_lds_bytes(int p, int q);
 // Lattice kernel of dimension m over a queue.  grid > 0: persistent, `grid`
 // blocks draw tiles until the queue is empty; grid == 0: one block per tile
 // in queue order (tiles of at most 4 observations).  Mixed mode appends
