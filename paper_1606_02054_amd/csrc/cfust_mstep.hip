@@ -2,11 +2,12 @@
 //
 //   k_mstep_reduce  grid (blocks, component): FP64 weighted sums over the
 //                   observations of a component, in coordinates shifted by
-//                   mu_h^(k) for conditioning.  A tile of 64 observations is
-//                   staged in LDS (coalesced SoA reads, each input read once);
-//                   every thread then owns one or two statistics.  Partials
-//                   per block are written out and summed in a fixed order, so
-//                   results are reproducible run to run.
+//                   mu_h^(k) for conditioning.  Tiles of 64 observations:
+//                   coalesced SoA reads into registers (each input read once),
+//                   plain sums kept per lane, the two product blocks from LDS
+//                   in 4x4 register blocks.  Partials per block are written
+//                   out and summed in a fixed order, so results are
+//                   reproducible run to run.
 //   k_mstep_solve   one block per component: sums the partials, then the
 //                   closed-form updates pi, mu, Delta, Sigma and the nu root.
 #include <type_traits>
@@ -16,172 +17,244 @@
 
 namespace cfust {
 
-constexpr int MS_TILE = 64;
-constexpr int MS_STRIDE = MS_TILE + 1;           // pad: rows land in different banks
-constexpr int MS_ROWS64_PER_WAVE = (MAXP + 1 + 3) / 4;                       // y rows + tau, 4 waves
-constexpr int MS_EROWS_PER_WAVE = (2 + MAXQ + MAXQ * (MAXQ + 1) / 2 + 3) / 4;  // w, e1, e2, e3
+constexpr int MS_TILE = 64;                      // observations per block iteration
+constexpr int MS_STRIDE = MS_TILE + 1;           // LDS row pitch (doubles)
+constexpr int MS_E_PER_WAVE = (1 + MAXQ + MAXQ * (MAXQ + 1) / 2 + 3) / 4;      // rows e1, e2_l, e3_t
+static_assert(MAXP <= 16 && MAXQ <= 8, "product blocks are sized for p <= 16, q <= 8");
 
-// Row layout of the staged tile.  Raw rows r_i = y_i - mu_i, tau, w, e1;
-// rows weighted in place tau e2_l, tau e3_t; rows added by the weighting
-// pass tau w, tau (e1 - w), tau w r_i; and a row of ones.  Every statistic is
-// then the sum over the tile of the product of two rows.
-struct MsRows {
-    int r0, tau, w, e1, e20, e30, tw, te1w, twr0, one, nrows;
+// Two sizes of the reduction: NR rows r_i per wave (4 waves), so p <= 4 NR.
+//   NR = 2: p <= 8,  at most 3 + 4 = 7 product blocks: 8 groups of 32 lanes, one each
+//   NR = 4: p <= 16, at most 10 + 8 = 18 blocks: 16 groups of 16 lanes, two each
+// LDS rows of one buffer: A_i = r_i (i < 4 NR), then B_c = tau w r_c
+// (c < 4 NR) and B_{4 NR + l} = tau e2_l (l < MAXQ).  Two buffers: the rows of
+// the next tile are written while other waves still read the current one.
+template <int NR> struct MsShape {
+    static constexpr int AROWS = 4 * NR, BROWS = 4 * NR + MAXQ;
+    static constexpr int BUF = (AROWS + BROWS) * MS_STRIDE;
+    static constexpr int OGW = NR == 2 ? 32 : 16;        // lanes sharing a block (observation groups)
+    static constexpr int NGRP = 256 / OGW;               // thread groups
+    static constexpr int NBT = NR == 2 ? 1 : 2;          // product blocks per thread group
+    static_assert(NGRP * NBT >= (NR * (NR + 1) / 2 + NR * ((MAXQ + 3) / 4)), "too few block slots");
 };
 
-__host__ __device__ inline MsRows ms_rows(int p, int q) {
-    MsRows R;
-    R.r0 = 0; R.tau = p; R.w = p + 1; R.e1 = p + 2; R.e20 = p + 3; R.e30 = p + 3 + q;
-    R.tw = R.e30 + q * (q + 1) / 2; R.te1w = R.tw + 1; R.twr0 = R.tw + 2;
-    R.one = R.twr0 + p;
-    R.nrows = R.one + 1;
-    return R;
+__host__ __device__ inline int ms_nr(int p) { return p <= 8 ? 2 : 4; }
+
+// LDS bytes of the reduction for p.
+__host__ __device__ inline size_t ms_lds_bytes(int p, int) {
+    return 2 * (size_t)(ms_nr(p) == 2 ? MsShape<2>::BUF : MsShape<4>::BUF) * sizeof(double);
 }
 
-// LDS bytes of the staged tile.
-__host__ __device__ inline size_t ms_lds_bytes(int p, int q) {
-    return (size_t)ms_rows(p, q).nrows * MS_STRIDE * sizeof(double);
+// Statistic indices (the order mstep_solve_body reads):
+//   0 n_h = sum tau             1 sum tau w            2 sum tau (e1 - w)
+//   3 + i          sum tau w r_i                      (p)
+//   3 + p + l      sum tau e2_l                        (q)
+//   O1(i, k)       sum tau w r_i r_k, i <= k, i-major  (p(p+1)/2)
+//   O2(i, l)       sum r_i tau e2_l                    (p q)
+//   last q(q+1)/2  sum tau e3_t
+__device__ inline int ms_idx_o1(int p, int q, int i, int k) { return 3 + p + q + i * p - i * (i - 1) / 2 + (k - i); }
+__device__ inline int ms_idx_o2(int p, int q, int i, int l) { return 3 + p + q + p * (p + 1) / 2 + i * q + l; }
+__device__ inline int ms_idx_e3(int p, int q, int t) { return 3 + p + q + p * (p + 1) / 2 + p * q + t; }
+
+// Sum over `width` adjacent lanes (fixed butterfly: reproducible).
+__device__ inline double ms_lane_sum(double v, int width) {
+    for (int m = width >> 1; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
 }
 
-// Statistic s as the product of two staged rows:
-//   0 n_h            tau . 1
-//   1 sum tau w      tau w . 1
-//   2 sum tau (e1-w) tau (e1-w) . 1
-//   3.. p            tau w r_i . 1
-//   q                tau e2_l . 1
-//   p(p+1)/2         tau w r_i . r_k   (i <= k)
-//   p q              r_i . tau e2_l
-//   q(q+1)/2         tau e3_t . 1
-__device__ inline void ms_stat_rows(int s, int p, int q, const MsRows &R, int *f) {
-    f[1] = R.one;
-    if (s == 0) { f[0] = R.tau; return; }
-    if (s == 1) { f[0] = R.tw; return; }
-    if (s == 2) { f[0] = R.te1w; return; }
-    s -= 3;
-    if (s < p) { f[0] = R.twr0 + s; return; }
-    s -= p;
-    if (s < q) { f[0] = R.e20 + s; return; }
-    s -= q;
-    if (s < p * (p + 1) / 2) {
-        int i = 0;
-        while (s >= p - i) { s -= p - i; ++i; }
-        f[0] = R.twr0 + i; f[1] = R.r0 + i + s;
-        return;
+// Product block b of 4x4 entries: A rows ab*4.., B rows bbase..  The blocks
+// are the lower triangle (cb <= ab) of r_i . tau w r_c, then r_i . tau e2_l.
+__device__ inline void ms_block(int b, int na, int nq, int arows, int &ab, int &bbase) {
+    const int ntri = na * (na + 1) / 2;
+    if (b < ntri) {
+        ab = 0;
+        while ((ab + 1) * (ab + 2) / 2 <= b) ++ab;
+        bbase = 4 * (b - ab * (ab + 1) / 2);
+    } else {
+        ab = (b - ntri) / nq;
+        bbase = arows + 4 * ((b - ntri) % nq);
     }
-    s -= p * (p + 1) / 2;
-    if (s < p * q) { f[0] = R.r0 + s / q; f[1] = R.e20 + s % q; return; }
-    s -= p * q;
-    f[0] = R.e30 + s;
 }
 
-// Block bx of component h of one fit; `tile` is the block's dynamic LDS
-// (ms_lds_bytes).
-template <bool MIXED>
-__device__ inline void mstep_reduce_prec(const MstepArgs &a, int bx, int h, double *tile) {
+// Block bx of component h of one fit; `lds` is the block's dynamic LDS
+// (ms_lds_bytes).  Work split:
+//   * loads: wave w loads rows r_i (i = w, w+4, ...) and e1 / e2_l / e3_t
+//     rows w, w+4, ..., one observation per lane; every wave also loads tau
+//     and w of its lanes.  Row base pointers are wave-uniform and set up once;
+//     the loads carry no per-lane branches (indices clamped into range,
+//     values of observations past n zeroed afterwards) and the next tile's
+//     loads are issued before the current tile's products, so their latency
+//     is hidden.
+//   * weighting in registers: tau w r_i, tau (e1 - w), tau e2_l, tau e3_t;
+//     every statistic that is a plain sum over observations accumulates in a
+//     per-lane register and is summed over lanes once, at the end.
+//   * the product blocks r_i . [tau w r_c | tau e2_l] from LDS: thread =
+//     (block group, observation group), 16 accumulators per 4x4 block,
+//     summed over the lanes of the group at the end.
+template <bool MIXED, int NR>
+__device__ inline void mstep_reduce_prec(const MstepArgs &a, int bx, int h, double *lds) {
     using E = typename std::conditional<MIXED, float, double>::type;   // storage of w, e1, e2, e3
+    using S = MsShape<NR>;
     const int p = a.p, q = a.q, n = a.n;
     const int nq2 = q * (q + 1) / 2;
-    const MsRows R = ms_rows(p, q);
-    const int NS = nstat(p, q);
-    int fa[2], fb[2];
-    const int s0 = threadIdx.x, s1 = threadIdx.x + 256;
-    if (s0 < NS) ms_stat_rows(s0, p, q, R, fa);
-    if (s1 < NS) ms_stat_rows(s1, p, q, R, fb);
-    double acc0 = 0.0, acc1 = 0.0;
-    const double *mu0 = a.mu0 + (size_t)h * p;
+    const int ne = 1 + q + nq2;                  // rows e1, e2_l, e3_t
     const int ntiles = (n + MS_TILE - 1) / MS_TILE;
-    // Raw rows of one tile, held in registers: wave w takes rows w, w+4, ...,
-    // one observation per lane (coalesced).  A wave's rows are fixed, so their
-    // base pointers are wave-uniform values set up once; the loads carry no
-    // branches (indices clamped into range; rows past the last one re-read
-    // the last row and are dropped at the store), so all of a wave's loads
-    // are in flight together, and the next tile's loads are issued before the
-    // current tile is weighted and reduced.
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int ne = 2 + q + nq2;                  // rows w, e1, e2_l, e3_t
     const size_t hn = (size_t)h * n;
-    const double *src64[MS_ROWS64_PER_WAVE];
-    double off64[MS_ROWS64_PER_WAVE];
+    const double *mu0 = a.mu0 + (size_t)h * p;
+
+    // both LDS buffers start at zero: rows past p and q are never written
+    for (int t = threadIdx.x; t < 2 * S::BUF; t += blockDim.x) lds[t] = 0.0;
+
+    const double *srcr[NR];
+    double offr[NR];
 #pragma unroll
-    for (int k = 0; k < MS_ROWS64_PER_WAVE; ++k) {
-        const int row = min(wave + 4 * k, p);    // rows 0..p-1: y_i - mu_i; row p: tau
-        src64[k] = row < p ? a.y + (size_t)row * n : a.tau + hn;
-        off64[k] = row < p ? mu0[row] : 0.0;
+    for (int k = 0; k < NR; ++k) {
+        const int i = min(wave + 4 * k, p - 1);
+        srcr[k] = a.y + (size_t)i * n;
+        offr[k] = mu0[i];
     }
-    const E *srce[MS_EROWS_PER_WAVE];
+    const E *srce[MS_E_PER_WAVE];
 #pragma unroll
-    for (int k = 0; k < MS_EROWS_PER_WAVE; ++k) {
+    for (int k = 0; k < MS_E_PER_WAVE; ++k) {
         const int e = min(wave + 4 * k, ne - 1);
-        srce[k] = e == 0 ? (const E *)a.w + hn
-                : e == 1 ? (const E *)a.e1 + hn
-                : e < 2 + q ? (const E *)a.e2 + ((size_t)h * q + (e - 2)) * n
-                            : (const E *)a.e3 + ((size_t)h * nq2 + (e - 2 - q)) * n;
+        srce[k] = e == 0 ? (const E *)a.e1 + hn
+                : e <= q ? (const E *)a.e2 + ((size_t)h * q + (e - 1)) * n
+                         : (const E *)a.e3 + ((size_t)h * nq2 + (e - 1 - q)) * n;
     }
-    double v64[MS_ROWS64_PER_WAVE];
-    E ve[MS_EROWS_PER_WAVE];
+    const double *srct = a.tau + hn;
+    const E *srcw = (const E *)a.w + hn;
+
+    double vt = 0.0, vr[NR] = {};
+    E vw = 0, ve[MS_E_PER_WAVE] = {};
     auto load_tile = [&](int tl) {
         if (tl >= ntiles) return;                // uniform: nothing past the last tile
         const int jc = min(tl * MS_TILE + lane, n - 1);
+        vt = srct[jc];
+        vw = srcw[jc];
 #pragma unroll
-        for (int k = 0; k < MS_ROWS64_PER_WAVE; ++k) v64[k] = src64[k][jc];
+        for (int k = 0; k < NR; ++k)
+            if (wave + 4 * k < p) vr[k] = srcr[k][jc];
 #pragma unroll
-        for (int k = 0; k < MS_EROWS_PER_WAVE; ++k) ve[k] = srce[k][jc];
+        for (int k = 0; k < MS_E_PER_WAVE; ++k)
+            if (wave + 4 * k < ne) ve[k] = srce[k][jc];
     };
-    load_tile(bx);
-    for (int tl = bx; tl < ntiles; tl += a.nblk) {
-        const bool in = tl * MS_TILE + lane < n;
+
+    double sr[NR] = {}, se[MS_E_PER_WAVE] = {}, s_tau = 0.0, s_tw = 0.0;
+    // product blocks of this thread group: blk, blk + NGRP; observations og, og + OGW, ...
+    const int blk = threadIdx.x / S::OGW, og = threadIdx.x % S::OGW;
+    const int na = (p + 3) / 4, nq = (q + 3) / 4, nb = na * (na + 1) / 2 + na * nq;
+    int aoff[S::NBT], boff[S::NBT];
 #pragma unroll
-        for (int k = 0; k < MS_ROWS64_PER_WAVE; ++k) {
-            const int row = wave + 4 * k;
-            if (row <= p) tile[row * MS_STRIDE + lane] = in ? v64[k] - off64[k] : 0.0;
+    for (int u = 0; u < S::NBT; ++u) {
+        int ab = 0, bbase = 0;
+        if (blk + S::NGRP * u < nb) ms_block(blk + S::NGRP * u, na, nq, S::AROWS, ab, bbase);
+        aoff[u] = ab * 4 * MS_STRIDE;
+        boff[u] = bbase * MS_STRIDE;
+    }
+    double acc[S::NBT][4][4] = {};
+
+    __syncthreads();
+    load_tile(bx);
+    int buf = 0;
+    for (int tl = bx; tl < ntiles; tl += a.nblk, buf ^= 1) {
+        double *A = lds + buf * S::BUF, *B = A + S::AROWS * MS_STRIDE;
+        const bool in = tl * MS_TILE + lane < n;
+        const double t = in ? vt : 0.0, w = in ? (double)vw : 0.0, tw = t * w;
+        if (wave == 0) { s_tau += t; s_tw += tw; }
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const int i = wave + 4 * k;
+            if (i < p) {
+                const double r = in ? vr[k] - offr[k] : 0.0, x = tw * r;
+                A[i * MS_STRIDE + lane] = r;
+                B[i * MS_STRIDE + lane] = x;
+                sr[k] += x;
+            }
         }
 #pragma unroll
-        for (int k = 0; k < MS_EROWS_PER_WAVE; ++k) {
+        for (int k = 0; k < MS_E_PER_WAVE; ++k) {
             const int e = wave + 4 * k;
-            if (e < ne) tile[(R.w + e) * MS_STRIDE + lane] = in ? (double)ve[k] : 0.0;
+            const double v = in ? (double)ve[k] : 0.0;
+            if (e == 0) {
+                se[k] += t * (v - w);
+            } else if (e <= q) {
+                const double x = t * v;
+                B[(S::AROWS + e - 1) * MS_STRIDE + lane] = x;
+                se[k] += x;
+            } else if (e < ne) {
+                se[k] += t * v;
+            }
         }
         __syncthreads();
         load_tile(tl + a.nblk);
-        // weight by tau: e2, e3 in place; tau w, tau (e1 - w), tau w r_i, ones as new rows
-        for (int e = threadIdx.x; e < (R.nrows - R.e20) * MS_TILE; e += blockDim.x) {
-            const int row = R.e20 + e / MS_TILE, o = e % MS_TILE;
-            const double t = tile[R.tau * MS_STRIDE + o], w = tile[R.w * MS_STRIDE + o];
-            double v;
-            if (row < R.tw) v = t * tile[row * MS_STRIDE + o];
-            else if (row == R.tw) v = t * w;
-            else if (row == R.te1w) v = t * (tile[R.e1 * MS_STRIDE + o] - w);
-            else if (row < R.one) v = t * w * tile[(R.r0 + row - R.twr0) * MS_STRIDE + o];
-            else v = 1.0;
-            tile[row * MS_STRIDE + o] = v;
+#pragma unroll
+        for (int u = 0; u < S::NBT; ++u) {
+            if (blk + S::NGRP * u >= nb) continue;
+            const double *Ab = A + aoff[u], *Bb = B + boff[u];
+#pragma unroll
+            for (int oo = 0; oo < MS_TILE / S::OGW; ++oo) {
+                const int o = og + S::OGW * oo;
+                double x[4], y[4];
+#pragma unroll
+                for (int ii = 0; ii < 4; ++ii) x[ii] = Ab[ii * MS_STRIDE + o];
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) y[jj] = Bb[jj * MS_STRIDE + o];
+#pragma unroll
+                for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) acc[u][ii][jj] += x[ii] * y[jj];
+            }
         }
-        __syncthreads();
-        if (s0 < NS) {
-            const double *t0 = tile + fa[0] * MS_STRIDE, *t1 = tile + fa[1] * MS_STRIDE;
-            double s = 0.0;
-            for (int o = 0; o < MS_TILE; ++o) s += t0[o] * t1[o];
-            acc0 += s;
-        }
-        if (s1 < NS) {
-            const double *t0 = tile + fb[0] * MS_STRIDE, *t1 = tile + fb[1] * MS_STRIDE;
-            double s = 0.0;
-            for (int o = 0; o < MS_TILE; ++o) s += t0[o] * t1[o];
-            acc1 += s;
-        }
-        __syncthreads();
     }
-    double *out = a.partial + ((size_t)h * a.nblk + bx) * NS;
-    if (s0 < NS) out[s0] = acc0;
-    if (s1 < NS) out[s1] = acc1;
+
+    // lane sums, then the block's partials
+    // partials are stat-major, [g][nstat][nblk], so the solve sums them coalesced
+    double *out = a.partial + (size_t)h * nstat(p, q) * a.nblk + bx;
+    const size_t ld = a.nblk;
+    s_tau = ms_lane_sum(s_tau, 64);
+    s_tw = ms_lane_sum(s_tw, 64);
+    if (wave == 0 && lane == 0) { out[0] = s_tau; out[ld] = s_tw; }
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        const double v = ms_lane_sum(sr[k], 64);
+        const int i = wave + 4 * k;
+        if (lane == 0 && i < p) out[(3 + i) * ld] = v;
+    }
+#pragma unroll
+    for (int k = 0; k < MS_E_PER_WAVE; ++k) {
+        const double v = ms_lane_sum(se[k], 64);
+        const int e = wave + 4 * k;
+        if (lane == 0 && e < ne) out[(e == 0 ? 2 : e <= q ? 3 + p + (e - 1) : ms_idx_e3(p, q, e - 1 - q)) * ld] = v;
+    }
+#pragma unroll
+    for (int u = 0; u < S::NBT; ++u)
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                const double v = ms_lane_sum(acc[u][ii][jj], S::OGW);   // over og
+                if (og != 0 || blk + S::NGRP * u >= nb) continue;
+                const int i = aoff[u] / MS_STRIDE + ii, c = boff[u] / MS_STRIDE + jj;
+                if (i >= p) continue;
+                if (c < S::AROWS) {
+                    // r_i . tau w r_c = statistic O1(c, i) when c <= i
+                    if (c <= i) out[ms_idx_o1(p, q, c, i) * ld] = v;
+                } else if (c - S::AROWS < q) {
+                    out[ms_idx_o2(p, q, i, c - S::AROWS) * ld] = v;
+                }
+            }
 }
 
+template <int NR>
 __device__ inline void mstep_reduce_body(const MstepArgs &a, int bx, int h, double *tile) {
-    if (a.mixed) mstep_reduce_prec<true>(a, bx, h, tile);
-    else mstep_reduce_prec<false>(a, bx, h, tile);
+    if (a.mixed) mstep_reduce_prec<true, NR>(a, bx, h, tile);
+    else mstep_reduce_prec<false, NR>(a, bx, h, tile);
 }
 
+template <int NR>
 __global__ __launch_bounds__(256) void k_mstep_reduce(MstepArgs a) {
     extern __shared__ double ms_tile[];
-    mstep_reduce_body(a, blockIdx.x, blockIdx.y, ms_tile);
+    mstep_reduce_body<NR>(a, blockIdx.x, blockIdx.y, ms_tile);
 }
 
 __device__ inline bool ms_chol(double *A, int n) {
@@ -210,10 +283,17 @@ __device__ inline void mstep_solve_body(const MsolveArgs &a, int32_t *cstat, int
     __shared__ double st[512];
     const int p = a.p, q = a.q;
     const int NS = nstat(p, q);
-    for (int s = threadIdx.x; s < NS; s += blockDim.x) {
-        double v = 0.0;
-        for (int b = 0; b < a.nblk; ++b) v += a.partial[((size_t)h * a.nblk + b) * NS + s];
-        st[s] = v;
+    // block partials of statistic s: one wave per statistic, lanes over blocks
+    // (coalesced), then a fixed butterfly, so the sum is reproducible
+    {
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+        for (int s = wave; s < NS; s += nw) {
+            const double *src = a.partial + ((size_t)h * NS + s) * a.nblk;
+            double v = 0.0;
+            for (int b = lane; b < a.nblk; b += 64) v += src[b];
+            v = ms_lane_sum(v, 64);
+            if (lane == 0) st[s] = v;
+        }
     }
     __syncthreads();
     __shared__ int s_mode;                       // 0 keep theta, 1 clamp, 2 root search
@@ -346,7 +426,8 @@ __global__ void k_mstep_status(const int32_t *__restrict__ cstat, int g, int32_t
 
 hipError_t launch_mstep(const MstepArgs &r, const MsolveArgs &s, hipStream_t st) {
     // always launched: with n = 0 it writes zero partials
-    hipLaunchKernelGGL(k_mstep_reduce, dim3(r.nblk, r.g), dim3(256), ms_lds_bytes(r.p, r.q), st, r);
+    if (ms_nr(r.p) == 2) hipLaunchKernelGGL(k_mstep_reduce<2>, dim3(r.nblk, r.g), dim3(256), ms_lds_bytes(r.p, r.q), st, r);
+    else hipLaunchKernelGGL(k_mstep_reduce<4>, dim3(r.nblk, r.g), dim3(256), ms_lds_bytes(r.p, r.q), st, r);
     int32_t *cstat = (int32_t *)(r.partial + (size_t)r.g * r.nblk * nstat(r.p, r.q));
     hipLaunchKernelGGL(k_mstep_solve, dim3(s.g), dim3(256), 0, st, s, cstat);
     if (s.status) hipLaunchKernelGGL(k_mstep_status, dim3(1), dim3(64), 0, st, cstat, s.g, s.status);
@@ -365,6 +446,7 @@ __device__ inline int mbatch_fit(const int *__restrict__ prefix, int nfits, int 
     return lo;
 }
 
+template <int NR>
 __global__ __launch_bounds__(256) void k_batch_mreduce(BatchArgs B) {
     const int *pf = B.prefix + BK_MRED * (B.nfits + 1);
     const int f = mbatch_fit(pf, B.nfits, blockIdx.x);
@@ -372,7 +454,7 @@ __global__ __launch_bounds__(256) void k_batch_mreduce(BatchArgs B) {
     const MstepArgs a = B.fits[f].ma;
     const int local = blockIdx.x - pf[f];
     extern __shared__ double ms_tile[];
-    mstep_reduce_body(a, local % a.nblk, local / a.nblk, ms_tile);
+    mstep_reduce_body<NR>(a, local % a.nblk, local / a.nblk, ms_tile);
 }
 
 __global__ __launch_bounds__(256) void k_batch_msolve(BatchArgs B) {
@@ -397,7 +479,9 @@ __global__ void k_batch_mstatus(BatchArgs B) {
 size_t mstep_lds_bytes(int p, int q) { return ms_lds_bytes(p, q); }
 
 hipError_t launch_batch_mstep(const BatchArgs &b, int nred, int nsol, size_t lds, hipStream_t s) {
-    if (nred > 0) hipLaunchKernelGGL(k_batch_mreduce, dim3(nred), dim3(256), lds, s, b);
+    // the larger reduction when any fit needs it (lds is the largest of the fits')
+    if (nred > 0 && lds <= ms_lds_bytes(8, 0)) hipLaunchKernelGGL(k_batch_mreduce<2>, dim3(nred), dim3(256), lds, s, b);
+    else if (nred > 0) hipLaunchKernelGGL(k_batch_mreduce<4>, dim3(nred), dim3(256), lds, s, b);
     if (nsol > 0) hipLaunchKernelGGL(k_batch_msolve, dim3(nsol), dim3(256), 0, s, b);
     if (b.nfits > 0) hipLaunchKernelGGL(k_batch_mstatus, dim3(b.nfits), dim3(64), 0, s, b);
     return hipGetLastError();

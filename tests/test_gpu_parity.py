@@ -181,17 +181,39 @@ def test_loglik_matches_estep_and_oracle(lib, orc):
 
 # ------------------------------------------------------------------- M-step --
 
-@pytest.mark.parametrize("p,q,g,n,seed", [(2, 2, 2, 300, 11), (4, 4, 3, 200, 12), (5, 3, 2, 130, 13)])
+def _point_mass_estep(rng, P, n):
+    """E-step outputs of posteriors that are point masses at drawn latent values
+    (a valid input to eqs. 18-22, and far cheaper than the oracle E-step at
+    q = 8): tau from a Dirichlet, w ~ Gamma(nu/2, rate nu/2), u >= 0
+    half-normal; w, e1 = log w, e2 = w u, e3 = w u u^T (upper triangle, row by
+    row)."""
+    from types import SimpleNamespace
+    g, q = P.g, P.q
+    tau = rng.dirichlet(np.ones(g), size=n).T.copy()
+    w = np.stack([rng.gamma(P.nu[h] / 2.0, 2.0 / P.nu[h], size=n) for h in range(g)])
+    u = np.abs(rng.standard_normal((g, q, n)))
+    iu = [(i, k) for i in range(q) for k in range(i, q)]
+    e3 = np.stack([np.stack([w[h] * u[h, i] * u[h, k] for (i, k) in iu]) for h in range(g)])
+    return SimpleNamespace(tau=tau, w=w, e1=np.log(w), e2=w[:, None, :] * u, e3=e3, logf_obs=np.zeros(n))
+
+
+@pytest.mark.parametrize("p,q,g,n,seed", [(2, 2, 2, 300, 11), (4, 4, 3, 200, 12), (5, 3, 2, 130, 13),
+                                          (8, 8, 2, 3000, 14), (12, 5, 2, 700, 15), (16, 8, 2, 300, 16)])
 @pytest.mark.parametrize("mode", ["fp64", "mixed"])
 def test_mstep_vs_oracle(lib, orc, p, q, g, n, seed, mode):
     """Same E-step outputs into both M-steps (in mixed mode the e-terms are the
-    FP32 roundings the GPU path stores)."""
+    FP32 roundings the GPU path stores).  The shapes cover both sizes of the
+    reduction (p <= 8, p <= 16), the largest p and q, and many tiles per block
+    with a ragged last tile."""
     cf = lib
+    print(f"mstep vs oracle p={p} q={q} g={g} n={n} {mode}", flush=True)
     rng = np.random.default_rng(seed)
     P = draw_params(rng, p, q, g, sigma="aat")
     y, _ = sample_hierarchy(rng, P, n)
-    des = make_design(256, 4, seed=seed)
-    es = orc.estep(y, P, des)
+    if p <= 5:
+        es = orc.estep(y, P, make_design(256, 4, seed=seed))
+    else:
+        es = _point_mass_estep(rng, P, n)
     if mode == "mixed":
         for name in ("w", "e1", "e2", "e3"):
             setattr(es, name, getattr(es, name).astype(np.float32).astype(np.float64))
