@@ -273,8 +273,8 @@ cfust_status cfust_mstep(cfust_handle h, const double *y, cfust_dims d, const cf
         return fail(h, CFUST_EINVAL, "precision %d is neither CFUST_FP64 nor CFUST_MIXED", precision);
     if (d.n > 0 && (!y || !es || !es->tau || !es->w || !es->e1 || !es->e2 || !es->e3))
         return fail(h, CFUST_EINVAL, "y or an E-step array is NULL");
-    const int nblk = mstep_nblk(d);
-    if ((st = ensure_ws(h, mstep_bytes(d))) != CFUST_OK) return st;
+    const int nblk = mstep_nblk(d, h->ncu);
+    if ((st = ensure_ws(h, mstep_bytes(d, h->ncu))) != CFUST_OK) return st;
     if ((st = hip_check(h, hipSetDevice(h->device), "hipSetDevice")) != CFUST_OK) return st;
     MstepArgs r;
     r.y = y; r.tau = es ? es->tau : nullptr;
@@ -475,7 +475,7 @@ cfust_status cfust_reserve(cfust_handle h, cfust_dims d, const cfust_qmc *qmc) {
     if ((st = check_dims(h, d)) != CFUST_OK) return st;
     (void)qmc;
     size_t need = estep_layout(d, nint_qmc(d.q), true).total;
-    const size_t ms = mstep_bytes(d);
+    const size_t ms = mstep_bytes(d, h->ncu);
     if (ms > need) need = ms;
     if ((st = hip_check(h, hipSetDevice(h->device), "hipSetDevice")) != CFUST_OK) return st;
     return ensure_ws(h, need);

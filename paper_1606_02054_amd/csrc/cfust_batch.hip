@@ -278,7 +278,7 @@ cfust_status cfust_batch_create(cfust_handle h, int32_t nfits, const cfust_fit *
         fo[f].lnA = c.take<double>((size_t)d.g * n1);
         fo[f].logf = c.take<double>(fits[f].out.logf_comp ? 1 : (size_t)d.g * n1);
         fo[f].lse = c.take<double>((size_t)(d.n + 255) / 256 + 1);
-        fo[f].mpart = c.take<double>(dn ? 1 : (size_t)d.g * mstep_nblk(d) * nstat(d.p, d.q));
+        fo[f].mpart = c.take<double>(dn ? 1 : (size_t)d.g * mstep_nblk(d, h->ncu) * nstat(d.p, d.q));
         fo[f].cstat = c.take<int32_t>(d.g);
     }
     const size_t o_fits = c.take<FitDesc>(nfits);
@@ -328,7 +328,7 @@ cfust_status cfust_batch_create(cfust_handle h, int32_t nfits, const cfust_fit *
         float *tabs = bat<float>(b, fo[f].tabs);
         double *est = bat<double>(b, fo[f].est), *lnA = bat<double>(b, fo[f].lnA);
         double *lfc = F.out.logf_comp ? F.out.logf_comp : bat<double>(b, fo[f].logf);
-        const int nblk = mstep_nblk(d);
+        const int nblk = mstep_nblk(d, b->h->ncu);
         if (!dn) b->mred_lds = std::max(b->mred_lds, mstep_lds_bytes(d.p, d.q));
         D.g = d.g;
         D.pc.pi = F.params.pi; D.pc.Sigma = F.params.Sigma; D.pc.Delta = F.params.Delta; D.pc.nu = F.params.nu;

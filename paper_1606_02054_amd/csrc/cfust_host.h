@@ -127,16 +127,21 @@ inline cfust_status check_params(cfust_handle h, const cfust_params *P) {
 // M-step reduction blocks per component: about 16 tiles of 64 observations
 // each, at most 1024 (the partition fixes the summation order, so it depends
 // on n only).
-inline int mstep_nblk(const cfust_dims &d) {
+// Blocks per component of the M-step reduction: about three resident blocks
+// per compute unit over the g components (a grid-stride loop over the tiles
+// balances them), never more than one per tile.  Few blocks keep the block
+// partials, which the solve sums per statistic, short.
+inline int mstep_nblk(const cfust_dims &d, int ncu) {
     const int ntiles = (d.n + 63) / 64;
-    int nb = (ntiles + 15) / 16;
+    const int want = (3 * (ncu > 0 ? ncu : 256) + d.g - 1) / (d.g > 0 ? d.g : 1);
+    int nb = ntiles < want ? ntiles : want;
     if (nb < 1) nb = 1;
     if (nb > 1024) nb = 1024;
     return nb;
 }
 
-inline size_t mstep_bytes(const cfust_dims &d) {
-    return align256((size_t)d.g * mstep_nblk(d) * nstat(d.p, d.q) * sizeof(double) + (size_t)d.g * sizeof(int32_t));
+inline size_t mstep_bytes(const cfust_dims &d, int ncu) {
+    return align256((size_t)d.g * mstep_nblk(d, ncu) * nstat(d.p, d.q) * sizeof(double) + (size_t)d.g * sizeof(int32_t));
 }
 
 // Lattice points per lane chosen by the autotuner for (m, N, S, precision).

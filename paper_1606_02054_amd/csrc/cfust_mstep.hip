@@ -278,138 +278,153 @@ __device__ inline double ms_nu_eq(double v, double m) {
     return log(0.5 * v) - dm_digamma(0.5 * v) + 1.0 + m;
 }
 
-// Component h of one fit.
+// Component h of one fit, by one block: the sums of the block partials, then
+// eqs. (18)-(22).  The matrices live in LDS; each step runs one thread per
+// output entry, the two small Cholesky factorisations (q x q and the p x p
+// positivity check) on one thread.
 __device__ inline void mstep_solve_body(const MsolveArgs &a, int32_t *cstat, int h) {
     __shared__ double st[512];
-    const int p = a.p, q = a.q;
+    __shared__ double dl[MAXP], X[MAXP * MAXQ], E3[MAXQ * MAXQ], Lc[MAXQ * MAXQ], Dnew[MAXP * MAXQ];
+    __shared__ double DE3[MAXP * MAXQ], Snew[MAXP * MAXP], Ls[MAXP * MAXP];
+    __shared__ int s_keep, s_status, s_mode;     // s_mode: 0 keep theta, 1 clamp, 2 root search
+    __shared__ double s_m, s_lo, s_hi, s_nu;
+    __shared__ unsigned long long s_mask[4];
+    const int p = a.p, q = a.q, tid = threadIdx.x, nt = blockDim.x;
     const int NS = nstat(p, q);
     // block partials of statistic s: one wave per statistic, lanes over blocks
     // (coalesced), then a fixed butterfly, so the sum is reproducible
     {
-        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+        const int wave = tid >> 6, lane = tid & 63, nw = nt >> 6;
         for (int s = wave; s < NS; s += nw) {
             const double *src = a.partial + ((size_t)h * NS + s) * a.nblk;
             double v = 0.0;
+#pragma unroll 4
             for (int b = lane; b < a.nblk; b += 64) v += src[b];
             v = ms_lane_sum(v, 64);
             if (lane == 0) st[s] = v;
         }
     }
     __syncthreads();
-    __shared__ int s_mode;                       // 0 keep theta, 1 clamp, 2 root search
-    __shared__ double s_m, s_lo, s_hi;
-    __shared__ unsigned long long s_mask[4];
-    int status = 0;
-    double mu[MAXP], Sg[MAXP * MAXP], Dn[MAXP * MAXQ], nu = a.nu0[h];
-    if (threadIdx.x == 0) {
     const double nh = st[0], Sw = st[1], Sew = st[2];
     const double *Swr = st + 3, *Se2 = st + 3 + p, *Swrr = st + 3 + p + q;
     const double *Sre2 = Swrr + p * (p + 1) / 2, *Se3 = Sre2 + p * q;
     const double *mu0 = a.mu0 + (size_t)h * p, *S0 = a.Sigma0 + (size_t)h * p * p;
     const double *D0 = a.Delta0 + (size_t)h * p * q;
-    for (int i = 0; i < p; ++i) mu[i] = mu0[i];
-    for (int i = 0; i < p * p; ++i) Sg[i] = S0[i];
-    for (int i = 0; i < p * q; ++i) Dn[i] = D0[i];
-    a.pi1[h] = a.n > 0 ? nh / a.n : 0.0;                               // (18)
-    bool keep = false;
-    if (!(nh >= p + 1.0)) { status |= CFUST_DEV_FROZEN; keep = true; }
-    double dl[MAXP], X[MAXP * MAXQ], E3[MAXQ * MAXQ], Lc[MAXQ * MAXQ], Dnew[MAXP * MAXQ], Snew[MAXP * MAXP];
-    if (!keep) {
-        for (int i = 0; i < p; ++i) {                                  // (19), Delta^(k)
-            double s = Swr[i];
-            for (int l = 0; l < q; ++l) s -= D0[i * q + l] * Se2[l];
-            dl[i] = s / Sw;
-        }
-        for (int i = 0; i < p; ++i)                                    // sum tau (y - mu1) e2^T
-            for (int l = 0; l < q; ++l) X[i * q + l] = Sre2[i * q + l] - dl[i] * Se2[l];
-        int t = 0;
-        for (int i = 0; i < q; ++i)
-            for (int k = i; k < q; ++k, ++t) E3[i * q + k] = E3[k * q + i] = Se3[t];
-        for (int i = 0; i < q * q; ++i) Lc[i] = E3[i];
-        if (!ms_chol(Lc, q)) { status |= CFUST_DEV_NOTSPD_E3; keep = true; }
-        if (!keep) {
-            for (int i = 0; i < p; ++i) {                              // (20): Delta E3 = X
-                double z[MAXQ];
-                for (int l = 0; l < q; ++l) {
-                    double s = X[i * q + l];
-                    for (int k = 0; k < l; ++k) s -= Lc[l * q + k] * z[k];
-                    z[l] = s / Lc[l * q + l];
-                }
-                for (int l = q - 1; l >= 0; --l) {
-                    double s = z[l];
-                    for (int k = l + 1; k < q; ++k) s -= Lc[k * q + l] * z[k];
-                    z[l] = s / Lc[l * q + l];
-                }
-                for (int l = 0; l < q; ++l) Dnew[i * q + l] = z[l];
-            }
-            // (21) with mu^(k+1), Delta^(k+1)
-            double DE3[MAXP * MAXQ];
-            for (int i = 0; i < p; ++i)
-                for (int l = 0; l < q; ++l) {
-                    double s = 0.0;
-                    for (int k = 0; k < q; ++k) s += Dnew[i * q + k] * E3[k * q + l];
-                    DE3[i * q + l] = s;
-                }
-            for (int i = 0; i < p; ++i)
-                for (int k = i; k < p; ++k) {
-                    const int ik = i * p - i * (i - 1) / 2 + (k - i);
-                    double Wik = Swrr[ik] - dl[i] * Swr[k] - Swr[i] * dl[k] + Sw * dl[i] * dl[k];
-                    double cross = 0.0, quad = 0.0;
-                    for (int l = 0; l < q; ++l) {
-                        cross += Dnew[i * q + l] * X[k * q + l] + X[i * q + l] * Dnew[k * q + l];
-                        quad += DE3[i * q + l] * Dnew[k * q + l];
-                    }
-                    const double v = (Wik - cross + quad) / nh;
-                    Snew[i * p + k] = v;
-                    Snew[k * p + i] = v;
-                }
-            double Ls[MAXP * MAXP];
-            for (int i = 0; i < p * p; ++i) Ls[i] = Snew[i];
-            if (!ms_chol(Ls, p)) { status |= CFUST_DEV_NOTSPD_SIGMA; keep = true; }
-        }
+    if (tid == 0) {
+        a.pi1[h] = a.n > 0 ? nh / a.n : 0.0;                           // (18)
+        const bool frozen = !(nh >= p + 1.0);
+        s_keep = frozen;
+        s_status = frozen ? CFUST_DEV_FROZEN : 0;
+        s_mode = 0;
     }
-    s_mode = 0;
-    if (!keep) {
-        for (int i = 0; i < p; ++i) mu[i] = mu0[i] + dl[i];
-        for (int i = 0; i < p * q; ++i) Dn[i] = Dnew[i];
-        for (int i = 0; i < p * p; ++i) Sg[i] = Snew[i];
+    for (int i = tid; i < p; i += nt) {                                // (19), Delta^(k)
+        double v = Swr[i];
+        for (int l = 0; l < q; ++l) v -= D0[i * q + l] * Se2[l];
+        dl[i] = v / Sw;
+    }
+    for (int t = tid; t < q * q; t += nt) {                            // E3 from its upper triangle
+        const int i = min(t / q, t % q), k = max(t / q, t % q);
+        const double v = Se3[i * q - i * (i - 1) / 2 + (k - i)];
+        E3[t] = v;
+        Lc[t] = v;
+    }
+    __syncthreads();
+    for (int t = tid; t < p * q; t += nt) {                            // sum tau (y - mu1) e2^T
+        const int i = t / q, l = t % q;
+        X[t] = Sre2[t] - dl[i] * Se2[l];
+    }
+    if (tid == 0 && !s_keep && !ms_chol(Lc, q)) { s_status |= CFUST_DEV_NOTSPD_E3; s_keep = 1; }
+    __syncthreads();
+    if (!s_keep) {
+        for (int i = tid; i < p; i += nt) {                            // (20): Delta E3 = X, row i
+            double z[MAXQ];                      // unrolled to MAXQ: z stays in registers
+#pragma unroll
+            for (int l = 0; l < MAXQ; ++l) {
+                if (l >= q) break;
+                double v = X[i * q + l];
+#pragma unroll
+                for (int k = 0; k < l; ++k) v -= Lc[l * q + k] * z[k];
+                z[l] = v / Lc[l * q + l];
+            }
+#pragma unroll
+            for (int l = MAXQ - 1; l >= 0; --l) {
+                if (l >= q) continue;
+                double v = z[l];
+#pragma unroll
+                for (int k = l + 1; k < MAXQ; ++k)
+                    if (k < q) v -= Lc[k * q + l] * z[k];
+                z[l] = v / Lc[l * q + l];
+            }
+#pragma unroll
+            for (int l = 0; l < MAXQ; ++l)
+                if (l < q) Dnew[i * q + l] = z[l];
+        }
+        __syncthreads();
+        for (int t = tid; t < p * q; t += nt) {                        // Delta^(k+1) E3
+            const int i = t / q, l = t % q;
+            double v = 0.0;
+            for (int k = 0; k < q; ++k) v += Dnew[i * q + k] * E3[k * q + l];
+            DE3[t] = v;
+        }
+        __syncthreads();
+        for (int t = tid; t < p * p; t += nt) {                        // (21) with mu^(k+1), Delta^(k+1)
+            const int i = min(t / p, t % p), k = max(t / p, t % p);
+            const int ik = i * p - i * (i - 1) / 2 + (k - i);
+            const double Wik = Swrr[ik] - dl[i] * Swr[k] - Swr[i] * dl[k] + Sw * dl[i] * dl[k];
+            double cross = 0.0, quad = 0.0;
+            for (int l = 0; l < q; ++l) {
+                cross += Dnew[i * q + l] * X[k * q + l] + X[i * q + l] * Dnew[k * q + l];
+                quad += DE3[i * q + l] * Dnew[k * q + l];
+            }
+            Snew[t] = (Wik - cross + quad) / nh;
+        }
+        __syncthreads();
+        for (int t = tid; t < p * p; t += nt) Ls[t] = Snew[t];
+        __syncthreads();
+        if (tid == 0 && !ms_chol(Ls, p)) { s_status |= CFUST_DEV_NOTSPD_SIGMA; s_keep = 1; }
+        __syncthreads();
+    }
+    if (tid == 0 && !s_keep) {
         const double m = Sew / nh;                                     // (22)
         s_m = m;
         s_lo = 1.0; s_hi = 200.0;
         s_mode = 2;
-        if (ms_nu_eq(1.0, m) <= 0.0) { nu = 1.0; s_mode = 1; status |= CFUST_DEV_NU_CLAMPED; }
-        else if (ms_nu_eq(200.0, m) >= 0.0) { nu = 200.0; s_mode = 1; status |= CFUST_DEV_NU_CLAMPED; }
-    }
+        if (ms_nu_eq(1.0, m) <= 0.0) { s_nu = 1.0; s_mode = 1; s_status |= CFUST_DEV_NU_CLAMPED; }
+        else if (ms_nu_eq(200.0, m) >= 0.0) { s_nu = 200.0; s_mode = 1; s_status |= CFUST_DEV_NU_CLAMPED; }
     }
     __syncthreads();
     if (s_mode == 2) {
         // eq. (22) decreases in nu: multisection of [lo, hi] by the block, each
         // round evaluating it at blockDim.x interior points and keeping the
         // interval of the first sign change (257-fold shrink per round)
-        const double m = s_m, np1 = blockDim.x + 1.0;
+        const double m = s_m, np1 = nt + 1.0;
         for (int round = 0; round < 8; ++round) {
             const double lo = s_lo, hi = s_hi;
-            const double x = lo + (hi - lo) * (threadIdx.x + 1) / np1;
+            const double x = lo + (hi - lo) * (tid + 1) / np1;
             const unsigned long long bal = __ballot(ms_nu_eq(x, m) <= 0.0);
-            if ((threadIdx.x & 63) == 0) s_mask[threadIdx.x >> 6] = bal;
+            if ((tid & 63) == 0) s_mask[tid >> 6] = bal;
             __syncthreads();
-            if (threadIdx.x == 0) {
-                int first = blockDim.x;
-                for (int w = 0; w < (int)(blockDim.x >> 6); ++w)
+            if (tid == 0) {
+                int first = nt;
+                for (int w = 0; w < (nt >> 6); ++w)
                     if (s_mask[w]) { first = w * 64 + __ffsll(s_mask[w]) - 1; break; }
                 s_lo = lo + (hi - lo) * first / np1;
-                s_hi = first == (int)blockDim.x ? hi : lo + (hi - lo) * (first + 1) / np1;
+                s_hi = first == nt ? hi : lo + (hi - lo) * (first + 1) / np1;
             }
             __syncthreads();
         }
-        nu = 0.5 * (s_lo + s_hi);
+        if (tid == 0) s_nu = 0.5 * (s_lo + s_hi);
+        __syncthreads();
     }
-    if (threadIdx.x != 0) return;
-    for (int i = 0; i < p; ++i) a.mu1[(size_t)h * p + i] = mu[i];
-    for (int i = 0; i < p * q; ++i) a.Delta1[(size_t)h * p * q + i] = Dn[i];
-    for (int i = 0; i < p * p; ++i) a.Sigma1[(size_t)h * p * p + i] = Sg[i];
-    a.nu1[h] = nu;
-    cstat[h] = status;
+    // outputs: the updates, or theta^(k) where the update was refused
+    const bool keep = s_keep;
+    for (int i = tid; i < p; i += nt) a.mu1[(size_t)h * p + i] = keep ? mu0[i] : mu0[i] + dl[i];
+    for (int i = tid; i < p * q; i += nt) a.Delta1[(size_t)h * p * q + i] = keep ? D0[i] : Dnew[i];
+    for (int i = tid; i < p * p; i += nt) a.Sigma1[(size_t)h * p * p + i] = keep ? S0[i] : Snew[i];
+    if (tid == 0) {
+        a.nu1[h] = s_mode == 0 ? a.nu0[h] : s_nu;
+        cstat[h] = s_status;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_mstep_solve(MsolveArgs a, int32_t *cstat) {
