@@ -41,8 +41,8 @@ FLOPS_QUANTILE = 29          # quantile draw y_i
 # kernel sources with this digest only; otherwise the figure is reported null.
 TRAFFIC_SOURCES = ["paper_1606_02054_amd/csrc/cfust_sov.h", "paper_1606_02054_amd/csrc/cfust_devmath.h",
                    "paper_1606_02054_amd/csrc/cfust_estep.hip"]
-TRAFFIC_DIGEST = "29ac73d40971f146"
-TRAFFIC_MIB = {"read": 3.38 + 2.97 + 2.97, "write": 2.44 + 3.66 + 5.49}
+TRAFFIC_DIGEST = "a5746a8e5d75c456"
+TRAFFIC_MIB = {"read": 3.22 + 2.72 + 2.73, "write": 4.44 + 5.66 + 7.50}
 
 
 def kernel_digest() -> str:
@@ -407,6 +407,8 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate-vs-lattice comparison")
     ap.add_argument("--no-components", action="store_true",
                     help="skip the M-step and network roofline figures")
+    ap.add_argument("--components-only", action="store_true",
+                    help="run only the M-step and network roofline figures (one JSON line)")
     ap.add_argument("--n", type=int, default=0, help="observations (0: the workload's own n)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a known-size "
@@ -433,6 +435,10 @@ def main():
 
     if args.workload == "batched_fit":
         print(json.dumps(batched_main(args)), flush=True)
+        return
+    if args.components_only:
+        cf.default_handle(0)
+        print(json.dumps({"components": component_rooflines(cf, torch.device("cuda:0"))}), flush=True)
         return
 
     ds = workload(args.workload, **({"n": args.n} if args.n else {}))

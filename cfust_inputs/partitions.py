@@ -1,10 +1,10 @@
 """Seeded starting partitions of a data set for the restarts of the
-initialisation (Sec. 3.3, Algorithm 1: "generate a new partition of the
-data").  They are inputs of the initialiser on both sides, like the lattice
+initialisation (Sec. 3.3, Algorithm 1, which draws a fresh partition of the
+data for every start).  They are inputs of the initialiser on both sides, like the lattice
 design; how a partition is found is not part of the CFUST method.
 
   random_partitions  uniform labels in [0, g)
-  kmeans_partitions  Lloyd's k-means from k-means++ seeds (one per start)
+  kmeans_partitions  Lloyd's k-means from k-means++ seeds (one per start), at most `iters` rounds
 """
 from __future__ import annotations
 
