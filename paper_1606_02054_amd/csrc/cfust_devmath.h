@@ -146,7 +146,6 @@ __device__ inline double dm_tcdf(double x, double v) {
 __device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float flog2(float x) { return __builtin_amdgcn_logf(x); }
 __device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 __device__ __forceinline__ float tab_poly(const float *row, float x) {
     const float4 lo = *reinterpret_cast<const float4 *>(row);
@@ -161,18 +160,23 @@ __device__ __forceinline__ float tab_poly(const float *row, float x) {
     return r;
 }
 
-// F(tau) from the CDF rows of one dof's table; tau in [0, 1] (anything else,
-// NaN included, is clamped into the table so the index stays in range).
-__device__ __forceinline__ float tab_cdf_F(const float *tab, float tau) {
-    const float pos = fminf(fmaxf(tau * 8.0f, 0.0f), 8.0f);
-    const int k = min((int)pos, TAB_CDF_ROWS - 1);
-    const float x = fmaf(2.0f, pos - (float)k, -1.0f);
+// H(tau) = log2 T_lower - (nu/2) log2(tau (2 - tau)) from the CDF rows of one
+// dof's table, at pos = 8 tau in [0, 8) (8 equal intervals of tau = 1 - |s|).
+// Anything outside, NaN included, is clamped into the table so the index
+// stays in range; the position within the interval is the fraction of pos.
+__device__ __forceinline__ float tab_cdf_H(const float *tab, float pos) {
+    pos = fminf(fmaxf(pos, 0.0f), 7.99999952f);
+    const int k = (int)pos;
+    const float x = fmaf(2.0f, __builtin_amdgcn_fractf(pos), -1.0f);
     return tab_poly(tab + 8 * k, x);
 }
 
-// log2 tau from the quantile rows; lam = -log2(2p) >= 0.
-__device__ __forceinline__ float tab_inv_G(const float *tab, float lam) {
-    const float zz = fminf(fmaxf(lam, 0.0f), INV_LAMBDA_MAX) + 0.25f;
+// log2 tau from the quantile rows, given l2p = log2 p of the tail probability
+// p <= 1/2; the table variable is lam = -log2(2p) = -1 - l2p, clamped to
+// [0, INV_LAMBDA_MAX] and offset by 1/4 (both folded into one clamp of
+// -3/4 - l2p).
+__device__ __forceinline__ float tab_inv_G(const float *tab, float l2p) {
+    const float zz = fminf(fmaxf(-0.75f - l2p, 0.25f), INV_LAMBDA_MAX + 0.25f);
     const int e = __builtin_amdgcn_frexp_expf(zz);     // zz = mant 2^e, mant in [0.5, 1)
     const float mant = __builtin_amdgcn_frexp_mantf(zz);
     const int k = e + 1;                               // interval 0..10

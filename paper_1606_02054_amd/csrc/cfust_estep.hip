@@ -208,7 +208,7 @@ __device__ inline double table_node_value(double nu, int row, int n) {
         const double tau = (row + 0.5 * (x + 1.0)) / 8.0;
         const double s = 1.0 - tau;
         const double lt = dm_lnT_lower(tau * (2.0 - tau), s * s, a, lb);
-        return lt / LN2 - a * log2(tau);
+        return lt / LN2 - a * log2(tau * (2.0 - tau));
     }
     const int k = row - TAB_CDF_ROWS;
     const double w = 0.25 * (double)(1 << k);

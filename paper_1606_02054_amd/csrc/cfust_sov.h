@@ -125,7 +125,7 @@ __device__ __forceinline__ float quantile_step32(float x, float xb, float e, flo
     const bool lower = lowt || p <= 0.5f;
     const float arg = lowt ? x : (lower ? p : pb);
     const float l2q = flog2(arg) + (lowt ? l2e : 0.0f);
-    const float G = fmaxf(tab_inv_G(tab, -1.0f - l2q), -100.0f);
+    const float G = fmaxf(tab_inv_G(tab, l2q), -100.0f);
     const float tq = fexp2(G);
     const float sabs = 1.0f - tq;
     Q = fminf(Q * frsq(tq * (2.0f - tq)), 1e15f);
@@ -156,12 +156,14 @@ __device__ __forceinline__ float sov_point32(const Sov32Setup &P, const float *t
         float num = P.b[i];
 #pragma unroll
         for (int j = 0; j < i; ++j) num = fmaf(-P.L[i * M + j], y[j], num);
+        // lower-tail probability of the conditional t: with s = num / sqrt(num^2 + K),
+        // log2 T_lower = a log2(1 - s^2) + H(1 - |s|), and 1 - s^2 = K R^2 needs no division
         const float LQ = P.L[i * M + i] * Q;
         const float K = LQ * LQ;
         const float R = frsq(fmaf(num, num, K));
-        const float tau = K * R * R * frcp(fmaf(fabsf(num), R, 1.0f));
+        const float KR2 = K * R * R;
         const float *tab = tabs + i * TAB_FLOATS;
-        const float l2 = fmaf(P.a[i], flog2(tau), tab_cdf_F(tab, tau));
+        const float l2 = fmaf(P.a[i], flog2(KR2), tab_cdf_H(tab, fmaf(-8.0f, fabsf(num) * R, 8.0f)));
         const float small = fexp2(l2);
         const bool lowt = num <= 0.0f;
         const float e = lowt ? small : 1.0f - small;
@@ -219,15 +221,15 @@ __device__ inline SovHead sov_head(const double *b, const double *L, double nu) 
 }
 
 // The same first factor from the FP32 table of dof nu (mixed precision): the
-// table gives F(tau) = log2 T_lower - (nu/2) log2 tau with tau = 1 - |s|,
-// s = u / sqrt(nu + u^2), u = b_0 / L_00.  tau and log2 tau are formed in
-// FP64, so no range is lost; only F carries the table's FP32 accuracy.
+// table gives H(tau) = log2 T_lower - (nu/2) log2(tau (2 - tau)) with
+// tau = 1 - |s|, s = u / sqrt(nu + u^2), u = b_0 / L_00.  tau and the log are
+// formed in FP64, so no range is lost; only H carries the table's FP32 accuracy.
 __device__ inline SovHead sov_head_tab(const double *b, const double *L, double nu, const float *tab) {
     const double u = b[0] / L[0];
     const double au = fabs(u);
     const double r = au > 1.0 ? au * sqrt(1.0 + (nu / au) / au) : sqrt(nu + u * u);
     const double tau = nu / (r * (r + au));
-    const double l2 = 0.5 * nu * log2(tau) + (double)tab_cdf_F(tab, (float)tau);
+    const double l2 = 0.5 * nu * log2(tau * (2.0 - tau)) + (double)tab_cdf_H(tab, (float)(8.0 * tau));
     const double lt0 = l2 * LN2;
     const double small0 = exp(lt0);
     SovHead H;
