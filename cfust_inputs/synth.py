@@ -110,7 +110,8 @@ def sample_hierarchy(rng: np.random.Generator, params: Params, n: int):
         if m == 0:
             continue
         nu = params.nu[h]
-        w = rng.gamma(shape=nu / 2.0, scale=2.0 / nu, size=m)
+        # W ~ Gamma(nu/2, rate nu/2); nu = infinity (the normal limit) is W = 1
+        w = np.ones(m) if np.isinf(nu) else rng.gamma(shape=nu / 2.0, scale=2.0 / nu, size=m)
         u = np.abs(rng.standard_normal((m, q))) / np.sqrt(w)[:, None]
         L = np.linalg.cholesky(params.Sigma[h])
         e = (rng.standard_normal((m, p)) @ L.T) / np.sqrt(w)[:, None]

@@ -25,6 +25,11 @@
  *   - the truncated-t moments use the first/second moment identities obtained
  *     by integrating the gradient of the t kernel (they need T_{m-1} with dof
  *     nu-1 and T_{m-2} with dof nu-2), written recursively on dense matrices.
+ * The normal limit of Table 1 (CFUSN: nu -> infinity) is nu = +INFINITY for a
+ * component: every t law becomes the normal one (CDF 0.5 erfc(-x/sqrt 2) from
+ * the C library, its quantile by the same safeguarded Newton iteration), each
+ * dof ratio (nu+a)/(nu+b) becomes 1, W is 1 (w = 1, e1 = E[log W] = 0), and
+ * the M-step keeps nu.
  * Special functions come from published mathematics: the continued fraction
  * for the regularised incomplete beta (DLMF 8.17.22, modified Lentz), the
  * asymptotic series of the digamma function (DLMF 5.11.2) with upward
@@ -113,6 +118,7 @@ double or_tcdf(double t, double nu)
 {
     if (isnan(t)) return t;
     if (isinf(t)) return t > 0 ? 1.0 : 0.0;
+    if (isinf(nu)) return 0.5 * erfc(-t / M_SQRT2);   /* normal limit */
     double z, zc, lz, lzc;            /* z = nu/(nu+t^2), zc = t^2/(nu+t^2) */
     double at = fabs(t);
     if (at > 1.0) {
@@ -132,8 +138,15 @@ double or_tcdf(double t, double nu)
 /* Univariate t density with scale parameter s (variance-like) and dof nu. */
 double or_t1pdf(double x, double s, double nu)
 {
+    if (isinf(nu)) return exp(-0.5 * x * x / s) / sqrt(2.0 * M_PI * s);   /* normal limit */
     return exp(lgamma(0.5 * (nu + 1.0)) - lgamma(0.5 * nu) - 0.5 * log(M_PI * nu * s)
                - 0.5 * (nu + 1.0) * log1p(x * x / (nu * s)));
+}
+
+/* (nu + a) / (nu + b), with its limit 1 at nu = infinity. */
+static double or_ratio(double nu, double a, double b)
+{
+    return isinf(nu) ? 1.0 : (nu + a) / (nu + b);
 }
 
 /* t quantile: solve T_nu(y) = p.  Works on the lower half (p <= 1/2) and
@@ -251,7 +264,7 @@ double or_mvt(int m, const double *b, const double *L, double nu, const or_qmc *
             y[0] = or_tinv(or_point(Q, s, k, 0) * e0, nu);
             double s2 = y[0] * y[0];
             for (int i = 1; i < m; ++i) {
-                double sc = sqrt((nu + s2) / (nu + i));
+                double sc = sqrt(or_ratio(nu, s2, i));
                 double num = b[i];
                 for (int j = 0; j < i; ++j) num -= L[i * m + j] * y[j];
                 double e = or_tcdf(num / (L[i * m + i] * sc), nu + i);
@@ -300,7 +313,7 @@ void or_mvt_mom(int m, const double *b, const double *L, double nu, const or_qmc
             y[0] = or_tinv(or_point(Q, s, k, 0) * e0, nu);
             double s2 = y[0] * y[0];
             for (int i = 1; i < m && f > 0.0; ++i) {
-                double sc = sqrt((nu + s2) / (nu + i));
+                double sc = sqrt(or_ratio(nu, s2, i));
                 double num = b[i];
                 for (int j = 0; j < i; ++j) num -= L[i * m + j] * y[j];
                 double e = or_tcdf(num / (L[i * m + i] * sc), nu + i);
@@ -361,7 +374,7 @@ typedef struct {
 static void or_condition(int m, const double *a, const double *R, double nu, int i, or_cond *c)
 {
     double Rii = R[i * m + i];
-    c->kappa = (nu + a[i] * a[i] / Rii) / (nu - 1.0);
+    c->kappa = or_ratio(nu, a[i] * a[i] / Rii, -1.0);
     c->t1 = or_t1pdf(a[i], Rii, nu);
     int r = 0;
     for (int k = 0; k < m; ++k) {
@@ -400,7 +413,8 @@ void or_tmoments(int m, const double *a, const double *R, double nu, const or_qm
         for (int k = 0; k < m; ++k) s += R[i * m + k] * xi[k];
         M1[i] = -s;
     }
-    for (int k = 0; k < m * m; ++k) R2[k] = R[k] * nu / (nu - 2.0);
+    const double r2 = or_ratio(nu, 0.0, -2.0);
+    for (int k = 0; k < m * m; ++k) R2[k] = R[k] * r2;
     double t2 = or_mvt_dense(m, a, R2, nu - 2.0, Q);
     if (T2) *T2 = t2;
     for (int i = 0; i < m; ++i) {
@@ -424,7 +438,7 @@ void or_tmoments(int m, const double *a, const double *R, double nu, const or_qm
         for (int k = 0; k < m; ++k) {
             double s = 0.0;
             for (int l = 0; l < m; ++l) s += G[i * m + l] * R[l * m + k];
-            M2[i * m + k] = nu / (nu - 2.0) * t2 * R[i * m + k] - s;
+            M2[i * m + k] = r2 * t2 * R[i * m + k] - s;
         }
 }
 
@@ -509,15 +523,17 @@ int or_estep(int n, int p, int q, int g, const double *y,
                 for (int k = 0; k < p; ++k) s += Bh[k * q + i] * res[k];
                 c[i] = s;
             }
-            double logt = lgamma(0.5 * (nuh + p)) - lgamma(0.5 * nuh) - 0.5 * p * log(M_PI * nuh)
-                          - 0.5 * logdet[h] - 0.5 * (nuh + p) * log1p(d / nuh);
+            double logt = isinf(nuh)                /* normal limit: log phi_p(y; mu, Omega) */
+                          ? -0.5 * p * log(2.0 * M_PI) - 0.5 * logdet[h] - 0.5 * d
+                          : lgamma(0.5 * (nuh + p)) - lgamma(0.5 * nuh) - 0.5 * p * log(M_PI * nuh)
+                            - 0.5 * logdet[h] - 0.5 * (nuh + p) * log1p(d / nuh);
             /* A = T_q(c sqrt((nu+p)/(nu+d)); 0, Lambda, nu+p) */
             double ca[OR_MAXM];
-            double fa = sqrt((nuh + p) / (nuh + d));
+            double fa = sqrt(or_ratio(nuh, p, d));
             for (int i = 0; i < q; ++i) ca[i] = c[i] * fa;
             double A = or_mvt(q, ca, LLAM + (size_t)h * q * q, nuh + p, &Q, NULL);
             /* U | y ~ tt_q(c, s Lambda, nu*; R+) with s = (nu+d)/nu*, nu* = nu+p+2 */
-            double nus = nuh + p + 2.0, sc = (nuh + d) / nus;
+            double nus = nuh + p + 2.0, sc = or_ratio(nuh, d, p + 2.0);
             double Rm[OR_MAXM * OR_MAXM], M0, M1[OR_MAXM], M2[OR_MAXM * OR_MAXM], T2;
             if (direct && q >= 2) {
                 /* Z = sqrt(sc) Zs, Zs ~ t_q(0, Lambda, nu*) truncated to Zs <= c / sqrt(sc) */
@@ -540,8 +556,13 @@ int or_estep(int n, int p, int q, int g, const double *y,
             if (intB) intB[o] = Bv;
             double wv = 0.0, e1v = 0.0, EU[OR_MAXM], EUU[OR_MAXM * OR_MAXM];
             if (A > 0.0 && Bv > 0.0) {
-                wv = (nuh + p) / (nuh + d) * Bv / A;
-                e1v = wv - log(0.5 * (nuh + d)) - (nuh + p) / (nuh + d) + or_digamma(0.5 * (nuh + p));
+                if (isinf(nuh)) {                 /* normal limit: W = 1 */
+                    wv = 1.0;
+                    e1v = 0.0;
+                } else {
+                    wv = (nuh + p) / (nuh + d) * Bv / A;
+                    e1v = wv - log(0.5 * (nuh + d)) - (nuh + p) / (nuh + d) + or_digamma(0.5 * (nuh + p));
+                }
                 for (int i = 0; i < q; ++i) EU[i] = c[i] - M1[i] / Bv;
                 for (int i = 0; i < q; ++i)
                     for (int k = 0; k < q; ++k)
@@ -692,7 +713,8 @@ int or_mstep(int n, int p, int q, int g, const double *y,
         /* (22), last sum with "+": log(nu/2) - psi(nu/2) + 1 + (1/n_h) sum tau (e1 - w) = 0 */
         double m = sew / nh;
         double lo = 1.0, hi = 200.0;
-        if (or_nu_eq(lo, m) <= 0.0) nu1[h] = lo;
+        if (isinf(nu0[h])) nu1[h] = nu0[h];      /* normal limit: nu stays infinite */
+        else if (or_nu_eq(lo, m) <= 0.0) nu1[h] = lo;
         else if (or_nu_eq(hi, m) >= 0.0) nu1[h] = hi;
         else {
             for (int it = 0; it < 100; ++it) {
