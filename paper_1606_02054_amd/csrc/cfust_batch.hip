@@ -558,7 +558,7 @@ cfust_status cfust_init(cfust_handle h, const double *y, cfust_dims d, int32_t n
     if (!alpha) return fail(h, CFUST_EINVAL, "alpha is NULL");
     for (int a = 0; a < nalpha; ++a)
         if (!(alpha[a] > 0.0 && alpha[a] < 1.0)) return fail(h, CFUST_EINVAL, "alpha[%d] outside (0, 1)", a);
-    if (!(nu0 > 0.0) || !(nu0 < 1e300)) return fail(h, CFUST_EINVAL, "nu0 must be positive and finite");
+    if (!(nu0 > 0.0)) return fail(h, CFUST_EINVAL, "nu0 must be positive (+infinity: the normal limit)");
     if (!best || !best->pi || !best->mu || !best->Sigma || !best->Delta || !best->nu)
         return fail(h, CFUST_EINVAL, "an output parameter array is NULL");
     if ((st = check_qmc(h, qmc, d.q >= 2)) != CFUST_OK) return st;

@@ -117,20 +117,58 @@ __device__ inline double dm_tau_of_lnq(double lnq, double a, double lb) {
     return exp(l);
 }
 
+// (v + a) / (v + b), with its limit 1 at v = infinity (the normal limit of the
+// t laws: every dof ratio of the family tends to 1).
+__device__ inline double dm_ratio(double v, double a, double b) {
+    return isinf(v) ? 1.0 : (v + a) / (v + b);
+}
+
 // log of the univariate t_1 density with scale S (variance-like) and dof v,
-// given the log normaliser lnc = lgamma((v+1)/2) - lgamma(v/2) - 1/2 ln(pi v).
+// given the log normaliser lnc = lgamma((v+1)/2) - lgamma(v/2) - 1/2 ln(pi v);
+// at v = infinity the normal density, lnc = -1/2 ln(2 pi).
 __device__ inline double dm_lt1pdf(double x, double S, double v, double lnc) {
+    if (isinf(v)) return lnc - 0.5 * log(S) - 0.5 * x * x / S;
     return lnc - 0.5 * log(S) - 0.5 * (v + 1.0) * log1p(x * x / (v * S));
 }
 
 __device__ inline double dm_lt1_const(double v) {
+    if (isinf(v)) return -0.5 * log(2.0 * M_PI);
     return lgamma(0.5 * (v + 1.0)) - lgamma(0.5 * v) - 0.5 * log(M_PI * v);
+}
+
+// ------------------------------------------------ normal limit (FP64) ------
+
+// ln Phi(x) for x <= 0: erfc for moderate x, the scaled erfcx (erfc(t) =
+// exp(-t^2) erfcx(t)) in the tail so the log stays finite far past underflow.
+__device__ inline double dm_lnPhi_lower(double x) {
+    const double t = -x * M_SQRT1_2;                  // >= 0
+    if (t < 1.0) return log(0.5 * erfc(t));
+    return log(0.5 * erfcx(t)) - t * t;
+}
+
+// The z <= 0 with ln Phi(z) = lnq (lnq <= -ln 2): erfcinv start (or the
+// asymptotic z ~ -sqrt(-2 lnq - ln(-4 pi lnq)) where exp(lnq) underflows),
+// then Newton steps on ln Phi, whose slope is the inverse Mills ratio.
+__device__ inline double dm_ninv_lower(double lnq) {
+    if (!(lnq < -LN2)) return 0.0;
+    if (lnq == -INFINITY) return -INFINITY;
+    double z = lnq > -700.0 ? -M_SQRT2 * erfcinv(2.0 * exp(lnq))
+                            : -sqrt(-2.0 * lnq - log(-4.0 * M_PI * lnq));
+    for (int it = 0; it < 3; ++it) {
+        const double lp = dm_lnPhi_lower(z);
+        const double slope = exp(-0.5 * z * z - 0.5 * log(2.0 * M_PI) - lp);   // phi(z) / Phi(z)
+        const double zn = z - (lp - lnq) / slope;
+        if (!(zn <= 0.0) || !isfinite(zn)) break;
+        z = zn;
+    }
+    return z;
 }
 
 // Univariate t CDF T_v(x) in FP64 (the one-dimensional T_m).
 __device__ inline double dm_tcdf(double x, double v) {
     if (isnan(x)) return x;
     if (isinf(x)) return x > 0 ? 1.0 : 0.0;
+    if (isinf(v)) return 0.5 * erfc(-x * M_SQRT1_2);          // normal limit
     const double a = 0.5 * v, lb = dm_lbeta_half(a);
     // s = x / sqrt(v + x^2): z = v/(v+x^2), zc = x^2/(v+x^2)
     double z, zc;

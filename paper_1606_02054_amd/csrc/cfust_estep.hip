@@ -62,7 +62,8 @@ __device__ inline void precompute_body(const double *__restrict__ pi, const doub
     if (threadIdx.x == 0) {
         int status = 0;
         const double v = nu[h];
-        if (!(v > 0.0) || !isfinite(v) || !(pi[h] >= 0.0) || !isfinite(pi[h])) status |= CFUST_DEV_BADPARAM;
+        // nu = +infinity is the normal limit of the family (CFUSN)
+        if (!(v > 0.0) || !(pi[h] >= 0.0) || !isfinite(pi[h])) status |= CFUST_DEV_BADPARAM;
         double Om[MAXP * MAXP];
         const double *Sg = Sigma + (size_t)h * p * p;
         const double *Dl = Delta + (size_t)h * p * q;
@@ -109,8 +110,9 @@ __device__ inline void precompute_body(const double *__restrict__ pi, const doub
         if (!chol_inplace(LL, q)) { status |= CFUST_DEV_NOTSPD_LAMBDA; for (int i = 0; i < q; ++i) LL[i * q + i] = 1.0; }
         for (int i = 0; i < q * q; ++i) { P.LL[i] = LL[i]; P.LLf[i] = (float)LL[i]; }
         P.nu = v;
-        P.ltp_const = lgamma(0.5 * (v + p)) - lgamma(0.5 * v) - 0.5 * p * log(M_PI * v) - 0.5 * logdet;
-        P.digam = dm_digamma(0.5 * (v + p));
+        P.ltp_const = isinf(v) ? -0.5 * p * log(2.0 * M_PI) - 0.5 * logdet
+                               : lgamma(0.5 * (v + p)) - lgamma(0.5 * v) - 0.5 * p * log(M_PI * v) - 0.5 * logdet;
+        P.digam = isinf(v) ? 0.0 : dm_digamma(0.5 * (v + p));
         P.lt1_s = dm_lt1_const(v + p + 2.0);
         P.lt1_s1 = dm_lt1_const(v + p + 1.0);
         st = status;
@@ -244,6 +246,11 @@ __device__ inline void tables_body(const CompPre *__restrict__ pre, int p, int n
     const double nu = pre[h].nu + p + off;
     __shared__ double fv[TAB_NODES];
     const int t = threadIdx.x;
+    if (isinf(nu)) {                             // normal limit: the integrand needs no tables
+        float *dst = tabs + ((size_t)h * NDOF + off) * TAB_FLOATS;
+        for (int i = t; i < TAB_FLOATS; i += blockDim.x) dst[i] = 0.0f;
+        return;
+    }
     if (t < TAB_NODES) fv[t] = table_node_value(nu, t / 7, t % 7);
     __syncthreads();
     float *dst = tabs + ((size_t)h * NDOF + off) * TAB_FLOATS;
@@ -304,18 +311,18 @@ __device__ inline void pair_geometry_ws(const double *__restrict__ y, int n, int
 // folded into b.  Returns L (FP64).
 __device__ inline const double *integral_limits(const IntDesc &D, const CompPre &P, int p, int q,
                                                 const double *c, double d, double *b) {
-    const double v = P.nu;
+    const double v = P.nu;                       // infinite: the normal limit, every ratio below is 1
     const double nus = v + p + 2.0;
-    const double sc = (v + d) / nus;
+    const double sc = dm_ratio(v, d, p + 2.0);   // (v + d) / nus
     if (D.type == INT_A || D.type == INT_B) {
-        const double f = sqrt((D.type == INT_A ? v + p : nus) / (v + d));
+        const double f = sqrt(dm_ratio(v, D.type == INT_A ? p : p + 2.0, d));
         for (int l = 0; l < q; ++l) b[l] = c[l] * f;
         return P.LL;
     }
     if (D.type == INT_C) {
         const int i = D.i;
         const double Lii = P.Lam[i * q + i];
-        const double kap = (nus + c[i] * c[i] / (sc * Lii)) / (nus - 1.0);
+        const double kap = dm_ratio(nus, c[i] * c[i] / (sc * Lii), -1.0);
         const double f = 1.0 / sqrt(kap * sc);
         int r = 0;
         for (int k = 0; k < q; ++k) {
@@ -326,7 +333,7 @@ __device__ inline const double *integral_limits(const IntDesc &D, const CompPre 
     }
     const int i = D.i, k = D.k, t = D.pair;
     const double Qf = (c[i] * c[i] * P.ID[t][0] + 2.0 * c[i] * c[k] * P.ID[t][1] + c[k] * c[k] * P.ID[t][2]) / sc;
-    const double kk = (nus + Qf) / (nus - 2.0);
+    const double kk = dm_ratio(nus, Qf, -2.0);
     const double f = 1.0 / sqrt(kk * sc);
     int r = 0;
     for (int l = 0; l < q; ++l) {
@@ -365,7 +372,7 @@ __device__ __attribute__((noinline)) void item_head(const double *y, const doubl
     pair_geometry_ws(y, n, p, q, j, mu + (size_t)h * p, P, w->c, d, w->v);
     w->L = integral_limits(D, P, p, q, w->c, d, w->b);
     w->nu0 = P.nu + p + D.dofoff;
-    if (fp64_head) w->H = sov_head(w->b, w->L, w->nu0);
+    if (fp64_head || isinf(w->nu0)) w->H = sov_head(w->b, w->L, w->nu0);   // normal limit: no tables
 }
 
 __device__ __attribute__((noinline)) void item_head_tab(WaveItem *w, const float *tab) {
@@ -392,11 +399,14 @@ template <int M, bool MIXED, int PPL>
 __device__ inline bool qmc_item(const EstepQmcArgs &a, int h, int idx, int j, const float *tab, double *smean,
                                 WaveItem *w, int lane) {
     item_head(a.y, a.mu, a.pre, a.n, a.p, a.q, h, idx, j, w, !MIXED);
-    if (MIXED) item_head_tab(w, tab);
+    const bool normal = isinf(w->nu0);          // the normal limit of the family (dof infinite)
+    if (MIXED && !normal) item_head_tab(w, tab);
     ItemResult r{0.0, 0.0, -INFINITY};
     if (w->H.e0 > 0.0 || w->H.lne0 > -INFINITY) {
         if (MIXED) {
-            if (!sov_mixed<M, PPL>(w->H, w->b, w->L, w->nu0, a.lat, tab, smean, lane)) return false;
+            const bool ok = normal ? sov_mixed_normal<M, PPL>(w->H, w->b, w->L, a.lat, smean, lane)
+                                   : sov_mixed<M, PPL>(w->H, w->b, w->L, w->nu0, a.lat, tab, smean, lane);
+            if (!ok) return false;
         } else {
             sov_fp64<M>(w->H, w->b, w->L, w->nu0, a.lat, smean, lane);
         }
@@ -473,7 +483,7 @@ __device__ inline void assemble_body(const EstepAsmArgs &a, int gid) {
     double lnA;
     if (q >= 2) lnA = a.lnA[(size_t)h * a.n + j];
     else lnA = log(integral_value(a, P, h, j, 0, c, d));
-    const double logf = q * LN2 + P.ltp_const - 0.5 * (v + p) * log1p(d / v) + lnA;
+    const double logf = q * LN2 + P.ltp_const + (isinf(v) ? -0.5 * d : -0.5 * (v + p) * log1p(d / v)) + lnA;
     a.logf_comp[(size_t)h * a.n + j] = logf;
     if (a.density_only) return;
     const size_t o = (size_t)h * a.n + j;
@@ -484,14 +494,19 @@ __device__ inline void assemble_body(const EstepAsmArgs &a, int gid) {
     const double A = (q >= 2) ? integral_value(a, P, h, j, 0, c, d) : exp(lnA);
     const double Bv = integral_value(a, P, h, j, 1, c, d);
     if (A > 0.0 && Bv > 0.0 && isfinite(logf)) {
-        const double nus = v + p + 2.0, sc = (v + d) / nus;
-        w = (v + p) / (v + d) * Bv / A;                                   // eq. (13)
-        e1 = w - log(0.5 * (v + d)) - (v + p) / (v + d) + P.digam;        // eq. (15)
+        const double nus = v + p + 2.0, sc = dm_ratio(v, d, p + 2.0);
+        if (isinf(v)) {                          // normal limit: W = 1
+            w = 1.0;
+            e1 = 0.0;
+        } else {
+            w = (v + p) / (v + d) * Bv / A;                               // eq. (13)
+            e1 = w - log(0.5 * (v + d)) - (v + p) / (v + d) + P.digam;    // eq. (15)
+        }
         // xi_i and the conditional pieces of each i
         double xi[MAXQ], t1k[MAXQ];
         for (int i = 0; i < q; ++i) {
             const double Rii = sc * P.Lam[i * q + i];
-            const double kap = (nus + c[i] * c[i] / Rii) / (nus - 1.0);
+            const double kap = dm_ratio(nus, c[i] * c[i] / Rii, -1.0);
             const double t1 = exp(dm_lt1pdf(c[i], Rii, nus, P.lt1_s));
             t1k[i] = t1 * kap;
             xi[i] = t1k[i] * integral_value(a, P, h, j, 2 + i, c, d);
@@ -500,13 +515,13 @@ __device__ inline void assemble_body(const EstepAsmArgs &a, int gid) {
         double G[MAXQ * MAXQ];
         for (int i = 0; i < q; ++i) {
             const double Lii = P.Lam[i * q + i];
-            const double kap = (nus + c[i] * c[i] / (sc * Lii)) / (nus - 1.0);
+            const double kap = dm_ratio(nus, c[i] * c[i] / (sc * Lii), -1.0);
             double bb[MAXQ], xs[MAXQ];
             for (int k = 0; k < q; ++k) bb[k] = c[k] - P.Lam[k * q + i] / Lii * c[i];
             for (int k = 0; k < q; ++k) {
                 if (k == i) { xs[k] = 0.0; continue; }
                 const double Vkk = kap * sc * (P.Lam[k * q + k] - P.Lam[k * q + i] * P.Lam[i * q + k] / Lii);
-                const double kp = ((nus - 1.0) + bb[k] * bb[k] / Vkk) / (nus - 2.0);
+                const double kp = dm_ratio(nus - 1.0, bb[k] * bb[k] / Vkk, -1.0);
                 const double t1 = exp(dm_lt1pdf(bb[k], Vkk, nus - 1.0, P.lt1_s1));
                 const int pr = i < k ? pair_index(q, i, k) : pair_index(q, k, i);
                 xs[k] = t1 * kp * integral_value(a, P, h, j, 2 + q + pr, c, d);
@@ -534,7 +549,7 @@ __device__ inline void assemble_body(const EstepAsmArgs &a, int gid) {
             for (int k = 0; k < q; ++k) {
                 double s = 0.0;
                 for (int l = 0; l < q; ++l) s += G[i * q + l] * sc * P.Lam[l * q + k];
-                M2[i * q + k] = nus / (nus - 2.0) * A * sc * P.Lam[i * q + k] - s;
+                M2[i * q + k] = dm_ratio(nus, 0.0, -2.0) * A * sc * P.Lam[i * q + k] - s;
             }
         for (int i = 0; i < q; ++i) e2[i] = w * (c[i] - M1[i] / Bv);
         int t = 0;
@@ -663,7 +678,12 @@ __global__ __launch_bounds__(256) void k_mvt(MvtArgs a) {
     const SovHead H = sov_head(b, L, nu);
     double est = 0.0, se = 0.0, lnest = -INFINITY;
     if (H.e0 > 0.0 || H.lne0 > -INFINITY) {
-        if (MIXED) {
+        if (MIXED && isinf(nu)) {
+            const bool ok = (a.lat.N % 128 == 0) ? sov_mixed_normal<M, 2>(H, b, L, a.lat, smean[wave], lane)
+                                                 : sov_mixed_normal<M, 1>(H, b, L, a.lat, smean[wave], lane);
+            if (lane == 0) a.flag[it] = ok ? 0 : 1;
+            if (!ok) return;
+        } else if (MIXED) {
             for (int dof = 0; dof < M; ++dof) {
                 for (int t = lane; t < TAB_NODES; t += 64) fv[wave][t] = table_node_value(nu + dof, t / 7, t % 7);
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

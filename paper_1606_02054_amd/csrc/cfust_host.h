@@ -124,9 +124,6 @@ inline cfust_status check_params(cfust_handle h, const cfust_params *P) {
     return CFUST_OK;
 }
 
-// M-step reduction blocks per component: about 16 tiles of 64 observations
-// each, at most 1024 (the partition fixes the summation order, so it depends
-// on n only).
 // Blocks per component of the M-step reduction: about three resident blocks
 // per compute unit over the g components (a grid-stride loop over the tiles
 // balances them), never more than one per tile.  Few blocks keep the block

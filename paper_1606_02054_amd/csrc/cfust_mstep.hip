@@ -384,7 +384,7 @@ __device__ inline void mstep_solve_body(const MsolveArgs &a, int32_t *cstat, int
         if (tid == 0 && !ms_chol(Ls, p)) { s_status |= CFUST_DEV_NOTSPD_SIGMA; s_keep = 1; }
         __syncthreads();
     }
-    if (tid == 0 && !s_keep) {
+    if (tid == 0 && !s_keep && !isinf(a.nu0[h])) {                    // an infinite nu (normal limit) stays
         const double m = Sew / nh;                                     // (22)
         s_m = m;
         s_lo = 1.0; s_hi = 200.0;

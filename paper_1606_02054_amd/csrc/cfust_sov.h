@@ -103,19 +103,66 @@ __device__ double sov_lane_sum64(const double *b, const double *L, double nu, co
     return acc;
 }
 
+// Normal limit (dof infinite), FP64: the conditional laws are normal with
+// fixed scale, so y_i = Phi^-1(x_i e_i) and no scale is carried.
+__device__ __forceinline__ double nquantile_step64(double x, double xb, double e, double eb, double lne,
+                                                   bool lowt) {
+    const double p = x * e;
+    const double pb = xb * e + eb;
+    const bool lower = lowt || p <= 0.5;
+    const double lnq = lowt ? log(x) + lne : log(lower ? p : pb);
+    const double z = dm_ninv_lower(lnq);
+    return lower ? z : -z;
+}
+
+template <int M>
+__device__ double sov_lane_sum64_normal(const double *b, const double *L, const Lattice &Lt, int s, double e0,
+                                        double eb0, double lne0, bool low0, int lane) {
+    double acc = 0.0;
+    for (int k = lane; k < Lt.N; k += 64) {
+        double y[M];
+        double x, xb;
+        point64(Lt, s, k, 0, x, xb);
+        y[0] = nquantile_step64(x, xb, e0, eb0, lne0, low0);
+        double f = 1.0;
+#pragma unroll
+        for (int i = 1; i < M; ++i) {
+            double num = b[i];
+#pragma unroll
+            for (int j = 0; j < i; ++j) num -= L[i * M + j] * y[j];
+            const double lt = dm_lnPhi_lower(-fabs(num) / L[i * M + i]);
+            const double small = exp(lt);
+            const bool lowt = num <= 0.0;
+            const double e = lowt ? small : 1.0 - small;
+            const double eb = lowt ? 1.0 - small : small;
+            f *= e;
+            if (f == 0.0) break;
+            if (i < M - 1) {
+                point64(Lt, s, k, i, x, xb);
+                y[i] = nquantile_step64(x, xb, e, eb, lt, lowt);
+            }
+        }
+        acc += f;
+    }
+    return acc;
+}
+
 // ------------------------------------------------------------- FP32 path ---
 
 // Lattice coordinate (FP32): t in 32-bit fixed point so that x = 2 min(t, 1-t)
-// keeps full relative accuracy near 0 (it enters log2 x in the lower tail);
-// xb = 1 - x only enters the upper-tail complement.  Needs N a power of two.
+// keeps full relative accuracy near 0 (it enters log2 x in the lower tail),
+// and so does xb = 1 - x near 0, from the integer complement: it enters the
+// upper-tail complement p_b = xb e + e_b, whose relative accuracy sets the
+// quantile where the conditional law is sampled far in its upper tail.
+// Needs N a power of two.
 __device__ __forceinline__ void point32(uint32_t k, uint32_t zj, uint32_t mask, int sh, uint32_t shfix,
                                         float &x, float &xb) {
     const uint32_t r = (k * zj) & mask;
     const uint32_t t = (r << sh) + shfix;
     uint32_t u = min(t, 0u - t);                      // 2^32 min(t, 1-t), in [0, 2^31]
     u = min(max(u, 128u), 2147483520u);               // [2^-24, 1 - 2^-24] after scaling
-    x = (float)u * 4.656612873077393e-10f;            // 2^-31, relative accuracy near 0
-    xb = 1.0f - x;                                    // absolute accuracy suffices for 1 - x
+    x = (float)u * 4.656612873077393e-10f;            // 2^-31
+    xb = (float)(2147483648u - u) * 4.656612873077393e-10f;
 }
 
 __device__ __forceinline__ float quantile_step32(float x, float xb, float e, float eb, float l2e, bool lowt,
@@ -177,6 +224,62 @@ __device__ __forceinline__ float sov_point32(const Sov32Setup &P, const float *t
     return f;
 }
 
+// Normal limit, FP32: Phi from erfc, Phi^-1 from erfcinv polished by one
+// Newton step (the device library's FP32 routines).  The first coordinate's truncation probability
+// e_0 comes from FP64 and may be far below the FP32 range: its quantile is
+// taken from log2 p = log2 x + log2 e_0, which stays above 2^-120 because
+// items with log2 e_0 < -96 go to the FP64 integrand (sov_mixed_normal).
+// Later factors are part of the FP32 product, so where they underflow the
+// point carries no weight; their arguments are kept at or above 1e-37, so
+// the quantiles stay finite and no NaN can arise.
+__device__ __forceinline__ float nquantile_step32(float x, float xb, float e, float eb, float l2e, bool lowt,
+                                                  bool first) {
+    float arg;
+    bool lower;
+    if (first && lowt) {
+        arg = fexp2(flog2(x) + l2e);
+        lower = true;
+    } else {
+        const float p = x * e;
+        const float pb = fmaf(xb, e, eb);
+        lower = lowt || p <= 0.5f;
+        arg = fmaxf(lower ? p : pb, 1e-37f);
+    }
+    // erfcinv start, then one Newton step on Phi(z) = arg with Phi from erfc
+    // (relative accuracy in the lower tail): the start alone is not accurate
+    // enough there for the conditional limits that follow
+    float z = -1.41421356f * erfcinvf(2.0f * arg);
+    const float phi = 0.39894228f * fexp2(-0.72134752f * z * z);     // exp(-z^2/2) / sqrt(2 pi)
+    z -= (0.5f * erfcf(-0.70710678f * z) - arg) / phi;
+    return lower ? z : -z;
+}
+
+template <int M>
+__device__ __forceinline__ float sov_point32_normal(const Sov32Setup &P, uint32_t k, const uint32_t *zz,
+                                                    uint32_t mask, int sh, const uint32_t *shfix) {
+    float y[M];
+    float x, xb;
+    point32(k, zz[0], mask, sh, shfix[0], x, xb);
+    y[0] = nquantile_step32(x, xb, P.e0, P.eb0, P.l2e0, P.low0, true);
+    float f = 1.0f;
+#pragma unroll
+    for (int i = 1; i < M; ++i) {
+        float num = P.b[i];
+#pragma unroll
+        for (int j = 0; j < i; ++j) num = fmaf(-P.L[i * M + j], y[j], num);
+        const float small = 0.5f * erfcf(fabsf(num) * P.a[i]);      // a[i] = 1 / (sqrt 2 L_ii)
+        const bool lowt = num <= 0.0f;
+        const float e = lowt ? small : 1.0f - small;
+        const float eb = lowt ? 1.0f - small : small;
+        f *= e;
+        if (i < M - 1) {
+            point32(k, zz[i], mask, sh, shfix[i], x, xb);
+            y[i] = nquantile_step32(x, xb, e, eb, 0.0f, lowt, false);
+        }
+    }
+    return f;
+}
+
 // Per-lane FP32 sum over this lane's points of one shift.  PPL independent
 // points are evaluated per loop trip (instruction-level parallelism across
 // the dependency chains); needs N to be a multiple of 64 PPL when PPL > 1.
@@ -194,6 +297,20 @@ __device__ float sov_lane_sum32(const Sov32Setup &P, const float *tabs, const ui
     return acc;
 }
 
+template <int M, int PPL>
+__device__ float sov_lane_sum32_normal(const Sov32Setup &P, const uint32_t *zz, uint32_t mask, int sh,
+                                       const uint32_t *shfix, int N, int lane) {
+    float acc = 0.0f;
+    for (int k = lane; k < N; k += 64 * PPL) {
+        float f[PPL];
+#pragma unroll
+        for (int u = 0; u < PPL; ++u) f[u] = sov_point32_normal<M>(P, (uint32_t)(k + 64 * u), zz, mask, sh, shfix);
+#pragma unroll
+        for (int u = 0; u < PPL; ++u) acc += f[u];
+    }
+    return acc;
+}
+
 // ------------------------------------------------------------- driver -------
 
 // The first factor e_0 = T_nu(b_0 / L_00) of the SOV product, FP64, with its
@@ -204,6 +321,17 @@ struct SovHead {
 };
 
 __device__ inline SovHead sov_head(const double *b, const double *L, double nu) {
+    if (isinf(nu)) {                                  // normal limit: Phi(b_0 / L_00)
+        const double u = b[0] / L[0];
+        const double lt0 = dm_lnPhi_lower(-fabs(u));
+        const double small0 = exp(lt0);
+        SovHead H;
+        H.low0 = u <= 0.0;
+        H.e0 = H.low0 ? small0 : 1.0 - small0;
+        H.eb0 = H.low0 ? 1.0 - small0 : small0;
+        H.lne0 = H.low0 ? lt0 : log1p(-small0);
+        return H;
+    }
     const double a0 = 0.5 * nu, lb0 = dm_lbeta_half(a0);
     const double u = b[0] / L[0];
     const double au = fabs(u);
@@ -288,11 +416,43 @@ __device__ bool sov_mixed(const SovHead &H, const double *b, const double *L, do
     return tot / Lt.S > 1e-30;
 }
 
+// The same for the normal limit (dof infinite): no tables, Phi and Phi^-1.
+// An item whose first factor is below 2^-96 is left to the FP64 integrand
+// (returns false), so the FP32 first quantile never leaves the FP32 range.
+template <int M, int PPL>
+__device__ bool sov_mixed_normal(const SovHead &H, const double *b, const double *L, const Lattice &Lt,
+                                 double *smean, int lane) {
+    if (H.low0 && H.lne0 < -96.0 * LN2) return false;
+    Sov32Setup P;
+#pragma unroll
+    for (int i = 0; i < M; ++i) { P.b[i] = (float)b[i]; P.a[i] = (float)(M_SQRT1_2 / L[i * M + i]); }
+#pragma unroll
+    for (int i = 0; i < M * M; ++i) P.L[i] = (float)L[i];
+    P.e0 = (float)H.e0; P.eb0 = (float)H.eb0; P.l2e0 = (float)(H.lne0 / LN2); P.low0 = H.low0;
+    P.sqrtnu = 1.0f;
+    uint32_t zz[M], shfix[M];
+    const uint32_t mask = (uint32_t)Lt.N - 1u;
+    const int sh = 32 - Lt.log2N;
+#pragma unroll
+    for (int i = 0; i < M - 1; ++i) zz[i] = (uint32_t)Lt.z[i];
+    double tot = 0.0;
+    for (int s = 0; s < Lt.S; ++s) {
+#pragma unroll
+        for (int i = 0; i < M - 1; ++i) shfix[i] = (uint32_t)(Lt.shifts[s * LATD + i] * 4294967296.0);
+        const float ls = sov_lane_sum32_normal<M, PPL>(P, zz, mask, sh, shfix, Lt.N, lane);
+        const double ms = wave_sum((double)ls) / (double)Lt.N;
+        if (lane == 0) smean[s] = ms;
+        tot += ms;
+    }
+    return tot / Lt.S > 1e-30;
+}
+
 template <int M>
 __device__ __forceinline__ void sov_fp64(const SovHead &H, const double *b, const double *L, double nu, const Lattice &Lt,
                          double *smean, int lane) {
     for (int s = 0; s < Lt.S; ++s) {
-        const double ls = sov_lane_sum64<M>(b, L, nu, Lt, s, H.e0, H.eb0, H.lne0, H.low0, lane);
+        const double ls = isinf(nu) ? sov_lane_sum64_normal<M>(b, L, Lt, s, H.e0, H.eb0, H.lne0, H.low0, lane)
+                                    : sov_lane_sum64<M>(b, L, nu, Lt, s, H.e0, H.eb0, H.lne0, H.low0, lane);
         const double ms = wave_sum(ls) / (double)Lt.N;
         if (lane == 0) smean[s] = ms;
     }

@@ -1,0 +1,202 @@
+"""GPU parity for the normal limit of the family (CFUSN: nu = +infinity per
+component, Table 1) through the C ABI, against the oracle: the normal
+multivariate CDF batch, E-steps of all-normal and of mixed normal / t
+families (q = 1, the restricted skew normal; Delta = 0, a normal mixture),
+the M-step (nu stays infinite), EM iterations, batched fits and the
+initialiser with nu0 = infinity."""
+import numpy as np
+import pytest
+import torch
+
+from cfust_inputs import draw_mvt_problems, make_design, sample_hierarchy, kmeans_partitions
+from cfust_inputs.synth import draw_params
+from gpu_common import TOL, compare_estep, rel_err
+
+pytestmark = pytest.mark.gpu
+INF = float("inf")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1606_02054_amd as cf
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    cf.default_handle()
+    return cf
+
+
+def _mode(cf, mode):
+    return cf.CFUST_MIXED if mode == "mixed" else cf.CFUST_FP64
+
+
+def _gpu_estep(cf, y, P, design, mode):
+    yd = torch.as_tensor(np.ascontiguousarray(y.T)).cuda()
+    out = cf.cfust_estep(yd, cf.device_params(P), cf.device_qmc(design, _mode(cf, mode)))
+    torch.cuda.synchronize()
+    return out
+
+
+def _params(seed, p, q, g, normal_mask):
+    rng = np.random.default_rng(seed)
+    P = draw_params(rng, p, q, g, sigma="wishart" if p > 2 else "aat")
+    P.nu[np.asarray(normal_mask, dtype=bool)] = INF
+    return rng, P
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 8])
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_normal_mvt_batch_vs_oracle(lib, orc, m, mode):
+    cf = lib
+    print(f"normal mvt m={m} mode={mode}", flush=True)
+    rng = np.random.default_rng(900 + m)
+    batch = 37
+    b, L, idx, nu = draw_mvt_problems(rng, m, batch, nmat=3, lim=(-2.5, 2.5), dof=(2.0, 30.0))
+    nu[::2] = INF                                 # every other item normal, the rest t
+    des = make_design(256, 4, seed=79)
+    p, logp, se = cf.mvt_cdf_batch(torch.as_tensor(b).cuda(), torch.as_tensor(L).cuda(),
+                                   torch.as_tensor(idx).cuda(), torch.as_tensor(nu).cuda(),
+                                   cf.device_qmc(des, _mode(cf, mode)))
+    p, logp = p.cpu().numpy(), logp.cpu().numpy()
+    ref = np.array([orc.mvt(b[i], L[idx[i]], nu[i], des)[0] for i in range(batch)])
+    tol = 1e-10 if mode == "fp64" else 5e-5
+    assert np.all(rel_err(p, ref, 1e-300) <= tol), rel_err(p, ref, 1e-300).max()
+    assert np.all(np.abs(logp - np.log(ref)) <= tol * 2)
+
+
+CASES = [  # (p, q, g, n, seed, normal components)
+    (2, 2, 2, 203, 31, [True, True]),
+    (3, 1, 3, 60, 32, [True, True, True]),          # restricted skew normal
+    (3, 3, 2, 41, 33, [True, False]),               # one normal, one t component
+    (4, 4, 3, 23, 34, [True, False, True]),
+    (5, 2, 2, 17, 35, [True, True]),
+]
+
+
+@pytest.mark.parametrize("p,q,g,n,seed,normal", CASES)
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_normal_estep_vs_oracle(lib, orc, p, q, g, n, seed, normal, mode):
+    cf = lib
+    print(f"normal estep p={p} q={q} g={g} n={n} normal={normal} mode={mode}", flush=True)
+    rng, P = _params(seed, p, q, g, normal)
+    y, _ = sample_hierarchy(rng, P, n)
+    des = make_design(256, 4, seed=190 + seed)
+    ora = orc.estep(y, P, des)
+    gpu = _gpu_estep(cf, y, P, des, mode)
+    compare_estep(gpu, ora, mode, label=f"normal p{p}q{q}g{g}")
+    assert abs(float(gpu.loglik.cpu()[0]) - ora.loglik) <= TOL[mode]["logf"] * n
+    np.testing.assert_allclose(gpu.logf_comp.cpu().numpy(), ora.logf_comp, atol=TOL[mode]["logf"])
+    nm = np.asarray(normal)
+    w = gpu.w.cpu().numpy()
+    tau = gpu.tau.cpu().numpy()
+    assert np.all(w[nm][tau[nm] > 0] == 1.0)
+    assert int(gpu.status.cpu()[0]) == 0
+
+
+def test_normal_mixture_delta_zero(lib, orc):
+    cf = lib
+    rng, P = _params(36, 3, 2, 3, [True, True, True])
+    P.Delta[:] = 0.0
+    y, _ = sample_hierarchy(rng, P, 50)
+    des = make_design(256, 4, seed=37)
+    gpu = _gpu_estep(cf, y, P, des, "fp64")
+    compare_estep(gpu, orc.estep(y, P, des), "fp64", label="normal mixture")
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_normal_mstep_keeps_nu(lib, orc, mode):
+    cf = lib
+    rng, P = _params(38, 3, 2, 2, [True, False])
+    y, _ = sample_hierarchy(rng, P, 300)
+    es = orc.estep(y, P, make_design(256, 4, seed=39))
+    if mode == "mixed":
+        for name in ("w", "e1", "e2", "e3"):
+            setattr(es, name, getattr(es, name).astype(np.float32).astype(np.float64))
+    ref, _ = orc.mstep(y, es, P)
+    et = torch.float32 if mode == "mixed" else torch.float64
+    to = lambda a, dt=torch.float64: torch.as_tensor(np.ascontiguousarray(a), dtype=dt).cuda()
+    ges = cf.EStepResult(to(es.tau), to(es.logf_obs), to(np.zeros(1)), to(es.w, et), to(es.e1, et),
+                         to(es.e2, et), to(es.e3, et), precision=_mode(cf, mode))
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    out = cf.cfust_mstep(to(y.T), ges, cf.device_params(P), status=st)
+    torch.cuda.synchronize()
+    pi, mu, Sg, Dl, nu = out.to_host()
+    assert np.isinf(nu[0]) and np.isinf(ref.nu[0])
+    assert abs(nu[1] - ref.nu[1]) <= 1e-9 * ref.nu[1]
+    for a, b in ((pi, ref.pi), (mu, ref.mu), (Sg, ref.Sigma), (Dl, ref.Delta)):
+        assert np.abs(a - b).max() <= 1e-9 * max(1.0, np.abs(b).max())
+    assert int(st.cpu()[0]) & ~64 == 0
+
+
+def test_normal_em_iterations_vs_oracle(lib, orc):
+    """Three FP64 EM iterations of a CFUSN fit on the GPU track the oracle."""
+    cf = lib
+    rng, P = _params(40, 2, 2, 2, [True, True])
+    y, _ = sample_hierarchy(rng, P, 400)
+    des = make_design(256, 4, seed=41)
+    cur = P.copy()
+    cur.mu += 0.3
+    dp = cf.device_params(cur)
+    qm = cf.device_qmc(des, cf.CFUST_FP64)
+    yd = torch.as_tensor(np.ascontiguousarray(y.T)).cuda()
+    lls = []
+    for it in range(3):
+        es = orc.estep(y, cur, des)
+        cur, _ = orc.mstep(y, es, cur)
+        ges = cf.cfust_estep(yd, dp, qm)
+        dp = cf.cfust_mstep(yd, ges, dp)
+        torch.cuda.synchronize()
+        lls.append(es.loglik)
+        assert abs(float(ges.loglik.cpu()[0]) - es.loglik) <= 1e-6 * y.shape[0]
+    assert lls[2] >= lls[0]
+    pi, mu, Sg, Dl, nu = dp.to_host()
+    assert np.all(np.isinf(nu))
+    for a, b in ((pi, cur.pi), (mu, cur.mu), (Sg, cur.Sigma), (Dl, cur.Delta)):
+        assert np.abs(a - b).max() <= 1e-6 * max(1.0, np.abs(b).max())
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_normal_batch_equals_single(lib, precision):
+    cf = lib
+    print(f"normal batch precision {precision}", flush=True)
+    qmc = cf.device_qmc(make_design(512, 4, seed=42), precision)
+    fits, single = [], []
+    for k, (n, p, q, g, normal) in enumerate([(150, 2, 2, 2, [True, True]), (90, 3, 3, 2, [True, False]),
+                                              (70, 4, 1, 3, [False, True, True])]):
+        rng, P = _params(50 + k, p, q, g, normal)
+        y = torch.tensor(np.ascontiguousarray(sample_hierarchy(rng, P, n)[0].T)).cuda()
+        dp = cf.device_params(P)
+        fits.append((y, dp.clone(), cf.alloc_estep(n, p, q, g, precision, stderr=False)))
+        single.append((y, dp.clone()))
+    B = cf.Batch(fits, qmc)
+    B.estep()
+    B.mstep()
+    torch.cuda.synchronize()
+    for (y, dpb, esb), (ys, dps) in zip(fits, single):
+        es = cf.cfust_estep(ys, dps, qmc)
+        nxt = cf.cfust_mstep(ys, es, dps)
+        torch.cuda.synchronize()
+        assert torch.equal(esb.loglik, es.loglik)
+        assert torch.equal(esb.tau, es.tau)
+        for a, b in zip(dpb.to_host(), nxt.to_host()):
+            np.testing.assert_array_equal(a, b)
+    B.close()
+
+
+def test_normal_initialiser_vs_oracle(lib):
+    from oracle import init as oinit
+    cf = lib
+    rng, P = _params(60, 2, 2, 2, [True, True])
+    y, _ = sample_hierarchy(rng, P, 300)
+    labels = kmeans_partitions(y, 2, 3, seed=61)
+    design = make_design(256, 2, seed=62)
+    alphas = [0.2, 0.5, 0.8]
+    best, ll, k = cf.initialise(torch.tensor(np.ascontiguousarray(y.T)).cuda(), 2, 2,
+                                torch.tensor(labels).cuda(), cf.device_qmc(design, cf.CFUST_FP64),
+                                alphas=alphas, nu0=INF)
+    torch.cuda.synchronize()
+    obest, oll, ok = oinit.initialise(y, labels, 2, 2, alphas, design, nu0=INF)
+    ll = ll.cpu().numpy()
+    assert np.array_equal(np.isfinite(ll), np.isfinite(oll))
+    fin = np.isfinite(oll)
+    assert np.abs(ll[fin] - oll[fin]).max() <= 1e-6 * y.shape[0]
+    assert k == ok
+    assert np.all(np.isinf(best.nu.cpu().numpy()))
