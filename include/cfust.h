@@ -10,6 +10,12 @@
  *     Lambda = I_q - Delta^T Omega^{-1} Delta, d(y) = (y-mu)^T Omega^{-1}(y-mu);
  *   E-step  Sec. 3.1 eqs. (7)-(17); M-step  Sec. 3.2 eqs. (18)-(22);
  *   log-likelihood  Sec. 4.3 eq. (27).
+ * The normal limit nu -> infinity of the family (CFUSN in Table 1) is
+ * selected per component by nu_h = +INFINITY: t_p becomes the normal density
+ * phi_p(y; mu, Omega), every T becomes the normal CDF with limit c(y)
+ * (the dof ratios tend to 1), W = 1 so w = 1 and e1 = 0, the truncated
+ * moments are the normal ones, and the M-step keeps nu_h infinite.  A mixture
+ * may hold normal and t components together.
  * The q-variate t CDFs (T_q, and the T_{q-1}, T_{q-2} that the truncated-t
  * moments of eqs. (16)-(17) need) are estimated by separation of variables on
  * a randomly shifted rank-1 lattice whose generating vector and shifts the
@@ -78,7 +84,8 @@ typedef struct {
 } cfust_dims;
 
 /* Psi = (pi, theta_1..theta_g), Sec. 2: device FP64, row-major.
- * pi[g], mu[g][p], Sigma[g][p][p], Delta[g][p][q], nu[g]. */
+ * pi[g], mu[g][p], Sigma[g][p][p], Delta[g][p][q], nu[g] (nu > 0, or
+ * +INFINITY for the normal limit of that component). */
 typedef struct {
     const double *pi, *mu, *Sigma, *Delta, *nu;
 } cfust_params;
@@ -130,7 +137,8 @@ cfust_status cfust_estep(cfust_handle handle, const double *y, cfust_dims dims,
 
 /* M-step, Sec. 3.2 eqs. (18)-(22), in the order pi, mu (with Delta^(k)),
  * Delta (with mu^(k+1)), Sigma (with both), nu.  Eq. (22) is solved with the
- * last sum added ("+"), by 100 bisection steps on [1, 200] (clamped outside).
+ * last sum added ("+"), by 8 rounds of 256-point multisection of [1, 200]
+ * (clamped outside); an infinite nu (normal limit) is kept.
  * `es` is the output of cfust_estep at the same dims/precision; `in` is
  * Psi^(k) (only mu, Delta, Sigma, nu are read), `out` receives Psi^(k+1)
  * (`out` may alias `in`).  A component with n_h < p+1, or whose update is not
@@ -150,7 +158,7 @@ cfust_status cfust_loglik(cfust_handle handle, const double *y, cfust_dims dims,
 /* Batch of multivariate t probabilities T_m(b; 0, L L^T, nu) (the T_q of
  * Sec. 2 eq. 4), one per item.  1 <= m <= CFUST_MAX_Q.
  * b: device [batch][m] upper limits; L: device [nmat][m][m] lower Cholesky
- * factors; mat_idx: device int32 [batch] in [0, nmat); nu: device [batch] > 0.
+ * factors; mat_idx: device int32 [batch] in [0, nmat); nu: device [batch] > 0 (+INFINITY: the normal CDF).
  * p: device [batch] estimates; logp (optional): log of the estimate computed
  * without underflow of the first factor; stderr_ (optional): standard error
  * over shifts (0 for m = 1). */
@@ -361,7 +369,8 @@ cfust_status cfust_batch_tune(cfust_batch batch, int32_t *chosen, void *stream);
  *     Sigma_h = S - (1 - alpha) diag(s*)   on the skewed coordinates,
  *     mu_h = ybar - sqrt(2/pi) delta,   Delta_h[:, l] = delta_l e_l (l < q),
  *     nu_h = nu0,   pi_h = n_h / n
- * (the square root covers s*_i; with q < p the first q coordinates are
+ * (nu0 > 0, or +INFINITY for starting values of the normal limit; the
+ * square root covers s*_i; with q < p the first q coordinates are
  * skewed).  A candidate (s, a) is invalid when a cluster has n_h < p + 1 or a
  * Sigma_h that is not positive definite.  The log-likelihood (eq. 27) of
  * every valid candidate is evaluated in one density-only batch with the
