@@ -498,9 +498,9 @@ cfust_status cfust_batch_tune(cfust_batch b, int32_t *chosen, void *stream) {
     const int ncu = h->ncu > 0 ? h->ncu : 256;
     for (Queue &Q : b->queues) {
         if (e != hipSuccess) break;
-        double best = 1e300;
+        double best = 1e300, best_grid = 1e300;
         Cand bc{Q.persist, Q.rows, Q.mult};
-        int bppl = Q.ppl;
+        int bppl = Q.ppl, grid_ppl = 1;
         // the same prefix of the queue for every candidate: about 16 items
         // per wave the chip holds at 8 waves per SIMD
         const long long want = std::min(Q.items, (long long)ncu * 4 * 8 * 16);
@@ -527,7 +527,15 @@ cfust_status cfust_batch_tune(cfust_batch b, int32_t *chosen, void *stream) {
                 if (e == hipSuccess && per_item < best) {
                     best = per_item; bc = C; bppl = ppl;
                 }
+                if (e == hipSuccess && !C.persist && per_item < best_grid) {
+                    best_grid = per_item; grid_ppl = ppl;
+                }
             }
+        // a persistent form must win clearly on the prefix: its timing there
+        // has been seen to overstate it on the whole queue
+        if (bc.persist && best_grid < 1e300 && best > 0.95 * best_grid) {
+            bc = cands[6]; bppl = grid_ppl;
+        }
         Q.persist = bc.persist; Q.mult = bc.mult; Q.ppl = bppl;
         set_grid(b, Q);
         build_segments(b, Q, bc.rows);

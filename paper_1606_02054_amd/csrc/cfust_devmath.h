@@ -209,6 +209,17 @@ __device__ __forceinline__ float tab_cdf_H(const float *tab, float pos) {
     return tab_poly(tab + 8 * k, x);
 }
 
+// Normal limit: log2 Phi(-v), v >= 0, from the CDF rows of the dof-free
+// normal table (geometric intervals of v + 1/4; v is clamped to 63.5, where
+// the probability is far below any that matters).
+__device__ __forceinline__ float tab_ncdf_l2(const float *tab, float v) {
+    const float zz = fminf(v, 63.5f) + 0.25f;
+    const int e = __builtin_amdgcn_frexp_expf(zz);     // zz = mant 2^e, mant in [0.5, 1)
+    const float mant = __builtin_amdgcn_frexp_mantf(zz);
+    const float x = fmaf(4.0f, mant, -3.0f);
+    return tab_poly(tab + 8 * (e + 1), x);
+}
+
 // log2 tau from the quantile rows, given l2p = log2 p of the tail probability
 // p <= 1/2; the table variable is lam = -log2(2p) = -1 - l2p, clamped to
 // [0, INV_LAMBDA_MAX] and offset by 1/4 (both folded into one clamp of

@@ -204,8 +204,17 @@ __global__ void k_status_fold(const CompPre *__restrict__ pre, int g, int32_t *_
 // One block per (component, dof offset): 19 rows x 7 nodes evaluated in
 // parallel, then one thread per row fits and writes the row.
 __device__ inline double table_node_value(double nu, int row, int n) {
-    const double a = 0.5 * nu, lb = dm_lbeta_half(a);
     const double x = cos(M_PI * (n + 0.5) / 7.0);
+    if (isinf(nu)) {
+        // normal limit (dof-free): CDF rows hold log2 Phi(-v) on geometric
+        // intervals of v + 1/4, quantile rows Phi^-1(2^-(lam+1)) on those of
+        // lam + 1/4 (the same interval layout as the t quantile rows)
+        const int k = row < TAB_CDF_ROWS ? row : row - TAB_CDF_ROWS;
+        const double w = 0.25 * (double)(1 << k);
+        const double v = w - 0.25 + w * 0.5 * (x + 1.0);
+        return row < TAB_CDF_ROWS ? dm_lnPhi_lower(-v) / LN2 : dm_ninv_lower(-(v + 1.0) * LN2);
+    }
+    const double a = 0.5 * nu, lb = dm_lbeta_half(a);
     if (row < TAB_CDF_ROWS) {
         const double tau = (row + 0.5 * (x + 1.0)) / 8.0;
         const double s = 1.0 - tau;
@@ -246,11 +255,6 @@ __device__ inline void tables_body(const CompPre *__restrict__ pre, int p, int n
     const double nu = pre[h].nu + p + off;
     __shared__ double fv[TAB_NODES];
     const int t = threadIdx.x;
-    if (isinf(nu)) {                             // normal limit: the integrand needs no tables
-        float *dst = tabs + ((size_t)h * NDOF + off) * TAB_FLOATS;
-        for (int i = t; i < TAB_FLOATS; i += blockDim.x) dst[i] = 0.0f;
-        return;
-    }
     if (t < TAB_NODES) fv[t] = table_node_value(nu, t / 7, t % 7);
     __syncthreads();
     float *dst = tabs + ((size_t)h * NDOF + off) * TAB_FLOATS;
@@ -404,7 +408,7 @@ __device__ inline bool qmc_item(const EstepQmcArgs &a, int h, int idx, int j, co
     ItemResult r{0.0, 0.0, -INFINITY};
     if (w->H.e0 > 0.0 || w->H.lne0 > -INFINITY) {
         if (MIXED) {
-            const bool ok = normal ? sov_mixed_normal<M, PPL>(w->H, w->b, w->L, a.lat, smean, lane)
+            const bool ok = normal ? sov_mixed_normal<M, PPL>(w->H, w->b, w->L, a.lat, tab, smean, lane)
                                    : sov_mixed<M, PPL>(w->H, w->b, w->L, w->nu0, a.lat, tab, smean, lane);
             if (!ok) return false;
         } else {
@@ -679,8 +683,17 @@ __global__ __launch_bounds__(256) void k_mvt(MvtArgs a) {
     double est = 0.0, se = 0.0, lnest = -INFINITY;
     if (H.e0 > 0.0 || H.lne0 > -INFINITY) {
         if (MIXED && isinf(nu)) {
-            const bool ok = (a.lat.N % 128 == 0) ? sov_mixed_normal<M, 2>(H, b, L, a.lat, smean[wave], lane)
-                                                 : sov_mixed_normal<M, 1>(H, b, L, a.lat, smean[wave], lane);
+            // the normal tables are dof-free: one slot serves every coordinate
+            for (int t = lane; t < TAB_NODES; t += 64) fv[wave][t] = table_node_value(nu, t / 7, t % 7);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (lane < TAB_CDF_ROWS + TAB_INV_ROWS) table_fit_row(fv[wave] + 7 * lane, tab[wave] + 8 * lane);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const bool ok = (a.lat.N % 128 == 0) ? sov_mixed_normal<M, 2>(H, b, L, a.lat, tab[wave], smean[wave], lane)
+                                                 : sov_mixed_normal<M, 1>(H, b, L, a.lat, tab[wave], smean[wave], lane);
             if (lane == 0) a.flag[it] = ok ? 0 : 1;
             if (!ok) return;
         } else if (MIXED) {

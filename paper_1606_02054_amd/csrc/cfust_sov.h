@@ -224,57 +224,44 @@ __device__ __forceinline__ float sov_point32(const Sov32Setup &P, const float *t
     return f;
 }
 
-// Normal limit, FP32: Phi from erfc, Phi^-1 from erfcinv polished by one
-// Newton step (the device library's FP32 routines).  The first coordinate's truncation probability
-// e_0 comes from FP64 and may be far below the FP32 range: its quantile is
-// taken from log2 p = log2 x + log2 e_0, which stays above 2^-120 because
-// items with log2 e_0 < -96 go to the FP64 integrand (sov_mixed_normal).
-// Later factors are part of the FP32 product, so where they underflow the
-// point carries no weight; their arguments are kept at or above 1e-37, so
-// the quantiles stay finite and no NaN can arise.
+// Normal limit, FP32, from the dof-free normal table (`tab`): the CDF rows
+// give log2 Phi(-v), the quantile rows Phi^-1 directly, in the same
+// log-domain form as the t path (so the first coordinate, whose e_0 comes
+// from FP64 and may be far below the FP32 range, keeps its accuracy).
 __device__ __forceinline__ float nquantile_step32(float x, float xb, float e, float eb, float l2e, bool lowt,
-                                                  bool first) {
-    float arg;
-    bool lower;
-    if (first && lowt) {
-        arg = fexp2(flog2(x) + l2e);
-        lower = true;
-    } else {
-        const float p = x * e;
-        const float pb = fmaf(xb, e, eb);
-        lower = lowt || p <= 0.5f;
-        arg = fmaxf(lower ? p : pb, 1e-37f);
-    }
-    // erfcinv start, then one Newton step on Phi(z) = arg with Phi from erfc
-    // (relative accuracy in the lower tail): the start alone is not accurate
-    // enough there for the conditional limits that follow
-    float z = -1.41421356f * erfcinvf(2.0f * arg);
-    const float phi = 0.39894228f * fexp2(-0.72134752f * z * z);     // exp(-z^2/2) / sqrt(2 pi)
-    z -= (0.5f * erfcf(-0.70710678f * z) - arg) / phi;
+                                                  const float *tab) {
+    const float p = x * e;
+    const float pb = fmaf(xb, e, eb);
+    const bool lower = lowt || p <= 0.5f;
+    const float arg = lowt ? x : (lower ? p : pb);
+    const float l2q = flog2(arg) + (lowt ? l2e : 0.0f);
+    const float z = tab_inv_G(tab, l2q);             // Phi^-1(2^l2q) <= 0
     return lower ? z : -z;
 }
 
 template <int M>
-__device__ __forceinline__ float sov_point32_normal(const Sov32Setup &P, uint32_t k, const uint32_t *zz,
-                                                    uint32_t mask, int sh, const uint32_t *shfix) {
+__device__ __forceinline__ float sov_point32_normal(const Sov32Setup &P, const float *tab, uint32_t k,
+                                                    const uint32_t *zz, uint32_t mask, int sh,
+                                                    const uint32_t *shfix) {
     float y[M];
     float x, xb;
     point32(k, zz[0], mask, sh, shfix[0], x, xb);
-    y[0] = nquantile_step32(x, xb, P.e0, P.eb0, P.l2e0, P.low0, true);
+    y[0] = nquantile_step32(x, xb, P.e0, P.eb0, P.l2e0, P.low0, tab);
     float f = 1.0f;
 #pragma unroll
     for (int i = 1; i < M; ++i) {
         float num = P.b[i];
 #pragma unroll
         for (int j = 0; j < i; ++j) num = fmaf(-P.L[i * M + j], y[j], num);
-        const float small = 0.5f * erfcf(fabsf(num) * P.a[i]);      // a[i] = 1 / (sqrt 2 L_ii)
+        const float l2 = tab_ncdf_l2(tab, fabsf(num) * P.a[i]);      // a[i] = 1 / L_ii
+        const float small = fexp2(l2);
         const bool lowt = num <= 0.0f;
         const float e = lowt ? small : 1.0f - small;
         const float eb = lowt ? 1.0f - small : small;
         f *= e;
         if (i < M - 1) {
             point32(k, zz[i], mask, sh, shfix[i], x, xb);
-            y[i] = nquantile_step32(x, xb, e, eb, 0.0f, lowt, false);
+            y[i] = nquantile_step32(x, xb, e, eb, l2, lowt, tab);
         }
     }
     return f;
@@ -298,13 +285,13 @@ __device__ float sov_lane_sum32(const Sov32Setup &P, const float *tabs, const ui
 }
 
 template <int M, int PPL>
-__device__ float sov_lane_sum32_normal(const Sov32Setup &P, const uint32_t *zz, uint32_t mask, int sh,
-                                       const uint32_t *shfix, int N, int lane) {
+__device__ float sov_lane_sum32_normal(const Sov32Setup &P, const float *tab, const uint32_t *zz, uint32_t mask,
+                                       int sh, const uint32_t *shfix, int N, int lane) {
     float acc = 0.0f;
     for (int k = lane; k < N; k += 64 * PPL) {
         float f[PPL];
 #pragma unroll
-        for (int u = 0; u < PPL; ++u) f[u] = sov_point32_normal<M>(P, (uint32_t)(k + 64 * u), zz, mask, sh, shfix);
+        for (int u = 0; u < PPL; ++u) f[u] = sov_point32_normal<M>(P, tab, (uint32_t)(k + 64 * u), zz, mask, sh, shfix);
 #pragma unroll
         for (int u = 0; u < PPL; ++u) acc += f[u];
     }
@@ -416,16 +403,17 @@ __device__ bool sov_mixed(const SovHead &H, const double *b, const double *L, do
     return tot / Lt.S > 1e-30;
 }
 
-// The same for the normal limit (dof infinite): no tables, Phi and Phi^-1.
-// An item whose first factor is below 2^-96 is left to the FP64 integrand
-// (returns false), so the FP32 first quantile never leaves the FP32 range.
+// The same for the normal limit (dof infinite), with the dof-free normal
+// table `tab` (every coordinate uses it).  An item whose first factor is
+// below 2^-480 (past the quantile table's range) is left to the FP64
+// integrand (returns false).
 template <int M, int PPL>
 __device__ bool sov_mixed_normal(const SovHead &H, const double *b, const double *L, const Lattice &Lt,
-                                 double *smean, int lane) {
-    if (H.low0 && H.lne0 < -96.0 * LN2) return false;
+                                 const float *tab, double *smean, int lane) {
+    if (H.low0 && H.lne0 < -480.0 * LN2) return false;
     Sov32Setup P;
 #pragma unroll
-    for (int i = 0; i < M; ++i) { P.b[i] = (float)b[i]; P.a[i] = (float)(M_SQRT1_2 / L[i * M + i]); }
+    for (int i = 0; i < M; ++i) { P.b[i] = (float)b[i]; P.a[i] = (float)(1.0 / L[i * M + i]); }
 #pragma unroll
     for (int i = 0; i < M * M; ++i) P.L[i] = (float)L[i];
     P.e0 = (float)H.e0; P.eb0 = (float)H.eb0; P.l2e0 = (float)(H.lne0 / LN2); P.low0 = H.low0;
@@ -439,7 +427,7 @@ __device__ bool sov_mixed_normal(const SovHead &H, const double *b, const double
     for (int s = 0; s < Lt.S; ++s) {
 #pragma unroll
         for (int i = 0; i < M - 1; ++i) shfix[i] = (uint32_t)(Lt.shifts[s * LATD + i] * 4294967296.0);
-        const float ls = sov_lane_sum32_normal<M, PPL>(P, zz, mask, sh, shfix, Lt.N, lane);
+        const float ls = sov_lane_sum32_normal<M, PPL>(P, tab, zz, mask, sh, shfix, Lt.N, lane);
         const double ms = wave_sum((double)ls) / (double)Lt.N;
         if (lane == 0) smean[s] = ms;
         tot += ms;
