@@ -28,13 +28,21 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint
 constexpr float GELU_C = 0.7978845608028654f;   // sqrt(2/pi)
 constexpr float GELU_A = 0.044715f;
 
+// tanh u = 1 - 2 / (e^(2u) + 1): one exp2 and one reciprocal.  Its absolute
+// error (a few 1e-8) is far below the BF16 rounding of the activations; the
+// limits +-1 come out exactly when e^(2u) overflows or underflows.
+__device__ __forceinline__ float fast_tanh(float u) {
+    const float e = __builtin_amdgcn_exp2f(2.8853900817779268f * u);     // e^(2u)
+    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+}
+
 __device__ __forceinline__ float gelu(float z) {
     const float u = GELU_C * (z + GELU_A * z * z * z);
-    return 0.5f * z * (1.0f + tanhf(u));
+    return 0.5f * z * (1.0f + fast_tanh(u));
 }
 __device__ __forceinline__ float gelu_grad(float z) {
     const float u = GELU_C * (z + GELU_A * z * z * z);
-    const float t = tanhf(u);
+    const float t = fast_tanh(u);
     return 0.5f * (1.0f + t) + 0.5f * z * (1.0f - t * t) * GELU_C * (1.0f + 3.0f * GELU_A * z * z);
 }
 
@@ -230,9 +238,89 @@ static hipError_t gemm(const uint16_t *P, const uint16_t *Q, int M, int N, int K
     return hipGetLastError();
 }
 
+// Inference (no activations saved): the whole network for a tile of 64 rows
+// in one block, the tile's activations staying in LDS between layers.  Each
+// wave computes 64 rows x 64 output columns of a hidden layer (4 x 4 MFMA
+// tiles; weight fragments read straight from global memory, so every block
+// reads each weight matrix once), then, after every wave has read the layer's
+// input, writes its BF16 outputs back over it.  The operands, the K order,
+// the bias, GELU and BF16 rounding are those of k_gemm_bf16, so the results
+// equal the layer-by-layer pass bit for bit.
+constexpr int FU_ROWS = 64;
+constexpr int FU_STRIDE = CFUST_MLP_HIDDEN + 8;     // LDS row pitch (BF16): rows fall in different banks
+
+// One hidden layer of the fused pass (K inputs, 256 outputs), in place in xs.
+template <int K>
+__device__ __forceinline__ void fused_hidden_layer(uint16_t *xs, const uint16_t *__restrict__ Wl,
+                                                   const float *__restrict__ bl, int wave, int lr, int lk) {
+    const int col_w = 64 * wave;
+    v4f acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        v4s pa[4], qb[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            qb[b] = *reinterpret_cast<const v4s *>(Wl + (size_t)(col_w + 16 * b + lr) * K + k0 + lk);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+            pa[a] = *reinterpret_cast<const v4s *>(xs + (16 * a + lr) * FU_STRIDE + k0 + lk);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(pa[a], qb[b], acc[a][b], 0, 0, 0);
+    }
+    __syncthreads();                                                       // the layer's input is read
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int col = col_w + 16 * b + lr;
+        const float bias = bl[col];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                xs[(16 * a + lk + i) * FU_STRIDE + col] = f2bf(gelu(acc[a][b][i] + bias));
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_mlp_fwd_fused(const uint16_t *__restrict__ X0, cfust_mlp_weights W,
+                                                       float *__restrict__ out) {
+    __shared__ __align__(16) uint16_t xs[FU_ROWS * FU_STRIDE];
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int lr = l & 15, lk = 4 * (l >> 4);
+    const size_t row0 = (size_t)blockIdx.x * FU_ROWS;
+    for (int t = threadIdx.x; t < FU_ROWS * CFUST_MLP_IN; t += blockDim.x)
+        xs[(t / CFUST_MLP_IN) * FU_STRIDE + t % CFUST_MLP_IN] = X0[row0 * CFUST_MLP_IN + t];
+    __syncthreads();
+    fused_hidden_layer<CFUST_MLP_IN>(xs, (const uint16_t *)W.W[0], W.b[0], wave, lr, lk);
+    for (int layer = 1; layer < CFUST_MLP_LAYERS - 1; ++layer)
+        fused_hidden_layer<CFUST_MLP_HIDDEN>(xs, (const uint16_t *)W.W[layer], W.b[layer], wave, lr, lk);
+    // output layer, 256 -> 16: wave w takes rows 16 w .. 16 w + 15
+    const int L = CFUST_MLP_LAYERS - 1;
+    const uint16_t *Wl = (const uint16_t *)W.W[L];                          // [16][256]
+    v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < CFUST_MLP_HIDDEN; k0 += 16) {
+        const v4s pa = *reinterpret_cast<const v4s *>(xs + (16 * wave + lr) * FU_STRIDE + k0 + lk);
+        const v4s qb = *reinterpret_cast<const v4s *>(Wl + (size_t)lr * CFUST_MLP_HIDDEN + k0 + lk);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(pa, qb, acc, 0, 0, 0);
+    }
+    const float bias = W.b[L][lr];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) out[(row0 + 16 * wave + lk + i) * CFUST_MLP_OUT + lr] = acc[i] + bias;
+}
+
 hipError_t launch_mlp_forward(const cfust_mlp_weights &W, const uint16_t *X0, int B, float *out,
                               const cfust_mlp_acts *acts, uint16_t *scratch_a, uint16_t *scratch_b,
                               hipStream_t s) {
+    if (!acts) {                                 // inference: the fused kernel (B is a multiple of 64)
+        hipLaunchKernelGGL(k_mlp_fwd_fused, dim3(B / FU_ROWS), dim3(256), 0, s, X0, W, out);
+        return hipGetLastError();
+    }
     const uint16_t *x = X0;
     hipError_t e = hipSuccess;
     for (int l = 0; l < CFUST_MLP_LAYERS && e == hipSuccess; ++l) {

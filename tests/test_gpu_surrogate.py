@@ -70,6 +70,28 @@ def test_forward_backward_vs_reference(sur):
         assert relb <= 3e-2, (l, relb)
 
 
+@pytest.mark.parametrize("rows", [64, 192, 8192])
+def test_fused_inference_equals_layered_forward(sur, rows):
+    """The inference pass (no activations kept: one fused kernel, the tile's
+    activations in LDS) against the per-layer pass the training uses: the
+    same MFMA operands, K order and roundings, so the outputs are equal bit
+    for bit; and against the FP64 reference with BF16 rounding."""
+    cf, S = sur
+    print(f"fused inference rows={rows}", flush=True)
+    rng = np.random.default_rng(17)
+    net = S.SurrogateNet(3, seed=9)
+    Xb, X0 = _bf16_input(rng, rows)
+    out_f = torch.zeros((rows, 16), dtype=torch.float32, device="cuda")
+    out_l = torch.zeros_like(out_f)
+    S.mlp_forward(net, X0, out_f)
+    S.mlp_forward(net, X0, out_l, S.Activations(rows, "cuda"))
+    torch.cuda.synchronize()
+    assert torch.equal(out_f, out_l)
+    Ws, bs = _host_net(net)
+    ref_out, _ = omlp.forward(Ws, bs, Xb, bf16=True)
+    assert np.abs(out_f.cpu().numpy() - ref_out).max() <= 2e-2 * np.abs(ref_out).max()
+
+
 def test_adam_step_vs_reference(sur):
     cf, S = sur
     net = S.SurrogateNet(3, seed=9)
