@@ -94,7 +94,7 @@ cfust_status run_estep(cfust_handle h, const double *y, const cfust_dims &d, con
             G.base = c.take<double>((size_t)(G.rows > 0 ? G.rows : 1));
             sg[nsg++] = G;
         }
-        sa_off = c.take<uint16_t>((size_t)SUR_CHUNK * CFUST_MLP_HIDDEN);
+        sa_off = c.take<uint16_t>(std::max((size_t)SUR_CHUNK * CFUST_MLP_HIDDEN, mlp_packed_elems()));
         sb_off = c.take<uint16_t>((size_t)SUR_CHUNK * CFUST_MLP_HIDDEN);
         total = c.off;
     }
@@ -386,7 +386,7 @@ cfust_status cfust_mlp_forward(cfust_handle h, const cfust_mlp_weights *w, const
                 return fail(h, CFUST_EINVAL, "an activation buffer is NULL");
     }
     Carve c;
-    const size_t sa = c.take<uint16_t>((size_t)B * CFUST_MLP_HIDDEN);
+    const size_t sa = c.take<uint16_t>(std::max((size_t)B * CFUST_MLP_HIDDEN, mlp_packed_elems()));
     const size_t sb = c.take<uint16_t>((size_t)B * CFUST_MLP_HIDDEN);
     if (!acts && (st = ensure_ws(h, c.off)) != CFUST_OK) return st;
     if ((st = hip_check(h, hipSetDevice(h->device), "hipSetDevice")) != CFUST_OK) return st;

@@ -232,6 +232,10 @@ hipError_t launch_mvt_features(int m, int batch, int rows_pad, const double *b, 
 
 int mlp_layer_k(int l);
 int mlp_layer_n(int l);
+// BF16 elements of the weights in the fused pass's fragment order; without
+// acts, launch_mlp_forward packs the weights into scratch_a (at least this
+// many elements) and runs the fused inference kernel.
+size_t mlp_packed_elems();
 hipError_t launch_mlp_forward(const cfust_mlp_weights &W, const uint16_t *X0, int B, float *out,
                               const cfust_mlp_acts *acts, uint16_t *scratch_a, uint16_t *scratch_b,
                               hipStream_t s);

@@ -249,10 +249,33 @@ static hipError_t gemm(const uint16_t *P, const uint16_t *Q, int M, int N, int K
 constexpr int FU_ROWS = 64;
 constexpr int FU_STRIDE = CFUST_MLP_HIDDEN + 8;     // LDS row pitch (BF16): rows fall in different banks
 
+// Weights in MFMA fragment order for the fused pass: for layer l (N x K),
+// element (column tile ct, K step ks, lane, j) = W_l[16 ct + lane % 16][16 ks + 4 (lane / 16) + j],
+// at offset ((ct (K/16) + ks) 64 + lane) 4 + j of the layer's block, so each
+// wave-wide fragment load reads 512 contiguous bytes.  Layer blocks follow
+// one another (N_l K_l elements each).
+constexpr int FU_OFF[CFUST_MLP_LAYERS + 1] = {
+    0, CFUST_MLP_HIDDEN * CFUST_MLP_IN, CFUST_MLP_HIDDEN * CFUST_MLP_IN + CFUST_MLP_HIDDEN * CFUST_MLP_HIDDEN,
+    CFUST_MLP_HIDDEN * CFUST_MLP_IN + 2 * CFUST_MLP_HIDDEN * CFUST_MLP_HIDDEN,
+    CFUST_MLP_HIDDEN * CFUST_MLP_IN + 3 * CFUST_MLP_HIDDEN * CFUST_MLP_HIDDEN,
+    CFUST_MLP_HIDDEN * CFUST_MLP_IN + 3 * CFUST_MLP_HIDDEN * CFUST_MLP_HIDDEN + CFUST_MLP_OUT * CFUST_MLP_HIDDEN};
+
+__global__ __launch_bounds__(256) void k_mlp_pack(cfust_mlp_weights W, uint16_t *__restrict__ Wp) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= FU_OFF[CFUST_MLP_LAYERS]) return;
+    int l = 0;
+    while (t >= FU_OFF[l + 1]) ++l;
+    const int K = l == 0 ? CFUST_MLP_IN : CFUST_MLP_HIDDEN;
+    const int e = t - FU_OFF[l];
+    const int j = e & 3, lane = (e >> 2) & 63, tile = e >> 8;     // tile = ct (K/16) + ks
+    const int ct = tile / (K / 16), ks = tile % (K / 16);
+    Wp[t] = ((const uint16_t *)W.W[l])[(size_t)(16 * ct + (lane & 15)) * K + 16 * ks + 4 * (lane >> 4) + j];
+}
+
 // One hidden layer of the fused pass (K inputs, 256 outputs), in place in xs.
 template <int K>
 __device__ __forceinline__ void fused_hidden_layer(uint16_t *xs, const uint16_t *__restrict__ Wl,
-                                                   const float *__restrict__ bl, int wave, int lr, int lk) {
+                                                   const float *__restrict__ bl, int wave, int l, int lr, int lk) {
     const int col_w = 64 * wave;
     v4f acc[4][4];
 #pragma unroll
@@ -264,7 +287,7 @@ __device__ __forceinline__ void fused_hidden_layer(uint16_t *xs, const uint16_t 
         v4s pa[4], qb[4];
 #pragma unroll
         for (int b = 0; b < 4; ++b)
-            qb[b] = *reinterpret_cast<const v4s *>(Wl + (size_t)(col_w + 16 * b + lr) * K + k0 + lk);
+            qb[b] = *reinterpret_cast<const v4s *>(Wl + ((size_t)((4 * wave + b) * (K / 16) + k0 / 16) * 64 + l) * 4);
 #pragma unroll
         for (int a = 0; a < 4; ++a)
             pa[a] = *reinterpret_cast<const v4s *>(xs + (16 * a + lr) * FU_STRIDE + k0 + lk);
@@ -289,7 +312,7 @@ __device__ __forceinline__ void fused_hidden_layer(uint16_t *xs, const uint16_t 
 }
 
 __global__ __launch_bounds__(256) void k_mlp_fwd_fused(const uint16_t *__restrict__ X0, cfust_mlp_weights W,
-                                                       float *__restrict__ out) {
+                                                       const uint16_t *__restrict__ Wp, float *__restrict__ out) {
     __shared__ __align__(16) uint16_t xs[FU_ROWS * FU_STRIDE];
     const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int lr = l & 15, lk = 4 * (l >> 4);
@@ -297,16 +320,16 @@ __global__ __launch_bounds__(256) void k_mlp_fwd_fused(const uint16_t *__restric
     for (int t = threadIdx.x; t < FU_ROWS * CFUST_MLP_IN; t += blockDim.x)
         xs[(t / CFUST_MLP_IN) * FU_STRIDE + t % CFUST_MLP_IN] = X0[row0 * CFUST_MLP_IN + t];
     __syncthreads();
-    fused_hidden_layer<CFUST_MLP_IN>(xs, (const uint16_t *)W.W[0], W.b[0], wave, lr, lk);
+    fused_hidden_layer<CFUST_MLP_IN>(xs, Wp + FU_OFF[0], W.b[0], wave, l, lr, lk);
     for (int layer = 1; layer < CFUST_MLP_LAYERS - 1; ++layer)
-        fused_hidden_layer<CFUST_MLP_HIDDEN>(xs, (const uint16_t *)W.W[layer], W.b[layer], wave, lr, lk);
+        fused_hidden_layer<CFUST_MLP_HIDDEN>(xs, Wp + FU_OFF[layer], W.b[layer], wave, l, lr, lk);
     // output layer, 256 -> 16: wave w takes rows 16 w .. 16 w + 15
     const int L = CFUST_MLP_LAYERS - 1;
-    const uint16_t *Wl = (const uint16_t *)W.W[L];                          // [16][256]
+    const uint16_t *Wl = Wp + FU_OFF[L];                                    // one column tile
     v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
     for (int k0 = 0; k0 < CFUST_MLP_HIDDEN; k0 += 16) {
         const v4s pa = *reinterpret_cast<const v4s *>(xs + (16 * wave + lr) * FU_STRIDE + k0 + lk);
-        const v4s qb = *reinterpret_cast<const v4s *>(Wl + (size_t)lr * CFUST_MLP_HIDDEN + k0 + lk);
+        const v4s qb = *reinterpret_cast<const v4s *>(Wl + ((size_t)(k0 / 16) * 64 + l) * 4);
         acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(pa, qb, acc, 0, 0, 0);
     }
     const float bias = W.b[L][lr];
@@ -314,11 +337,15 @@ __global__ __launch_bounds__(256) void k_mlp_fwd_fused(const uint16_t *__restric
     for (int i = 0; i < 4; ++i) out[(row0 + 16 * wave + lk + i) * CFUST_MLP_OUT + lr] = acc[i] + bias;
 }
 
+size_t mlp_packed_elems() { return (size_t)FU_OFF[CFUST_MLP_LAYERS]; }
+
 hipError_t launch_mlp_forward(const cfust_mlp_weights &W, const uint16_t *X0, int B, float *out,
                               const cfust_mlp_acts *acts, uint16_t *scratch_a, uint16_t *scratch_b,
                               hipStream_t s) {
     if (!acts) {                                 // inference: the fused kernel (B is a multiple of 64)
-        hipLaunchKernelGGL(k_mlp_fwd_fused, dim3(B / FU_ROWS), dim3(256), 0, s, X0, W, out);
+        // scratch_a receives the weights in fragment order (mlp_packed_elems() BF16)
+        hipLaunchKernelGGL(k_mlp_pack, dim3((FU_OFF[CFUST_MLP_LAYERS] + 255) / 256), dim3(256), 0, s, W, scratch_a);
+        hipLaunchKernelGGL(k_mlp_fwd_fused, dim3(B / FU_ROWS), dim3(256), 0, s, X0, W, scratch_a, out);
         return hipGetLastError();
     }
     const uint16_t *x = X0;
