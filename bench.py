@@ -41,8 +41,8 @@ FLOPS_QUANTILE = 29          # quantile draw y_i
 # kernel sources with this digest only; otherwise the figure is reported null.
 TRAFFIC_SOURCES = ["paper_1606_02054_amd/csrc/cfust_sov.h", "paper_1606_02054_amd/csrc/cfust_devmath.h",
                    "paper_1606_02054_amd/csrc/cfust_estep.hip"]
-TRAFFIC_DIGEST = "a5746a8e5d75c456"
-TRAFFIC_MIB = {"read": 3.22 + 2.72 + 2.73, "write": 4.44 + 5.66 + 7.50}
+TRAFFIC_DIGEST = "c05cf21fbfce52b4"
+TRAFFIC_MIB = {"read": 3.36 + 2.74 + 2.74, "write": 4.78 + 5.66 + 7.50}
 
 
 def kernel_digest() -> str:
