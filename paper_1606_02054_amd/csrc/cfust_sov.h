@@ -154,11 +154,11 @@ __device__ double sov_lane_sum64_normal(const double *b, const double *L, const 
 // and so does xb = 1 - x near 0, from the integer complement: it enters the
 // upper-tail complement p_b = xb e + e_b, whose relative accuracy sets the
 // quantile where the conditional law is sampled far in its upper tail.
-// Needs N a power of two.
-__device__ __forceinline__ void point32(uint32_t k, uint32_t zj, uint32_t mask, int sh, uint32_t shfix,
-                                        float &x, float &xb) {
-    const uint32_t r = (k * zj) & mask;
-    const uint32_t t = (r << sh) + shfix;
+// Needs N a power of two.  t = 2^32 frac(k z_j / N + shift) in fixed point:
+// ((k z_j) << (32 - log2 N)) + shift (the shift drops the bits of k z_j above
+// log2 N, so no reduction mod N is needed), carried from point to point by
+// adding the constant ((64 z_j) << (32 - log2 N)).
+__device__ __forceinline__ void point32(uint32_t t, float &x, float &xb) {
     uint32_t u = min(t, 0u - t);                      // 2^32 min(t, 1-t), in [0, 2^31]
     u = min(max(u, 128u), 2147483520u);               // [2^-24, 1 - 2^-24] after scaling
     x = (float)u * 4.656612873077393e-10f;            // 2^-31
@@ -189,13 +189,11 @@ struct Sov32Setup {
 
 // Integrand value of lattice point k (FP32), product e_1 ... e_{M-1}.
 template <int M>
-__device__ __forceinline__ float sov_point32(const Sov32Setup &P, const float *tabs, uint32_t k,
-                                             const uint32_t *zz, uint32_t mask, int sh,
-                                             const uint32_t *shfix) {
+__device__ __forceinline__ float sov_point32(const Sov32Setup &P, const float *tabs, const uint32_t *t) {
     float y[M];
     float Q = P.sqrtnu;
     float x, xb;
-    point32(k, zz[0], mask, sh, shfix[0], x, xb);
+    point32(t[0], x, xb);
     y[0] = quantile_step32(x, xb, P.e0, P.eb0, P.l2e0, P.low0, tabs, Q);
     float f = 1.0f;
 #pragma unroll
@@ -217,7 +215,7 @@ __device__ __forceinline__ float sov_point32(const Sov32Setup &P, const float *t
         const float eb = lowt ? 1.0f - small : small;
         f *= e;
         if (i < M - 1) {
-            point32(k, zz[i], mask, sh, shfix[i], x, xb);
+            point32(t[i], x, xb);
             y[i] = quantile_step32(x, xb, e, eb, l2, lowt, tab, Q);
         }
     }
@@ -240,12 +238,10 @@ __device__ __forceinline__ float nquantile_step32(float x, float xb, float e, fl
 }
 
 template <int M>
-__device__ __forceinline__ float sov_point32_normal(const Sov32Setup &P, const float *tab, uint32_t k,
-                                                    const uint32_t *zz, uint32_t mask, int sh,
-                                                    const uint32_t *shfix) {
+__device__ __forceinline__ float sov_point32_normal(const Sov32Setup &P, const float *tab, const uint32_t *t) {
     float y[M];
     float x, xb;
-    point32(k, zz[0], mask, sh, shfix[0], x, xb);
+    point32(t[0], x, xb);
     y[0] = nquantile_step32(x, xb, P.e0, P.eb0, P.l2e0, P.low0, tab);
     float f = 1.0f;
 #pragma unroll
@@ -260,40 +256,46 @@ __device__ __forceinline__ float sov_point32_normal(const Sov32Setup &P, const f
         const float eb = lowt ? 1.0f - small : small;
         f *= e;
         if (i < M - 1) {
-            point32(k, zz[i], mask, sh, shfix[i], x, xb);
+            point32(t[i], x, xb);
             y[i] = nquantile_step32(x, xb, e, eb, l2, lowt, tab);
         }
     }
     return f;
 }
 
-// Per-lane FP32 sum over this lane's points of one shift.  PPL independent
-// points are evaluated per loop trip (instruction-level parallelism across
-// the dependency chains); needs N to be a multiple of 64 PPL when PPL > 1.
-template <int M, int PPL>
-__device__ float sov_lane_sum32(const Sov32Setup &P, const float *tabs, const uint32_t *zz,
-                                uint32_t mask, int sh, const uint32_t *shfix, int N, int lane) {
-    float acc = 0.0f;
-    for (int k = lane; k < N; k += 64 * PPL) {
-        float f[PPL];
+// Per-lane FP32 sum over this lane's points of one shift: lane l takes points
+// l, l + 64, ...  PPL independent points are evaluated per loop trip
+// (instruction-level parallelism across the dependency chains).  With N a
+// multiple of 64 PPL the trip count is the same for every lane, so the loop
+// is counted in scalar registers; N < 64 (PPL 1) is one weighted trip.  NORMAL
+// selects the normal-limit integrand.
+template <int M, int PPL, bool NORMAL>
+__device__ float sov_lane_sum32(const Sov32Setup &P, const float *tabs, const uint32_t *zz, int sh,
+                                const uint32_t *shfix, int N, int lane) {
+    uint32_t t[PPL][M], step[M];
 #pragma unroll
-        for (int u = 0; u < PPL; ++u) f[u] = sov_point32<M>(P, tabs, (uint32_t)(k + 64 * u), zz, mask, sh, shfix);
+    for (int i = 0; i < M - 1; ++i) {
+        step[i] = ((uint32_t)(64 * PPL) * zz[i]) << sh;
 #pragma unroll
-        for (int u = 0; u < PPL; ++u) acc += f[u];
+        for (int u = 0; u < PPL; ++u) t[u][i] = (((uint32_t)(lane + 64 * u) * zz[i]) << sh) + shfix[i];
     }
-    return acc;
-}
-
-template <int M, int PPL>
-__device__ float sov_lane_sum32_normal(const Sov32Setup &P, const float *tab, const uint32_t *zz, uint32_t mask,
-                                       int sh, const uint32_t *shfix, int N, int lane) {
+    auto point = [&](const uint32_t *tt) {
+        return NORMAL ? sov_point32_normal<M>(P, tabs, tt) : sov_point32<M>(P, tabs, tt);
+    };
+    // N < 64 (PPL 1): one trip in which the lanes at or past N weigh 0
+    const float wl = (N >= 64 * PPL || lane < N) ? 1.0f : 0.0f;
+    const int trips = max(N / (64 * PPL), 1);
     float acc = 0.0f;
-    for (int k = lane; k < N; k += 64 * PPL) {
+    for (int it = 0; it < trips; ++it) {
         float f[PPL];
 #pragma unroll
-        for (int u = 0; u < PPL; ++u) f[u] = sov_point32_normal<M>(P, tab, (uint32_t)(k + 64 * u), zz, mask, sh, shfix);
+        for (int u = 0; u < PPL; ++u) f[u] = point(t[u]);
 #pragma unroll
-        for (int u = 0; u < PPL; ++u) acc += f[u];
+        for (int u = 0; u < PPL; ++u) acc = fmaf(f[u], wl, acc);
+#pragma unroll
+        for (int u = 0; u < PPL; ++u)
+#pragma unroll
+            for (int i = 0; i < M - 1; ++i) t[u][i] += step[i];
     }
     return acc;
 }
@@ -387,7 +389,6 @@ __device__ bool sov_mixed(const SovHead &H, const double *b, const double *L, do
     P.e0 = (float)H.e0; P.eb0 = (float)H.eb0; P.l2e0 = (float)(H.lne0 / LN2); P.low0 = H.low0;
     P.sqrtnu = (float)sqrt(nu);
     uint32_t zz[M], shfix[M];
-    const uint32_t mask = (uint32_t)Lt.N - 1u;
     const int sh = 32 - Lt.log2N;
 #pragma unroll
     for (int i = 0; i < M - 1; ++i) zz[i] = (uint32_t)Lt.z[i];
@@ -395,7 +396,7 @@ __device__ bool sov_mixed(const SovHead &H, const double *b, const double *L, do
     for (int s = 0; s < Lt.S; ++s) {
 #pragma unroll
         for (int i = 0; i < M - 1; ++i) shfix[i] = (uint32_t)(Lt.shifts[s * LATD + i] * 4294967296.0);
-        const float ls = sov_lane_sum32<M, PPL>(P, tabs, zz, mask, sh, shfix, Lt.N, lane);
+        const float ls = sov_lane_sum32<M, PPL, false>(P, tabs, zz, sh, shfix, Lt.N, lane);
         const double ms = wave_sum((double)ls) / (double)Lt.N;
         if (lane == 0) smean[s] = ms;
         tot += ms;
@@ -419,7 +420,6 @@ __device__ bool sov_mixed_normal(const SovHead &H, const double *b, const double
     P.e0 = (float)H.e0; P.eb0 = (float)H.eb0; P.l2e0 = (float)(H.lne0 / LN2); P.low0 = H.low0;
     P.sqrtnu = 1.0f;
     uint32_t zz[M], shfix[M];
-    const uint32_t mask = (uint32_t)Lt.N - 1u;
     const int sh = 32 - Lt.log2N;
 #pragma unroll
     for (int i = 0; i < M - 1; ++i) zz[i] = (uint32_t)Lt.z[i];
@@ -427,7 +427,7 @@ __device__ bool sov_mixed_normal(const SovHead &H, const double *b, const double
     for (int s = 0; s < Lt.S; ++s) {
 #pragma unroll
         for (int i = 0; i < M - 1; ++i) shfix[i] = (uint32_t)(Lt.shifts[s * LATD + i] * 4294967296.0);
-        const float ls = sov_lane_sum32_normal<M, PPL>(P, tab, zz, mask, sh, shfix, Lt.N, lane);
+        const float ls = sov_lane_sum32<M, PPL, true>(P, tab, zz, sh, shfix, Lt.N, lane);
         const double ms = wave_sum((double)ls) / (double)Lt.N;
         if (lane == 0) smean[s] = ms;
         tot += ms;
