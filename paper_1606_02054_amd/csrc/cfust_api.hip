@@ -207,10 +207,11 @@ cfust_status cfust_create(cfust_handle *handle, int device) {
 
 cfust_status cfust_destroy(cfust_handle h) {
     if (!h) return CFUST_EINVAL;
-    hipSetDevice(h->device);
-    for (auto &r : h->rec) { hipEventSynchronize(r.e1); hipEventDestroy(r.e0); hipEventDestroy(r.e1); }
-    for (auto e : h->pool) hipEventDestroy(e);
-    if (h->ws) hipFree(h->ws);
+    // teardown: errors here have no caller left to act on them
+    (void)hipSetDevice(h->device);
+    for (auto &r : h->rec) { (void)hipEventSynchronize(r.e1); (void)hipEventDestroy(r.e0); (void)hipEventDestroy(r.e1); }
+    for (auto e : h->pool) (void)hipEventDestroy(e);
+    if (h->ws) (void)hipFree(h->ws);
     delete h;
     return CFUST_OK;
 }

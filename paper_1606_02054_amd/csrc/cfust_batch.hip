@@ -158,8 +158,8 @@ QueueArgs queue_args(cfust_batch b, const Queue &Q, long long ntiles) {
 }
 
 void drop_graph(cfust_batch b) {
-    if (b->exec) hipGraphExecDestroy(b->exec);
-    if (b->graph) hipGraphDestroy(b->graph);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
     b->graph = nullptr;
 }
@@ -398,12 +398,13 @@ cfust_status cfust_batch_create(cfust_handle h, int32_t nfits, const cfust_fit *
 
 cfust_status cfust_batch_destroy(cfust_batch b) {
     if (!b) return CFUST_EINVAL;
-    hipSetDevice(b->h->device);
+    // teardown: errors here have no caller left to act on them
+    (void)hipSetDevice(b->h->device);
     drop_graph(b);
-    if (b->cap) hipStreamDestroy(b->cap);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
     if (b->ws) {
-        hipDeviceSynchronize();
-        hipFree(b->ws);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(b->ws);
     }
     delete b;
     return CFUST_OK;
@@ -462,7 +463,7 @@ cfust_status cfust_fit_batch(cfust_batch b, int32_t iters, double tol, int32_t u
             e = hipStreamEndCapture(b->cap, &g);
             if (el != hipSuccess) e = el;
             if (e == hipSuccess) b->graph = g;
-            else if (g) hipGraphDestroy(g);
+            else if (g) (void)hipGraphDestroy(g);
         }
         if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
         if (e != hipSuccess) {
@@ -546,8 +547,8 @@ cfust_status cfust_batch_tune(cfust_batch b, int32_t *chosen, void *stream) {
             chosen[Q.m * 3 + 2] = Q.ppl;
         }
     }
-    if (e0) hipEventDestroy(e0);
-    if (e1) hipEventDestroy(e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
     drop_graph(b);
     if (e == hipSuccess) e = launch_fill_i32(b->counters, 4 * b->queues.size(), 0, s);
     return hip_check(h, e, "cfust_batch_tune");
@@ -620,7 +621,7 @@ cfust_status cfust_init(cfust_handle h, const double *y, cfust_dims d, int32_t n
     hipError_t e = hipMemcpy((void *)A.alpha, alpha, sizeof(double) * nalpha, hipMemcpyHostToDevice);
     if (e == hipSuccess) {
         st = cfust_batch_create(h, C, fits.data(), qmc, &b);
-        if (st != CFUST_OK) { hipFree(ws); return st; }
+        if (st != CFUST_OK) { (void)hipFree(ws); return st; }
     }
     // statistics, candidates, and their validity as the batch's active mask
     if (e == hipSuccess) e = launch_init_stats(A, s);
@@ -629,7 +630,7 @@ cfust_status cfust_init(cfust_handle h, const double *y, cfust_dims d, int32_t n
     if (e == hipSuccess) e = launch_init_select(A, b->active, llc, loglik, best_index, *best, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (b) cfust_batch_destroy(b);
-    hipFree(ws);
+    (void)hipFree(ws);
     return hip_check(h, e, "cfust_init");
 }
 
