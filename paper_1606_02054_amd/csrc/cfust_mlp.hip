@@ -6,8 +6,9 @@
 // GEMM convention: C[M][N] = P[M][K] * Q[N][K]^T with P, Q row-major BF16
 // (K contiguous).  One 256-thread block computes a 64 x 64 tile of C; each
 // wave a 32 x 32 quarter as 2 x 2 MFMA tiles of 16 x 16, stepping K by 16.
-// Operand fragments are read straight from global memory (8 bytes per lane:
-// four consecutive K values), the layout the 16x16x16 BF16 MFMA expects:
+// 64 x 32 slices of P and Q are staged in LDS with coalesced 16-byte loads;
+// operand fragments (8 bytes per lane: four consecutive K values) are read
+// from there in the layout the 16x16x16 BF16 MFMA expects:
 //   lane l holds P[row0 + l%16][k0 + 4(l/16) + 0..3] and Q[col0 + l%16][k0 + 4(l/16) + 0..3],
 //   and receives C[row0 + 4(l/16) + i][col0 + l%16], i = 0..3.
 #include "cfust_kernels.h"
@@ -58,9 +59,16 @@ struct GemmOut {
 
 __global__ __launch_bounds__(256) void k_gemm_bf16(const uint16_t *__restrict__ P, const uint16_t *__restrict__ Q,
                                                    int M, int N, int K, int kchunk, GemmOut o) {
+    // 64 x 32 slices of P and Q staged in LDS per step, one 16-byte load per
+    // thread and operand (row t/4, K offset 8 (t%4)); rows past M or N and K
+    // past the chunk are zero, which adds exact zeros to the same MFMA
+    // sequence (K ascending by 16) as fragments read straight from memory
+    constexpr int KC = 32, KP = KC + 8;          // pitch: 80-byte rows spread over the banks
+    __shared__ __align__(16) uint16_t ps[64 * KP], qs[64 * KP];
     const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int row_w = blockIdx.y * 64 + 32 * (wave >> 1);
-    const int col_w = blockIdx.x * 64 + 32 * (wave & 1);
+    const int wr = 32 * (wave >> 1), wc = 32 * (wave & 1);          // the wave's quarter of the tile
+    const int row_w = blockIdx.y * 64 + wr;
+    const int col_w = blockIdx.x * 64 + wc;
     const int k_beg = blockIdx.z * kchunk;
     const int k_end = min(K, k_beg + kchunk);
     v4f acc[2][2];
@@ -71,20 +79,33 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const uint16_t *__restrict__ 
     const bool colok[2] = {col_w < N, col_w + 16 < N};
     const bool rowok[2] = {row_w < M, row_w + 16 < M};
     const int lr = l & 15, lk = 4 * (l >> 4);
-    for (int k0 = k_beg; k0 < k_end; k0 += 16) {
-        v4s pa[2], qb[2];
-#pragma unroll
-        for (int a = 0; a < 2; ++a) {
-            if (rowok[a]) pa[a] = *reinterpret_cast<const v4s *>(P + (size_t)(row_w + 16 * a + lr) * K + k0 + lk);
-            else pa[a] = v4s{0, 0, 0, 0};
-            if (colok[a]) qb[a] = *reinterpret_cast<const v4s *>(Q + (size_t)(col_w + 16 * a + lr) * K + k0 + lk);
-            else qb[a] = v4s{0, 0, 0, 0};
+    const int srow = threadIdx.x >> 2, sk = 8 * (threadIdx.x & 3);
+    const int prow = blockIdx.y * 64 + srow, qrow = blockIdx.x * 64 + srow;
+    for (int k0 = k_beg; k0 < k_end; k0 += KC) {
+        uint4 pv = make_uint4(0, 0, 0, 0), qv = make_uint4(0, 0, 0, 0);
+        if (k0 + sk < k_end) {                  // K, kchunk multiples of 16: the 8 values are all in range
+            if (prow < M) pv = *reinterpret_cast<const uint4 *>(P + (size_t)prow * K + k0 + sk);
+            if (qrow < N) qv = *reinterpret_cast<const uint4 *>(Q + (size_t)qrow * K + k0 + sk);
         }
+        *reinterpret_cast<uint4 *>(ps + srow * KP + sk) = pv;
+        *reinterpret_cast<uint4 *>(qs + srow * KP + sk) = qv;
+        __syncthreads();
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int kk = 0; kk < KC; kk += 16) {
+            if (k0 + kk >= k_end) break;
+            v4s pa[2], qb[2];
 #pragma unroll
-            for (int b = 0; b < 2; ++b)
-                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(pa[a], qb[b], acc[a][b], 0, 0, 0);
+            for (int a = 0; a < 2; ++a) {
+                pa[a] = *reinterpret_cast<const v4s *>(ps + (wr + 16 * a + lr) * KP + kk + lk);
+                qb[a] = *reinterpret_cast<const v4s *>(qs + (wc + 16 * a + lr) * KP + kk + lk);
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(pa[a], qb[b], acc[a][b], 0, 0, 0);
+        }
+        __syncthreads();
     }
 #pragma unroll
     for (int a = 0; a < 2; ++a)
