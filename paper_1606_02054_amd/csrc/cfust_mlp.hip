@@ -151,15 +151,32 @@ __global__ void k_sum_split(const float *__restrict__ part, int nsplit, size_t c
 
 // dZ = dY * gelu'(Z) (or dY when the layer has no activation), written as BF16
 // in both layouts, and the bias gradient by a column reduction.
-__global__ void k_act_back(const float *__restrict__ dY, const float *__restrict__ Z, int M, int N, int act,
-                           uint16_t *__restrict__ dZb, uint16_t *__restrict__ dZbT) {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (size_t)M * N) return;
-    const int r = (int)(i / N), c = (int)(i % N);
-    const float g = act ? dY[i] * gelu_grad(Z[i]) : dY[i];
-    const uint16_t h = f2bf(g);
-    dZb[i] = h;
-    dZbT[(size_t)c * M + r] = h;
+// dZ = dY * GELU'(Z) (or dY) in BF16, row-major and transposed.  One block
+// per 64 x 64 tile: coalesced row-major reads and writes, the transposed copy
+// written through an LDS tile so its stores are coalesced too.
+__global__ __launch_bounds__(256) void k_act_back(const float *__restrict__ dY, const float *__restrict__ Z, int M,
+                                                  int N, int act, uint16_t *__restrict__ dZb,
+                                                  uint16_t *__restrict__ dZbT) {
+    __shared__ uint16_t tile[64][66];            // odd dword pitch: column reads hit distinct banks
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+#pragma unroll 4
+    for (int j = 0; j < 16; ++j) {
+        const int rr = ty + 4 * j, r = r0 + rr, c = c0 + tx;
+        if (r < M && c < N) {
+            const size_t i = (size_t)r * N + c;
+            const float g = act ? dY[i] * gelu_grad(Z[i]) : dY[i];
+            const uint16_t h = f2bf(g);
+            dZb[i] = h;
+            tile[rr][tx] = h;
+        }
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int j = 0; j < 16; ++j) {
+        const int cc = ty + 4 * j, c = c0 + cc, r = r0 + tx;
+        if (r < M && c < N) dZbT[(size_t)c * M + r] = tile[tx][cc];
+    }
 }
 
 __global__ void k_col_sum(const uint16_t *__restrict__ dZbT, int M, int N, float *__restrict__ db) {
@@ -167,7 +184,16 @@ __global__ void k_col_sum(const uint16_t *__restrict__ dZbT, int M, int N, float
     __shared__ float red[256];
     const int c = blockIdx.x;
     float s = 0.0f;
-    for (int r = threadIdx.x; r < M; r += blockDim.x) s += bf2f(dZbT[(size_t)c * M + r]);
+    // 8 values per 16-byte load (M is a multiple of 64)
+    for (int r = 8 * threadIdx.x; r < M; r += 8 * blockDim.x) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(dZbT + (size_t)c * M + r);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            s += bf2f((uint16_t)(w[k] & 0xffffu));
+            s += bf2f((uint16_t)(w[k] >> 16));
+        }
+    }
     red[threadIdx.x] = s;
     __syncthreads();
     for (int k = 128; k > 0; k >>= 1) {
@@ -399,8 +425,7 @@ hipError_t launch_mlp_backward(const cfust_mlp_weights &W, const cfust_mlp_acts 
     for (int l = CFUST_MLP_LAYERS - 1; l >= 0 && e == hipSuccess; --l) {
         const int N = LAYER_N[l], K = LAYER_K[l];
         const bool last = l == CFUST_MLP_LAYERS - 1;
-        const size_t mn = (size_t)B * N;
-        hipLaunchKernelGGL(k_act_back, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, s, dy,
+        hipLaunchKernelGGL(k_act_back, dim3((N + 63) / 64, (B + 63) / 64), dim3(256), 0, s, dy,
                            last ? nullptr : A.Z[l], B, N, last ? 0 : 1, dZb, dZbT);
         hipLaunchKernelGGL(k_col_sum, dim3(N), dim3(256), 0, s, dZbT, B, N, G.db[l]);
         // dW[N][K] = dZ^T X : P = dZ^T [N][B], Q = X^T [K][B], split over the batch
