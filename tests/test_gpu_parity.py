@@ -163,6 +163,23 @@ def test_estep_bench_workload_sampled(lib, orc):
     np.testing.assert_allclose(gpu.tau.cpu().numpy().sum(0), 1.0, atol=1e-12)
 
 
+def test_estep_cytometry_shape_sampled(lib, orc):
+    """The cytometry-shaped recipe (p = q = 8, g = 5: integrals of dimension
+    6, 7 and 8) at n = 2048 in mixed precision, lattice 1024 x 4: sampled
+    observations against the oracle (the full-size lattice is left to the
+    bench: the FP64 oracle needs minutes per observation there)."""
+    cf = lib
+    print("estep cytometry shape, sampled", flush=True)
+    ds = workload("cfust_n1e6_p8_q8_g5_box1024", n=2048)
+    des = make_design(1024, 4, seed=1606)
+    gpu = _gpu_estep(cf, ds.y, ds.params, des, "mixed")
+    rows = np.array([5, 1500])
+    ora = orc.estep(ds.y, ds.params, des, rows=rows)
+    compare_estep(gpu, ora, "mixed", rows=rows, label="cytometry-sampled")
+    np.testing.assert_allclose(gpu.logf_comp.cpu().numpy()[:, rows], ora.logf_comp, atol=1e-4)
+    assert int(gpu.status.cpu()[0]) == 0
+
+
 def test_loglik_matches_estep_and_oracle(lib, orc):
     cf = lib
     rng = np.random.default_rng(41)
