@@ -41,8 +41,8 @@ FLOPS_QUANTILE = 29          # quantile draw y_i
 # kernel sources with this digest only; otherwise the figure is reported null.
 TRAFFIC_SOURCES = ["paper_1606_02054_amd/csrc/cfust_sov.h", "paper_1606_02054_amd/csrc/cfust_devmath.h",
                    "paper_1606_02054_amd/csrc/cfust_estep.hip"]
-TRAFFIC_DIGEST = "c05cf21fbfce52b4"
-TRAFFIC_MIB = {"read": 3.36 + 2.74 + 2.74, "write": 4.78 + 5.66 + 7.50}
+TRAFFIC_DIGEST = "7bdb8cd0f45d7d72"
+TRAFFIC_MIB = {"read": 3.34 + 2.73 + 2.74, "write": 4.78 + 5.66 + 7.50}
 
 
 def kernel_digest() -> str:
@@ -208,6 +208,67 @@ def initialisation(cf, ds, y, qmc, dev, nstarts: int = 8) -> dict:
     return {"starts": nstarts, "alphas": 9, "candidates": nstarts * 9, "valid": int(np.isfinite(llv).sum()),
             "ms": ms, "candidate_pairs_per_s": nstarts * 9 * n * g / (ms / 1e3), "best_index": k,
             "best_loglik": float(llv.ravel()[k]) if k >= 0 else None}
+
+
+def progress(msg: str) -> None:
+    """One line on stderr per finished bench section (stdout carries only the
+    JSON result)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def precision_split(cf, y, params, design, dev, rows: int = 1024) -> dict:
+    """One E-step over the first ``rows`` observations of the bench workload in
+    mixed precision (FP32 lattice integrand) and in FP64 throughout, on the same
+    lattice: the time of each and the largest difference of the
+    per-observation log-density.  The FP64 path evaluates every t CDF by a
+    continued fraction and every quantile by a root search, so it is timed on
+    a slice of the data."""
+    import torch
+    ys = y[:, :rows].contiguous()
+    out = {"rows": int(ys.shape[1])}
+    res = {}
+    for name, prec in (("mixed", cf.CFUST_MIXED), ("fp64", cf.CFUST_FP64)):
+        qmc = cf.device_qmc(design, prec, device=dev)
+        cf.cfust_estep(ys[:, :64].contiguous(), params, qmc)       # allocations, tables
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        es = cf.cfust_estep(ys, params, qmc)
+        torch.cuda.synchronize()
+        out[f"{name}_estep_ms"] = (time.perf_counter() - t0) * 1e3
+        res[name] = es.logf_obs.cpu().numpy()
+        progress(f"precision split: {name} E-step over {rows} rows {out[name + '_estep_ms']:.1f} ms")
+    out["fp64_over_mixed_time"] = out["fp64_estep_ms"] / out["mixed_estep_ms"]
+    out["max_abs_dlogf_obs"] = float(abs(res["mixed"] - res["fp64"]).max())
+    return out
+
+
+def small_fit(cf, dev, nstarts: int = 4, iters: int = 20) -> dict:
+    """The small configuration end to end in FP64: n = 1000, p = q = 2, g = 2,
+    lattice 1024 x 4; Algorithm 1 over nstarts k-means partitions (seeded
+    input, computed on the host and not timed) x 9 values of alpha, then
+    iters EM iterations."""
+    import torch
+    from cfust_inputs import kmeans_partitions, make_design, workload
+    ds = workload("cfust_n1000_p2_q2_g2")
+    g, q = ds.params.g, ds.params.q
+    y = torch.as_tensor(ds.y_soa, device=dev)
+    qmc = cf.device_qmc(make_design(ds.meta["N"], ds.meta["S"], seed=1606), cf.CFUST_FP64, device=dev)
+    labels = torch.as_tensor(kmeans_partitions(ds.y, g, nstarts, seed=7), device=dev)
+    cf.initialise(y, g, q, labels, qmc)                # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    params, ll0, k = cf.initialise(y, g, q, labels, qmc)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(iters):
+        es = cf.cfust_estep(y, params, qmc)
+        params = cf.cfust_mstep(y, es, params)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    return {"n": int(ds.y.shape[0]), "p": int(ds.y.shape[1]), "q": q, "g": g, "N": ds.meta["N"],
+            "S": ds.meta["S"], "precision": "fp64", "starts": nstarts, "alphas": 9,
+            "init_ms": (t1 - t0) * 1e3, "em_ms_per_iteration": (t2 - t1) * 1e3 / iters, "iterations": iters,
+            "loglik_start": float(ll0.cpu().numpy().ravel()[k]), "loglik_end": float(es.loglik.cpu()[0])}
 
 
 def small_restarts(cf, h, prec, dev, nstarts: int = 64, iters: int = 5) -> dict:
@@ -463,6 +524,7 @@ def main():
         cf.cfust_mstep(y, es, cur, out=nxt)
 
     tuned = h.autotune(y, start, qmc)
+    progress(f"autotuned {args.workload}")
     for k in range(args.warmup):
         step(k)
     torch.cuda.synchronize()
@@ -477,6 +539,7 @@ def main():
     prof = h.profile_read()
     h.profile(False)
     ms_step = (t1 - t0) * 1e3 / args.steps
+    progress(f"timed {args.steps} EM iterations: {ms_step:.2f} ms each")
     pairs = n * g
     value = pairs / (ms_step / 1e3)
     ll = float(es.loglik.cpu()[0])
@@ -513,9 +576,15 @@ def main():
 
     if not args.no_surrogate and prec == cf.CFUST_MIXED:
         out["surrogate"] = surrogate_vs_lattice(cf, ds, y, start, design, n * g)
+        progress("surrogate section done")
     if not args.no_components and args.workload == "cfust_n20000_p4_q4_g3":
         out["component_rooflines"] = component_rooflines(cf, dev)
+        progress("component rooflines done")
         out["initialisation"] = initialisation(cf, ds, y, qmc, dev)
+        progress("initialisation done")
+        out["precision_split"] = precision_split(cf, y, start, design, dev)
+        out["small_fit"] = small_fit(cf, dev)
+        progress("small fit done")
 
     if not args.no_cpu:
         import oracle
@@ -524,8 +593,10 @@ def main():
         rows_n = args.cpu_rows or max(2, threads)
         rows = np.arange(rows_n, dtype=np.int32)
         c0 = time.perf_counter()
+        progress(f"CPU oracle on {rows_n} rows ...")
         oracle.estep(ds.y, ds.params, design, rows=rows)
         c1 = time.perf_counter()
+        progress(f"CPU oracle done in {c1 - c0:.1f} s")
         out["cpu_baseline"] = {"value": rows_n * g / (c1 - c0), "unit": "(obs*comp)/s", "cores": threads,
                                "kind": "oracle",
                                "sample": f"E-step of the first {rows_n} observations x {g} components, "
