@@ -25,7 +25,7 @@ bool weights_ok(const cfust_mlp_weights *w) {
 
 // Workspace layout of an E-step (or log-likelihood) call.
 struct EstepWs {
-    size_t pre, tabs, est, lnA, flag, logf, partial, total;
+    size_t pre, tabs, tabs64, est, lnA, flag, logf, partial, total;
 };
 
 EstepWs estep_layout(const cfust_dims &d, int J, bool own_logf) {
@@ -33,6 +33,7 @@ EstepWs estep_layout(const cfust_dims &d, int J, bool own_logf) {
     EstepWs w;
     w.pre = c.take<CompPre>(d.g);
     w.tabs = c.take<float>((size_t)d.g * NDOF * TAB_FLOATS);
+    w.tabs64 = c.take<double>((size_t)d.g * NDOF * TAB64_DOUBLES);
     w.est = c.take<double>((size_t)d.g * (J > 0 ? J : 1) * (d.n > 0 ? d.n : 1));
     w.lnA = c.take<double>((size_t)d.g * (d.n > 0 ? d.n : 1));
     w.flag = c.take<int32_t>((size_t)d.g * (J > 0 ? J : 1) * (d.n > 0 ? d.n : 1));
@@ -104,6 +105,7 @@ cfust_status run_estep(cfust_handle h, const double *y, const cfust_dims &d, con
     double *lfc = logf_comp ? logf_comp : at<double>(h, L.logf);
     hipError_t e = launch_precompute(*P, d.p, d.q, d.g, pre, s);
     if (e == hipSuccess && mixed && J > 0) e = launch_tables(pre, d.p, d.g, d.q + 2, at<float>(h, L.tabs), s);
+    if (e == hipSuccess && !mixed && J > 0) e = launch_tables64(pre, d.p, d.g, d.q + 2, at<double>(h, L.tabs64), s);
     int32_t *need = nullptr;
     if (e == hipSuccess && sur && J > 0) {
         need = at<int32_t>(h, need_off);
@@ -139,6 +141,7 @@ cfust_status run_estep(cfust_handle h, const double *y, const cfust_dims &d, con
         EstepQmcArgs a;
         a.need = need;
         a.y = y; a.mu = P->mu; a.pre = pre; a.tabs = at<float>(h, L.tabs);
+        a.tabs64 = mixed ? nullptr : at<double>(h, L.tabs64);
         a.lat = lattice_of(Q);
         a.n = d.n; a.p = d.p; a.q = d.q; a.g = d.g; a.J = J; a.mixed = mixed ? 1 : 0;
         a.est = at<double>(h, L.est); a.lnA = at<double>(h, L.lnA); a.se = se;
@@ -336,9 +339,11 @@ cfust_status cfust_autotune(cfust_handle h, const double *y, cfust_dims d, const
     CompPre *pre = at<CompPre>(h, L.pre);
     hipError_t e = launch_precompute(*P, d.p, d.q, d.g, pre, s);
     if (e == hipSuccess && mixed) e = launch_tables(pre, d.p, d.g, d.q + 2, at<float>(h, L.tabs), s);
+    if (e == hipSuccess && !mixed) e = launch_tables64(pre, d.p, d.g, d.q + 2, at<double>(h, L.tabs64), s);
     if (e != hipSuccess) return hip_check(h, e, "cfust_autotune");
     EstepQmcArgs a;
     a.y = y; a.mu = P->mu; a.pre = pre; a.tabs = at<float>(h, L.tabs);
+    a.tabs64 = mixed ? nullptr : at<double>(h, L.tabs64);
     a.lat = lattice_of(Q);
     a.n = d.n; a.p = d.p; a.q = d.q; a.g = d.g; a.J = J; a.mixed = mixed ? 1 : 0;
     a.est = at<double>(h, L.est); a.lnA = at<double>(h, L.lnA); a.se = nullptr;

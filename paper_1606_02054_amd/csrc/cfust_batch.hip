@@ -265,7 +265,7 @@ cfust_status cfust_batch_create(cfust_handle h, int32_t nfits, const cfust_fit *
 
     // workspace layout
     Carve c;
-    struct FitOff { size_t pre, tabs, est, lnA, logf, lse, mpart, cstat; };
+    struct FitOff { size_t pre, tabs, tabs64, est, lnA, logf, lse, mpart, cstat; };
     std::vector<FitOff> fo(nfits);
     for (int f = 0; f < nfits; ++f) {
         const cfust_dims &d = fits[f].dims;
@@ -274,6 +274,7 @@ cfust_status cfust_batch_create(cfust_handle h, int32_t nfits, const cfust_fit *
         const int J = dn ? (d.q >= 2 ? 1 : 0) : nint_qmc(d.q);
         fo[f].pre = c.take<CompPre>(d.g);
         fo[f].tabs = c.take<float>(b->mixed && J > 0 ? (size_t)d.g * NDOF * TAB_FLOATS : 1);
+        fo[f].tabs64 = c.take<double>(!b->mixed && J > 0 ? (size_t)d.g * NDOF * TAB64_DOUBLES : 1);
         fo[f].est = c.take<double>((size_t)d.g * (J > 0 ? J : 1) * n1);
         fo[f].lnA = c.take<double>((size_t)d.g * n1);
         fo[f].logf = c.take<double>(fits[f].out.logf_comp ? 1 : (size_t)d.g * n1);
@@ -335,8 +336,9 @@ cfust_status cfust_batch_create(cfust_handle h, int32_t nfits, const cfust_fit *
         D.pc.p = d.p; D.pc.q = d.q; D.pc.pre = pre;
         D.ndof = d.q + 2;
         D.tabs = tabs;
+        D.tabs64 = !b->mixed && J > 0 ? bat<double>(b, fo[f].tabs64) : nullptr;
         EstepQmcArgs &q = D.qa;
-        q.y = F.y; q.mu = F.params.mu; q.pre = pre; q.tabs = tabs; q.lat = b->lat;
+        q.y = F.y; q.mu = F.params.mu; q.pre = pre; q.tabs = tabs; q.tabs64 = D.tabs64; q.lat = b->lat;
         q.n = d.n; q.p = d.p; q.q = d.q; q.g = d.g; q.J = J > 0 ? J : 1; q.idx0 = 0; q.mixed = b->mixed;
         q.est = est; q.lnA = lnA; q.se = F.out.cdf_stderr; q.flag = nullptr; q.need = nullptr;
         EstepAsmArgs &a = D.aa;
@@ -368,7 +370,7 @@ cfust_status cfust_batch_create(cfust_handle h, int32_t nfits, const cfust_fit *
         sv.status = nullptr;
         D.cstat = bat<int32_t>(b, fo[f].cstat);
         const int cnt[BK_NKIND] = {d.g,
-                                   b->mixed && J > 0 ? d.g * D.ndof : 0,
+                                   J > 0 ? d.g * D.ndof : 0,
                                    (d.n * d.g + 127) / 128,
                                    (d.n + 255) / 256,
                                    dn ? 0 : nblk * d.g,

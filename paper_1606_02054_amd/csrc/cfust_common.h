@@ -18,8 +18,9 @@ constexpr int MAXJ = 2 + MAXQ + MAXPAIR;          // integrals per (obs, comp)
 constexpr int NDOF = MAXQ + 2;                    // dofs nu+p .. nu+p+q+1 per component
 
 // FP32 piecewise-polynomial tables of the univariate t law for one dof:
-//   rows 0..7  : lower-tail CDF, F(tau) = log2 T_lower(tau) - a log2(tau) on
-//                8 equal intervals of tau = 1 - |s| in [0,1], s = u / sqrt(nu+u^2);
+//   rows 0..7  : lower-tail CDF, H(tau) = log2 T_lower(tau) - a log2(tau (2 - tau))
+//                (a = nu/2) on 8 equal intervals of tau = 1 - |s| in [0,1],
+//                s = u / sqrt(nu+u^2);
 //   rows 8..18 : quantile, log2 tau as a function of lambda = -log2(2p) on the
 //                11 intervals [c(2^k - 1), c(2^{k+1} - 1)], c = 1/4.
 // Each row holds 7 monomial coefficients in x in [-1,1] (x = 2t - 1, t the
@@ -29,6 +30,21 @@ constexpr int TAB_INV_ROWS = 11;
 constexpr int TAB_ROWS = 20;                      // 8 + 11 + 1 pad row
 constexpr int TAB_FLOATS = TAB_ROWS * 8;          // 160 floats per dof
 constexpr float INV_LAMBDA_MAX = 511.0f;
+
+// FP64 tables of the univariate t law for one dof (FP64 integrand), the same
+// variables in natural logs, as Chebyshev series of degree TAB64_NC - 1:
+//   rows 0..15  : H(tau) = ln T_lower(tau) - a ln(tau (2 - tau)) on 16 equal
+//                 intervals of tau in [0,1];
+//   rows 16..30 : ln tau as a function of lambda = -log2(2p) on the 15
+//                 intervals [c(2^k - 1), c(2^{k+1} - 1)], c = 1/4 (lambda < 8191.75).
+// Degree 11 on these intervals keeps H within about 1e-14 of its value for
+// every dof from 1 to 210; the quantile rows only start a Newton step.
+constexpr int TAB64_NC = 12;
+constexpr int TAB64_CDF_ROWS = 16;
+constexpr int TAB64_INV_ROWS = 15;
+constexpr int TAB64_ROWS = TAB64_CDF_ROWS + TAB64_INV_ROWS;
+constexpr int TAB64_DOUBLES = TAB64_ROWS * TAB64_NC;            // 372 doubles per dof
+constexpr double TAB64_ZZ_END = 8192.0;                          // 2^(TAB64_INV_ROWS - 2)
 
 // Per-component quantities that every observation shares (Sec. 2 eq. 4 and the
 // conditional pieces of the truncated-t moments).  FP64 unless noted.

@@ -85,10 +85,18 @@ __device__ inline double dm_lnT_lower(double z, double zc, double a, double lb) 
     return log1p(-v) - LN2;
 }
 
-// Quantile in the tau variable: tau in (0,1] with ln T_lower(tau) = lnq (lnq <= -ln 2).
-__device__ inline double dm_tau_of_lnq(double lnq, double a, double lb) {
-    if (!(lnq < -LN2)) return 1.0;
-    if (lnq == -INFINITY) return 0.0;
+// H = ln T_lower - a ln z, formed without the cancellation of the two large
+// terms where z is small (the values the FP64 tables are fitted to).
+__device__ inline double dm_H_lower(double z, double zc, double a, double lb) {
+    if (z < (a + 1.0) / (a + 2.5)) return 0.5 * log(zc) - log(a) - lb - log(dm_beta_cf(a, 0.5, z)) - LN2;
+    return dm_lnT_lower(z, zc, a, lb) - a * log(z);
+}
+
+// Quantile in the tau variable: l = ln tau, tau in (0,1] with
+// ln T_lower(tau) = lnq (lnq <= -ln 2).
+__device__ inline double dm_l_of_lnq(double lnq, double a, double lb) {
+    if (!(lnq < -LN2)) return 0.0;
+    if (lnq == -INFINITY) return -INFINITY;
     auto g = [&](double l, double *dg) {
         const double tau = exp(l);
         const double s = -expm1(l);          // 1 - tau
@@ -114,7 +122,11 @@ __device__ inline double dm_tau_of_lnq(double lnq, double a, double lb) {
         if (step <= 4e-16 * fmax(1.0, fabs(l)) || hi - lo <= 4e-16 * fmax(1.0, fabs(lo))) break;
         gl = g(l, &dg);
     }
-    return exp(l);
+    return l;
+}
+
+__device__ inline double dm_tau_of_lnq(double lnq, double a, double lb) {
+    return exp(dm_l_of_lnq(lnq, a, lb));
 }
 
 // (v + a) / (v + b), with its limit 1 at v = infinity (the normal limit of the
@@ -177,6 +189,59 @@ __device__ inline double dm_tcdf(double x, double v) {
     else { const double den = v + x * x; z = v / den; zc = x * x / den; }
     const double lo = exp(dm_lnT_lower(z, zc, a, lb));
     return x <= 0.0 ? lo : 1.0 - lo;
+}
+
+// ------------------------------------------------- FP64 dof tables ------
+
+// c[0] + sum_k c[k] T_k(x), x in [-1, 1], by Clenshaw's recurrence.
+__device__ __forceinline__ double tab64_cheb(const double *c, double x) {
+    const double x2 = 2.0 * x;
+    double b1 = 0.0, b2 = 0.0;
+#pragma unroll
+    for (int k = TAB64_NC - 1; k >= 1; --k) {
+        const double t = fma(x2, b1, c[k] - b2);
+        b2 = b1;
+        b1 = t;
+    }
+    return fma(x, b1, c[0] - b2);
+}
+
+// H(tau) = ln T_lower(tau) - a ln(tau (2 - tau)) from the CDF rows of one
+// dof's table; tau is clamped into [0, 1] (NaN to 0), so the row index is
+// always in range.
+__device__ __forceinline__ double tab64_H(const double *tab, double tau) {
+    const double pos = fmin(fmax(tau, 0.0), 1.0) * (double)TAB64_CDF_ROWS;
+    const int k = min((int)pos, TAB64_CDF_ROWS - 1);
+    return tab64_cheb(tab + k * TAB64_NC, 2.0 * (pos - (double)k) - 1.0);
+}
+
+// l = ln tau with ln T_lower(tau) = lnq for dof 2a (lb = ln B(a, 1/2)): a
+// start from the quantile rows (lambda = -log2(2p) = -1 - lnq / ln 2), or
+// past the last row from the tail law T ~ e^H(0) (2 tau)^a, then Newton steps
+// on g(l) = H(tau) + a (l + ln(2 - tau)) - lnq, whose slope is
+// g'(l) = e^(-lb - H(tau)) / (2 - tau) (the t density in the tau variable).
+// One step from the table's start (error ~1e-11) reaches the accuracy of H;
+// the tail start takes four.  l is kept <= 0 (tau <= 1).
+__device__ inline double tab64_quantile_l(const double *tab, double lnq, double a, double lb) {
+    const double zz = fmax(-lnq * (1.0 / LN2) - 1.0, 0.0) + 0.25;
+    double l;
+    int steps = 1;
+    if (zz < TAB64_ZZ_END) {
+        const int e = __builtin_amdgcn_frexp_exp(zz);          // zz = mant 2^e, mant in [0.5, 1)
+        const double mant = __builtin_amdgcn_frexp_mant(zz);
+        l = tab64_cheb(tab + (TAB64_CDF_ROWS + e + 1) * TAB64_NC, 4.0 * mant - 3.0);
+    } else {
+        l = (lnq - tab64_H(tab, 0.0)) / a - LN2;
+        steps = 4;
+    }
+    for (int it = 0; it < steps; ++it) {
+        const double tau = exp(l);
+        const double u = 2.0 - tau;
+        const double H = tab64_H(tab, tau);
+        const double g = H + a * (l + log(u)) - lnq;
+        l = fmin(l - g * u * exp(lb + H), 0.0);
+    }
+    return l;
 }
 
 // ---------------------------------------------------------------- FP32 ------

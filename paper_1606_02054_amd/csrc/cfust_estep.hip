@@ -269,6 +269,51 @@ __global__ __launch_bounds__(192) void k_tables(const CompPre *__restrict__ pre,
     tables_body(pre, p, ndof, tabs, blockIdx.x);
 }
 
+// FP64 tables: node n of row `row` (Chebyshev nodes of degree TAB64_NC - 1).
+__device__ inline double table64_node_value(double nu, int row, int n) {
+    const double x = cos(M_PI * (n + 0.5) / (double)TAB64_NC);
+    const double a = 0.5 * nu, lb = dm_lbeta_half(a);
+    if (row < TAB64_CDF_ROWS) {
+        const double tau = (row + 0.5 * (x + 1.0)) / (double)TAB64_CDF_ROWS;
+        const double s = 1.0 - tau;
+        return dm_H_lower(tau * (2.0 - tau), s * s, a, lb);
+    }
+    const double w = 0.25 * (double)(1 << (row - TAB64_CDF_ROWS));
+    const double lam = w - 0.25 + w * 0.5 * (x + 1.0);
+    return dm_l_of_lnq(-(lam + 1.0) * LN2, a, lb);
+}
+
+// Block `bid` = (component, dof offset): every node of the dof's rows, then
+// one thread per row turns its node values into Chebyshev coefficients.  A
+// component with infinite dof (normal limit) has no t tables: zeros.
+__device__ inline void tables64_body(const CompPre *__restrict__ pre, int p, int ndof, double *__restrict__ tabs,
+                                     int bid) {
+    const int h = bid / ndof, off = bid % ndof;
+    const double nu = pre[h].nu + p + off;
+    __shared__ double fv64[TAB64_DOUBLES];
+    double *dst = tabs + ((size_t)h * NDOF + off) * TAB64_DOUBLES;
+    if (isinf(nu)) {
+        for (int t = threadIdx.x; t < TAB64_DOUBLES; t += blockDim.x) dst[t] = 0.0;
+        return;
+    }
+    for (int t = threadIdx.x; t < TAB64_DOUBLES; t += blockDim.x)
+        fv64[t] = table64_node_value(nu, t / TAB64_NC, t % TAB64_NC);
+    __syncthreads();
+    for (int row = threadIdx.x; row < TAB64_ROWS; row += blockDim.x) {
+        const double *f = fv64 + row * TAB64_NC;
+        for (int j = 0; j < TAB64_NC; ++j) {
+            double acc = 0.0;
+            for (int n = 0; n < TAB64_NC; ++n) acc += f[n] * cos(M_PI * j * (n + 0.5) / (double)TAB64_NC);
+            dst[row * TAB64_NC + j] = acc * (j == 0 ? 1.0 : 2.0) / (double)TAB64_NC;
+        }
+    }
+}
+
+__global__ __launch_bounds__(192) void k_tables64(const CompPre *__restrict__ pre, int p, int ndof,
+                                                  double *__restrict__ tabs) {
+    tables64_body(pre, p, ndof, tabs, blockIdx.x);
+}
+
 // ------------------------------------------------------------- geometry ----
 
 // r = y_j - mu_h, d = r^T Omega^{-1} r, c = Delta^T Omega^{-1} r (Sec. 2 eq. 4).
@@ -399,9 +444,12 @@ __device__ __attribute__((noinline)) ItemResult item_finish(const WaveItem *w, c
 // when the FP32 product underflowed (the item then needs the FP64 integrand).
 // w: this wave's LDS work slot.  Lane 0 writes the estimate (and, for idx 0,
 // ln A and its standard error).
-template <int M, bool MIXED, int PPL>
-__device__ inline bool qmc_item(const EstepQmcArgs &a, int h, int idx, int j, const float *tab, double *smean,
-                                WaveItem *w, int lane) {
+// !MIXED: with T64 the FP64 integrand reads the FP64 dof tables of the
+// integral in tab64 (LDS); without, it uses the exact transforms (the redo
+// pass of mixed mode, whose FP32 tables do not serve it).
+template <int M, bool MIXED, int PPL, bool T64 = false>
+__device__ inline bool qmc_item(const EstepQmcArgs &a, int h, int idx, int j, const float *tab,
+                                const double *tab64, double *smean, WaveItem *w, int lane) {
     item_head(a.y, a.mu, a.pre, a.n, a.p, a.q, h, idx, j, w, !MIXED);
     const bool normal = isinf(w->nu0);          // the normal limit of the family (dof infinite)
     if (MIXED && !normal) item_head_tab(w, tab);
@@ -411,6 +459,8 @@ __device__ inline bool qmc_item(const EstepQmcArgs &a, int h, int idx, int j, co
             const bool ok = normal ? sov_mixed_normal<M, PPL>(w->H, w->b, w->L, a.lat, tab, smean, lane)
                                    : sov_mixed<M, PPL>(w->H, w->b, w->L, w->nu0, a.lat, tab, smean, lane);
             if (!ok) return false;
+        } else if (T64) {
+            sov_fp64_tab<M>(w->H, w->b, w->L, w->nu0, a.lat, tab64, smean, lane);
         } else {
             sov_fp64<M>(w->H, w->b, w->L, w->nu0, a.lat, smean, lane);
         }
@@ -434,18 +484,31 @@ __device__ inline void load_tables(const float *__restrict__ tabs, int h, int do
     for (int t = threadIdx.x; t < M * TAB_FLOATS; t += blockDim.x) tab[t] = src[t];
 }
 
+// Stage the FP64 tables of the dofs an integral of dimension M uses.
+template <int M>
+__device__ inline void load_tables64(const double *__restrict__ tabs64, int h, int dofoff, double *tab64) {
+    const double *src = tabs64 + ((size_t)h * NDOF + dofoff) * TAB64_DOUBLES;
+    for (int t = threadIdx.x; t < M * TAB64_DOUBLES; t += blockDim.x) tab64[t] = src[t];
+}
+
 // One wave per (observation j, integral idx, component h); 4 observations per
 // block share the integral's tables.  MIXED: FP32 integrand, items whose FP32
 // product underflows are flagged for the FP64 pass.  !MIXED: FP64 integrand;
 // with FLAGGED_ONLY it processes only the flagged items.
 template <int M, bool MIXED, bool FLAGGED_ONLY, int PPL>
 __global__ __launch_bounds__(256) void k_estep_qmc(EstepQmcArgs a) {
+    constexpr bool TAB64 = !MIXED && !FLAGGED_ONLY;
     __shared__ __align__(16) float tab[MIXED ? M * TAB_FLOATS : 4];
+    __shared__ double tab64[TAB64 ? M * TAB64_DOUBLES : 1];
     __shared__ double smean[4][MAXS];
     __shared__ WaveItem witem[4];
     const int h = blockIdx.z, idx = a.idx0 + blockIdx.y;
     if (MIXED) {
         load_tables<M>(a.tabs, h, int_desc(a.q, idx).dofoff, tab);
+        __syncthreads();
+    }
+    if (TAB64 && a.tabs64) {
+        load_tables64<M>(a.tabs64, h, int_desc(a.q, idx).dofoff, tab64);
         __syncthreads();
     }
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -457,7 +520,7 @@ __global__ __launch_bounds__(256) void k_estep_qmc(EstepQmcArgs a) {
         if (MIXED && lane == 0) a.flag[o] = 0;
         return;
     }
-    const bool ok = qmc_item<M, MIXED, PPL>(a, h, idx, j, tab, smean[wave], &witem[wave], lane);
+    const bool ok = qmc_item<M, MIXED, PPL, TAB64>(a, h, idx, j, tab, tab64, smean[wave], &witem[wave], lane);
     if (MIXED && lane == 0) a.flag[o] = ok ? 0 : 1;
 }
 
@@ -930,6 +993,11 @@ hipError_t launch_tables(const CompPre *pre, int p, int g, int ndof, float *tabs
     return hipGetLastError();
 }
 
+hipError_t launch_tables64(const CompPre *pre, int p, int g, int ndof, double *tabs, hipStream_t s) {
+    hipLaunchKernelGGL(k_tables64, dim3(g * ndof), dim3(192), 0, s, pre, p, ndof, tabs);
+    return hipGetLastError();
+}
+
 template <int M>
 static void launch_qmc_m(const EstepQmcArgs &a, int nidx, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, int ppl) {
     dim3 grid((a.n + 3) / 4, nidx, a.g);
@@ -1029,7 +1097,8 @@ __global__ __launch_bounds__(192) void k_batch_tables(BatchArgs B) {
     const int f = batch_fit(pf, B.nfits, blockIdx.x);
     if (!B.active[f]) return;
     const FitDesc &F = B.fits[f];
-    tables_body(F.pc.pre, F.pc.p, F.ndof, F.tabs, blockIdx.x - pf[f]);
+    if (F.tabs64) tables64_body(F.pc.pre, F.pc.p, F.ndof, F.tabs64, blockIdx.x - pf[f]);
+    else tables_body(F.pc.pre, F.pc.p, F.ndof, F.tabs, blockIdx.x - pf[f]);
 }
 
 __global__ __launch_bounds__(128) void k_batch_assemble(BatchArgs B) {
@@ -1067,6 +1136,7 @@ __global__ __launch_bounds__(256) void k_batch_sum(BatchArgs B) {
 template <int M, bool MIXED, int PPL>
 __global__ __launch_bounds__(256) void k_queue_qmc(QueueArgs Q) {
     __shared__ __align__(16) float tab[MIXED ? M * TAB_FLOATS : 4];
+    __shared__ double tab64[MIXED ? 1 : M * TAB64_DOUBLES];
     __shared__ double smean[4][MAXS];
     __shared__ WaveItem witem[4];
     __shared__ long long s_tile;
@@ -1096,18 +1166,18 @@ __global__ __launch_bounds__(256) void k_queue_qmc(QueueArgs Q) {
         const int idx = S.idx0 + (int)(rest % S.nidx);
         const int h = (int)(rest / S.nidx);
         const EstepQmcArgs &a = Q.fits[S.fit].qa;     // in device memory (its lattice is Q.lat)
-        if (MIXED) {
-            const int dof = int_desc(a.q, idx).dofoff;
-            if (S.fit != cur_f || h != cur_h || dof != cur_dof) {
-                load_tables<M>(a.tabs, h, dof, tab);
-                __syncthreads();
-                cur_f = S.fit; cur_h = h; cur_dof = dof;
-            }
+        const int dof = int_desc(a.q, idx).dofoff;
+        if (S.fit != cur_f || h != cur_h || dof != cur_dof) {
+            if (MIXED) load_tables<M>(a.tabs, h, dof, tab);
+            else if (a.tabs64) load_tables64<M>(a.tabs64, h, dof, tab64);
+            __syncthreads();
+            cur_f = S.fit; cur_h = h; cur_dof = dof;
         }
         const int jb = S.j0 + rt * S.rows;
         for (int r = wave; r < S.rows; r += 4) {
             const int j = jb + r;
-            const bool ok = qmc_item<M, MIXED, PPL>(a, h, idx, j, tab, smean[wave], &witem[wave], lane);
+            const bool ok = qmc_item<M, MIXED, PPL, !MIXED>(a, h, idx, j, tab, tab64, smean[wave], &witem[wave],
+                                                            lane);
             if (MIXED && !ok && lane == 0) {
                 const unsigned slot = atomicAdd(Q.redo_count, 1u);
                 Q.redo[slot] = ((unsigned long long)S.fit << 43) | ((unsigned long long)h << 37) |
@@ -1125,6 +1195,7 @@ __global__ __launch_bounds__(256) void k_queue_qmc(QueueArgs Q) {
 template <int M, bool MIXED, int PPL>
 __global__ __launch_bounds__(256) void k_queue_grid(QueueArgs Q) {
     __shared__ __align__(16) float tab[MIXED ? M * TAB_FLOATS : 4];
+    __shared__ double tab64[MIXED ? 1 : M * TAB64_DOUBLES];
     __shared__ double smean[4][MAXS];
     __shared__ WaveItem witem[4];
     const long long t = (long long)blockIdx.y * gridDim.x + blockIdx.x;
@@ -1146,11 +1217,14 @@ __global__ __launch_bounds__(256) void k_queue_grid(QueueArgs Q) {
     if (MIXED) {
         load_tables<M>(a.tabs, h, int_desc(a.q, idx).dofoff, tab);
         __syncthreads();
+    } else if (a.tabs64) {
+        load_tables64<M>(a.tabs64, h, int_desc(a.q, idx).dofoff, tab64);
+        __syncthreads();
     }
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (wave >= S.rows) return;
     const int j = S.j0 + rt * S.rows + wave;
-    const bool ok = qmc_item<M, MIXED, PPL>(a, h, idx, j, tab, smean[wave], &witem[wave], lane);
+    const bool ok = qmc_item<M, MIXED, PPL, !MIXED>(a, h, idx, j, tab, tab64, smean[wave], &witem[wave], lane);
     if (MIXED && !ok && lane == 0) {
         const unsigned slot = atomicAdd(Q.redo_count, 1u);
         Q.redo[slot] = ((unsigned long long)S.fit << 43) | ((unsigned long long)h << 37) |
@@ -1171,7 +1245,7 @@ __global__ __launch_bounds__(256) void k_queue_redo(QueueArgs Q) {
                                      (unsigned)__builtin_amdgcn_readfirstlane((unsigned)v0);
         const int f = (int)(v >> 43), h = (int)((v >> 37) & 63), idx = (int)((v >> 31) & 63);
         const int j = (int)(v & 0x7fffffffULL);
-        qmc_item<M, false, 1>(Q.fits[f].qa, h, idx, j, nullptr, smean[wave], &witem[wave], lane);
+        qmc_item<M, false, 1>(Q.fits[f].qa, h, idx, j, nullptr, nullptr, smean[wave], &witem[wave], lane);
     }
 }
 

@@ -15,6 +15,7 @@ struct EstepQmcArgs {
     const double *mu;           // [g][p]
     const CompPre *pre;         // [g]
     const float *tabs;          // [g][NDOF][TAB_FLOATS] (mixed)
+    const double *tabs64 = nullptr;   // [g][NDOF][TAB64_DOUBLES] (FP64 mode), or null: exact transforms
     LatticeArgs lat;
     int n, p, q, g;
     int J;                      // integrals stored per pair in est
@@ -111,6 +112,7 @@ struct FitDesc {
     PrecompArgs pc;
     int ndof;                   // dof tables per component (mixed)
     float *tabs;                // [g][NDOF][TAB_FLOATS]
+    double *tabs64;             // [g][NDOF][TAB64_DOUBLES] (FP64 batches) or null
     EstepQmcArgs qa;
     EstepAsmArgs aa;
     EstepLseArgs la;
@@ -209,6 +211,7 @@ hipError_t launch_init_select(const InitArgs &a, const int32_t *active, const do
 hipError_t launch_precompute(const cfust_params &P, int p, int q, int g, CompPre *pre, hipStream_t s);
 hipError_t launch_status_fold(const CompPre *pre, int g, int32_t *status, hipStream_t s);
 hipError_t launch_tables(const CompPre *pre, int p, int g, int ndof, float *tabs, hipStream_t s);
+hipError_t launch_tables64(const CompPre *pre, int p, int g, int ndof, double *tabs, hipStream_t s);
 // Lattice integrals idx0 .. idx0+nidx-1 of every pair; all must share the
 // same dimension m >= 2.  In mixed mode the FP32 kernel runs first and an
 // FP64 pass then redoes only the flagged (underflowed) items.

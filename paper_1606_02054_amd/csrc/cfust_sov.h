@@ -103,6 +103,89 @@ __device__ double sov_lane_sum64(const double *b, const double *L, double nu, co
     return acc;
 }
 
+// FP64 integrand with the dof tables (tab: TAB64_DOUBLES per dof, dof nu + i
+// for coordinate i, in LDS): the same steps as sov_lane_sum64, with ln T_lower
+// = H(tau) + a ln(K R^2) from the CDF rows (K R^2 = tau (2 - tau)) and the
+// quantile from tab64_quantile_l.  The lattice residues k z_j mod N advance by
+// 64 z_j mod N per lane step (the same integers as point64's product).
+__device__ __forceinline__ double quantile_step64_tab(double x, double xb, double e, double eb, double lne,
+                                                      bool lowt, double a, double lb, const double *tab,
+                                                      double &Q) {
+    const double p = x * e;
+    const double pb = xb * e + eb;
+    const bool lower = lowt || p <= 0.5;
+    const double lnq = lowt ? log(x) + lne : log(lower ? p : pb);
+    const double tq = exp(tab64_quantile_l(tab, lnq, a, lb));
+    const double sabs = 1.0 - tq;
+    Q *= 1.0 / sqrt(tq * (2.0 - tq));
+    return (lower ? -sabs : sabs) * Q;
+}
+
+__device__ __forceinline__ void point64_r(const Lattice &Lt, int s, int j, uint32_t r, double &x, double &xb) {
+    double t = (double)r / (double)Lt.N + Lt.shifts[s * LATD + j];
+    if (t >= 1.0) t -= 1.0;
+    double xbv = fabs(2.0 * t - 1.0);
+    double xv = 1.0 - xbv;
+    const double lo = 1.0 / 16777216.0;
+    if (xv < lo) { xv = lo; xbv = 1.0 - lo; }
+    if (xv > 1.0 - lo) { xv = 1.0 - lo; xbv = lo; }
+    x = xv;
+    xb = xbv;
+}
+
+template <int M>
+__device__ double sov_lane_sum64_tab(const double *b, const double *L, double nu, const Lattice &Lt, int s,
+                                     const double *tab, double e0, double eb0, double lne0, bool low0, int lane) {
+    constexpr int MQ = M > 1 ? M - 1 : 1;       // coordinates that draw a quantile
+    double a[M], lb[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) { a[i] = 0.5 * (nu + i); lb[i] = dm_lbeta_half(a[i]); }
+    const uint32_t N = (uint32_t)Lt.N;
+    uint32_t r[MQ], st[MQ];
+#pragma unroll
+    for (int j = 0; j < MQ; ++j) {
+        const uint32_t z = (uint32_t)Lt.z[j];
+        r[j] = (uint32_t)(((uint64_t)lane * z) % N);
+        st[j] = (uint32_t)((64ull * z) % N);
+    }
+    double acc = 0.0;
+    for (int k = lane; k < Lt.N; k += 64) {
+        double y[M];
+        double Q = sqrt(nu);
+        double x, xb;
+        point64_r(Lt, s, 0, r[0], x, xb);
+        y[0] = quantile_step64_tab(x, xb, e0, eb0, lne0, low0, a[0], lb[0], tab, Q);
+        double f = 1.0;
+#pragma unroll
+        for (int i = 1; i < M; ++i) {
+            double num = b[i];
+#pragma unroll
+            for (int j = 0; j < i; ++j) num -= L[i * M + j] * y[j];
+            const double LQ = L[i * M + i] * Q;
+            const double K = LQ * LQ;
+            const double R = 1.0 / sqrt(K + num * num);
+            const double lt = tab64_H(tab + i * TAB64_DOUBLES, 1.0 - fabs(num) * R) + a[i] * log(K * R * R);
+            const double small = exp(lt);
+            const bool lowt = num <= 0.0;
+            const double e = lowt ? small : 1.0 - small;
+            const double eb = lowt ? 1.0 - small : small;
+            f *= e;
+            if (f == 0.0) break;
+            if (i < M - 1) {
+                point64_r(Lt, s, i, r[i], x, xb);
+                y[i] = quantile_step64_tab(x, xb, e, eb, lt, lowt, a[i], lb[i], tab + i * TAB64_DOUBLES, Q);
+            }
+        }
+        acc += f;
+#pragma unroll
+        for (int j = 0; j < MQ; ++j) {
+            r[j] += st[j];
+            r[j] = r[j] >= N ? r[j] - N : r[j];
+        }
+    }
+    return acc;
+}
+
 // Normal limit (dof infinite), FP64: the conditional laws are normal with
 // fixed scale, so y_i = Phi^-1(x_i e_i) and no scale is carried.
 __device__ __forceinline__ double nquantile_step64(double x, double xb, double e, double eb, double lne,
@@ -433,6 +516,19 @@ __device__ bool sov_mixed_normal(const SovHead &H, const double *b, const double
         tot += ms;
     }
     return tot / Lt.S > 1e-30;
+}
+
+// FP64 integrand from the dof tables (the normal limit has its own
+// dof-free transforms).
+template <int M>
+__device__ __forceinline__ void sov_fp64_tab(const SovHead &H, const double *b, const double *L, double nu,
+                                             const Lattice &Lt, const double *tab, double *smean, int lane) {
+    for (int s = 0; s < Lt.S; ++s) {
+        const double ls = isinf(nu) ? sov_lane_sum64_normal<M>(b, L, Lt, s, H.e0, H.eb0, H.lne0, H.low0, lane)
+                                    : sov_lane_sum64_tab<M>(b, L, nu, Lt, s, tab, H.e0, H.eb0, H.lne0, H.low0, lane);
+        const double ms = wave_sum(ls) / (double)Lt.N;
+        if (lane == 0) smean[s] = ms;
+    }
 }
 
 template <int M>
