@@ -116,6 +116,9 @@ __device__ inline double dm_l_of_lnq(double lnq, double a, double lb) {
     for (int it = 0; it < 200; ++it) {
         if (gl > 0.0) hi = l; else lo = l;
         double ln = l - gl / dg;
+        // a converged Newton step ends the search before the bracket test (a
+        // zero step lands on the bracket end and would restart bisection)
+        if (fabs(ln - l) <= 4e-16 * fmax(1.0, fabs(l))) { l = ln; break; }
         if (!(ln > lo && ln < hi)) ln = 0.5 * (lo + hi);
         const double step = fabs(ln - l);
         l = ln;
@@ -240,6 +243,40 @@ __device__ inline double tab64_quantile_l(const double *tab, double lnq, double 
         const double H = tab64_H(tab, tau);
         const double g = H + a * (l + log(u)) - lnq;
         l = fmin(l - g * u * exp(lb + H), 0.0);
+    }
+    return l;
+}
+
+// The root of the same equation solved to rounding on the CDF rows (the
+// quantile nodes of the table builds): the tail-law start (at most 0),
+// widened until g changes sign, then Newton steps kept inside the bracket
+// [lo, 0], bisecting where a step would leave it; relative tolerance 2e-15
+// (the rounding noise of g at large |ln p|).  Every loop is bounded.
+__device__ inline double tab64_l_solve(const double *tab, double lnq, double a, double lb) {
+    if (!(lnq < -LN2)) return 0.0;
+    auto g = [&](double l, double *dg) {
+        const double tau = exp(l), u = 2.0 - tau, H = tab64_H(tab, tau);
+        *dg = exp(-lb - H) / u;
+        return H + a * (l + log(u)) - lnq;
+    };
+    double hi = 0.0, lo = fmin((lnq - tab64_H(tab, 0.0)) / a - LN2, 0.0), dg;
+    double glo = g(lo, &dg);
+    double l = lo, gl = glo, dgl = dg;     // Newton starts from the bracket end nearest the root
+    for (int guard = 0; glo > 0.0 && guard < 64; ++guard) {
+        hi = lo; l = lo; gl = glo; dgl = dg;
+        lo = 2.0 * lo - 1.0;
+        glo = g(lo, &dg);
+    }
+    dg = dgl;
+    for (int it = 0; it < 100; ++it) {
+        if (gl > 0.0) hi = l; else lo = l;
+        double ln = l - gl / dg;
+        if (fabs(ln - l) <= 2e-15 * fmax(1.0, fabs(l))) { l = fmin(ln, 0.0); break; }
+        if (!(ln > lo && ln < hi)) ln = 0.5 * (lo + hi);
+        const double step = fabs(ln - l);
+        l = ln;
+        if (step <= 2e-15 * fmax(1.0, fabs(l)) || hi - lo <= 2e-15 * fmax(1.0, fabs(lo))) break;
+        gl = g(l, &dg);
     }
     return l;
 }

@@ -248,14 +248,61 @@ __device__ inline void table_fit_row(const double *f, float *dst) {
 
 constexpr int TAB_NODES = (TAB_CDF_ROWS + TAB_INV_ROWS) * 7;   // 133
 
+// Chebyshev coefficients of the TAB64_NC node values f of one row.
+__device__ inline void cheb_fit64(const double *f, double *c) {
+    for (int j = 0; j < TAB64_NC; ++j) {
+        double acc = 0.0;
+        for (int n = 0; n < TAB64_NC; ++n) acc += f[n] * cos(M_PI * j * (n + 0.5) / (double)TAB64_NC);
+        c[j] = acc * (j == 0 ? 1.0 : 2.0) / (double)TAB64_NC;
+    }
+}
+
+// First step of both table builds (finite dof): the FP64 CDF rows of dof nu
+// into h64 (LDS), one continued fraction per node and thread; fv is LDS
+// scratch for the node values.  Every thread of the block takes part.
+__device__ inline void build_cdf64(double nu, double *fv, double *h64) {
+    const double a = 0.5 * nu, lb = dm_lbeta_half(a);
+    for (int t = threadIdx.x; t < TAB64_CDF_ROWS * TAB64_NC; t += blockDim.x) {
+        const int row = t / TAB64_NC, n = t % TAB64_NC;
+        const double x = cos(M_PI * (n + 0.5) / (double)TAB64_NC);
+        const double tau = (row + 0.5 * (x + 1.0)) / (double)TAB64_CDF_ROWS;
+        const double s = 1.0 - tau;
+        fv[t] = dm_H_lower(tau * (2.0 - tau), s * s, a, lb);
+    }
+    __syncthreads();
+    for (int row = threadIdx.x; row < TAB64_CDF_ROWS; row += blockDim.x)
+        cheb_fit64(fv + row * TAB64_NC, h64 + row * TAB64_NC);
+    __syncthreads();
+}
+
+// Node of the FP32 tables (finite dof) from the FP64 CDF rows: H in log2
+// units, and log2 tau of the quantile solved on those rows.
+__device__ inline double table_node_from64(double nu, const double *h64, int row, int n) {
+    const double x = cos(M_PI * (n + 0.5) / 7.0);
+    const double a = 0.5 * nu;
+    if (row < TAB_CDF_ROWS) return tab64_H(h64, (row + 0.5 * (x + 1.0)) / 8.0) / LN2;
+    const double w = 0.25 * (double)(1 << (row - TAB_CDF_ROWS));
+    const double lam = w - 0.25 + w * 0.5 * (x + 1.0);
+    return tab64_l_solve(h64, -(lam + 1.0) * LN2, a, dm_lbeta_half(a)) / LN2;
+}
+
 // Block `bid` = (component, dof offset) of one parameter set; 192 threads.
+// Finite dof: the FP64 CDF rows first, then the 19 x 7 nodes from them;
+// infinite dof (normal limit): the dof-free closed forms.  One thread per row
+// fits and writes the row.
 __device__ inline void tables_body(const CompPre *__restrict__ pre, int p, int ndof, float *__restrict__ tabs,
                                    int bid) {
     const int h = bid / ndof, off = bid % ndof;
     const double nu = pre[h].nu + p + off;
     __shared__ double fv[TAB_NODES];
+    __shared__ double fv64[TAB64_CDF_ROWS * TAB64_NC], h64[TAB64_CDF_ROWS * TAB64_NC];
     const int t = threadIdx.x;
-    if (t < TAB_NODES) fv[t] = table_node_value(nu, t / 7, t % 7);
+    if (isinf(nu)) {
+        if (t < TAB_NODES) fv[t] = table_node_value(nu, t / 7, t % 7);
+    } else {
+        build_cdf64(nu, fv64, h64);
+        if (t < TAB_NODES) fv[t] = table_node_from64(nu, h64, t / 7, t % 7);
+    }
     __syncthreads();
     float *dst = tabs + ((size_t)h * NDOF + off) * TAB_FLOATS;
     if (t < TAB_CDF_ROWS + TAB_INV_ROWS) table_fit_row(fv + 7 * t, dst + 8 * t);
@@ -269,44 +316,35 @@ __global__ __launch_bounds__(192) void k_tables(const CompPre *__restrict__ pre,
     tables_body(pre, p, ndof, tabs, blockIdx.x);
 }
 
-// FP64 tables: node n of row `row` (Chebyshev nodes of degree TAB64_NC - 1).
-__device__ inline double table64_node_value(double nu, int row, int n) {
-    const double x = cos(M_PI * (n + 0.5) / (double)TAB64_NC);
-    const double a = 0.5 * nu, lb = dm_lbeta_half(a);
-    if (row < TAB64_CDF_ROWS) {
-        const double tau = (row + 0.5 * (x + 1.0)) / (double)TAB64_CDF_ROWS;
-        const double s = 1.0 - tau;
-        return dm_H_lower(tau * (2.0 - tau), s * s, a, lb);
-    }
-    const double w = 0.25 * (double)(1 << (row - TAB64_CDF_ROWS));
-    const double lam = w - 0.25 + w * 0.5 * (x + 1.0);
-    return dm_l_of_lnq(-(lam + 1.0) * LN2, a, lb);
-}
-
-// Block `bid` = (component, dof offset): every node of the dof's rows, then
-// one thread per row turns its node values into Chebyshev coefficients.  A
-// component with infinite dof (normal limit) has no t tables: zeros.
+// Block `bid` = (component, dof offset): the FP64 CDF rows, then every
+// quantile node solved on them, one per thread, and one thread per row for
+// the fits.  A component with infinite dof (normal limit) has no t tables:
+// zeros.
 __device__ inline void tables64_body(const CompPre *__restrict__ pre, int p, int ndof, double *__restrict__ tabs,
                                      int bid) {
     const int h = bid / ndof, off = bid % ndof;
     const double nu = pre[h].nu + p + off;
-    __shared__ double fv64[TAB64_DOUBLES];
+    __shared__ double fv64[TAB64_DOUBLES], t64[TAB64_DOUBLES];
     double *dst = tabs + ((size_t)h * NDOF + off) * TAB64_DOUBLES;
     if (isinf(nu)) {
         for (int t = threadIdx.x; t < TAB64_DOUBLES; t += blockDim.x) dst[t] = 0.0;
         return;
     }
-    for (int t = threadIdx.x; t < TAB64_DOUBLES; t += blockDim.x)
-        fv64[t] = table64_node_value(nu, t / TAB64_NC, t % TAB64_NC);
-    __syncthreads();
-    for (int row = threadIdx.x; row < TAB64_ROWS; row += blockDim.x) {
-        const double *f = fv64 + row * TAB64_NC;
-        for (int j = 0; j < TAB64_NC; ++j) {
-            double acc = 0.0;
-            for (int n = 0; n < TAB64_NC; ++n) acc += f[n] * cos(M_PI * j * (n + 0.5) / (double)TAB64_NC);
-            dst[row * TAB64_NC + j] = acc * (j == 0 ? 1.0 : 2.0) / (double)TAB64_NC;
-        }
+    build_cdf64(nu, fv64, t64);
+    const double a = 0.5 * nu, lb = dm_lbeta_half(a);
+    constexpr int Q0 = TAB64_CDF_ROWS * TAB64_NC;
+    for (int t = threadIdx.x; t < TAB64_INV_ROWS * TAB64_NC; t += blockDim.x) {
+        const int row = t / TAB64_NC, n = t % TAB64_NC;
+        const double x = cos(M_PI * (n + 0.5) / (double)TAB64_NC);
+        const double w = 0.25 * (double)(1 << row);
+        const double lam = w - 0.25 + w * 0.5 * (x + 1.0);
+        fv64[Q0 + t] = tab64_l_solve(t64, -(lam + 1.0) * LN2, a, lb);
     }
+    __syncthreads();
+    for (int row = threadIdx.x; row < TAB64_INV_ROWS; row += blockDim.x)
+        cheb_fit64(fv64 + Q0 + row * TAB64_NC, t64 + Q0 + row * TAB64_NC);
+    __syncthreads();
+    for (int t = threadIdx.x; t < TAB64_DOUBLES; t += blockDim.x) dst[t] = t64[t];
 }
 
 __global__ __launch_bounds__(192) void k_tables64(const CompPre *__restrict__ pre, int p, int ndof,

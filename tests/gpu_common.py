@@ -16,9 +16,10 @@ def rel_err(a, b, floor=1.0):
     return np.abs(a - b) / np.maximum(np.abs(b), floor)
 
 
-def compare_estep(gpu, ora, mode, rows=None, label=""):
-    """Element-wise comparison of a GPU E-step (torch tensors) with the oracle."""
-    t = TOL[mode]
+def compare_estep(gpu, ora, mode, rows=None, label="", tol=None):
+    """Element-wise comparison of a GPU E-step (torch tensors) with the oracle
+    (tolerances TOL[mode], or the dict ``tol``)."""
+    t = tol or TOL[mode]
     sel = (lambda x: x[..., rows]) if rows is not None else (lambda x: x)
     lf_g = sel(gpu.logf_obs.cpu().numpy())
     d_lf = np.abs(lf_g - ora.logf_obs)

@@ -97,6 +97,30 @@ def test_estep_vs_oracle(lib, orc, p, q, g, n, seed, mode):
     assert int(gpu.status.cpu()[0]) == 0
 
 
+@pytest.mark.parametrize("p,q", [(2, 2), (4, 4)])
+def test_fp64_tables_track_exact_transforms(lib, orc, p, q):
+    """FP64 mode draws its univariate t probabilities and quantiles from FP64
+    Chebyshev tables of each dof; the oracle uses the continued fraction and
+    a root search.  On the same lattice the two agree far inside the FP64
+    tolerance: dofs from 1.05 to 150 (integral dofs up to 150 + p + q + 1),
+    and observations far in the tails (log-densities of several hundred)."""
+    cf = lib
+    print(f"fp64 tables vs exact transforms p={p} q={q}", flush=True)
+    rng = np.random.default_rng(4200 + p)
+    P = draw_params(rng, p, q, 2, sigma="wishart" if p > 2 else "aat")
+    P.nu[:] = [1.05, 150.0]
+    y, _ = sample_hierarchy(rng, P, 30)
+    y[-1] = P.mu[0] + 40.0
+    y[-2] = P.mu[1] - 25.0
+    des = make_design(256, 4, seed=4300 + p)
+    ora = orc.estep(y, P, des)
+    gpu = _gpu_estep(cf, y, P, des, "fp64")
+    lf = gpu.logf_comp.cpu().numpy()
+    assert lf.min() < -100.0
+    np.testing.assert_allclose(lf, ora.logf_comp, rtol=0, atol=1e-10)
+    compare_estep(gpu, ora, "fp64", label=f"tables p{p}", tol=dict(logf=1e-10, tau=1e-12, eterm=1e-10))
+
+
 def test_estep_small_workload_full(lib, orc):
     """The n=1000, p=q=2, g=2 workload in FP64 at its lattice (N=1024 x 4), every observation."""
     cf = lib
