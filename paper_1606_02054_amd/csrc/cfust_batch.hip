@@ -180,7 +180,9 @@ hipError_t enqueue_estep(cfust_batch b, hipStream_t s) {
         if (e == hipSuccess) e = launch_queue_qmc(qa, Q.m, b->mixed, Q.ppl, Q.grid, s);
         if (e == hipSuccess && r.e1) e = hipEventRecord(r.e1, s);
         if (r.e0 && r.e1) b->h->rec.push_back(r);
-        if (e == hipSuccess && b->mixed) e = launch_queue_redo(qa, Q.m, Q.redo_grid, s);
+        // mixed: items whose FP32 product underflowed; FP64: items of integrals
+        // whose dof is past the FP64 tables
+        if (e == hipSuccess) e = launch_queue_redo(qa, Q.m, Q.redo_grid, s);
     }
     if (e == hipSuccess) e = launch_batch_assemble(A, b->nblocks[BK_ASM], s);
     if (e == hipSuccess) e = launch_batch_lse(A, b->nblocks[BK_LSE], s);
@@ -292,7 +294,7 @@ cfust_status cfust_batch_create(cfust_handle h, int32_t nfits, const cfust_fit *
     std::vector<size_t> o_seg(b->queues.size()), o_redo(b->queues.size());
     for (size_t k = 0; k < b->queues.size(); ++k) {
         o_seg[k] = c.take<QSeg>(b->queues[k].seg_cap);
-        o_redo[k] = c.take<unsigned long long>(b->mixed ? (size_t)b->queues[k].items : 1);
+        o_redo[k] = c.take<unsigned long long>((size_t)b->queues[k].items);
     }
     b->ws_size = c.off;
     if (hipMalloc(&b->ws, b->ws_size) != hipSuccess) {

@@ -45,6 +45,10 @@ constexpr int TAB64_INV_ROWS = 15;
 constexpr int TAB64_ROWS = TAB64_CDF_ROWS + TAB64_INV_ROWS;
 constexpr int TAB64_DOUBLES = TAB64_ROWS * TAB64_NC;            // 372 doubles per dof
 constexpr double TAB64_ZZ_END = 8192.0;                          // 2^(TAB64_INV_ROWS - 2)
+// Largest dof the FP64 tables serve (H within ~4e-12 at 1000; the intervals
+// cannot follow the boundary layer near tau ~ 1/nu beyond): integrals with a
+// larger dof take the exact transforms.
+constexpr double TAB64_NU_MAX = 1000.0;
 
 // Per-component quantities that every observation shares (Sec. 2 eq. 4 and the
 // conditional pieces of the truncated-t moments).  FP64 unless noted.

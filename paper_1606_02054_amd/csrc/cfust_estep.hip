@@ -522,6 +522,14 @@ __device__ inline void load_tables(const float *__restrict__ tabs, int h, int do
     for (int t = threadIdx.x; t < M * TAB_FLOATS; t += blockDim.x) tab[t] = src[t];
 }
 
+// True when integral idx of component h (dimension M) uses a finite dof past
+// the FP64 tables' range: its items take the exact FP64 transforms.
+template <int M>
+__device__ inline bool beyond_tab64(const CompPre *__restrict__ pre, int p, int q, int h, int idx) {
+    const double nu_hi = pre[h].nu + p + int_desc(q, idx).dofoff + (M - 1);
+    return isfinite(nu_hi) && nu_hi > TAB64_NU_MAX;
+}
+
 // Stage the FP64 tables of the dofs an integral of dimension M uses.
 template <int M>
 __device__ inline void load_tables64(const double *__restrict__ tabs64, int h, int dofoff, double *tab64) {
@@ -555,11 +563,15 @@ __global__ __launch_bounds__(256) void k_estep_qmc(EstepQmcArgs a) {
     const size_t o = ((size_t)h * a.J + idx) * a.n + j;
     if (FLAGGED_ONLY && a.flag[o] == 0) return;
     if (!FLAGGED_ONLY && a.need && a.need[o] == 0) {   // answered by the surrogate
-        if (MIXED && lane == 0) a.flag[o] = 0;
+        if ((MIXED || TAB64) && lane == 0) a.flag[o] = 0;
+        return;
+    }
+    if (TAB64 && beyond_tab64<M>(a.pre, a.p, a.q, h, idx)) {   // left to the exact pass
+        if (lane == 0) a.flag[o] = 1;
         return;
     }
     const bool ok = qmc_item<M, MIXED, PPL, TAB64>(a, h, idx, j, tab, tab64, smean[wave], &witem[wave], lane);
-    if (MIXED && lane == 0) a.flag[o] = ok ? 0 : 1;
+    if ((MIXED || TAB64) && lane == 0) a.flag[o] = ok ? 0 : 1;
 }
 
 // ------------------------------------------------------------- assembly ----
@@ -1048,6 +1060,8 @@ static void launch_qmc_m(const EstepQmcArgs &a, int nidx, hipStream_t s, hipEven
     } else {
         hipLaunchKernelGGL((k_estep_qmc<M, false, false, 1>), grid, dim3(256), 0, s, a);
         if (ev1) (void)hipEventRecord(ev1, s);
+        // integrals whose dof is past the FP64 tables: exact transforms
+        hipLaunchKernelGGL((k_estep_qmc<M, false, true, 1>), grid, dim3(256), 0, s, a);
     }
 }
 
@@ -1212,11 +1226,12 @@ __global__ __launch_bounds__(256) void k_queue_qmc(QueueArgs Q) {
             cur_f = S.fit; cur_h = h; cur_dof = dof;
         }
         const int jb = S.j0 + rt * S.rows;
+        const bool exact = !MIXED && beyond_tab64<M>(a.pre, a.p, a.q, h, idx);
         for (int r = wave; r < S.rows; r += 4) {
             const int j = jb + r;
-            const bool ok = qmc_item<M, MIXED, PPL, !MIXED>(a, h, idx, j, tab, tab64, smean[wave], &witem[wave],
-                                                            lane);
-            if (MIXED && !ok && lane == 0) {
+            const bool ok = !exact && qmc_item<M, MIXED, PPL, !MIXED>(a, h, idx, j, tab, tab64, smean[wave],
+                                                                      &witem[wave], lane);
+            if (!ok && lane == 0) {
                 const unsigned slot = atomicAdd(Q.redo_count, 1u);
                 Q.redo[slot] = ((unsigned long long)S.fit << 43) | ((unsigned long long)h << 37) |
                                ((unsigned long long)idx << 31) | (unsigned long long)j;
@@ -1262,8 +1277,10 @@ __global__ __launch_bounds__(256) void k_queue_grid(QueueArgs Q) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (wave >= S.rows) return;
     const int j = S.j0 + rt * S.rows + wave;
-    const bool ok = qmc_item<M, MIXED, PPL, !MIXED>(a, h, idx, j, tab, tab64, smean[wave], &witem[wave], lane);
-    if (MIXED && !ok && lane == 0) {
+    const bool exact = !MIXED && beyond_tab64<M>(a.pre, a.p, a.q, h, idx);
+    const bool ok = !exact && qmc_item<M, MIXED, PPL, !MIXED>(a, h, idx, j, tab, tab64, smean[wave],
+                                                              &witem[wave], lane);
+    if (!ok && lane == 0) {
         const unsigned slot = atomicAdd(Q.redo_count, 1u);
         Q.redo[slot] = ((unsigned long long)S.fit << 43) | ((unsigned long long)h << 37) |
                        ((unsigned long long)idx << 31) | (unsigned long long)j;

@@ -121,6 +121,35 @@ def test_fp64_tables_track_exact_transforms(lib, orc, p, q):
     compare_estep(gpu, ora, "fp64", label=f"tables p{p}", tol=dict(logf=1e-10, tau=1e-12, eterm=1e-10))
 
 
+def test_fp64_dof_past_tables_uses_exact_transforms(lib, orc):
+    """A component with dof 3000: its integrals use dofs past the range the
+    FP64 tables serve, so they are flagged and evaluated with the exact
+    transforms (single fit: the flagged pass; batch: the redo list).  Both
+    match the oracle far inside the FP64 tolerance (e-terms to 1e-9: at dof
+    3000 the exact transforms of the two implementations differ by ~3e-10
+    in the second moments, which are differences of nearly equal terms),
+    and the batch gives the single fit's bits."""
+    cf = lib
+    print("fp64, dof past the tables", flush=True)
+    rng = np.random.default_rng(4400)
+    P = draw_params(rng, 3, 3, 2, sigma="wishart")
+    P.nu[:] = [6.0, 3000.0]
+    y, _ = sample_hierarchy(rng, P, 25)
+    des = make_design(256, 4, seed=4401)
+    ora = orc.estep(y, P, des)
+    gpu = _gpu_estep(cf, y, P, des, "fp64")
+    np.testing.assert_allclose(gpu.logf_comp.cpu().numpy(), ora.logf_comp, rtol=0, atol=1e-10)
+    compare_estep(gpu, ora, "fp64", label="dof 3000", tol=dict(logf=1e-10, tau=1e-12, eterm=1e-9))
+    yd = torch.as_tensor(np.ascontiguousarray(y.T)).cuda()
+    es = cf.alloc_estep(y.shape[0], 3, 3, 2, cf.CFUST_FP64)
+    B = cf.Batch([(yd, cf.device_params(P), es)], cf.device_qmc(des, cf.CFUST_FP64))
+    B.estep()
+    torch.cuda.synchronize()
+    for name in ("tau", "logf_obs", "loglik", "w", "e1", "e2", "e3", "logf_comp"):
+        assert torch.equal(getattr(es, name), getattr(gpu, name)), name
+    B.close()
+
+
 def test_estep_small_workload_full(lib, orc):
     """The n=1000, p=q=2, g=2 workload in FP64 at its lattice (N=1024 x 4), every observation."""
     cf = lib
