@@ -23,8 +23,9 @@ constexpr int NDOF = MAXQ + 2;                    // dofs nu+p .. nu+p+q+1 per c
 //                s = u / sqrt(nu+u^2);
 //   rows 8..18 : quantile, log2 tau as a function of lambda = -log2(2p) on the
 //                11 intervals [c(2^k - 1), c(2^{k+1} - 1)], c = 1/4.
-// Each row holds 7 monomial coefficients in x in [-1,1] (x = 2t - 1, t the
-// position inside the interval) plus one pad float.
+// Each row holds 7 monomial coefficients in the lookup's variable -- the
+// position inside the interval (fraction of 8 tau) for the CDF rows, the float
+// mantissa in [1/2, 1) for the geometric rows -- plus one pad float.
 constexpr int TAB_CDF_ROWS = 8;
 constexpr int TAB_INV_ROWS = 11;
 constexpr int TAB_ROWS = 20;                      // 8 + 11 + 1 pad row

@@ -303,12 +303,11 @@ __device__ __forceinline__ float tab_poly(const float *row, float x) {
 // H(tau) = log2 T_lower - (nu/2) log2(tau (2 - tau)) from the CDF rows of one
 // dof's table, at pos = 8 tau in [0, 8) (8 equal intervals of tau = 1 - |s|).
 // Anything outside, NaN included, is clamped into the table so the index
-// stays in range; the position within the interval is the fraction of pos.
+// stays in range; the rows are polynomials in the fraction of pos.
 __device__ __forceinline__ float tab_cdf_H(const float *tab, float pos) {
     pos = fminf(fmaxf(pos, 0.0f), 7.99999952f);
     const int k = (int)pos;
-    const float x = fmaf(2.0f, __builtin_amdgcn_fractf(pos), -1.0f);
-    return tab_poly(tab + 8 * k, x);
+    return tab_poly(tab + 8 * k, __builtin_amdgcn_fractf(pos));
 }
 
 // Normal limit: log2 Phi(-v), v >= 0, from the CDF rows of the dof-free
@@ -318,8 +317,7 @@ __device__ __forceinline__ float tab_ncdf_l2(const float *tab, float v) {
     const float zz = fminf(v, 63.5f) + 0.25f;
     const int e = __builtin_amdgcn_frexp_expf(zz);     // zz = mant 2^e, mant in [0.5, 1)
     const float mant = __builtin_amdgcn_frexp_mantf(zz);
-    const float x = fmaf(4.0f, mant, -3.0f);
-    return tab_poly(tab + 8 * (e + 1), x);
+    return tab_poly(tab + 8 * (e + 1), mant);           // rows are polynomials in mant
 }
 
 // log2 tau from the quantile rows, given l2p = log2 p of the tail probability
@@ -331,8 +329,7 @@ __device__ __forceinline__ float tab_inv_G(const float *tab, float l2p) {
     const int e = __builtin_amdgcn_frexp_expf(zz);     // zz = mant 2^e, mant in [0.5, 1)
     const float mant = __builtin_amdgcn_frexp_mantf(zz);
     const int k = e + 1;                               // interval 0..10
-    const float x = fmaf(4.0f, mant, -3.0f);
-    return tab_poly(tab + 8 * (TAB_CDF_ROWS + k), x);
+    return tab_poly(tab + 8 * (TAB_CDF_ROWS + k), mant);   // rows are polynomials in mant
 }
 
 }  // namespace cfust

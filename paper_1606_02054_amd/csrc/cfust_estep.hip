@@ -227,7 +227,13 @@ __device__ inline double table_node_value(double nu, int row, int n) {
     return log2(dm_tau_of_lnq(-(lam + 1.0) * LN2, a, lb));
 }
 
-__device__ inline void table_fit_row(const double *f, float *dst) {
+// Row of an FP32 table: the Chebyshev fit of the 7 node values on x in
+// [-1, 1], stored as monomial coefficients in the lookup's own variable v,
+// x = alpha v + beta (v = the fraction of the position for the equal-width
+// CDF rows of the t tables, alpha = 2, beta = -1; v = the float mantissa in
+// [1/2, 1) for the geometric rows, alpha = 4, beta = -3), so a lookup
+// evaluates the polynomial at v directly.
+__device__ inline void table_fit_row(const double *f, float *dst, double alpha, double beta) {
     double c[7];
     for (int j = 0; j < 7; ++j) {
         double sacc = 0.0;
@@ -242,9 +248,19 @@ __device__ inline void table_fit_row(const double *f, float *dst) {
         for (int i = 0; i < 7; ++i) Tj[i] = (i > 0 ? 2.0 * Tm1[i - 1] : 0.0) - Tm2[i];
         for (int i = 0; i < 7; ++i) { mono[i] += c[j] * Tj[i]; Tm2[i] = Tm1[i]; Tm1[i] = Tj[i]; }
     }
-    for (int i = 0; i < 7; ++i) dst[i] = (float)mono[i];
+    double r[7] = {0, 0, 0, 0, 0, 0, 0};             // r(v) = sum_i mono_i (alpha v + beta)^i, Horner in x
+    for (int i = 6; i >= 0; --i) {
+        for (int k = 6; k >= 1; --k) r[k] = alpha * r[k - 1] + beta * r[k];
+        r[0] = beta * r[0] + mono[i];
+    }
+    for (int i = 0; i < 7; ++i) dst[i] = (float)r[i];
     dst[7] = 0.0f;
 }
+
+// Variable of row `row` (see table_fit_row): the t tables' CDF rows are
+// equal intervals of tau, every other row geometric.
+__device__ inline double row_alpha(int row, bool normal) { return row < TAB_CDF_ROWS && !normal ? 2.0 : 4.0; }
+__device__ inline double row_beta(int row, bool normal) { return row < TAB_CDF_ROWS && !normal ? -1.0 : -3.0; }
 
 constexpr int TAB_NODES = (TAB_CDF_ROWS + TAB_INV_ROWS) * 7;   // 133
 
@@ -305,7 +321,8 @@ __device__ inline void tables_body(const CompPre *__restrict__ pre, int p, int n
     }
     __syncthreads();
     float *dst = tabs + ((size_t)h * NDOF + off) * TAB_FLOATS;
-    if (t < TAB_CDF_ROWS + TAB_INV_ROWS) table_fit_row(fv + 7 * t, dst + 8 * t);
+    if (t < TAB_CDF_ROWS + TAB_INV_ROWS)
+        table_fit_row(fv + 7 * t, dst + 8 * t, row_alpha(t, isinf(nu)), row_beta(t, isinf(nu)));
     if (t >= TAB_CDF_ROWS + TAB_INV_ROWS && t < TAB_ROWS) {   // pad row
         for (int i = 0; i < 8; ++i) dst[8 * t + i] = 0.0f;
     }
@@ -801,7 +818,8 @@ __global__ __launch_bounds__(256) void k_mvt(MvtArgs a) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            if (lane < TAB_CDF_ROWS + TAB_INV_ROWS) table_fit_row(fv[wave] + 7 * lane, tab[wave] + 8 * lane);
+            if (lane < TAB_CDF_ROWS + TAB_INV_ROWS)
+                table_fit_row(fv[wave] + 7 * lane, tab[wave] + 8 * lane, row_alpha(lane, true), row_beta(lane, true));
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -816,7 +834,8 @@ __global__ __launch_bounds__(256) void k_mvt(MvtArgs a) {
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 if (lane < TAB_CDF_ROWS + TAB_INV_ROWS)
-                    table_fit_row(fv[wave] + 7 * lane, tab[wave] + dof * TAB_FLOATS + 8 * lane);
+                    table_fit_row(fv[wave] + 7 * lane, tab[wave] + dof * TAB_FLOATS + 8 * lane, row_alpha(lane, false),
+                                  row_beta(lane, false));
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
