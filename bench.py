@@ -476,7 +476,8 @@ def main():
                          "reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part of it",
+        print(json.dumps({"error": "the bench runs on one GPU only (the kernels take one GPU's share of the data); "
+                                   "--gpus above 1 is not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
