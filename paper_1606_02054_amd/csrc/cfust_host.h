@@ -134,6 +134,10 @@ inline int mstep_nblk(const cfust_dims &d, int ncu) {
     int nb = ntiles < want ? ntiles : want;
     if (nb < 1) nb = 1;
     if (nb > 1024) nb = 1024;
+    // a multiple of 8: blocks go to the 8 XCDs in turn, so the g blocks that
+    // walk the same tiles of y (same x, one per component) share an XCD and
+    // its L2, which then serves y to all but the first of them
+    if (nb >= 8) nb -= nb % 8;
     return nb;
 }
 
