@@ -57,60 +57,84 @@ struct GemmOut {
     int act;                // 0: identity, 1: GELU
 };
 
+// C = P Q^T in BF16 with FP32 accumulation (P [M][K], Q [N][K] row-major),
+// block tile 64 x 64 over 4 waves, each 32 x 32 in 16 x 16 MFMA tiles.
+// 64 x 64 slices of P and Q are staged in LDS per step with 16-byte loads;
+// the next slice's loads are issued before the current slice's MFMAs, so
+// their latency is hidden.  Rows past M or N and K past the chunk are zero,
+// which adds exact zeros to the same MFMA sequence (K ascending by 16) as
+// fragments read straight from memory.  (A 128 x 128 tile was no faster: the
+// forward products are bound by their epilogue writes, FP32 pre-activations
+// and two BF16 layouts, not by feeding the MFMAs.)
 __global__ __launch_bounds__(256) void k_gemm_bf16(const uint16_t *__restrict__ P, const uint16_t *__restrict__ Q,
                                                    int M, int N, int K, int kchunk, GemmOut o) {
-    // 64 x 32 slices of P and Q staged in LDS per step, one 16-byte load per
-    // thread and operand (row t/4, K offset 8 (t%4)); rows past M or N and K
-    // past the chunk are zero, which adds exact zeros to the same MFMA
-    // sequence (K ascending by 16) as fragments read straight from memory
-    constexpr int KC = 32, KP = KC + 8;          // pitch: 80-byte rows spread over the banks
-    __shared__ __align__(16) uint16_t ps[64 * KP], qs[64 * KP];
+    constexpr int BT = 64;                       // block tile
+    constexpr int TW = BT / 32;                  // 16 x 16 tiles per wave and dimension
+    constexpr int NLD = BT / 32;                 // 16-byte loads per thread and operand
+    constexpr int KC = 64, KP = KC + 8;          // pitch: 144-byte rows spread over the banks
+    __shared__ __align__(16) uint16_t ps[BT * KP], qs[BT * KP];
     const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int wr = 32 * (wave >> 1), wc = 32 * (wave & 1);          // the wave's quarter of the tile
-    const int row_w = blockIdx.y * 64 + wr;
-    const int col_w = blockIdx.x * 64 + wc;
+    const int wr = (BT / 2) * (wave >> 1), wc = (BT / 2) * (wave & 1);   // the wave's quarter of the tile
+    const int row_w = blockIdx.y * BT + wr;
+    const int col_w = blockIdx.x * BT + wc;
     const int k_beg = blockIdx.z * kchunk;
     const int k_end = min(K, k_beg + kchunk);
-    v4f acc[2][2];
+    v4f acc[TW][TW];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < TW; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
-    const bool colok[2] = {col_w < N, col_w + 16 < N};
-    const bool rowok[2] = {row_w < M, row_w + 16 < M};
+        for (int b = 0; b < TW; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+    bool colok[TW], rowok[TW];
+#pragma unroll
+    for (int a = 0; a < TW; ++a) { colok[a] = col_w + 16 * a < N; rowok[a] = row_w + 16 * a < M; }
     const int lr = l & 15, lk = 4 * (l >> 4);
-    const int srow = threadIdx.x >> 2, sk = 8 * (threadIdx.x & 3);
-    const int prow = blockIdx.y * 64 + srow, qrow = blockIdx.x * 64 + srow;
-    for (int k0 = k_beg; k0 < k_end; k0 += KC) {
-        uint4 pv = make_uint4(0, 0, 0, 0), qv = make_uint4(0, 0, 0, 0);
-        if (k0 + sk < k_end) {                  // K, kchunk multiples of 16: the 8 values are all in range
-            if (prow < M) pv = *reinterpret_cast<const uint4 *>(P + (size_t)prow * K + k0 + sk);
-            if (qrow < N) qv = *reinterpret_cast<const uint4 *>(Q + (size_t)qrow * K + k0 + sk);
+    uint4 pv[NLD], qv[NLD];
+    // load i of this thread: slice row (t + 256 i) / 8, K offset 8 ((t + 256 i) % 8);
+    // K, kchunk multiples of 16: a load that starts before k_end has its 8 values in range
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < NLD; ++i) {
+            const int u = threadIdx.x + 256 * i, srow = u >> 3, kq = k0 + 8 * (u & 7);
+            const int prow = blockIdx.y * BT + srow, qrow = blockIdx.x * BT + srow;
+            pv[i] = make_uint4(0, 0, 0, 0);
+            qv[i] = make_uint4(0, 0, 0, 0);
+            if (kq < k_end) {
+                if (prow < M) pv[i] = *reinterpret_cast<const uint4 *>(P + (size_t)prow * K + kq);
+                if (qrow < N) qv[i] = *reinterpret_cast<const uint4 *>(Q + (size_t)qrow * K + kq);
+            }
         }
-        *reinterpret_cast<uint4 *>(ps + srow * KP + sk) = pv;
-        *reinterpret_cast<uint4 *>(qs + srow * KP + sk) = qv;
+    };
+    if (k_beg < k_end) fetch(k_beg);
+    for (int k0 = k_beg; k0 < k_end; k0 += KC) {
+#pragma unroll
+        for (int i = 0; i < NLD; ++i) {
+            const int u = threadIdx.x + 256 * i, srow = u >> 3, sk = 8 * (u & 7);
+            *reinterpret_cast<uint4 *>(ps + srow * KP + sk) = pv[i];
+            *reinterpret_cast<uint4 *>(qs + srow * KP + sk) = qv[i];
+        }
         __syncthreads();
+        if (k0 + KC < k_end) fetch(k0 + KC);
 #pragma unroll
         for (int kk = 0; kk < KC; kk += 16) {
             if (k0 + kk >= k_end) break;
-            v4s pa[2], qb[2];
+            v4s pa[TW], qb[TW];
 #pragma unroll
-            for (int a = 0; a < 2; ++a) {
+            for (int a = 0; a < TW; ++a) {
                 pa[a] = *reinterpret_cast<const v4s *>(ps + (wr + 16 * a + lr) * KP + kk + lk);
                 qb[a] = *reinterpret_cast<const v4s *>(qs + (wc + 16 * a + lr) * KP + kk + lk);
             }
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+            for (int a = 0; a < TW; ++a)
 #pragma unroll
-                for (int b = 0; b < 2; ++b)
+                for (int b = 0; b < TW; ++b)
                     acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(pa[a], qb[b], acc[a][b], 0, 0, 0);
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < TW; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < TW; ++b) {
             if (!rowok[a] || !colok[b]) continue;
             const int col = col_w + 16 * b + lr;
             const int r0 = row_w + 16 * a + lk;
