@@ -210,6 +210,20 @@ def initialisation(cf, ds, y, qmc, dev, nstarts: int = 8) -> dict:
             "best_loglik": float(llv.ravel()[k]) if k >= 0 else None}
 
 
+def host_cpu() -> dict:
+    """Model name and logical CPU count of the host (for the CPU baseline)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count()}
+
+
 def progress(msg: str) -> None:
     """One line on stderr per finished bench section (stdout carries only the
     JSON result)."""
@@ -451,7 +465,8 @@ def batched_main(args) -> dict:
                                "sample": f"E-step of max(1, {threads}//g) observations of the first fit of each q "
                                          f"({sample_rows} rows, {c_tot:.1f} s), per (row, component) time "
                                          f"extrapolated to all pairs of the fits of that q; same lattice "
-                                         f"(N={N}, S={S}), FP64"}
+                                         f"(N={N}, S={S}), FP64",
+                               "host": host_cpu()}
     B.close()
     return out
 
@@ -601,7 +616,8 @@ def main():
         out["cpu_baseline"] = {"value": rows_n * g / (c1 - c0), "unit": "(obs*comp)/s", "cores": threads,
                                "kind": "oracle",
                                "sample": f"E-step of the first {rows_n} observations x {g} components, "
-                                         f"same lattice (N={N}, S={S}), FP64, {c1 - c0:.1f} s"}
+                                         f"same lattice (N={N}, S={S}), FP64, {c1 - c0:.1f} s",
+                               "host": host_cpu()}
     print(json.dumps(out), flush=True)
 
 
