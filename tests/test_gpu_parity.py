@@ -150,6 +150,25 @@ def test_fp64_dof_past_tables_uses_exact_transforms(lib, orc):
     B.close()
 
 
+@pytest.mark.parametrize("p,q,g,n,seed,N,S", [(16, 8, 2, 6, 61, 128, 2), (2, 2, 64, 24, 62, 256, 4)])
+def test_estep_max_sizes(lib, orc, p, q, g, n, seed, N, S):
+    """The largest p and q the C ABI takes (16 and 8: 38 lattice integrals
+    per pair, of every dimension 2..8) and the most components (64), in both
+    modes, against the oracle on the same lattice."""
+    cf = lib
+    print(f"estep max sizes p={p} q={q} g={g} n={n}", flush=True)
+    rng = np.random.default_rng(seed)
+    P = draw_params(rng, p, q, g, sigma="wishart")
+    y, _ = sample_hierarchy(rng, P, n)
+    des = make_design(N, S, seed=seed)
+    ora = orc.estep(y, P, des)
+    for mode in ("fp64", "mixed"):
+        gpu = _gpu_estep(cf, y, P, des, mode)
+        compare_estep(gpu, ora, mode, label=f"p{p}q{q}g{g} {mode}")
+        np.testing.assert_allclose(gpu.logf_comp.cpu().numpy(), ora.logf_comp, rtol=0, atol=TOL[mode]["logf"])
+        assert abs(float(gpu.loglik.cpu()[0]) - ora.loglik) <= TOL[mode]["logf"] * n
+
+
 def test_estep_small_workload_full(lib, orc):
     """The n=1000, p=q=2, g=2 workload in FP64 at its lattice (N=1024 x 4), every observation."""
     cf = lib
