@@ -233,11 +233,13 @@ __device__ inline double table_node_value(double nu, int row, int n) {
 // CDF rows of the t tables, alpha = 2, beta = -1; v = the float mantissa in
 // [1/2, 1) for the geometric rows, alpha = 4, beta = -3), so a lookup
 // evaluates the polynomial at v directly.
-__device__ inline void table_fit_row(const double *f, float *dst, double alpha, double beta) {
+// cos7: the 7 x 7 cosines cos(pi j (n + 1/2) / 7) at [j][n], or null to compute them here.
+__device__ inline void table_fit_row(const double *f, float *dst, double alpha, double beta,
+                                     const double *cos7 = nullptr) {
     double c[7];
     for (int j = 0; j < 7; ++j) {
         double sacc = 0.0;
-        for (int n = 0; n < 7; ++n) sacc += f[n] * cos(M_PI * j * (n + 0.5) / 7.0);
+        for (int n = 0; n < 7; ++n) sacc += f[n] * (cos7 ? cos7[7 * j + n] : cos(M_PI * j * (n + 0.5) / 7.0));
         c[j] = sacc * (2.0 / 7.0);
     }
     c[0] *= 0.5;
@@ -264,19 +266,33 @@ __device__ inline double row_beta(int row, bool normal) { return row < TAB_CDF_R
 
 constexpr int TAB_NODES = (TAB_CDF_ROWS + TAB_INV_ROWS) * 7;   // 133
 
-// Chebyshev coefficients of the TAB64_NC node values f of one row.
-__device__ inline void cheb_fit64(const double *f, double *c) {
-    for (int j = 0; j < TAB64_NC; ++j) {
+// The cosines of the Chebyshev fits, computed once per block into LDS:
+// cos64[j][n] = cos(pi j (n + 1/2) / TAB64_NC), cos7[j][n] likewise for 7.
+// Every thread of the block takes part; a barrier follows.
+__device__ inline void fit_cosines(double *cos64, double *cos7) {
+    for (int t = threadIdx.x; t < TAB64_NC * TAB64_NC; t += blockDim.x)
+        cos64[t] = cos(M_PI * (t / TAB64_NC) * ((t % TAB64_NC) + 0.5) / (double)TAB64_NC);
+    if (cos7)
+        for (int t = threadIdx.x; t < 49; t += blockDim.x) cos7[t] = cos(M_PI * (t / 7) * ((t % 7) + 0.5) / 7.0);
+    __syncthreads();
+}
+
+// Chebyshev coefficients of rows [row0, row0 + nrows) from their TAB64_NC
+// node values in fv (same row layout), one thread per coefficient.
+__device__ inline void cheb_fit64_rows(const double *fv, double *c, int row0, int nrows, const double *cos64) {
+    for (int u = threadIdx.x; u < nrows * TAB64_NC; u += blockDim.x) {
+        const int row = row0 + u / TAB64_NC, j = u % TAB64_NC;
+        const double *f = fv + row * TAB64_NC;
         double acc = 0.0;
-        for (int n = 0; n < TAB64_NC; ++n) acc += f[n] * cos(M_PI * j * (n + 0.5) / (double)TAB64_NC);
-        c[j] = acc * (j == 0 ? 1.0 : 2.0) / (double)TAB64_NC;
+        for (int n = 0; n < TAB64_NC; ++n) acc += f[n] * cos64[j * TAB64_NC + n];
+        c[row * TAB64_NC + j] = acc * (j == 0 ? 1.0 : 2.0) / (double)TAB64_NC;
     }
 }
 
 // First step of both table builds (finite dof): the FP64 CDF rows of dof nu
 // into h64 (LDS), one continued fraction per node and thread; fv is LDS
 // scratch for the node values.  Every thread of the block takes part.
-__device__ inline void build_cdf64(double nu, double *fv, double *h64) {
+__device__ inline void build_cdf64(double nu, double *fv, double *h64, const double *cos64) {
     const double a = 0.5 * nu, lb = dm_lbeta_half(a);
     for (int t = threadIdx.x; t < TAB64_CDF_ROWS * TAB64_NC; t += blockDim.x) {
         const int row = t / TAB64_NC, n = t % TAB64_NC;
@@ -286,8 +302,7 @@ __device__ inline void build_cdf64(double nu, double *fv, double *h64) {
         fv[t] = dm_H_lower(tau * (2.0 - tau), s * s, a, lb);
     }
     __syncthreads();
-    for (int row = threadIdx.x; row < TAB64_CDF_ROWS; row += blockDim.x)
-        cheb_fit64(fv + row * TAB64_NC, h64 + row * TAB64_NC);
+    cheb_fit64_rows(fv, h64, 0, TAB64_CDF_ROWS, cos64);
     __syncthreads();
 }
 
@@ -312,17 +327,19 @@ __device__ inline void tables_body(const CompPre *__restrict__ pre, int p, int n
     const double nu = pre[h].nu + p + off;
     __shared__ double fv[TAB_NODES];
     __shared__ double fv64[TAB64_CDF_ROWS * TAB64_NC], h64[TAB64_CDF_ROWS * TAB64_NC];
+    __shared__ double cos64[TAB64_NC * TAB64_NC], cos7[49];
     const int t = threadIdx.x;
+    fit_cosines(cos64, cos7);
     if (isinf(nu)) {
         if (t < TAB_NODES) fv[t] = table_node_value(nu, t / 7, t % 7);
     } else {
-        build_cdf64(nu, fv64, h64);
+        build_cdf64(nu, fv64, h64, cos64);
         if (t < TAB_NODES) fv[t] = table_node_from64(nu, h64, t / 7, t % 7);
     }
     __syncthreads();
     float *dst = tabs + ((size_t)h * NDOF + off) * TAB_FLOATS;
     if (t < TAB_CDF_ROWS + TAB_INV_ROWS)
-        table_fit_row(fv + 7 * t, dst + 8 * t, row_alpha(t, isinf(nu)), row_beta(t, isinf(nu)));
+        table_fit_row(fv + 7 * t, dst + 8 * t, row_alpha(t, isinf(nu)), row_beta(t, isinf(nu)), cos7);
     if (t >= TAB_CDF_ROWS + TAB_INV_ROWS && t < TAB_ROWS) {   // pad row
         for (int i = 0; i < 8; ++i) dst[8 * t + i] = 0.0f;
     }
@@ -341,13 +358,14 @@ __device__ inline void tables64_body(const CompPre *__restrict__ pre, int p, int
                                      int bid) {
     const int h = bid / ndof, off = bid % ndof;
     const double nu = pre[h].nu + p + off;
-    __shared__ double fv64[TAB64_DOUBLES], t64[TAB64_DOUBLES];
+    __shared__ double fv64[TAB64_DOUBLES], t64[TAB64_DOUBLES], cos64[TAB64_NC * TAB64_NC];
     double *dst = tabs + ((size_t)h * NDOF + off) * TAB64_DOUBLES;
     if (isinf(nu)) {
         for (int t = threadIdx.x; t < TAB64_DOUBLES; t += blockDim.x) dst[t] = 0.0;
         return;
     }
-    build_cdf64(nu, fv64, t64);
+    fit_cosines(cos64, nullptr);
+    build_cdf64(nu, fv64, t64, cos64);
     const double a = 0.5 * nu, lb = dm_lbeta_half(a);
     constexpr int Q0 = TAB64_CDF_ROWS * TAB64_NC;
     for (int t = threadIdx.x; t < TAB64_INV_ROWS * TAB64_NC; t += blockDim.x) {
@@ -358,8 +376,7 @@ __device__ inline void tables64_body(const CompPre *__restrict__ pre, int p, int
         fv64[Q0 + t] = tab64_l_solve(t64, -(lam + 1.0) * LN2, a, lb);
     }
     __syncthreads();
-    for (int row = threadIdx.x; row < TAB64_INV_ROWS; row += blockDim.x)
-        cheb_fit64(fv64 + Q0 + row * TAB64_NC, t64 + Q0 + row * TAB64_NC);
+    cheb_fit64_rows(fv64, t64, TAB64_CDF_ROWS, TAB64_INV_ROWS, cos64);
     __syncthreads();
     for (int t = threadIdx.x; t < TAB64_DOUBLES; t += blockDim.x) dst[t] = t64[t];
 }
