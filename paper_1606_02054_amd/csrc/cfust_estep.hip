@@ -575,8 +575,10 @@ __device__ inline void load_tables64(const double *__restrict__ tabs64, int h, i
 // block share the integral's tables.  MIXED: FP32 integrand, items whose FP32
 // product underflows are flagged for the FP64 pass.  !MIXED: FP64 integrand;
 // with FLAGGED_ONLY it processes only the flagged items.
+// The FP32 kernels up to m = 4 are held to 64 VGPRs, 8 waves per SIMD (the
+// m = 4 kernel needs 69 otherwise; the extra few spill outside the lattice loop).
 template <int M, bool MIXED, bool FLAGGED_ONLY, int PPL>
-__global__ __launch_bounds__(256) void k_estep_qmc(EstepQmcArgs a) {
+__global__ __launch_bounds__(256, (MIXED && M <= 4 && PPL == 1) ? 8 : 1) void k_estep_qmc(EstepQmcArgs a) {
     constexpr bool TAB64 = !MIXED && !FLAGGED_ONLY;
     __shared__ __align__(16) float tab[MIXED ? M * TAB_FLOATS : 4];
     __shared__ double tab64[TAB64 ? M * TAB64_DOUBLES : 1];
