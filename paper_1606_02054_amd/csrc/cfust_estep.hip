@@ -571,14 +571,17 @@ __device__ inline void load_tables64(const double *__restrict__ tabs64, int h, i
     for (int t = threadIdx.x; t < M * TAB64_DOUBLES; t += blockDim.x) tab64[t] = src[t];
 }
 
+// Blocks per CU (= waves per SIMD) the FP32 lattice kernels are held to.
+constexpr int fp32_min_blocks(int m) { return m <= 4 ? 8 : m == 5 ? 6 : m == 6 ? 5 : 1; }
+
 // One wave per (observation j, integral idx, component h); 4 observations per
 // block share the integral's tables.  MIXED: FP32 integrand, items whose FP32
 // product underflows are flagged for the FP64 pass.  !MIXED: FP64 integrand;
 // with FLAGGED_ONLY it processes only the flagged items.
-// The FP32 kernels up to m = 4 are held to 64 VGPRs, 8 waves per SIMD (the
-// m = 4 kernel needs 69 otherwise; the extra few spill outside the lattice loop).
+// The FP32 kernels are held to fp32_min_blocks(m) waves per SIMD (m <= 4: 8,
+// m = 5: 6, m = 6: 5); what no longer fits spills outside the lattice loop.
 template <int M, bool MIXED, bool FLAGGED_ONLY, int PPL>
-__global__ __launch_bounds__(256, (MIXED && M <= 4 && PPL == 1) ? 8 : 1) void k_estep_qmc(EstepQmcArgs a) {
+__global__ __launch_bounds__(256, MIXED && PPL == 1 ? fp32_min_blocks(M) : 1) void k_estep_qmc(EstepQmcArgs a) {
     constexpr bool TAB64 = !MIXED && !FLAGGED_ONLY;
     __shared__ __align__(16) float tab[MIXED ? M * TAB_FLOATS : 4];
     __shared__ double tab64[TAB64 ? M * TAB64_DOUBLES : 1];
@@ -1224,7 +1227,7 @@ __global__ __launch_bounds__(256) void k_batch_sum(BatchArgs B) {
 // is empty; the 4 waves of a block share the tile's component and integral,
 // hence its LDS tables, and take its observations in turn.
 template <int M, bool MIXED, int PPL>
-__global__ __launch_bounds__(256) void k_queue_qmc(QueueArgs Q) {
+__global__ __launch_bounds__(256, MIXED && PPL == 1 ? fp32_min_blocks(M) : 1) void k_queue_qmc(QueueArgs Q) {
     __shared__ __align__(16) float tab[MIXED ? M * TAB_FLOATS : 4];
     __shared__ double tab64[MIXED ? 1 : M * TAB64_DOUBLES];
     __shared__ double smean[4][MAXS];
@@ -1284,7 +1287,7 @@ __global__ __launch_bounds__(256) void k_queue_qmc(QueueArgs Q) {
 // item its registers are not held across items, which the persistent form
 // pays for; the autotuner picks between the two.  Block t = y * gridDim.x + x.
 template <int M, bool MIXED, int PPL>
-__global__ __launch_bounds__(256) void k_queue_grid(QueueArgs Q) {
+__global__ __launch_bounds__(256, MIXED && PPL == 1 ? fp32_min_blocks(M) : 1) void k_queue_grid(QueueArgs Q) {
     __shared__ __align__(16) float tab[MIXED ? M * TAB_FLOATS : 4];
     __shared__ double tab64[MIXED ? 1 : M * TAB64_DOUBLES];
     __shared__ double smean[4][MAXS];
