@@ -571,15 +571,17 @@ __device__ inline void load_tables64(const double *__restrict__ tabs64, int h, i
     for (int t = threadIdx.x; t < M * TAB64_DOUBLES; t += blockDim.x) tab64[t] = src[t];
 }
 
-// Blocks per CU (= waves per SIMD) the FP32 lattice kernels are held to.
-constexpr int fp32_min_blocks(int m) { return m <= 4 ? 8 : m == 5 ? 6 : m == 6 ? 5 : 1; }
+// Blocks per CU (= waves per SIMD) the FP32 lattice kernels are held to
+// (m = 5, 6; no bound elsewhere).  Held to 8 waves, the m = 4 kernel was 1.5%
+// faster but spilled its prologue to memory (8 -> 46 MiB of HBM traffic per
+// launch of the bench workload), so it keeps 69 VGPRs and 7 waves.
+constexpr int fp32_min_blocks(int m) { return m == 5 ? 6 : m == 6 ? 5 : 1; }
 
 // One wave per (observation j, integral idx, component h); 4 observations per
 // block share the integral's tables.  MIXED: FP32 integrand, items whose FP32
 // product underflows are flagged for the FP64 pass.  !MIXED: FP64 integrand;
 // with FLAGGED_ONLY it processes only the flagged items.
-// The FP32 kernels are held to fp32_min_blocks(m) waves per SIMD (m <= 4: 8,
-// m = 5: 6, m = 6: 5); what no longer fits spills outside the lattice loop.
+// The FP32 kernels are held to fp32_min_blocks(m) waves per SIMD.
 template <int M, bool MIXED, bool FLAGGED_ONLY, int PPL>
 __global__ __launch_bounds__(256, MIXED && PPL == 1 ? fp32_min_blocks(M) : 1) void k_estep_qmc(EstepQmcArgs a) {
     constexpr bool TAB64 = !MIXED && !FLAGGED_ONLY;
