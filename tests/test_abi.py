@@ -74,3 +74,17 @@ def test_bench_flop_bookkeeping():
     assert bench.integral_dims(2) == [2, 2]
     assert len(bench.integral_dims(8)) == 38
     assert bench.lattice_flops_per_point(2) == bench.FLOPS_CDF + bench.FLOPS_QUANTILE + 2
+
+
+def test_bench_refuses_several_gpus():
+    """The bench measures one GPU; --gpus above 1 exits with status 2 and a
+    JSON line saying so, before any GPU work."""
+    import json
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=root)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert msg["n_gpus"] == 2 and "one GPU" in msg["error"]
