@@ -1237,6 +1237,7 @@ __global__ __launch_bounds__(256, MIXED && PPL == 1 ? fp32_min_blocks(M) : 1) vo
     __shared__ long long s_tile;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int cur_f = -1, cur_h = -1, cur_dof = -1;
+    EstepQmcArgs acopy;
     for (;;) {
         if (threadIdx.x == 0) s_tile = (long long)atomicAdd(Q.counter, 1ULL);
         __syncthreads();              // also: every wave is done with the previous tile
@@ -1260,7 +1261,12 @@ __global__ __launch_bounds__(256, MIXED && PPL == 1 ? fp32_min_blocks(M) : 1) vo
         const long long rest = local / S.rtiles;
         const int idx = S.idx0 + (int)(rest % S.nidx);
         const int h = (int)(rest / S.nidx);
-        const EstepQmcArgs &a = Q.fits[S.fit].qa;     // in device memory (its lattice is Q.lat)
+        // FP64: a copy, not a reference into device memory (read through the
+        // reference its fields were kept in VGPRs and the kernel spilled); the
+        // FP32 form keeps the reference (a copy held across the tile loop costs
+        // it registers instead)
+        if (!MIXED) acopy = Q.fits[S.fit].qa;
+        const EstepQmcArgs &a = MIXED ? Q.fits[S.fit].qa : acopy;
         const int dof = int_desc(a.q, idx).dofoff;
         if (S.fit != cur_f || h != cur_h || dof != cur_dof) {
             if (MIXED) load_tables<M>(a.tabs, h, dof, tab);
@@ -1309,7 +1315,7 @@ __global__ __launch_bounds__(256, MIXED && PPL == 1 ? fp32_min_blocks(M) : 1) vo
     const long long rest = local / S.rtiles;
     const int idx = S.idx0 + (int)(rest % S.nidx);
     const int h = (int)(rest / S.nidx);
-    const EstepQmcArgs &a = Q.fits[S.fit].qa;
+    const EstepQmcArgs a = Q.fits[S.fit].qa;       // a copy: through a reference its fields took VGPRs
     if (MIXED) {
         load_tables<M>(a.tabs, h, int_desc(a.q, idx).dofoff, tab);
         __syncthreads();
@@ -1343,7 +1349,8 @@ __global__ __launch_bounds__(256) void k_queue_redo(QueueArgs Q) {
                                      (unsigned)__builtin_amdgcn_readfirstlane((unsigned)v0);
         const int f = (int)(v >> 43), h = (int)((v >> 37) & 63), idx = (int)((v >> 31) & 63);
         const int j = (int)(v & 0x7fffffffULL);
-        qmc_item<M, false, 1>(Q.fits[f].qa, h, idx, j, nullptr, nullptr, smean[wave], &witem[wave], lane);
+        const EstepQmcArgs a = Q.fits[f].qa;
+        qmc_item<M, false, 1>(a, h, idx, j, nullptr, nullptr, smean[wave], &witem[wave], lane);
     }
 }
 
