@@ -291,17 +291,23 @@ __device__ inline void mstep_solve_body(const MsolveArgs &a, int32_t *cstat, int
     __shared__ unsigned long long s_mask[4];
     const int p = a.p, q = a.q, tid = threadIdx.x, nt = blockDim.x;
     const int NS = nstat(p, q);
-    // block partials of statistic s: one wave per statistic, lanes over blocks
-    // (coalesced), then a fixed butterfly, so the sum is reproducible
+    // block partials of statistic s: lanes over blocks (coalesced), then a
+    // fixed butterfly, so the sum is reproducible; each wave takes 4
+    // statistics per pass so that their loads are in flight together
     {
         const int wave = tid >> 6, lane = tid & 63, nw = nt >> 6;
-        for (int s = wave; s < NS; s += nw) {
-            const double *src = a.partial + ((size_t)h * NS + s) * a.nblk;
-            double v = 0.0;
-#pragma unroll 4
-            for (int b = lane; b < a.nblk; b += 64) v += src[b];
-            v = ms_lane_sum(v, 64);
-            if (lane == 0) st[s] = v;
+        for (int s0 = 4 * wave; s0 < NS; s0 += 4 * nw) {
+            double v[4] = {0.0, 0.0, 0.0, 0.0};
+            const double *src = a.partial + ((size_t)h * NS + s0) * a.nblk;
+            for (int b = lane; b < a.nblk; b += 64)
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (s0 + u < NS) v[u] += src[(size_t)u * a.nblk + b];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                v[u] = ms_lane_sum(v[u], 64);
+                if (lane == 0 && s0 + u < NS) st[s0 + u] = v[u];
+            }
         }
     }
     __syncthreads();
