@@ -42,7 +42,7 @@ FLOPS_QUANTILE = 29          # quantile draw y_i
 TRAFFIC_SOURCES = ["paper_1606_02054_amd/csrc/cfust_sov.h", "paper_1606_02054_amd/csrc/cfust_devmath.h",
                    "paper_1606_02054_amd/csrc/cfust_estep.hip"]
 TRAFFIC_DIGEST = "2234b3b7afdfac28"
-TRAFFIC_MIB = {"read": 3.40 + 2.73 + 2.75, "write": 4.77 + 5.66 + 7.50}
+TRAFFIC_MIB = {"read": 3.47 + 2.73 + 2.75, "write": 4.77 + 5.66 + 7.50}
 
 
 def kernel_digest() -> str:
