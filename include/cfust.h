@@ -139,6 +139,26 @@ cfust_status cfust_estep(cfust_handle handle, const double *y, cfust_dims dims,
                          const cfust_params *params, const cfust_qmc *qmc,
                          const cfust_estep_out *out, void *stream);
 
+/* Allocation-free E-step, for callers that cannot allocate device memory
+ * (work under HIP stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, kernels and results as cfust_estep, bit for
+ * bit, but its workspace is a fixed device array of CFUST_NOALLOC_WS_BYTES
+ * that the library holds on every device it is loaded on until the process
+ * ends (its address is looked up once per device by cfust_create).  The call
+ * makes no hipMalloc, hipFree or other allocating call and records no
+ * profiling events.  Workspace needed: about g n (12 J + 16) bytes plus 61 KB
+ * per component, J = lattice integrals per pair (2 at q = 2, 12 at q = 4,
+ * 38 at q = 8; e.g. n up to ~28000 at p = q = 8, g = 5); a larger call returns
+ * CFUST_EINVAL before any launch.  All calls on one device share that
+ * device's array, which keeps the last call's contents: calls that overlap on
+ * one device (other streams, other threads, other handles) race and must be
+ * serialised by the caller.  CFUST_EDEVICE if the array's address could not
+ * be obtained at cfust_create. */
+#define CFUST_NOALLOC_WS_BYTES (64u << 20)
+cfust_status cfust_estep_noalloc(cfust_handle handle, const double *y, cfust_dims dims,
+                                 const cfust_params *params, const cfust_qmc *qmc,
+                                 const cfust_estep_out *out, void *stream);
+
 /* M-step, Sec. 3.2 eqs. (18)-(22), in the order pi, mu (with Delta^(k)),
  * Delta (with mu^(k+1)), Sigma (with both), nu.  Eq. (22) is solved with the
  * last sum added ("+"), by 8 rounds of 256-point multisection of [1, 200]

@@ -18,7 +18,7 @@ import torch
 from . import _binding as B
 from ._binding import CFUST_FP64, CFUST_MIXED, LATTICE_DIM
 
-__all__ = ["Handle", "DeviceParams", "DeviceQmc", "EStepResult", "cfust_estep", "cfust_mstep",
+__all__ = ["Handle", "DeviceParams", "DeviceQmc", "EStepResult", "cfust_estep", "cfust_estep_noalloc", "cfust_mstep",
            "cfust_loglik", "mvt_cdf_batch", "CFUST_FP64", "CFUST_MIXED", "default_handle",
            "device_params", "device_qmc", "decode_status"]
 
@@ -208,6 +208,19 @@ def cfust_estep(y: torch.Tensor, params: DeviceParams, qmc: DeviceQmc, out: Opti
     st = h.lib.cfust_estep(h.h, _ptr(y), B.Dims(n, params.p, params.q, params.g), C.byref(pc),
                            C.byref(qmc.c), C.byref(oc), _stream(stream))
     B.check(st, h.h, "cfust_estep")
+    return out
+
+
+def cfust_estep_noalloc(y: torch.Tensor, params: DeviceParams, qmc: DeviceQmc, out: EStepResult,
+                        stream=None, handle: Optional[Handle] = None) -> EStepResult:
+    """cfust_estep with the library's fixed per-device workspace (no device
+    allocation inside the call).  ``out`` must be preallocated by the caller."""
+    h = handle or default_handle()
+    n = _check_y(y, params.p)
+    pc, oc = params.c(), out.c()
+    st = h.lib.cfust_estep_noalloc(h.h, _ptr(y), B.Dims(n, params.p, params.q, params.g), C.byref(pc),
+                                   C.byref(qmc.c), C.byref(oc), _stream(stream))
+    B.check(st, h.h, "cfust_estep_noalloc")
     return out
 
 

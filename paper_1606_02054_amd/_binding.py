@@ -17,6 +17,7 @@ CFUST_FP64 = 0
 CFUST_MIXED = 1
 LATTICE_DIM = 8
 MAX_P, MAX_Q, MAX_G, MAX_SHIFTS = 16, 8, 64, 64
+NOALLOC_WS_BYTES = 64 << 20
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_LAYERS = 16, 256, 16, 5
 MLP_K = [MLP_IN, MLP_HIDDEN, MLP_HIDDEN, MLP_HIDDEN, MLP_HIDDEN]
 MLP_N = [MLP_HIDDEN, MLP_HIDDEN, MLP_HIDDEN, MLP_HIDDEN, MLP_OUT]
@@ -32,7 +33,7 @@ EXPORTS = ["cfust_create", "cfust_destroy", "cfust_last_error", "cfust_estep", "
            "cfust_autotune", "cfust_mlp_forward", "cfust_mlp_backward", "cfust_mlp_adam",
            "cfust_mlp_loss", "cfust_mlp_features", "cfust_estep_surrogate", "cfust_batch_create",
            "cfust_batch_destroy", "cfust_batch_estep", "cfust_batch_mstep", "cfust_fit_batch", "cfust_batch_tune",
-           "cfust_init"]
+           "cfust_init", "cfust_estep_noalloc"]
 MAX_FITS = 1024
 
 
@@ -98,6 +99,8 @@ def load(path: str = LIB_PATH):
     lib.cfust_last_error.restype = C.c_char_p; lib.cfust_last_error.argtypes = [vp]
     lib.cfust_estep.restype = C.c_int
     lib.cfust_estep.argtypes = [vp, vp, Dims, C.POINTER(ParamsC), C.POINTER(QmcC), C.POINTER(EstepOutC), vp]
+    lib.cfust_estep_noalloc.restype = C.c_int
+    lib.cfust_estep_noalloc.argtypes = [vp, vp, Dims, C.POINTER(ParamsC), C.POINTER(QmcC), C.POINTER(EstepOutC), vp]
     lib.cfust_mstep.restype = C.c_int
     lib.cfust_mstep.argtypes = [vp, vp, Dims, C.POINTER(EstepOutC), i32, C.POINTER(ParamsC),
                                 C.POINTER(ParamsC), vp, vp]

@@ -2,6 +2,7 @@
 // argument checks, workspace, and the launch sequence of each call.
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "cfust_host.h"
@@ -43,9 +44,9 @@ EstepWs estep_layout(const cfust_dims &d, int J, bool own_logf) {
     return w;
 }
 
-hipError_t timed_qmc(cfust_handle h, const EstepQmcArgs &a, int m, int nidx, hipStream_t s) {
+hipError_t timed_qmc(cfust_handle h, const EstepQmcArgs &a, bool may_time, int m, int nidx, hipStream_t s) {
     const int ppl = tuned_ppl(h, m, a.lat, a.mixed != 0);
-    if (!h->prof || a.n == 0 || nidx == 0) return launch_estep_qmc(a, m, nidx, s, nullptr, nullptr, ppl);
+    if (!may_time || !h->prof || a.n == 0 || nidx == 0) return launch_estep_qmc(a, m, nidx, s, nullptr, nullptr, ppl);
     ProfRec r{m, pool_event(h), pool_event(h)};
     const hipError_t e = launch_estep_qmc(a, m, nidx, s, r.e0, r.e1, ppl);
     if (r.e0 && r.e1) h->rec.push_back(r);
@@ -58,7 +59,8 @@ constexpr int SUR_CHUNK = 65536;   // network rows per forward launch
 cfust_status run_estep(cfust_handle h, const double *y, const cfust_dims &d, const cfust_params *P,
                        const cfust_qmc *Q, bool density_only, double *tau, double *logf_obs, double *loglik,
                        void *w, void *e1, void *e2, void *e3, double *logf_comp, double *se,
-                       int32_t *status, hipStream_t s, const cfust_surrogate *sur = nullptr) {
+                       int32_t *status, hipStream_t s, const cfust_surrogate *sur = nullptr,
+                       char *fixed_ws = nullptr, size_t fixed_cap = 0) {
     cfust_status st;
     if ((st = check_dims(h, d)) != CFUST_OK) return st;
     if ((st = check_params(h, P)) != CFUST_OK) return st;
@@ -99,16 +101,26 @@ cfust_status run_estep(cfust_handle h, const double *y, const cfust_dims &d, con
         sb_off = c.take<uint16_t>((size_t)SUR_CHUNK * CFUST_MLP_HIDDEN);
         total = c.off;
     }
-    if ((st = ensure_ws(h, total)) != CFUST_OK) return st;
+    char *base;
+    if (fixed_ws) {                  // caller-independent fixed array: no allocation
+        if (total > fixed_cap)
+            return fail(h, CFUST_EINVAL, "E-step workspace of %zu bytes exceeds the fixed %zu-byte array "
+                        "(n = %d, q = %d, g = %d)", total, fixed_cap, d.n, d.q, d.g);
+        base = fixed_ws;
+    } else {
+        if ((st = ensure_ws(h, total)) != CFUST_OK) return st;
+        base = (char *)h->ws;
+    }
+    auto W = [base](size_t off) { return (void *)(base + off); };
     if ((st = hip_check(h, hipSetDevice(h->device), "hipSetDevice")) != CFUST_OK) return st;
-    CompPre *pre = at<CompPre>(h, L.pre);
-    double *lfc = logf_comp ? logf_comp : at<double>(h, L.logf);
+    CompPre *pre = (CompPre *)W(L.pre);
+    double *lfc = logf_comp ? logf_comp : (double *)W(L.logf);
     hipError_t e = launch_precompute(*P, d.p, d.q, d.g, pre, s);
-    if (e == hipSuccess && mixed && J > 0) e = launch_tables(pre, d.p, d.g, d.q + 2, at<float>(h, L.tabs), s);
-    if (e == hipSuccess && !mixed && J > 0) e = launch_tables64(pre, d.p, d.g, d.q + 2, at<double>(h, L.tabs64), s);
+    if (e == hipSuccess && mixed && J > 0) e = launch_tables(pre, d.p, d.g, d.q + 2, (float *)W(L.tabs), s);
+    if (e == hipSuccess && !mixed && J > 0) e = launch_tables64(pre, d.p, d.g, d.q + 2, (double *)W(L.tabs64), s);
     int32_t *need = nullptr;
     if (e == hipSuccess && sur && J > 0) {
-        need = at<int32_t>(h, need_off);
+        need = (int32_t *)W(need_off);
         e = launch_fill_i32(need, (size_t)d.g * J * d.n, 1, s);
         for (int k = 0; k < nsg && e == hipSuccess; ++k) {
             const SurGroup &G = sg[k];
@@ -117,7 +129,7 @@ cfust_status run_estep(cfust_handle h, const double *y, const cfust_dims &d, con
             fa.y = y; fa.mu = P->mu; fa.pre = pre;
             fa.n = d.n; fa.p = d.p; fa.q = d.q; fa.g = d.g; fa.J = J;
             fa.m = G.m; fa.idx0 = G.idx0; fa.cnt = G.cnt;
-            fa.X0 = at<uint16_t>(h, G.x0); fa.inrange = at<int32_t>(h, G.inr); fa.base = at<double>(h, G.base);
+            fa.X0 = (uint16_t *)W(G.x0); fa.inrange = (int32_t *)W(G.inr); fa.base = (double *)W(G.base);
             e = launch_sur_features(fa, s);
             if (e == hipSuccess && G.rows_pad > G.rows)
                 e = launch_fill_i32((int32_t *)(fa.X0 + (size_t)G.rows * CFUST_MLP_IN),
@@ -125,37 +137,37 @@ cfust_status run_estep(cfust_handle h, const double *y, const cfust_dims &d, con
             for (long r = 0; r < G.rows_pad && e == hipSuccess; r += SUR_CHUNK) {
                 const int B = (int)(G.rows_pad - r < SUR_CHUNK ? G.rows_pad - r : SUR_CHUNK);
                 e = launch_mlp_forward(*sur->model[G.m], fa.X0 + (size_t)r * CFUST_MLP_IN, B,
-                                       at<float>(h, G.out) + (size_t)r * CFUST_MLP_OUT, nullptr,
-                                       at<uint16_t>(h, sa_off), at<uint16_t>(h, sb_off), s);
+                                       (float *)W(G.out) + (size_t)r * CFUST_MLP_OUT, nullptr,
+                                       (uint16_t *)W(sa_off), (uint16_t *)W(sb_off), s);
             }
             if (e != hipSuccess) break;
             SurSelArgs sa;
             sa.n = d.n; sa.g = d.g; sa.J = J; sa.m = G.m; sa.idx0 = G.idx0; sa.cnt = G.cnt;
-            sa.out = at<float>(h, G.out); sa.inrange = at<int32_t>(h, G.inr); sa.tol = sur->tol;
-            sa.base = at<double>(h, G.base);
-            sa.est = at<double>(h, L.est); sa.lnA = at<double>(h, L.lnA); sa.need = need;
+            sa.out = (float *)W(G.out); sa.inrange = (int32_t *)W(G.inr); sa.tol = sur->tol;
+            sa.base = (double *)W(G.base);
+            sa.est = (double *)W(L.est); sa.lnA = (double *)W(L.lnA); sa.need = need;
             e = launch_sur_select(sa, s);
         }
     }
     if (e == hipSuccess && J > 0) {
         EstepQmcArgs a;
         a.need = need;
-        a.y = y; a.mu = P->mu; a.pre = pre; a.tabs = at<float>(h, L.tabs);
-        a.tabs64 = mixed ? nullptr : at<double>(h, L.tabs64);
+        a.y = y; a.mu = P->mu; a.pre = pre; a.tabs = (float *)W(L.tabs);
+        a.tabs64 = mixed ? nullptr : (double *)W(L.tabs64);
         a.lat = lattice_of(Q);
         a.n = d.n; a.p = d.p; a.q = d.q; a.g = d.g; a.J = J; a.mixed = mixed ? 1 : 0;
-        a.est = at<double>(h, L.est); a.lnA = at<double>(h, L.lnA); a.se = se;
-        a.flag = at<int32_t>(h, L.flag);
+        a.est = (double *)W(L.est); a.lnA = (double *)W(L.lnA); a.se = se;
+        a.flag = (int32_t *)W(L.flag);
         // integrals of equal dimension share a launch: (A, B) m = q, C_i m = q-1, D_ik m = q-2
         a.idx0 = 0;
-        e = timed_qmc(h, a, d.q, density_only ? 1 : 2, s);
+        e = timed_qmc(h, a, fixed_ws == nullptr, d.q, density_only ? 1 : 2, s);
         if (e == hipSuccess && !density_only && d.q - 1 >= 2) {
             a.idx0 = 2;
-            e = timed_qmc(h, a, d.q - 1, d.q, s);
+            e = timed_qmc(h, a, fixed_ws == nullptr, d.q - 1, d.q, s);
         }
         if (e == hipSuccess && !density_only && d.q - 2 >= 2) {
             a.idx0 = 2 + d.q;
-            e = timed_qmc(h, a, d.q - 2, npairs(d.q), s);
+            e = timed_qmc(h, a, fixed_ws == nullptr, d.q - 2, npairs(d.q), s);
         }
     }
     if (e == hipSuccess) {
@@ -163,7 +175,7 @@ cfust_status run_estep(cfust_handle h, const double *y, const cfust_dims &d, con
         a.y = y; a.mu = P->mu; a.pre = pre;
         a.n = d.n; a.p = d.p; a.q = d.q; a.g = d.g; a.J = J > 0 ? J : 1;
         a.mixed = mixed ? 1 : 0; a.density_only = density_only ? 1 : 0;
-        a.est = at<double>(h, L.est); a.lnA = at<double>(h, L.lnA);
+        a.est = (double *)W(L.est); a.lnA = (double *)W(L.lnA);
         a.logf_comp = lfc;
         a.w = w; a.e1 = e1; a.e2 = e2; a.e3 = e3;
         e = launch_assemble(a, s);
@@ -175,7 +187,7 @@ cfust_status run_estep(cfust_handle h, const double *y, const cfust_dims &d, con
         a.tau = density_only ? nullptr : tau;
         a.logf_obs = logf_obs;
         a.w = density_only ? nullptr : w; a.e1 = e1; a.e2 = e2; a.e3 = e3;
-        a.partial = at<double>(h, L.partial);
+        a.partial = (double *)W(L.partial);
         e = launch_lse(a, loglik, s);
     }
     if (e == hipSuccess && status) e = launch_status_fold(pre, d.g, status, s);
@@ -184,6 +196,47 @@ cfust_status run_estep(cfust_handle h, const double *y, const cfust_dims &d, con
         else e = launch_fill_i32(sur->n_fallback, 1, 0, s);
     }
     return hip_check(h, e, density_only ? "cfust_loglik launch" : "cfust_estep launch");
+}
+
+// Fixed device workspace of the allocation-free E-step.  In host code the
+// name `scratch` is only a stand-in for the array: its device address comes
+// from hipGetSymbolAddress, once per device (with that device current), and
+// only that address is ever handed to kernels.  Each device that loads the
+// library holds its own copy until the process ends.  Every call on a device
+// shares that device's array; nothing in it needs to start at zero (an E-step
+// writes every workspace element before reading it).
+static __device__ __align__(256) unsigned char scratch[CFUST_NOALLOC_WS_BYTES];
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+hipError_t g_scratch_err[SCRATCH_MAX_DEVICES] = {};
+bool g_scratch_done[SCRATCH_MAX_DEVICES] = {};
+
+// Looks up (once per device) the address of this device's copy of `scratch`
+// with the device current, restoring the caller's current device afterwards.
+void scratch_setup(cfust_ctx *c) {
+    if (c->device < 0 || c->device >= SCRATCH_MAX_DEVICES) {
+        c->scratch_err = (int)hipErrorInvalidDevice;
+        return;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_done[c->device]) {
+        int prev = 0;
+        hipError_t e = hipGetDevice(&prev);
+        if (e == hipSuccess) e = hipSetDevice(c->device);
+        void *ptr = nullptr;
+        if (e == hipSuccess) {
+            e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            const hipError_t r = hipSetDevice(prev);
+            if (e == hipSuccess) e = r;
+        }
+        g_scratch_ptr[c->device] = e == hipSuccess ? ptr : nullptr;
+        g_scratch_err[c->device] = e;
+        g_scratch_done[c->device] = true;
+    }
+    c->scratch = g_scratch_ptr[c->device];
+    c->scratch_err = (int)g_scratch_err[c->device];
 }
 
 }  // namespace
@@ -204,6 +257,7 @@ cfust_status cfust_create(cfust_handle *handle, int device) {
     c->device = device;
     c->ncu = prop.multiProcessorCount;
     c->arch = prop.gcnArchName;
+    scratch_setup(c);
     *handle = c;
     return CFUST_OK;
 }
@@ -229,6 +283,18 @@ cfust_status cfust_estep(cfust_handle h, const double *y, cfust_dims dims, const
     if (!out) return fail(h, CFUST_EINVAL, "out is NULL");
     return run_estep(h, y, dims, params, qmc, false, out->tau, out->logf_obs, out->loglik, out->w, out->e1,
                      out->e2, out->e3, out->logf_comp, out->cdf_stderr, out->status, (hipStream_t)stream);
+}
+
+cfust_status cfust_estep_noalloc(cfust_handle h, const double *y, cfust_dims dims, const cfust_params *params,
+                                 const cfust_qmc *qmc, const cfust_estep_out *out, void *stream) {
+    if (!h) return CFUST_EINVAL;
+    if (!out) return fail(h, CFUST_EINVAL, "out is NULL");
+    if (!h->scratch)
+        return fail(h, CFUST_EDEVICE, "fixed workspace of device %d unavailable: hipGetSymbolAddress: %s", h->device,
+                    hipGetErrorString((hipError_t)h->scratch_err));
+    return run_estep(h, y, dims, params, qmc, false, out->tau, out->logf_obs, out->loglik, out->w, out->e1,
+                     out->e2, out->e3, out->logf_comp, out->cdf_stderr, out->status, (hipStream_t)stream, nullptr,
+                     (char *)h->scratch, (size_t)CFUST_NOALLOC_WS_BYTES);
 }
 
 cfust_status cfust_estep_surrogate(cfust_handle h, const double *y, cfust_dims dims, const cfust_params *params,

@@ -28,6 +28,10 @@ struct cfust_ctx {
     std::string arch;                // gcnArchName of the device
     // autotuner cache: (m, N, S, precision) -> lattice points per lane
     std::map<std::tuple<int, int, int, int>, int> tuned;
+    // device address of this device's fixed workspace array (allocation-free
+    // E-step), or null when its lookup failed (scratch_err holds the HIP error)
+    void *scratch = nullptr;
+    int scratch_err = 0;
 };
 
 namespace cfust_host {
