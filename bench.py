@@ -28,20 +28,35 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "CFUST E-step (obs×comp)/s at stated tol vs FP64 oracle; surrogate vs QMC speedup"
-PEAK_FP32_TFLOPS = 157.3     # MI355X vector FP32 (chip figure)
-# FP32 operations of one (lattice point, coordinate) step of the integrand,
-# counted from the routine (FMA = 2, add/mul = 1, transcendental = 1):
-FLOPS_CDF = 32               # conditional truncation probability e_i
-FLOPS_QUANTILE = 29          # quantile draw y_i
+PEAK_FP32_TFLOPS = 157.3     # MI355X vector FP32 (chip figure: 2 wave64 FMA issues per CU per cycle)
 
-
-# HBM bytes of the FP32 lattice kernels per E-step of the default workload,
-# from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a 1 GiB copy
-# (profiles/k_estep_qmc_cfust_n20000_p4_q4_g3_counters.md), valid for the
-# kernel sources with this digest only; otherwise the figure is reported null.
+# Kernel sources that the measured constants below belong to: the FP32
+# operations per lattice point and the HBM bytes of the lattice kernels were
+# read from rocprofv3 counters for sources with this digest; when the sources
+# change, the bench reports those figures as null until they are measured
+# again (profiles/k_estep_qmc_counters.md).
 TRAFFIC_SOURCES = ["paper_1606_02054_amd/csrc/cfust_sov.h", "paper_1606_02054_amd/csrc/cfust_devmath.h",
-                   "paper_1606_02054_amd/csrc/cfust_estep.hip"]
-TRAFFIC_DIGEST = "2234b3b7afdfac28"
+                   "paper_1606_02054_amd/csrc/cfust_estep.hip", "paper_1606_02054_amd/csrc/cfust_common.h"]
+KERNEL_DIGEST = "df6d8abddb1c4ec9"
+# FP32 arithmetic of one lattice point of the m-variate integrand in the FP32
+# lattice kernel: (2 x SQ_INSTS_VALU_FMA_F32 + MUL_F32 + ADD_F32 + TRANS_F32)
+# of a launch divided by the lattice points it evaluates.
+LATTICE_FLOPS_PER_POINT = {2: 58.02, 3: 117.02, 4: 178.02, 5: 241.02, 6: 306.02, 7: 373.02, 8: 442.02}
+# VALU issue of each kernel from SQ_INSTS_VALU, SQ_ACTIVE_INST_VALU2 and
+# GRBM_GUI_ACTIVE: wave64 VALU instructions per CU per cycle (the chip issues
+# at most 2: one pair per SIMD per 4-cycle slot) and the share of them issued
+# in pairs.
+LATTICE_VALU_ISSUE = {
+    2: {'valu_per_point': 67.1, 'valu_per_cu_cycle': 1.180, 'dual_issue_frac': 0.638, 'valu_slot_busy': 0.912},
+    3: {'valu_per_point': 132.0, 'valu_per_cu_cycle': 1.282, 'dual_issue_frac': 0.673, 'valu_slot_busy': 0.969},
+    4: {'valu_per_point': 199.1, 'valu_per_cu_cycle': 1.183, 'dual_issue_frac': 0.568, 'valu_slot_busy': 0.955},
+    5: {'valu_per_point': 267.0, 'valu_per_cu_cycle': 1.125, 'dual_issue_frac': 0.555, 'valu_slot_busy': 0.914},
+    6: {'valu_per_point': 337.2, 'valu_per_cu_cycle': 1.232, 'dual_issue_frac': 0.589, 'valu_slot_busy': 0.980},
+    7: {'valu_per_point': 407.3, 'valu_per_cu_cycle': 1.215, 'dual_issue_frac': 0.584, 'valu_slot_busy': 0.968},
+    8: {'valu_per_point': 478.1, 'valu_per_cu_cycle': 1.100, 'dual_issue_frac': 0.502, 'valu_slot_busy': 0.921},
+}
+# HBM bytes of the FP32 lattice kernels per E-step of the default workload
+# (FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy).
 TRAFFIC_MIB = {"read": 3.47 + 2.73 + 2.75, "write": 4.77 + 5.66 + 7.50}
 
 
@@ -54,16 +69,57 @@ def kernel_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def lattice_flops_per_point(m: int) -> int:
-    """Flops of one lattice point of an m-variate T_m: quantiles for
-    coordinates 0..m-2, probabilities for 1..m-1, plus the Cholesky rows
-    (2 flops per off-diagonal entry)."""
-    return (m - 1) * (FLOPS_CDF + FLOPS_QUANTILE) + m * (m - 1)
+def counters_current() -> bool:
+    return kernel_digest() == KERNEL_DIGEST
+
+
+def lattice_flops_per_point(m: int):
+    """Counter-measured FP32 flops of one lattice point of an m-variate T_m
+    (None when the kernel sources changed since the counters were taken)."""
+    if not counters_current():
+        return None
+    return LATTICE_FLOPS_PER_POINT.get(m)
 
 
 def integral_dims(q: int):
     dims = [q, q] + [q - 1] * q + [q - 2] * (q * (q - 1) // 2)
     return [m for m in dims if m >= 2]
+
+
+def lattice_roofline(prof, points_by_m, steps: int, kernel: str, traffic=None) -> dict:
+    """Roofline of the FP32 lattice kernels from the HIP events that bracket
+    them (prof: {m: (total ms, launches)} over `steps` steps) and the lattice
+    points each dimension evaluates per step.  The top level is the dominant
+    kernel (the dimension with the most time); `all_lattice` aggregates every
+    dimension."""
+    per = {}
+    for m in sorted(prof):
+        if m not in points_by_m or prof[m][1] == 0:
+            continue
+        ms_launch = prof[m][0] / prof[m][1]
+        launches = prof[m][1] / steps
+        fpp = lattice_flops_per_point(m)
+        flops = fpp * points_by_m[m] / launches if fpp is not None else None
+        per[m] = {"avg_ms": ms_launch, "launches_per_step": launches, "points_per_launch": points_by_m[m] / launches,
+                  "flops_per_point": fpp, "achieved": flops / (ms_launch / 1e3) / 1e12 if flops else None,
+                  "valu_issue": LATTICE_VALU_ISSUE.get(m) if counters_current() else None}
+    if not per:
+        return {"bound": "alu", "achieved": None, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": None,
+                "traffic": traffic, "kernel": kernel}
+    dom = max(per, key=lambda m: per[m]["avg_ms"] * per[m]["launches_per_step"])
+    d = per[dom]
+    tot_ms = sum(v["avg_ms"] * v["launches_per_step"] for v in per.values())
+    tot_f = None
+    if all(v["flops_per_point"] is not None for v in per.values()):
+        tot_f = sum(v["flops_per_point"] * v["points_per_launch"] * v["launches_per_step"] for v in per.values())
+    return {"bound": "alu", "achieved": d["achieved"], "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": d["achieved"] / PEAK_FP32_TFLOPS if d["achieved"] else None, "traffic": traffic,
+            "kernel": f"{kernel}, m = {dom} (the dimension with the most time)",
+            "flops_per_launch": d["flops_per_point"] * d["points_per_launch"] if d["flops_per_point"] else None,
+            "avg_launch_ms": d["avg_ms"], "valu_issue": d["valu_issue"],
+            "all_lattice": {"ms_per_step": tot_ms, "achieved": tot_f / (tot_ms / 1e3) / 1e12 if tot_f else None,
+                            "frac": tot_f / (tot_ms / 1e3) / 1e12 / PEAK_FP32_TFLOPS if tot_f else None},
+            "per_kernel": {f"m{m}": v for m, v in per.items()}}
 
 
 def surrogate_vs_lattice(cf, ds, y, params, design, pairs):
@@ -293,7 +349,6 @@ def small_restarts(cf, h, prec, dev, nstarts: int = 64, iters: int = 5) -> dict:
     from cfust_inputs import make_design, workload
     from cfust_inputs.synth import restart_params
 
-    log("small restarts: 64 starts on the n = 1000 data")
     ds = workload("cfust_n1000_p2_q2_g2")
     qmc = cf.device_qmc(make_design(1024, 4, seed=1606), prec, device=dev)
     y = torch.as_tensor(ds.y_soa, device=dev)
@@ -331,7 +386,7 @@ def small_restarts(cf, h, prec, dev, nstarts: int = 64, iters: int = 5) -> dict:
             "sequential_value": pairs / (ms_s / 1e3), "unit": "(obs*comp)/s"}
 
 
-def batched_main(args) -> dict:
+def batched_run(cf, h, prec, dev, steps: int, warmup: int, with_cpu: bool, precision_name: str) -> dict:
     """The restart workload: 64 independent fits (n ~ logU[5e3, 2e5], p = q in
     3..8, g in 2..6) run as one batch, one step = one EM iteration of every fit
     (a replay of the captured graph), against the same fits run one after the
@@ -340,16 +395,12 @@ def batched_main(args) -> dict:
     import numpy as np
     import torch
 
-    import paper_1606_02054_amd as cf
     from cfust_inputs import make_design, workload
 
-    prec = cf.CFUST_MIXED if args.precision == "mixed" else cf.CFUST_FP64
-    log("batched: drawing 64 fits")
+    progress("batched: drawing 64 fits")
     sets = workload("batched_fit")
     N, S = sets[0].meta["N"], sets[0].meta["S"]
     design = make_design(N, S, seed=1606)
-    dev = torch.device("cuda:0")
-    h = cf.default_handle(0)
     qmc = cf.device_qmc(design, prec, device=dev)
 
     def make():
@@ -364,73 +415,64 @@ def batched_main(args) -> dict:
     pairs = sum(int(ds.y.shape[0]) * ds.params.g for ds in sets)
     rows = sum(int(ds.y.shape[0]) for ds in sets)
     B = cf.Batch(fb, qmc, handle=h)
-    log("batched: tuning queues")
+    progress("batched: tuning queues")
     tuned = B.tune()
-    iters = args.warmup + args.steps
     # batched: warm-up iterations, then the timed ones (graph replays)
-    log("batched: warm-up")
-    B.fit(args.warmup, tol=0.0, use_graph=True)
+    progress("batched: warm-up")
+    B.fit(max(warmup, 1), tol=0.0, use_graph=True)
     torch.cuda.synchronize()
     for (_, dp, _), ds in zip(fb, sets):          # restart from the initial parameters
         src = cf.device_params(ds.params, device=dev)
         for f in ("pi", "mu", "Sigma", "Delta", "nu"):
             getattr(dp, f).copy_(getattr(src, f))
     torch.cuda.synchronize()
-    log("batched: timed")
+    progress("batched: timed")
     t0 = time.perf_counter()
-    trace, done = B.fit(args.steps, tol=0.0, use_graph=True)
+    trace, done = B.fit(steps, tol=0.0, use_graph=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ms_batched = (t1 - t0) * 1e3 / args.steps
+    ms_batched = (t1 - t0) * 1e3 / steps
 
     # sequential: the same fits one after the other, same number of iterations
     for ds in {ds.params.q: ds for ds in sets}.values():
-        h.autotune(torch.as_tensor(ds.y_soa, device=dev), cf.device_params(ds.params, device=dev), qmc)
-    log("sequential: warm-up")
+        h.autotune(torch.as_tensor(ds.y_soa[:, :4096].copy(), device=dev), cf.device_params(ds.params, device=dev),
+                   qmc)
+    progress("sequential: warm-up")
     for (y, P, es) in fs[:4]:
         cf.cfust_estep(y, P.clone(), qmc, out=es)
     torch.cuda.synchronize()
-    log("sequential: timed")
-    seq_trace = torch.zeros((args.steps, len(fs)), dtype=torch.float64, device=dev)
+    progress("sequential: timed")
+    seq_trace = torch.zeros((steps, len(fs)), dtype=torch.float64, device=dev)
     t0 = time.perf_counter()
-    for it in range(args.steps):
+    for it in range(steps):
         for k, (y, P, es) in enumerate(fs):
             cf.cfust_estep(y, P, qmc, out=es)
             seq_trace[it, k].copy_(es.loglik[0])
             cf.cfust_mstep(y, es, P, out=P)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ms_seq = (t1 - t0) * 1e3 / args.steps
+    ms_seq = (t1 - t0) * 1e3 / steps
     equal = bool(torch.equal(seq_trace, trace))
 
     # lattice kernel time of one batched E-step (events around the queue kernels)
-    log("batched: profiled E-step")
+    progress("batched: profiled E-step")
     h.profile(True)
     h.profile_read()
     B.estep()
     torch.cuda.synchronize()
     prof = h.profile_read()
     h.profile(False)
-    flops_by_m = {}
+    points = {}
     for ds in sets:
         n = int(ds.y.shape[0])
         for m in integral_dims(ds.params.q):
-            flops_by_m[m] = flops_by_m.get(m, 0) + lattice_flops_per_point(m) * N * S * n * ds.params.g
-    lat_ms = sum(v[0] for v in prof.values())
-    achieved = sum(flops_by_m.values()) / (lat_ms / 1e3) / 1e12 if lat_ms > 0 else None
-    per_kernel = {f"m{m}": {"ms": prof[m][0], "tflops": flops_by_m[m] / (prof[m][0] / 1e3) / 1e12}
-                  for m in sorted(prof) if m in flops_by_m}
-    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": (achieved / PEAK_FP32_TFLOPS) if achieved else None, "traffic": None,
-                "kernel": "k_queue_qmc / k_queue_grid (lattice queue kernels in the tuned form, all "
-                          "dimensions of one batched E-step)",
-                "lattice_ms_per_estep": lat_ms, "per_kernel": per_kernel}
-    out = {"metric": METRIC, "value": pairs / (ms_batched / 1e3), "unit": "(obs*comp)/s", "n_gpus": 1,
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_batched, "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f32" if prec == cf.CFUST_MIXED else "f64",
-           "data": "synthetic (drawn from the CFUST hierarchy, seeded)",
+            points[m] = points.get(m, 0) + N * S * n * ds.params.g
+    roofline = lattice_roofline(prof, points, 1, "k_queue_grid / k_queue_qmc (lattice queue kernels in the "
+                                                 "tuned form, one batched E-step)")
+    out = {"value": pairs / (ms_batched / 1e3), "unit": "(obs*comp)/s", "steps": steps,
+           "ms_per_step": ms_batched,
            "config": {"workload": "batched_fit", "fits": len(sets), "rows": rows, "pairs": pairs,
-                      "N": N, "S": S, "precision": args.precision,
+                      "N": N, "S": S, "precision": precision_name,
                       "step": "one EM iteration of every fit (graph replay)",
                       "tuned_queues": {f"m{m}": {"rows": v[0], "blocks_per_slot": v[1], "points_per_lane": v[2]}
                                        for m, v in tuned.items()}},
@@ -439,8 +481,11 @@ def batched_main(args) -> dict:
                                      "speedup": ms_seq / ms_batched,
                                      "sequential_value": pairs / (ms_seq / 1e3),
                                      "loglik_traces_bit_equal": equal}}
+    B.close()
+    del fb, fs
+    progress("small restarts: 64 starts on the n = 1000 data")
     out["small_restarts"] = small_restarts(cf, h, prec, dev)
-    if not args.no_cpu:
+    if with_cpu:
         # one fit per q (the cost of a row depends on q and grows with g):
         # max(1, threads // g) rows of it, per-row time scaled by g to every
         # fit of that q and multiplied by its n
@@ -456,7 +501,7 @@ def batched_main(args) -> dict:
             c0 = time.perf_counter()
             oracle.estep(ds.y, ds.params, design, rows=np.arange(r, dtype=np.int32))
             dt = time.perf_counter() - c0
-            log(f"cpu baseline: q = {q}, g = {g}, {r} rows: {dt:.1f} s")
+            progress(f"cpu baseline: q = {q}, g = {g}, {r} rows: {dt:.1f} s")
             per_row_comp[q] = dt / (r * g)
             c_tot += dt
             sample_rows += r
@@ -467,7 +512,192 @@ def batched_main(args) -> dict:
                                          f"extrapolated to all pairs of the fits of that q; same lattice "
                                          f"(N={N}, S={S}), FP64",
                                "host": host_cpu()}
-    B.close()
+    return out
+
+
+def batched_main(args) -> dict:
+    """--workload batched_fit: the restart workload as the headline line."""
+    import torch
+
+    import paper_1606_02054_amd as cf
+
+    prec = cf.CFUST_MIXED if args.precision == "mixed" else cf.CFUST_FP64
+    dev = torch.device("cuda:0")
+    h = cf.default_handle(0)
+    r = batched_run(cf, h, prec, dev, args.steps, args.warmup, not args.no_cpu, args.precision)
+    out = {"metric": METRIC, "value": r.pop("value"), "unit": r.pop("unit"), "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": r.pop("ms_per_step"), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32" if prec == cf.CFUST_MIXED else "f64",
+           "data": "synthetic (drawn from the CFUST hierarchy, seeded)"}
+    r.pop("steps")
+    out.update(r)
+    return out
+
+
+def cytometry_iteration(cf, h, dev, n: int = 1_000_000) -> dict:
+    """One EM iteration of the cytometry-shaped workload at full size: n = 10^6
+    observations, p = q = 8, g = 5 (38 lattice integrals of dimensions 6, 7, 8
+    per pair), lattice 8192 x 8, mixed precision; the lattice points per lane
+    are tuned on the first 32768 observations (the choice depends on m, N, S
+    and precision only)."""
+    import torch
+    from cfust_inputs import make_design, workload
+
+    progress(f"cytometry: drawing n = {n}")
+    ds = workload("cfust_n1e6_p8_q8_g5_box1024", n=n)
+    p, q, g = ds.y.shape[1], ds.params.q, ds.params.g
+    N, S = ds.meta["N"], ds.meta["S"]
+    qmc = cf.device_qmc(make_design(N, S, seed=1606), cf.CFUST_MIXED, device=dev)
+    y = torch.as_tensor(ds.y_soa, device=dev)
+    P = cf.device_params(ds.params, device=dev)
+    nxt = P.clone()
+    tuned = h.autotune(y[:, :32768].contiguous(), P, qmc)
+    es = cf.alloc_estep(n, p, q, g, cf.CFUST_MIXED, device=dev)
+    h.reserve(n, p, q, g, qmc)
+    torch.cuda.synchronize()
+    progress("cytometry: timed EM iteration")
+    h.profile(True)
+    h.profile_read()
+    t0 = time.perf_counter()
+    cf.cfust_estep(y, P, qmc, out=es)
+    cf.cfust_mstep(y, es, P, out=nxt)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = h.profile_read()
+    h.profile(False)
+    ms = (t1 - t0) * 1e3
+    progress(f"cytometry: EM iteration {ms / 1e3:.1f} s")
+    points = {}
+    for m in integral_dims(q):
+        points[m] = points.get(m, 0) + N * S * n * g
+    return {"value": n * g / (ms / 1e3), "unit": "(obs*comp)/s", "ms_per_step": ms,
+            "config": {"workload": "cfust_n1e6_p8_q8_g5_box1024", "n": n, "p": p, "q": q, "g": g, "N": N, "S": S,
+                       "precision": "mixed", "step": "E-step + M-step (one EM iteration)",
+                       "autotuned_points_per_lane": {f"m{m}": v for m, v in tuned.items()}},
+            "loglik": float(es.loglik.cpu()[0]),
+            "roofline": lattice_roofline(prof, points, 1, "k_estep_qmc (FP32 lattice integrand)")}
+
+
+def cpu_baseline(ds, design, g: int, N: int, S: int, rows_n: int = 0) -> dict:
+    """The FP64 oracle on the host cores on a bounded sample of the workload
+    (its first observations x all components, same lattice): with every
+    thread (the reported rate), with one thread, and with g threads -- one per
+    component, the scheme of the paper's Sec. 4 (its runs used a quad-core
+    machine)."""
+    import numpy as np
+    import oracle
+    oracle.build(force=False)
+    threads = oracle.get_threads()
+    rows_n = rows_n or max(2, threads // 2)
+
+    def run(nthreads, nrows):
+        oracle.set_threads(nthreads)
+        c0 = time.perf_counter()
+        oracle.estep(ds.y, ds.params, design, rows=np.arange(nrows, dtype=np.int32))
+        return time.perf_counter() - c0
+
+    progress(f"CPU oracle: {rows_n} rows on {threads} threads ...")
+    t_all = run(threads, rows_n)
+    progress(f"CPU oracle: {t_all:.1f} s; one row on 1 thread ...")
+    t_one = run(1, 1)
+    progress(f"CPU oracle: {t_one:.1f} s; one row on {g} threads ...")
+    t_g = run(g, 1)
+    progress(f"CPU oracle: {t_g:.1f} s")
+    oracle.set_threads(threads)
+    return {"value": rows_n * g / t_all, "unit": "(obs*comp)/s", "cores": threads, "kind": "oracle",
+            "sample": f"E-step of the first {rows_n} observations x {g} components, same lattice (N={N}, S={S}), "
+                      f"FP64, {t_all:.1f} s",
+            "one_thread": {"value": g / t_one, "cores": 1, "sample": f"first observation x {g} components, "
+                                                                    f"{t_one:.1f} s"},
+            "paper_style_g_threads": {"value": g / t_g, "cores": g,
+                                      "sample": f"first observation x {g} components, one thread per component "
+                                                f"(the decomposition of the paper's Sec. 4), {t_g:.1f} s"},
+            "host": host_cpu()}
+
+
+SWEEP_N, SWEEP_S, SWEEP_ROWS = 4096, 8, 2048
+
+
+def counter_sweep(cf, dev) -> None:
+    """One mixed-precision E-step for q = 8, 5 and 2 (lattice integrals of every
+    dimension m = 2..8) at SWEEP_ROWS observations and lattice SWEEP_N x
+    SWEEP_S, for a counter run of the lattice kernels (each wave of
+    k_estep_qmc evaluates SWEEP_N x SWEEP_S lattice points)."""
+    import numpy as np
+    import torch
+    from cfust_inputs import draw_params, make_design, sample_hierarchy
+    qmc = cf.device_qmc(make_design(SWEEP_N, SWEEP_S, seed=1606), cf.CFUST_MIXED, device=dev)
+    for q in (8, 5, 2):
+        rng = np.random.default_rng(700 + q)
+        P = draw_params(rng, q, q, 3, sigma="wishart")
+        y, _ = sample_hierarchy(rng, P, SWEEP_ROWS)
+        es = cf.cfust_estep(torch.as_tensor(np.ascontiguousarray(y.T), device=dev), cf.device_params(P, device=dev),
+                            qmc)
+        torch.cuda.synchronize()
+        progress(f"counter sweep: q = {q} done (loglik {float(es.loglik.cpu()[0]):.1f})")
+
+
+def summarize_counters(dbs, points_per_wave: int) -> dict:
+    """Per-dimension figures of the FP32 lattice kernel k_estep_qmc<m, FP32, 1
+    point per lane> from rocprofv3 databases (counter runs of the same
+    command): FP32 flops per lattice point (2 FMA + MUL + ADD + TRANS per
+    wave / points per wave), VALU instructions per point, wave64 VALU
+    instructions per CU per cycle (GRBM_GUI_ACTIVE summed over the 8 XCDs),
+    the share issued as pairs (SQ_ACTIVE_INST_VALU2 counts 4-cycle slots
+    with two VALU issues) and the VALU busy share of the issue slots of the
+    1024 SIMDs (SQ_ACTIVE_INST_VALU counts a transcendental twice)."""
+    import re
+    import sqlite3
+    acc = {}
+    for db in dbs:
+        con = sqlite3.connect(db)
+        rows = con.execute("select dispatch_id, name, duration, counter_name, counter_value from pmc_events").fetchall()
+        per = {}
+        for did, name, dur, cn, cv in rows:
+            mm = re.search(r"k_estep_qmc<(\d), true, false, 1>", name)
+            if not mm:
+                continue
+            e = per.setdefault(did, {"m": int(mm.group(1)), "dur": dur})
+            e[cn] = e.get(cn, 0.0) + cv
+        for e in per.values():
+            a = acc.setdefault(e["m"], {"n": 0, "dur": [0.0, 0]})
+            a["n"] += 1
+            for k, v in e.items():
+                if k in ("m", "dur"):
+                    continue
+                c = a.setdefault(k, [0.0, 0])
+                c[0] += v
+                c[1] += 1
+            a["dur"][0] += e["dur"]
+            a["dur"][1] += 1
+    # each counter (and the duration) averaged over the dispatches that report
+    # it: counters that appear in several passes are not double-counted
+    acc = {m: {k: (v[0] / v[1] if isinstance(v, list) else v) for k, v in a.items()} for m, a in acc.items()}
+    out = {}
+    for m, a in sorted(acc.items()):
+        r = {}
+        waves = a.get("SQ_WAVES")
+        if waves:
+            pts = waves * points_per_wave / 64.0      # a wave64 instruction evaluates 64 lattice points
+            if all(k in a for k in ("SQ_INSTS_VALU_FMA_F32", "SQ_INSTS_VALU_MUL_F32", "SQ_INSTS_VALU_ADD_F32",
+                                    "SQ_INSTS_VALU_TRANS_F32")):
+                r["flops_per_point"] = (2 * a["SQ_INSTS_VALU_FMA_F32"] + a["SQ_INSTS_VALU_MUL_F32"]
+                                        + a["SQ_INSTS_VALU_ADD_F32"] + a["SQ_INSTS_VALU_TRANS_F32"]) / pts
+                r["trans_per_point"] = a["SQ_INSTS_VALU_TRANS_F32"] / pts
+            if "SQ_INSTS_VALU" in a:
+                r["valu_per_point"] = a["SQ_INSTS_VALU"] / pts
+        if "SQ_INSTS_VALU" in a and "GRBM_GUI_ACTIVE" in a:
+            cyc = a["GRBM_GUI_ACTIVE"] / 8.0
+            r["valu_per_cu_cycle"] = a["SQ_INSTS_VALU"] / 256.0 / cyc
+            r["clock_ghz"] = cyc / (a["dur"] * 1e-9) / 1e9
+            if "SQ_ACTIVE_INST_VALU2" in a:
+                r["dual_issue_frac"] = 2.0 * a["SQ_ACTIVE_INST_VALU2"] / a["SQ_INSTS_VALU"]
+            if "SQ_ACTIVE_INST_VALU2" in a and "SQ_ACTIVE_INST_VALU" in a:
+                # VALU busy: issue slots taken (a transcendental takes two, a
+                # pair one) per SIMD over the kernel's 4-cycle slots
+                r["valu_slot_busy"] = ((a["SQ_ACTIVE_INST_VALU"] - a["SQ_ACTIVE_INST_VALU2"]) / 1024.0) / (cyc / 4.0)
+        r["dispatches"] = a["n"]
+        out[m] = r
     return out
 
 
@@ -486,10 +716,22 @@ def main():
     ap.add_argument("--components-only", action="store_true",
                     help="run only the M-step and network roofline figures (one JSON line)")
     ap.add_argument("--n", type=int, default=0, help="observations (0: the workload's own n)")
+    ap.add_argument("--no-cytometry", action="store_true",
+                    help="skip the full-size cytometry-shaped EM iteration (n = 10^6, p = q = 8, g = 5)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-fit batched iteration")
+    ap.add_argument("--counter-sweep", action="store_true",
+                    help="only one E-step per q = 8, 5, 2 (lattice kernels of m = 2..8) for a counter run")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="DB",
+                    help="print the per-m lattice-kernel figures of rocprofv3 databases of a --counter-sweep "
+                         "run (no GPU needed)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a known-size "
                          "reference for the HBM byte counters)")
     args = ap.parse_args()
+    if args.summarize_counters:
+        print(json.dumps({"kernel_digest": kernel_digest(),
+                          "per_m": summarize_counters(args.summarize_counters, SWEEP_N * SWEEP_S)}, indent=1))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "the bench runs on one GPU only (the kernels take one GPU's share of the data); "
                                    "--gpus above 1 is not supported",
@@ -510,6 +752,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    if args.counter_sweep:
+        cf.default_handle(0)
+        counter_sweep(cf, torch.device("cuda:0"))
+        return
     if args.workload == "batched_fit":
         print(json.dumps(batched_main(args)), flush=True)
         return
@@ -561,24 +807,14 @@ def main():
     ll = float(es.loglik.cpu()[0])
 
     # roofline of the lattice kernels (FP32 VALU)
-    dims = integral_dims(q)
-    flops_by_m = {}
-    for m in dims:
-        flops_by_m[m] = flops_by_m.get(m, 0) + lattice_flops_per_point(m) * N * S * pairs
-    lat_ms = sum(v[0] for v in prof.values()) / args.steps
-    lat_flops = sum(flops_by_m.values())
-    achieved = lat_flops / (lat_ms / 1e3) / 1e12 if lat_ms > 0 else None
-    per_kernel = {f"m{m}": {"avg_ms": prof[m][0] / prof[m][1],
-                            "tflops": flops_by_m[m] / (prof[m][0] / prof[m][1] / 1e3) / 1e12}
-                  for m in sorted(prof) if m in flops_by_m}
+    points = {}
+    for m in integral_dims(q):
+        points[m] = points.get(m, 0) + N * S * pairs
     traffic = None
-    if args.workload == "cfust_n20000_p4_q4_g3" and prec == cf.CFUST_MIXED and kernel_digest() == TRAFFIC_DIGEST:
+    if args.workload == "cfust_n20000_p4_q4_g3" and prec == cf.CFUST_MIXED and counters_current() and TRAFFIC_MIB:
         traffic = {"bytes_per_estep": (TRAFFIC_MIB["read"] + TRAFFIC_MIB["write"]) * (1 << 20),
                    "read_MiB": TRAFFIC_MIB["read"], "write_MiB": TRAFFIC_MIB["write"]}
-    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": (achieved / PEAK_FP32_TFLOPS) if achieved else None, "traffic": traffic,
-                "kernel": "k_estep_qmc (FP32 lattice integrand, all dimensions of one E-step)",
-                "lattice_ms_per_step": lat_ms, "per_kernel": per_kernel}
+    roofline = lattice_roofline(prof, points, args.steps, "k_estep_qmc (FP32 lattice integrand)", traffic)
 
     out = {"metric": METRIC, "value": value, "unit": "(obs*comp)/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
@@ -602,22 +838,16 @@ def main():
         out["small_fit"] = small_fit(cf, dev)
         progress("small fit done")
 
+    default_run = args.workload == "cfust_n20000_p4_q4_g3" and prec == cf.CFUST_MIXED and not args.n
+    if default_run and not args.no_cytometry:
+        out["cytometry"] = cytometry_iteration(cf, h, dev)
+        progress("cytometry section done")
+    if default_run and not args.no_batched:
+        out["batched"] = batched_run(cf, h, prec, dev, 1, 1, False, args.precision)
+        progress("batched section done")
+
     if not args.no_cpu:
-        import oracle
-        oracle.build(force=False)
-        threads = oracle.get_threads()
-        rows_n = args.cpu_rows or max(2, threads)
-        rows = np.arange(rows_n, dtype=np.int32)
-        c0 = time.perf_counter()
-        progress(f"CPU oracle on {rows_n} rows ...")
-        oracle.estep(ds.y, ds.params, design, rows=rows)
-        c1 = time.perf_counter()
-        progress(f"CPU oracle done in {c1 - c0:.1f} s")
-        out["cpu_baseline"] = {"value": rows_n * g / (c1 - c0), "unit": "(obs*comp)/s", "cores": threads,
-                               "kind": "oracle",
-                               "sample": f"E-step of the first {rows_n} observations x {g} components, "
-                                         f"same lattice (N={N}, S={S}), FP64, {c1 - c0:.1f} s",
-                               "host": host_cpu()}
+        out["cpu_baseline"] = cpu_baseline(ds, design, g, N, S, args.cpu_rows)
     print(json.dumps(out), flush=True)
 
 

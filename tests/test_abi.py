@@ -73,7 +73,39 @@ def test_bench_flop_bookkeeping():
     assert bench.integral_dims(4) == [4, 4, 3, 3, 3, 3, 2, 2, 2, 2, 2, 2]
     assert bench.integral_dims(2) == [2, 2]
     assert len(bench.integral_dims(8)) == 38
-    assert bench.lattice_flops_per_point(2) == bench.FLOPS_CDF + bench.FLOPS_QUANTILE + 2
+    # the counter-measured flops per lattice point are used only for the kernel
+    # sources they were measured on
+    if bench.counters_current():
+        assert all(bench.lattice_flops_per_point(m) > 0 for m in range(2, 9))
+    else:
+        assert bench.lattice_flops_per_point(2) is None
+
+
+def test_bench_counter_summary(tmp_path):
+    """The counter summary of the bench reads rocprofv3's pmc_events table:
+    per dimension m, FP32 flops per lattice point = (2 FMA + MUL + ADD +
+    TRANS) x 64 lanes / (waves x points per wave), VALU issue per CU and cycle from
+    GRBM_GUI_ACTIVE summed over the 8 XCDs, and the dual-issued share."""
+    import sqlite3
+    import bench
+    db = tmp_path / "x.db"
+    con = sqlite3.connect(db)
+    con.execute("create table pmc_events (dispatch_id int, name text, duration real, counter_name text, "
+                "counter_value real)")
+    vals = {"SQ_WAVES": 10.0, "SQ_INSTS_VALU_FMA_F32": 300.0, "SQ_INSTS_VALU_MUL_F32": 50.0,
+            "SQ_INSTS_VALU_ADD_F32": 20.0, "SQ_INSTS_VALU_TRANS_F32": 10.0, "SQ_INSTS_VALU": 512.0,
+            "SQ_ACTIVE_INST_VALU2": 128.0, "GRBM_GUI_ACTIVE": 8.0}
+    for k, v in vals.items():
+        con.execute("insert into pmc_events values (1, 'void cfust::k_estep_qmc<3, true, false, 1>(x)', 1.0, ?, ?)",
+                    (k, v))
+    con.execute("insert into pmc_events values (2, 'void cfust::k_mstep_reduce(x)', 1.0, 'SQ_WAVES', 5.0)")
+    con.commit()
+    con.close()
+    r = bench.summarize_counters([str(db)], points_per_wave=4)
+    assert list(r) == [3]
+    assert r[3]["flops_per_point"] == (600 + 50 + 20 + 10) * 64 / 40.0
+    assert r[3]["valu_per_cu_cycle"] == 512.0 / 256.0 / 1.0
+    assert r[3]["dual_issue_frac"] == 0.5
 
 
 def test_bench_refuses_several_gpus():
