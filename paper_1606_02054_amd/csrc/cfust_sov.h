@@ -232,29 +232,57 @@ __device__ double sov_lane_sum64_normal(const double *b, const double *L, const 
 
 // ------------------------------------------------------------- FP32 path ---
 
-// Lattice coordinate (FP32): t in 32-bit fixed point so that x = 2 min(t, 1-t)
-// keeps full relative accuracy near 0 (it enters log2 x in the lower tail),
-// and so does xb = 1 - x near 0, from the integer complement: it enters the
-// upper-tail complement p_b = xb e + e_b, whose relative accuracy sets the
-// quantile where the conditional law is sampled far in its upper tail.
-// Needs N a power of two.  t = 2^32 frac(k z_j / N + shift) in fixed point:
-// ((k z_j) << (32 - log2 N)) + shift (the shift drops the bits of k z_j above
-// log2 N, so no reduction mod N is needed), carried from point to point by
-// adding the constant ((64 z_j) << (32 - log2 N)).
-__device__ __forceinline__ void point32(uint32_t t, float &x, float &xb) {
-    uint32_t u = min(t, 0u - t);                      // 2^32 min(t, 1-t), in [0, 2^31]
-    u = min(max(u, 128u), 2147483520u);               // [2^-24, 1 - 2^-24] after scaling
-    x = (float)u * 4.656612873077393e-10f;            // 2^-31
-    xb = (float)(2147483648u - u) * 4.656612873077393e-10f;
+// Lattice coordinate (FP32): t in 32-bit fixed point, t = 2^32 frac(k z_j / N
+// + shift) (needs N a power of two): ((k z_j) << (32 - log2 N)) + shift (the
+// shift drops the bits of k z_j above log2 N, so no reduction mod N is
+// needed), carried from point to point by adding ((64 z_j) << (32 - log2 N)).
+// As a signed integer, |t| = 2^31 min(t, 1-t) = 2^31 x (the tent transform),
+// and with the top bit flipped (t - 1/2 mod 1), |t ^ 2^31| = 2^31 |2t - 1| =
+// 2^31 (1 - x): both come straight from the integers, so x keeps full
+// relative accuracy near 0 (it enters log2 x in the lower tail) and so does
+// 1 - x near 0 (it enters the upper-tail complement p_b = (1 - x) e + e_b,
+// whose relative accuracy sets the quantile where the conditional law is
+// sampled far in its upper tail).  The clamp to [2^-24, 1 - 2^-24] is
+// [128, 2^31 - 128] in these units (exact floats); both values are returned
+// in units of 2^-31 (unscaled) or scaled.
+__device__ __forceinline__ float tent_units(uint32_t t) {
+    return __builtin_amdgcn_fmed3f(fabsf((float)(int32_t)t), 128.0f, 2147483520.0f);
 }
 
-__device__ __forceinline__ float quantile_step32(float x, float xb, float e, float eb, float l2e, bool lowt,
-                                                 const float *tab, float &Q) {
-    const float p = x * e;
-    const float pb = fmaf(xb, e, eb);
-    const bool lower = lowt || p <= 0.5f;
-    const float arg = lowt ? x : (lower ? p : pb);
-    const float l2q = flog2(arg) + (lowt ? l2e : 0.0f);
+__device__ __forceinline__ void point32(uint32_t t, float &x, float &xb) {
+    x = tent_units(t) * 4.656612873077393e-10f;                  // 2^-31
+    xb = tent_units(t ^ 0x80000000u) * 4.656612873077393e-10f;
+}
+
+// Quantile step of coordinate 0 (the truncation probability e_0 is the same
+// for every point).  LOW0: e_0 is a lower-tail probability that may be far
+// below the FP32 range, so p = x e_0 <= 1/2 is taken in the log domain,
+// log2 p = log2(2^31 x) + (log2 e_0 - 31); otherwise e_0 >= 1/2 and
+// p = (2^31 x)(2^-31 e_0), p_b = (2^31 (1-x))(2^-31 e_0) + e_b0.
+struct Sov32Setup {
+    float b[MAXQ];
+    float L[MAXQ * MAXQ];      // row-major, stride M
+    float a[MAXQ];             // (nu + i)/2
+    float e0s, eb0, l2e0m31, sqrtnu;   // 2^-31 e_0, 1 - e_0, log2 e_0 - 31
+    float e0, l2e0;                     // e_0, log2 e_0 (normal limit)
+    bool low0;
+};
+
+template <bool LOW0>
+__device__ __forceinline__ float quantile_step32_first(const Sov32Setup &P, uint32_t t, const float *tab, float &Q) {
+    const float xu = tent_units(t);
+    bool lower;
+    float l2q;
+    if (LOW0) {
+        lower = true;
+        l2q = flog2(xu) + P.l2e0m31;
+    } else {
+        const float xbu = tent_units(t ^ 0x80000000u);
+        const float p = xu * P.e0s;
+        const float pb = fmaf(xbu, P.e0s, P.eb0);
+        lower = p <= 0.5f;
+        l2q = flog2(lower ? p : pb);
+    }
     const float G = fmaxf(tab_inv_G(tab, l2q), -100.0f);
     const float tq = fexp2(G);
     const float sabs = 1.0f - tq;
@@ -262,22 +290,30 @@ __device__ __forceinline__ float quantile_step32(float x, float xb, float e, flo
     return (lower ? -sabs : sabs) * Q;
 }
 
-struct Sov32Setup {
-    float b[MAXQ];
-    float L[MAXQ * MAXQ];      // row-major, stride M
-    float a[MAXQ];             // (nu + i)/2
-    float e0, eb0, l2e0, sqrtnu;
-    bool low0;
-};
+// Quantile step of coordinate i >= 1, given the lower-tail value small =
+// T_lower of the coordinate's conditional law and lowt (its limit is in the
+// lower half, e = small; otherwise e = 1 - small).  p = x e is formed
+// directly: a point whose factor e is below the FP32 range contributes 0 to
+// the product, whatever it draws.  When !lowt the complement is
+// 1 - x e = (1 - x) e + small.
+__device__ __forceinline__ float quantile_step32(float x, float xb, float e, float small, const float *tab,
+                                                 float &Q) {
+    const float p = x * e;
+    const float pb = fmaf(xb, e, small);
+    const bool lower = p <= 0.5f;
+    const float G = fmaxf(tab_inv_G(tab, flog2(lower ? p : pb)), -100.0f);
+    const float tq = fexp2(G);
+    const float sabs = 1.0f - tq;
+    Q = fminf(Q * frsq(tq * (2.0f - tq)), 1e15f);
+    return (lower ? -sabs : sabs) * Q;
+}
 
 // Integrand value of lattice point k (FP32), product e_1 ... e_{M-1}.
-template <int M>
+template <int M, bool LOW0>
 __device__ __forceinline__ float sov_point32(const Sov32Setup &P, const float *tabs, const uint32_t *t) {
     float y[M];
     float Q = P.sqrtnu;
-    float x, xb;
-    point32(t[0], x, xb);
-    y[0] = quantile_step32(x, xb, P.e0, P.eb0, P.l2e0, P.low0, tabs, Q);
+    y[0] = quantile_step32_first<LOW0>(P, t[0], tabs, Q);
     float f = 1.0f;
 #pragma unroll
     for (int i = 1; i < M; ++i) {
@@ -293,13 +329,12 @@ __device__ __forceinline__ float sov_point32(const Sov32Setup &P, const float *t
         const float *tab = tabs + i * TAB_FLOATS;
         const float l2 = fmaf(P.a[i], flog2(KR2), tab_cdf_H(tab, fmaf(-8.0f, fabsf(num) * R, 8.0f)));
         const float small = fexp2(l2);
-        const bool lowt = num <= 0.0f;
-        const float e = lowt ? small : 1.0f - small;
-        const float eb = lowt ? 1.0f - small : small;
+        const float e = num <= 0.0f ? small : 1.0f - small;
         f *= e;
         if (i < M - 1) {
+            float x, xb;
             point32(t[i], x, xb);
-            y[i] = quantile_step32(x, xb, e, eb, l2, lowt, tab, Q);
+            y[i] = quantile_step32(x, xb, e, small, tab, Q);
         }
     }
     return f;
@@ -351,10 +386,11 @@ __device__ __forceinline__ float sov_point32_normal(const Sov32Setup &P, const f
 // (instruction-level parallelism across the dependency chains).  With N a
 // multiple of 64 PPL the trip count is the same for every lane, so the loop
 // is counted in scalar registers; N < 64 (PPL 1) is one weighted trip.  NORMAL
-// selects the normal-limit integrand.
-template <int M, int PPL, bool NORMAL>
-__device__ float sov_lane_sum32(const Sov32Setup &P, const float *tabs, const uint32_t *zz, int sh,
-                                const uint32_t *shfix, int N, int lane) {
+// selects the normal-limit integrand; LOW0 (t integrand) the form of the
+// first coordinate.
+template <int M, int PPL, bool NORMAL, bool LOW0>
+__device__ float sov_lane_sum32_f(const Sov32Setup &P, const float *tabs, const uint32_t *zz, int sh,
+                                  const uint32_t *shfix, int N, int lane) {
     uint32_t t[PPL][M], step[M];
 #pragma unroll
     for (int i = 0; i < M - 1; ++i) {
@@ -363,7 +399,7 @@ __device__ float sov_lane_sum32(const Sov32Setup &P, const float *tabs, const ui
         for (int u = 0; u < PPL; ++u) t[u][i] = (((uint32_t)(lane + 64 * u) * zz[i]) << sh) + shfix[i];
     }
     auto point = [&](const uint32_t *tt) {
-        return NORMAL ? sov_point32_normal<M>(P, tabs, tt) : sov_point32<M>(P, tabs, tt);
+        return NORMAL ? sov_point32_normal<M>(P, tabs, tt) : sov_point32<M, LOW0>(P, tabs, tt);
     };
     // N < 64 (PPL 1): one trip in which the lanes at or past N weigh 0
     const float wl = (N >= 64 * PPL || lane < N) ? 1.0f : 0.0f;
@@ -381,6 +417,16 @@ __device__ float sov_lane_sum32(const Sov32Setup &P, const float *tabs, const ui
             for (int i = 0; i < M - 1; ++i) t[u][i] += step[i];
     }
     return acc;
+}
+
+// The first coordinate's form is the same for every point of an item, so the
+// choice between the two loops is uniform across the wave.
+template <int M, int PPL, bool NORMAL>
+__device__ float sov_lane_sum32(const Sov32Setup &P, const float *tabs, const uint32_t *zz, int sh,
+                                const uint32_t *shfix, int N, int lane) {
+    if (NORMAL) return sov_lane_sum32_f<M, PPL, true, false>(P, tabs, zz, sh, shfix, N, lane);
+    if (P.low0) return sov_lane_sum32_f<M, PPL, false, true>(P, tabs, zz, sh, shfix, N, lane);
+    return sov_lane_sum32_f<M, PPL, false, false>(P, tabs, zz, sh, shfix, N, lane);
 }
 
 // ------------------------------------------------------------- driver -------
@@ -469,7 +515,8 @@ __device__ bool sov_mixed(const SovHead &H, const double *b, const double *L, do
     for (int i = 0; i < M; ++i) { P.b[i] = (float)b[i]; P.a[i] = (float)(0.5 * (nu + i)); }
 #pragma unroll
     for (int i = 0; i < M * M; ++i) P.L[i] = (float)L[i];
-    P.e0 = (float)H.e0; P.eb0 = (float)H.eb0; P.l2e0 = (float)(H.lne0 / LN2); P.low0 = H.low0;
+    P.e0s = (float)(H.e0 * 4.656612873077393e-10); P.eb0 = (float)H.eb0;
+    P.l2e0m31 = (float)(H.lne0 / LN2 - 31.0); P.low0 = H.low0;
     P.sqrtnu = (float)sqrt(nu);
     uint32_t zz[M], shfix[M];
     const int sh = 32 - Lt.log2N;
@@ -500,7 +547,9 @@ __device__ bool sov_mixed_normal(const SovHead &H, const double *b, const double
     for (int i = 0; i < M; ++i) { P.b[i] = (float)b[i]; P.a[i] = (float)(1.0 / L[i * M + i]); }
 #pragma unroll
     for (int i = 0; i < M * M; ++i) P.L[i] = (float)L[i];
-    P.e0 = (float)H.e0; P.eb0 = (float)H.eb0; P.l2e0 = (float)(H.lne0 / LN2); P.low0 = H.low0;
+    P.e0s = (float)(H.e0 * 4.656612873077393e-10); P.eb0 = (float)H.eb0;
+    P.l2e0m31 = (float)(H.lne0 / LN2 - 31.0); P.low0 = H.low0;
+    P.e0 = (float)H.e0; P.l2e0 = (float)(H.lne0 / LN2);
     P.sqrtnu = 1.0f;
     uint32_t zz[M], shfix[M];
     const int sh = 32 - Lt.log2N;
