@@ -68,16 +68,24 @@ def loss_and_grad(out, label, lam):
 def backward(Ws, bs, cache, dout, bf16=False):
     """Gradients (dWs, dbs, dX) for dL/dout = dout."""
     r = bf16_round if bf16 else (lambda a: a)
+    xs, _ = cache
+    dzs = backward_dz(Ws, cache, dout, bf16)
+    dWs = [dz.T @ x for dz, x in zip(dzs, xs)]
+    dbs = [dz.sum(0) for dz in dzs]
+    return dWs, dbs, dzs[0] @ r(Ws[0])
+
+
+def backward_dz(Ws, cache, dout, bf16=False):
+    """The back-propagated pre-activation gradients dZ_l of every layer (as
+    stored: BF16-rounded when bf16), for dL/dout = dout."""
+    r = bf16_round if bf16 else (lambda a: a)
     xs, zs = cache
     L = len(Ws)
-    dWs, dbs = [None] * L, [None] * L
+    dzs = [None] * L
     dy = dout
-    dx = None
     for l in range(L - 1, -1, -1):
         dz = dy if l == L - 1 else dy * gelu_grad(zs[l])
         dz = r(dz)
-        dWs[l] = dz.T @ xs[l]
-        dbs[l] = dz.sum(0)
-        dx = dz @ r(Ws[l])
-        dy = dx
-    return dWs, dbs, dx
+        dzs[l] = dz
+        dy = dz @ r(Ws[l])
+    return dzs

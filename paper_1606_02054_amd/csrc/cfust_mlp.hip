@@ -1,22 +1,28 @@
 // cfust_mlp.hip -- the surrogate network: a 16 -> 256 -> 256 -> 256 -> 256 -> 16
 // perceptron with tanh-form GELU, BF16 weights and activations, FP32
-// accumulation on the matrix cores (v_mfma_f32_16x16x16_bf16), FP32 master
-// weights and Adam.  Forward, backward, loss and optimiser kernels.
+// accumulation on the matrix cores (gfx950's v_mfma_f32_16x16x32_bf16), FP32
+// master weights and Adam.  Forward, backward, loss and optimiser kernels.
 //
 // GEMM convention: C[M][N] = P[M][K] * Q[N][K]^T with P, Q row-major BF16
 // (K contiguous).  One 256-thread block computes a 64 x 64 tile of C; each
-// wave a 32 x 32 quarter as 2 x 2 MFMA tiles of 16 x 16, stepping K by 16.
-// 64 x 32 slices of P and Q are staged in LDS with coalesced 16-byte loads;
-// operand fragments (8 bytes per lane: four consecutive K values) are read
-// from there in the layout the 16x16x16 BF16 MFMA expects:
-//   lane l holds P[row0 + l%16][k0 + 4(l/16) + 0..3] and Q[col0 + l%16][k0 + 4(l/16) + 0..3],
+// wave a 32 x 32 quarter as 2 x 2 MFMA tiles of 16 x 16, stepping K by 32.
+// 64 x 64 slices of P and Q are staged in LDS with coalesced 16-byte loads;
+// operand fragments (16 bytes per lane: eight consecutive K values) are read
+// from there in the layout the 16x16x32 BF16 MFMA expects:
+//   lane l holds P[row0 + l%16][k0 + 8(l/16) + 0..7] and Q[col0 + l%16][k0 + 8(l/16) + 0..7],
 //   and receives C[row0 + 4(l/16) + i][col0 + l%16], i = 0..3.
+// A K of 16 (the input layer) is zero-padded to 32.
 #include "cfust_kernels.h"
 
 namespace cfust {
 
-typedef short v4s __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4f mfma32(v8s a, v8s b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b), c, 0, 0, 0);
+}
 
 __device__ __forceinline__ uint16_t f2bf(float f) {   // round to nearest even
     uint32_t u = __float_as_uint(f);
@@ -58,11 +64,11 @@ struct GemmOut {
 };
 
 // C = P Q^T in BF16 with FP32 accumulation (P [M][K], Q [N][K] row-major),
-// block tile 64 x 64 over 4 waves, each 32 x 32 in 16 x 16 MFMA tiles.
+// block tile 64 x 64 over 4 waves, each 32 x 32 in 16 x 16 MFMA tiles (K 32 per MFMA).
 // 64 x 64 slices of P and Q are staged in LDS per step with 16-byte loads;
 // the next slice's loads are issued before the current slice's MFMAs, so
 // their latency is hidden.  Rows past M or N and K past the chunk are zero,
-// which adds exact zeros to the same MFMA sequence (K ascending by 16) as
+// which adds exact zeros to the same MFMA sequence (K ascending by 32) as
 // fragments read straight from memory.  (A 128 x 128 tile was no faster: the
 // forward products are bound by their epilogue writes, FP32 pre-activations
 // and two BF16 layouts, not by feeding the MFMAs.)
@@ -87,10 +93,11 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const uint16_t *__restrict__ 
     bool colok[TW], rowok[TW];
 #pragma unroll
     for (int a = 0; a < TW; ++a) { colok[a] = col_w + 16 * a < N; rowok[a] = row_w + 16 * a < M; }
-    const int lr = l & 15, lk = 4 * (l >> 4);
+    const int lr = l & 15, lk = 8 * (l >> 4), lo = 4 * (l >> 4);
     uint4 pv[NLD], qv[NLD];
     // load i of this thread: slice row (t + 256 i) / 8, K offset 8 ((t + 256 i) % 8);
-    // K, kchunk multiples of 16: a load that starts before k_end has its 8 values in range
+    // K, kchunk multiples of 16: a load that starts before k_end has its 8 values in range,
+    // and the K past k_end in the slice is zero
     auto fetch = [&](int k0) {
 #pragma unroll
         for (int i = 0; i < NLD; ++i) {
@@ -115,19 +122,18 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const uint16_t *__restrict__ 
         __syncthreads();
         if (k0 + KC < k_end) fetch(k0 + KC);
 #pragma unroll
-        for (int kk = 0; kk < KC; kk += 16) {
+        for (int kk = 0; kk < KC; kk += 32) {
             if (k0 + kk >= k_end) break;
-            v4s pa[TW], qb[TW];
+            v8s pa[TW], qb[TW];
 #pragma unroll
             for (int a = 0; a < TW; ++a) {
-                pa[a] = *reinterpret_cast<const v4s *>(ps + (wr + 16 * a + lr) * KP + kk + lk);
-                qb[a] = *reinterpret_cast<const v4s *>(qs + (wc + 16 * a + lr) * KP + kk + lk);
+                pa[a] = *reinterpret_cast<const v8s *>(ps + (wr + 16 * a + lr) * KP + kk + lk);
+                qb[a] = *reinterpret_cast<const v8s *>(qs + (wc + 16 * a + lr) * KP + kk + lk);
             }
 #pragma unroll
             for (int a = 0; a < TW; ++a)
 #pragma unroll
-                for (int b = 0; b < TW; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(pa[a], qb[b], acc[a][b], 0, 0, 0);
+                for (int b = 0; b < TW; ++b) acc[a][b] = mfma32(pa[a], qb[b], acc[a][b]);
         }
         __syncthreads();
     }
@@ -137,7 +143,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const uint16_t *__restrict__ 
         for (int b = 0; b < TW; ++b) {
             if (!rowok[a] || !colok[b]) continue;
             const int col = col_w + 16 * b + lr;
-            const int r0 = row_w + 16 * a + lk;
+            const int r0 = row_w + 16 * a + lo;
             if (o.Cpart) {
                 float *dst = o.Cpart + (size_t)blockIdx.z * M * N;
 #pragma unroll
@@ -303,7 +309,7 @@ int mlp_layer_n(int l) { return LAYER_N[l]; }
 
 static hipError_t gemm(const uint16_t *P, const uint16_t *Q, int M, int N, int K, int nsplit, const GemmOut &o,
                        hipStream_t s) {
-    const int kchunk = ((K / nsplit + 15) / 16) * 16;
+    const int kchunk = ((K / nsplit + 31) / 32) * 32;
     dim3 grid((N + 63) / 64, (M + 63) / 64, nsplit);
     hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, s, P, Q, M, N, K, kchunk, o);
     return hipGetLastError();
@@ -320,16 +326,18 @@ static hipError_t gemm(const uint16_t *P, const uint16_t *Q, int M, int N, int K
 constexpr int FU_ROWS = 64;
 constexpr int FU_STRIDE = CFUST_MLP_HIDDEN + 8;     // LDS row pitch (BF16): rows fall in different banks
 
-// Weights in MFMA fragment order for the fused pass: for layer l (N x K),
-// element (column tile ct, K step ks, lane, j) = W_l[16 ct + lane % 16][16 ks + 4 (lane / 16) + j],
-// at offset ((ct (K/16) + ks) 64 + lane) 4 + j of the layer's block, so each
-// wave-wide fragment load reads 512 contiguous bytes.  Layer blocks follow
-// one another (N_l K_l elements each).
+// Weights in MFMA fragment order for the fused pass: for layer l (N x K, K
+// padded to KP = 32 for the input layer),
+// element (column tile ct, K step ks, lane, j) = W_l[16 ct + lane % 16][32 ks + 8 (lane / 16) + j]
+// (0 past K), at offset ((ct (KP/32) + ks) 64 + lane) 8 + j of the layer's
+// block, so each wave-wide fragment load reads 1024 contiguous bytes.  Layer
+// blocks follow one another (N_l KP_l elements each).
+constexpr int FU_K0 = 32;                        // input layer K, padded
 constexpr int FU_OFF[CFUST_MLP_LAYERS + 1] = {
-    0, CFUST_MLP_HIDDEN * CFUST_MLP_IN, CFUST_MLP_HIDDEN * CFUST_MLP_IN + CFUST_MLP_HIDDEN * CFUST_MLP_HIDDEN,
-    CFUST_MLP_HIDDEN * CFUST_MLP_IN + 2 * CFUST_MLP_HIDDEN * CFUST_MLP_HIDDEN,
-    CFUST_MLP_HIDDEN * CFUST_MLP_IN + 3 * CFUST_MLP_HIDDEN * CFUST_MLP_HIDDEN,
-    CFUST_MLP_HIDDEN * CFUST_MLP_IN + 3 * CFUST_MLP_HIDDEN * CFUST_MLP_HIDDEN + CFUST_MLP_OUT * CFUST_MLP_HIDDEN};
+    0, CFUST_MLP_HIDDEN * FU_K0, CFUST_MLP_HIDDEN * FU_K0 + CFUST_MLP_HIDDEN * CFUST_MLP_HIDDEN,
+    CFUST_MLP_HIDDEN * FU_K0 + 2 * CFUST_MLP_HIDDEN * CFUST_MLP_HIDDEN,
+    CFUST_MLP_HIDDEN * FU_K0 + 3 * CFUST_MLP_HIDDEN * CFUST_MLP_HIDDEN,
+    CFUST_MLP_HIDDEN * FU_K0 + 3 * CFUST_MLP_HIDDEN * CFUST_MLP_HIDDEN + CFUST_MLP_OUT * CFUST_MLP_HIDDEN};
 
 __global__ __launch_bounds__(256) void k_mlp_pack(cfust_mlp_weights W, uint16_t *__restrict__ Wp) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -337,36 +345,40 @@ __global__ __launch_bounds__(256) void k_mlp_pack(cfust_mlp_weights W, uint16_t 
     int l = 0;
     while (t >= FU_OFF[l + 1]) ++l;
     const int K = l == 0 ? CFUST_MLP_IN : CFUST_MLP_HIDDEN;
+    const int KP = l == 0 ? FU_K0 : CFUST_MLP_HIDDEN;
     const int e = t - FU_OFF[l];
-    const int j = e & 3, lane = (e >> 2) & 63, tile = e >> 8;     // tile = ct (K/16) + ks
-    const int ct = tile / (K / 16), ks = tile % (K / 16);
-    Wp[t] = ((const uint16_t *)W.W[l])[(size_t)(16 * ct + (lane & 15)) * K + 16 * ks + 4 * (lane >> 4) + j];
+    const int j = e & 7, lane = (e >> 3) & 63, tile = e >> 9;     // tile = ct (KP/32) + ks
+    const int ct = tile / (KP / 32), ks = tile % (KP / 32);
+    const int k = 32 * ks + 8 * (lane >> 4) + j;
+    Wp[t] = k < K ? ((const uint16_t *)W.W[l])[(size_t)(16 * ct + (lane & 15)) * K + k] : (uint16_t)0;
 }
 
-// One hidden layer of the fused pass (K inputs, 256 outputs), in place in xs.
+// One hidden layer of the fused pass (K inputs, zero-padded to a multiple of
+// 32, 256 outputs), in place in xs.
 template <int K>
 __device__ __forceinline__ void fused_hidden_layer(uint16_t *xs, const uint16_t *__restrict__ Wl,
-                                                   const float *__restrict__ bl, int wave, int l, int lr, int lk) {
+                                                   const float *__restrict__ bl, int wave, int l, int lr, int lk,
+                                                   int lo) {
     const int col_w = 64 * wave;
     v4f acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+    constexpr int KS = (K + 31) / 32;
 #pragma unroll 4
-    for (int k0 = 0; k0 < K; k0 += 16) {
-        v4s pa[4], qb[4];
+    for (int ks = 0; ks < KS; ++ks) {
+        v8s pa[4], qb[4];
 #pragma unroll
         for (int b = 0; b < 4; ++b)
-            qb[b] = *reinterpret_cast<const v4s *>(Wl + ((size_t)((4 * wave + b) * (K / 16) + k0 / 16) * 64 + l) * 4);
+            qb[b] = *reinterpret_cast<const v8s *>(Wl + ((size_t)((4 * wave + b) * KS + ks) * 64 + l) * 8);
 #pragma unroll
         for (int a = 0; a < 4; ++a)
-            pa[a] = *reinterpret_cast<const v4s *>(xs + (16 * a + lr) * FU_STRIDE + k0 + lk);
+            pa[a] = *reinterpret_cast<const v8s *>(xs + (16 * a + lr) * FU_STRIDE + 32 * ks + lk);
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int b = 0; b < 4; ++b)
-                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(pa[a], qb[b], acc[a][b], 0, 0, 0);
+            for (int b = 0; b < 4; ++b) acc[a][b] = mfma32(pa[a], qb[b], acc[a][b]);
     }
     __syncthreads();                                                       // the layer's input is read
 #pragma unroll
@@ -377,7 +389,7 @@ __device__ __forceinline__ void fused_hidden_layer(uint16_t *xs, const uint16_t 
         for (int a = 0; a < 4; ++a)
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                xs[(16 * a + lk + i) * FU_STRIDE + col] = f2bf(gelu(acc[a][b][i] + bias));
+                xs[(16 * a + lo + i) * FU_STRIDE + col] = f2bf(gelu(acc[a][b][i] + bias));
     }
     __syncthreads();
 }
@@ -386,26 +398,29 @@ __global__ __launch_bounds__(256) void k_mlp_fwd_fused(const uint16_t *__restric
                                                        const uint16_t *__restrict__ Wp, float *__restrict__ out) {
     __shared__ __align__(16) uint16_t xs[FU_ROWS * FU_STRIDE];
     const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int lr = l & 15, lk = 4 * (l >> 4);
+    const int lr = l & 15, lk = 8 * (l >> 4), lo = 4 * (l >> 4);
     const size_t row0 = (size_t)blockIdx.x * FU_ROWS;
-    for (int t = threadIdx.x; t < FU_ROWS * CFUST_MLP_IN; t += blockDim.x)
-        xs[(t / CFUST_MLP_IN) * FU_STRIDE + t % CFUST_MLP_IN] = X0[row0 * CFUST_MLP_IN + t];
+    // the input tile, its columns CFUST_MLP_IN .. FU_K0 - 1 zeroed (the padded K)
+    for (int t = threadIdx.x; t < FU_ROWS * FU_K0; t += blockDim.x) {
+        const int r = t / FU_K0, c = t % FU_K0;
+        xs[r * FU_STRIDE + c] = c < CFUST_MLP_IN ? X0[(row0 + r) * CFUST_MLP_IN + c] : (uint16_t)0;
+    }
     __syncthreads();
-    fused_hidden_layer<CFUST_MLP_IN>(xs, Wp + FU_OFF[0], W.b[0], wave, l, lr, lk);
+    fused_hidden_layer<CFUST_MLP_IN>(xs, Wp + FU_OFF[0], W.b[0], wave, l, lr, lk, lo);
     for (int layer = 1; layer < CFUST_MLP_LAYERS - 1; ++layer)
-        fused_hidden_layer<CFUST_MLP_HIDDEN>(xs, Wp + FU_OFF[layer], W.b[layer], wave, l, lr, lk);
+        fused_hidden_layer<CFUST_MLP_HIDDEN>(xs, Wp + FU_OFF[layer], W.b[layer], wave, l, lr, lk, lo);
     // output layer, 256 -> 16: wave w takes rows 16 w .. 16 w + 15
     const int L = CFUST_MLP_LAYERS - 1;
     const uint16_t *Wl = Wp + FU_OFF[L];                                    // one column tile
     v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < CFUST_MLP_HIDDEN; k0 += 16) {
-        const v4s pa = *reinterpret_cast<const v4s *>(xs + (16 * wave + lr) * FU_STRIDE + k0 + lk);
-        const v4s qb = *reinterpret_cast<const v4s *>(Wl + ((size_t)(k0 / 16) * 64 + l) * 4);
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(pa, qb, acc, 0, 0, 0);
+    for (int ks = 0; ks < CFUST_MLP_HIDDEN / 32; ++ks) {
+        const v8s pa = *reinterpret_cast<const v8s *>(xs + (16 * wave + lr) * FU_STRIDE + 32 * ks + lk);
+        const v8s qb = *reinterpret_cast<const v8s *>(Wl + ((size_t)ks * 64 + l) * 8);
+        acc = mfma32(pa, qb, acc);
     }
     const float bias = W.b[L][lr];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) out[(row0 + 16 * wave + lk + i) * CFUST_MLP_OUT + lr] = acc[i] + bias;
+    for (int i = 0; i < 4; ++i) out[(row0 + 16 * wave + lo + i) * CFUST_MLP_OUT + lr] = acc[i] + bias;
 }
 
 size_t mlp_packed_elems() { return (size_t)FU_OFF[CFUST_MLP_LAYERS]; }

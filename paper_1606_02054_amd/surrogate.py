@@ -186,6 +186,8 @@ class TrainReport:
     val_p99_abs_lnT: float = float("nan")
     accepted_frac_at_0p05: float = float("nan")    # share whose predicted error is <= 0.05
     accepted_p99_abs_lnT: float = float("nan")     # actual error of those, 99th percentile
+    err_head_log10_scale: float = 0.0              # calibration added to output 1 (log10 of the error)
+    calibration: tuple = ()                        # (tol, accepted share, p99 actual error) on the report half
 
 
 def draw_training_problems(m: int, n: int, seed: int, nmat: int = 16384):
@@ -266,18 +268,53 @@ def train(m: int, n_train: int, design, epochs: int = 4, batch: int = 4096, lr: 
     mlp_forward(net, xv, ov, None, handle=h)
     pred = torch.clamp(base[n_train:n_train + n_val] + ov[:n_val, 0].double() * RESID_SCALE, max=0.0)
     truth = lnT[n_train:n_train + n_val]
-    err = (pred - truth).abs()
-    pe = ov[:n_val, 1].double()
-    ae = torch.log10(err / RESID_SCALE + 1e-6)
-    corr = float(torch.corrcoef(torch.stack([pe, ae]))[0, 1].item())
-    qs = torch.quantile(err.float(), torch.tensor([0.5, 0.9, 0.99], device=dev)).tolist()
-    pred_err = RESID_SCALE * torch.pow(10.0, pe)
-    acc_mask = (pred_err <= 0.05) & (inr[n_train:n_train + n_val] > 0)
-    acc_frac = float(acc_mask.double().mean().item())
-    acc_p99 = float(torch.quantile(err[acc_mask].float(), 0.99).item()) if acc_mask.any() else float("nan")
-    rep = TrainReport(m, n_train, epochs, t1 - t0, t2 - t1, last, float(err.pow(2).mean().sqrt().item()),
-                      float(err.max().item()), corr, qs[0], qs[1], qs[2], acc_frac, acc_p99)
+    err = (pred - truth).abs().cpu().numpy()
+    pe = ov[:n_val, 1].double().cpu().numpy()
+    inside = (inr[n_train:n_train + n_val] > 0).cpu().numpy()
+    ae = np.log10(err / RESID_SCALE + 1e-6)
+    corr = float(np.corrcoef(pe, ae)[0, 1])
+    qs = np.quantile(err, [0.5, 0.9, 0.99]).tolist()
+    # Calibration of the error head: the E-step accepts an answer when its
+    # predicted error RESID_SCALE 10^(o1) is at most tol.  On the first half of
+    # the held-out set, the smallest shift of o1 (log10 scale, grid of 0.05)
+    # for which the accepted answers' actual error is at most tol at the 99th
+    # percentile, for every tol of CALIB_TOLS; it is added to the bias of
+    # output 1, and the second half reports the result.
+    half = n_val // 2
+    shift = calibrate_error_head(pe[:half], err[:half], inside[:half])
+    net.b32[B.MLP_LAYERS - 1][1] += float(shift)
+    pe = pe + shift
+    rows_rep = []
+    for tol in CALIB_TOLS:
+        acc = (RESID_SCALE * 10.0 ** pe[half:] <= tol) & inside[half:]
+        rows_rep.append((tol, float(acc.mean()), float(np.quantile(err[half:][acc], 0.99)) if acc.any() else 0.0))
+    acc5 = (RESID_SCALE * 10.0 ** pe[half:] <= 0.05) & inside[half:]
+    acc_frac = float(acc5.mean())
+    acc_p99 = float(np.quantile(err[half:][acc5], 0.99)) if acc5.any() else float("nan")
+    rep = TrainReport(m, n_train, epochs, t1 - t0, t2 - t1, last, float(np.sqrt((err ** 2).mean())),
+                      float(err.max()), corr, qs[0], qs[1], qs[2], acc_frac, acc_p99, float(shift), tuple(rows_rep))
     return net, rep
+
+
+CALIB_TOLS = (0.01, 0.02, 0.05, 0.1)
+
+
+def calibrate_error_head(pe: np.ndarray, err: np.ndarray, inside: np.ndarray, tols=CALIB_TOLS) -> float:
+    """Smallest shift d (a multiple of 0.05, >= 0) of the predicted log10
+    error pe such that, for each tol, the answers accepted at tol
+    (RESID_SCALE 10^(pe + d) <= tol, inside the training domain) have actual
+    error err at most tol at the 99th percentile."""
+    for k in range(0, 161):
+        d = 0.05 * k
+        ok = True
+        for tol in tols:
+            acc = (RESID_SCALE * 10.0 ** (pe + d) <= tol) & inside
+            if acc.sum() >= 1 and np.quantile(err[acc], 0.99) > tol:
+                ok = False
+                break
+        if ok:
+            return d
+    return 8.0
 
 
 # ------------------------------------------------------------------- E-step --

@@ -60,14 +60,34 @@ def test_forward_backward_vs_reference(sur):
     rl, rdout = omlp.loss_and_grad(got, label.astype(np.float32).astype(np.float64), 0.2)
     assert abs(float(loss.cpu()[0]) / rows - rl) <= 1e-4 * max(1.0, rl)
     np.testing.assert_allclose(dout.cpu().numpy(), rdout, rtol=1e-4, atol=1e-7)
-    dWs, dbs, _ = omlp.backward(Ws, bs, cache, rdout, bf16=True)
+    # Gradients entry by entry.  The reference back-propagates from the
+    # activations the kernels saved (BF16 layer inputs X_l, FP32
+    # pre-activations Z_l) and the kernels' dL/dout, so the two differ only by
+    # the FP32 accumulation order and by the BF16 rounding of dZ, where an FP32
+    # and an FP64 product on either side of a rounding boundary round one BF16
+    # step (2^-8 relative) apart.  Bound per entry: 2 x 2^-8 sum_b |dZ_bi||X_bj|
+    # (two such steps) plus 1e-5 of the layer's largest gradient.
+    xs = [torch.as_tensor(acts.X[l]).view(torch.bfloat16).float().cpu().numpy().astype(np.float64)
+          for l in range(5)]
+    zs = [acts.Z[l].cpu().numpy().astype(np.float64) for l in range(4)]
+    gdout = dout.cpu().numpy().astype(np.float64)
+    dWs, dbs, _ = omlp.backward(Ws, bs, (xs, zs), gdout, bf16=True)
+    dzs = omlp.backward_dz(Ws, (xs, zs), gdout, bf16=True)
     for l in range(5):
         gW = net.dW[l].cpu().numpy().astype(np.float64)
-        rel = np.linalg.norm(gW - dWs[l]) / np.linalg.norm(dWs[l])
-        assert rel <= 3e-2, (l, rel)
+        bound = 2.0 * 2.0 ** -8 * (np.abs(dzs[l]).T @ np.abs(xs[l])) + 1e-5 * np.abs(dWs[l]).max()
+        bad = np.abs(gW - dWs[l]) > bound
+        assert not bad.any(), (l, int(bad.sum()), float(np.abs(gW - dWs[l]).max()))
         gb = net.db[l].cpu().numpy().astype(np.float64)
-        relb = np.linalg.norm(gb - dbs[l]) / max(np.linalg.norm(dbs[l]), 1e-12)
-        assert relb <= 3e-2, (l, relb)
+        bound_b = 2.0 * 2.0 ** -8 * np.abs(dzs[l]).sum(0) + 1e-5 * np.abs(dbs[l]).max()
+        badb = np.abs(gb - dbs[l]) > bound_b
+        assert not badb.any(), (l, int(badb.sum()), float(np.abs(gb - dbs[l]).max()))
+        # and the bound is tight enough to see one wrong term: an average
+        # row's contribution to an entry is above half of it (entries with a
+        # gradient; outputs 2..15 carry no loss)
+        contrib = np.abs(dzs[l]).T @ np.abs(xs[l]) / dzs[l].shape[0]
+        live = contrib > 0
+        assert np.median(contrib[live] / bound[live]) > 0.5
 
 
 @pytest.mark.parametrize("rows", [64, 192, 8192])
@@ -118,10 +138,17 @@ def test_training_reduces_error(sur):
     des = make_design(1024, 4, seed=31)
     net, rep = S.train(2, 262144, des, epochs=6, batch=4096, lr=2e-3, seed=7, n_val=8192, log=print)
     print(rep, flush=True)
-    # the typical problem is learned to a few hundredths in ln T, and the error
+    # the typical problem is learned to a few hundredths in ln T and the tail
+    # to a few tenths (the short run: 2.6e5 problems, 6 epochs), and the error
     # head ranks its own errors (it decides which answers are used)
-    assert rep.val_p50_abs_lnT < 0.1
+    assert rep.val_p50_abs_lnT < 0.05
+    assert rep.val_p99_abs_lnT < 0.5
     assert rep.err_head_corr > 0.3
+    # after calibration, the answers accepted at each tolerance meet it at the
+    # 99th percentile on held-out problems the calibration did not see (a
+    # 20% margin for the sampling of a 99th percentile)
+    for tol, share, p99 in rep.calibration:
+        assert p99 <= 1.2 * tol, (tol, share, p99)
 
 
 def _c1(cf):
@@ -153,10 +180,16 @@ def _trained(S, m, des):
 
 
 def test_surrogate_estep_accuracy_and_gain(sur, orc):
-    """E-step of the n=1000, p=q=2, g=2 data with the network for T_2 against
-    the lattice: prints the time and log-likelihood error of both (reference:
-    65536 x 16 points) and the speed-up at equal log-likelihood accuracy;
-    checks that the answers it accepts stay close to the oracle."""
+    """E-step of the n=1000, p=q=2, g=2 data with the trained network for
+    T_2 against the lattice (reference: 65536 x 16 points).
+
+    Asserted: the fallback rule works -- at the tightest tolerance some
+    integrals go to the lattice, and at every tolerance the observations'
+    log-densities stay within it of the oracle's at the 99th percentile (the answers accepted are
+    those whose calibrated predicted error in ln T is below it); and the
+    measured outcome: at equal log-likelihood accuracy the network gives no
+    speed-up over the lattice (a lattice of a few hundred points is already
+    more accurate than the BF16 network and cheaper than its evaluation)."""
     cf, S = sur
     print("surrogate E-step gain", flush=True)
     ds, y, dp = _c1(cf)
@@ -182,17 +215,21 @@ def test_surrogate_estep_accuracy_and_gain(sur, orc):
         print(f"lattice {N}x{Sh}: {t * 1e3:.3f} ms, |dl| = {rows[-1][3]:.3e}", flush=True)
     qmc_s = cf.device_qmc(make_design(1024, 4, seed=1606), cf.CFUST_MIXED)
     des_s = make_design(1024, 4, seed=1606)
-    sample = np.arange(0, 1000, 50)
-    ora = orc.estep(ds.y, ds.params, des_s, rows=sample)
+    ora = orc.estep(ds.y, ds.params, des_s)
+    speedups = []
     for tol in (0.02, 0.05, 0.1):
         nf = torch.zeros(1, dtype=torch.int32, device="cuda")
         t_sur, o_sur = timed(lambda: S.cfust_estep_surrogate(y, dp, qmc_s, {2: net}, tol=tol, n_fallback=nf))
         err_sur = abs(float(o_sur.loglik.cpu()[0]) - l_ref)
-        frac = int(nf.cpu()[0]) / 4000
+        nfb = int(nf.cpu()[0])
         match = [r for r in rows if r[3] <= err_sur]
         t_eq = min(r[2] for r in match) if match else rows[-1][2]
-        print(f"surrogate tol={tol}: {t_sur * 1e3:.3f} ms, |dl| = {err_sur:.3e}, lattice fallback {frac:.3f}, "
+        speedups.append(t_eq / t_sur)
+        d = np.abs(o_sur.logf_obs.cpu().numpy() - ora.logf_obs)
+        print(f"surrogate tol={tol}: {t_sur * 1e3:.3f} ms, |dl| = {err_sur:.3e}, lattice fallback {nfb}/4000, "
+              f"|dlogf| p99 {np.quantile(d, 0.99):.3e} max {d.max():.3e}, "
               f"speed-up at equal log-likelihood accuracy {t_eq / t_sur:.2f}x", flush=True)
-        got = o_sur.logf_obs.cpu().numpy()[sample]
-        # each accepted answer is within a few tolerances of the lattice value
-        assert np.abs(got - ora.logf_obs).max() < 0.1 + 4 * tol
+        if tol == 0.02:
+            assert nfb > 0          # the network is not trusted everywhere at the tightest tolerance
+        assert np.quantile(d, 0.99) <= tol + 1e-3, (tol, np.quantile(d, 0.99))
+    assert max(speedups) < 1.0, speedups
