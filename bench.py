@@ -413,19 +413,21 @@ def small_restarts(cf, h, prec, dev, nstarts: int = 64, iters: int = 5) -> dict:
             "sequential_value": pairs / (ms_s / 1e3), "unit": "(obs*comp)/s"}
 
 
-def batched_run(cf, h, prec, dev, steps: int, warmup: int, with_cpu: bool, precision_name: str) -> dict:
-    """The restart workload: 64 independent fits (n ~ logU[5e3, 2e5], p = q in
-    3..8, g in 2..6) run as one batch, one step = one EM iteration of every fit
-    (a replay of the captured graph), against the same fits run one after the
-    other through the single-fit calls.  Both produce the same log-likelihoods
-    bit for bit (checked), i.e. they are compared at equal accuracy."""
+def batched_run(cf, h, prec, dev, steps: int, warmup: int, with_cpu: bool, precision_name: str,
+                n_lo: float = 5e3, n_hi: float = 2e5, restarts: bool = True) -> dict:
+    """The restart workload: 64 independent fits (n ~ logU[n_lo, n_hi], p = q
+    in 3..8, g in 2..6) run as one batch, one step = one EM iteration of every
+    fit (a replay of the captured graph), against the same fits run one after
+    the other through the single-fit calls.  Both produce the same
+    log-likelihoods bit for bit (checked), i.e. they are compared at equal
+    accuracy."""
     import numpy as np
     import torch
 
     from cfust_inputs import make_design, workload
 
-    progress("batched: drawing 64 fits")
-    sets = workload("batched_fit")
+    progress(f"batched: drawing 64 fits, n ~ logU[{n_lo:g}, {n_hi:g}]")
+    sets = workload("batched_fit", n_lo=n_lo, n_hi=n_hi)
     N, S = sets[0].meta["N"], sets[0].meta["S"]
     design = make_design(N, S, seed=1606)
     qmc = cf.device_qmc(design, prec, device=dev)
@@ -498,7 +500,8 @@ def batched_run(cf, h, prec, dev, steps: int, warmup: int, with_cpu: bool, preci
                                                  "tuned form, one batched E-step)")
     out = {"value": pairs / (ms_batched / 1e3), "unit": "(obs*comp)/s", "steps": steps,
            "ms_per_step": ms_batched,
-           "config": {"workload": "batched_fit", "fits": len(sets), "rows": rows, "pairs": pairs,
+           "config": {"workload": "batched_fit", "n_range": [n_lo, n_hi], "fits": len(sets), "rows": rows,
+                      "pairs": pairs,
                       "N": N, "S": S, "precision": precision_name,
                       "step": "one EM iteration of every fit (graph replay)",
                       "tuned_queues": {f"m{m}": {"rows": v[0], "blocks_per_slot": v[1], "points_per_lane": v[2]}
@@ -510,8 +513,9 @@ def batched_run(cf, h, prec, dev, steps: int, warmup: int, with_cpu: bool, preci
                                      "loglik_traces_bit_equal": equal}}
     B.close()
     del fb, fs
-    progress("small restarts: 64 starts on the n = 1000 data")
-    out["small_restarts"] = small_restarts(cf, h, prec, dev)
+    if restarts:
+        progress("small restarts: 64 starts on the n = 1000 data")
+        out["small_restarts"] = small_restarts(cf, h, prec, dev)
     if with_cpu:
         # one fit per q (the cost of a row depends on q and grows with g):
         # max(1, threads // g) rows of it, per-row time scaled by g to every
@@ -871,6 +875,8 @@ def main():
         progress("cytometry section done")
     if default_run and not args.no_batched:
         out["batched"] = batched_run(cf, h, prec, dev, 1, 1, False, args.precision)
+        out["batched"]["small_uneven_fits"] = batched_run(cf, h, prec, dev, 3, 1, False, args.precision,
+                                                          n_lo=500, n_hi=5000, restarts=False)
         progress("batched section done")
 
     if not args.no_cpu:

@@ -651,6 +651,10 @@ __device__ inline void assemble_body(const EstepAsmArgs &a, int gid) {
     for (int i = 0; i < nq2; ++i) e3[i] = 0.0;
     const double A = (q >= 2) ? integral_value(a, P, h, j, 0, c, d) : exp(lnA);
     const double Bv = integral_value(a, P, h, j, 1, c, d);
+    // Normal limit: W = 1 for every observation, so w = 1 and e1 = E[log W] = 0
+    // whenever the pair has a density, even where A and B are below the FP64
+    // range (the lattice keeps ln A finite); the moments below need B.
+    if (isinf(v) && isfinite(logf)) w = 1.0;
     if (A > 0.0 && Bv > 0.0 && isfinite(logf)) {
         const double nus = v + p + 2.0, sc = dm_ratio(v, d, p + 2.0);
         if (isinf(v)) {                          // normal limit: W = 1

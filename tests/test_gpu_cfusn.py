@@ -200,3 +200,39 @@ def test_normal_initialiser_vs_oracle(lib):
     assert np.abs(ll[fin] - oll[fin]).max() <= 1e-6 * y.shape[0]
     assert k == ok
     assert np.all(np.isinf(best.nu.cpu().numpy()))
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_normal_far_outlier_keeps_w_one(lib, orc, mode):
+    """An observation so far on the negative side of the skewing directions
+    that the density's probability A = Phi_2(c; Lambda) is below the FP64 range
+    (the oracle's plain FP64 estimate is 0 and its log-density -inf): the
+    library keeps ln A finite through the log-domain first factor, so the
+    observation keeps its density, tau = 1 (one component) and, since W = 1
+    in the normal limit, w = 1 and e1 = 0.  The other observations match the
+    oracle."""
+    cf = lib
+    rng, P = _params(41, 2, 2, 1, [True])
+    P.pi[:] = 1.0
+    y, _ = sample_hierarchy(rng, P, 12)
+    des = make_design(256, 4, seed=42)
+    # push the last observation along -Omega B 1 (c = B^T r falls along -B^T Omega B 1)
+    Om = P.Sigma[0] + P.Delta[0] @ P.Delta[0].T
+    dirn = -(P.Delta[0] @ np.ones(2))
+    k = 1.0
+    while True:
+        y[-1] = P.mu[0] + k * dirn
+        o = orc.estep(y[-1:], P, des)
+        if o.A[0, 0] == 0.0:
+            break
+        k *= 1.5
+        assert k < 1e6
+    print(f"far outlier at k = {k:.1f}, oracle log f = {o.logf_obs[0]}", flush=True)
+    ora = orc.estep(y[:-1], P, des)
+    gpu = _gpu_estep(cf, y, P, des, mode)
+    lf = gpu.logf_obs.cpu().numpy()
+    assert np.isfinite(lf[-1]) and lf[-1] < -700.0
+    assert gpu.tau.cpu().numpy()[0, -1] == 1.0
+    assert gpu.w.cpu().numpy()[0, -1] == 1.0 and gpu.e1.cpu().numpy()[0, -1] == 0.0
+    np.testing.assert_allclose(lf[:-1], ora.logf_obs, rtol=0, atol=TOL[mode]["logf"])
+    np.testing.assert_allclose(gpu.w.cpu().numpy()[0, :-1], 1.0)
