@@ -37,27 +37,29 @@ PEAK_FP32_TFLOPS = 157.3     # MI355X vector FP32 (chip figure: 2 wave64 FMA iss
 # again (profiles/k_estep_qmc_counters.md).
 TRAFFIC_SOURCES = ["paper_1606_02054_amd/csrc/cfust_sov.h", "paper_1606_02054_amd/csrc/cfust_devmath.h",
                    "paper_1606_02054_amd/csrc/cfust_estep.hip", "paper_1606_02054_amd/csrc/cfust_common.h"]
-KERNEL_DIGEST = "df6d8abddb1c4ec9"
+KERNEL_DIGEST = "30184fc9e87f22e0"
 # FP32 arithmetic of one lattice point of the m-variate integrand in the FP32
 # lattice kernel: (2 x SQ_INSTS_VALU_FMA_F32 + MUL_F32 + ADD_F32 + TRANS_F32)
 # of a launch divided by the lattice points it evaluates.
-LATTICE_FLOPS_PER_POINT = {2: 58.02, 3: 117.02, 4: 178.02, 5: 241.02, 6: 306.02, 7: 373.02, 8: 442.02}
+LATTICE_FLOPS_PER_POINT = {2: 54.01, 3: 112.31, 4: 172.33, 5: 234.14, 6: 298.21, 7: 364.2, 8: 432.22}
 # VALU issue of each kernel from SQ_INSTS_VALU, SQ_ACTIVE_INST_VALU2 and
 # GRBM_GUI_ACTIVE: wave64 VALU instructions per CU per cycle (the chip issues
 # at most 2: one pair per SIMD per 4-cycle slot) and the share of them issued
 # in pairs.
 LATTICE_VALU_ISSUE = {
-    2: {'valu_per_point': 67.1, 'valu_per_cu_cycle': 1.180, 'dual_issue_frac': 0.638, 'valu_slot_busy': 0.912},
-    3: {'valu_per_point': 132.0, 'valu_per_cu_cycle': 1.282, 'dual_issue_frac': 0.673, 'valu_slot_busy': 0.969},
-    4: {'valu_per_point': 199.1, 'valu_per_cu_cycle': 1.183, 'dual_issue_frac': 0.568, 'valu_slot_busy': 0.955},
-    5: {'valu_per_point': 267.0, 'valu_per_cu_cycle': 1.125, 'dual_issue_frac': 0.555, 'valu_slot_busy': 0.914},
-    6: {'valu_per_point': 337.2, 'valu_per_cu_cycle': 1.232, 'dual_issue_frac': 0.589, 'valu_slot_busy': 0.980},
-    7: {'valu_per_point': 407.3, 'valu_per_cu_cycle': 1.215, 'dual_issue_frac': 0.584, 'valu_slot_busy': 0.968},
-    8: {'valu_per_point': 478.1, 'valu_per_cu_cycle': 1.100, 'dual_issue_frac': 0.502, 'valu_slot_busy': 0.921},
+    2: {'valu_per_point': 58.6, 'valu_per_cu_cycle': 1.108, 'dual_issue_frac': 0.603, 'valu_slot_busy': 0.891},
+    3: {'valu_per_point': 119.5, 'valu_per_cu_cycle': 1.234, 'dual_issue_frac': 0.646, 'valu_slot_busy': 0.961},
+    4: {'valu_per_point': 181.7, 'valu_per_cu_cycle': 1.191, 'dual_issue_frac': 0.614, 'valu_slot_busy': 0.945},
+    5: {'valu_per_point': 243.9, 'valu_per_cu_cycle': 1.107, 'dual_issue_frac': 0.527, 'valu_slot_busy': 0.925},
+    6: {'valu_per_point': 309.3, 'valu_per_cu_cycle': 1.220, 'dual_issue_frac': 0.584, 'valu_slot_busy': 0.983},
+    7: {'valu_per_point': 374.5, 'valu_per_cu_cycle': 1.205, 'dual_issue_frac': 0.591, 'valu_slot_busy': 0.966},
+    8: {'valu_per_point': 440.3, 'valu_per_cu_cycle': 1.085, 'dual_issue_frac': 0.493, 'valu_slot_busy': 0.921},
 }
-# HBM bytes of the FP32 lattice kernels per E-step of the default workload
-# (FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy).
-TRAFFIC_MIB = {"read": 3.47 + 2.73 + 2.75, "write": 4.77 + 5.66 + 7.50}
+# HBM bytes per launch of the FP32 lattice kernel of each dimension at the
+# default workload (MiB read, MiB written: FETCH_SIZE x 2 and WRITE_SIZE x 1 in
+# KiB, the factors that a 1 GiB device copy gives these counters).
+TRAFFIC_MIB = {4: (2 * 2530.1 / 1024, 6401.5 / 1024), 3: (2 * 1404.5 / 1024, 5800.2 / 1024),
+               2: (2 * 1409.0 / 1024, 7675.6 / 1024)}
 
 
 def kernel_digest() -> str:
@@ -112,8 +114,13 @@ def lattice_roofline(prof, points_by_m, steps: int, kernel: str, traffic=None) -
     tot_f = None
     if all(v["flops_per_point"] is not None for v in per.values()):
         tot_f = sum(v["flops_per_point"] * v["points_per_launch"] * v["launches_per_step"] for v in per.values())
+    tr = None
+    if traffic and dom in traffic:
+        rd, wr = traffic[dom]
+        tr = (rd + wr) * (1 << 20)
     return {"bound": "alu", "achieved": d["achieved"], "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-            "frac": d["achieved"] / PEAK_FP32_TFLOPS if d["achieved"] else None, "traffic": traffic,
+            "frac": d["achieved"] / PEAK_FP32_TFLOPS if d["achieved"] else None, "traffic": tr,
+            "traffic_MiB_read_write_per_launch": {f"m{m}": v for m, v in traffic.items()} if traffic else None,
             "kernel": f"{kernel}, m = {dom} (the dimension with the most time)",
             "flops_per_launch": d["flops_per_point"] * d["points_per_launch"] if d["flops_per_point"] else None,
             "avg_launch_ms": d["avg_ms"], "valu_issue": d["valu_issue"],
@@ -842,9 +849,8 @@ def main():
     for m in integral_dims(q):
         points[m] = points.get(m, 0) + N * S * pairs
     traffic = None
-    if args.workload == "cfust_n20000_p4_q4_g3" and prec == cf.CFUST_MIXED and counters_current() and TRAFFIC_MIB:
-        traffic = {"bytes_per_estep": (TRAFFIC_MIB["read"] + TRAFFIC_MIB["write"]) * (1 << 20),
-                   "read_MiB": TRAFFIC_MIB["read"], "write_MiB": TRAFFIC_MIB["write"]}
+    if args.workload == "cfust_n20000_p4_q4_g3" and prec == cf.CFUST_MIXED and not args.n and counters_current():
+        traffic = TRAFFIC_MIB
     roofline = lattice_roofline(prof, points, args.steps, "k_estep_qmc (FP32 lattice integrand)", traffic)
 
     out = {"metric": METRIC, "value": value, "unit": "(obs*comp)/s", "n_gpus": 1, "steps": args.steps,
