@@ -148,7 +148,9 @@ cfust_status cfust_estep(cfust_handle handle, const double *y, cfust_dims dims,
  * makes no hipMalloc, hipFree or other allocating call and records no
  * profiling events.  Workspace needed: about g n (12 J + 16) bytes plus 61 KB
  * per component, J = lattice integrals per pair (2 at q = 2, 12 at q = 4,
- * 38 at q = 8; e.g. n up to ~28000 at p = q = 8, g = 5); a larger call returns
+ * 38 at q = 8), plus 8 (q - 1) N S bytes of lattice coordinates in mixed
+ * precision when that table is at most 16 MB (e.g. n up to ~26000 at
+ * p = q = 8, g = 5, N = 8192, S = 8); a larger call returns
  * CFUST_EINVAL before any launch.  All calls on one device share that
  * device's array, which keeps the last call's contents: calls that overlap on
  * one device (other streams, other threads, other handles) race and must be

@@ -26,10 +26,24 @@ bool weights_ok(const cfust_mlp_weights *w) {
 
 // Workspace layout of an E-step (or log-likelihood) call.
 struct EstepWs {
-    size_t pre, tabs, tabs64, est, lnA, flag, logf, partial, total;
+    size_t pre, tabs, tabs64, est, lnA, flag, logf, partial, coords, total;
+    int coordC;
 };
 
-EstepWs estep_layout(const cfust_dims &d, int J, bool own_logf) {
+// Coordinates the FP32 integrand reads from a table (q - 1 of them: the
+// largest integral has dimension q), when the lattice allows it (mixed
+// precision, N a power of two >= 64) and the table stays small.
+constexpr size_t COORDS_MAX_BYTES = (size_t)16 << 20;
+int coord_count(const cfust_dims &d, const cfust_qmc *Q) {
+    if (!Q || Q->precision != CFUST_MIXED || d.q < 2 || d.n == 0) return 0;
+    const int lg = ilog2_exact(Q->N);
+    if (lg < 6) return 0;
+    const int C = d.q - 1;
+    if (lattice_coords_floats(Q->N, Q->S, C) * sizeof(float) > COORDS_MAX_BYTES) return 0;
+    return C;
+}
+
+EstepWs estep_layout(const cfust_dims &d, int J, bool own_logf, int coordC = 0, const cfust_qmc *Q = nullptr) {
     Carve c;
     EstepWs w;
     w.pre = c.take<CompPre>(d.g);
@@ -40,6 +54,8 @@ EstepWs estep_layout(const cfust_dims &d, int J, bool own_logf) {
     w.flag = c.take<int32_t>((size_t)d.g * (J > 0 ? J : 1) * (d.n > 0 ? d.n : 1));
     w.logf = c.take<double>(own_logf ? (size_t)d.g * (d.n > 0 ? d.n : 1) : 1);
     w.partial = c.take<double>((size_t)(d.n + 255) / 256 + 1);
+    w.coordC = coordC;
+    w.coords = c.take<float>(coordC > 0 ? lattice_coords_floats(Q->N, Q->S, coordC) : 1);
     w.total = c.off;
     return w;
 }
@@ -72,7 +88,7 @@ cfust_status run_estep(cfust_handle h, const double *y, const cfust_dims &d, con
         return fail(h, CFUST_EINVAL, "an E-step output array is NULL");
     const bool mixed = Q->precision == CFUST_MIXED;
     const int J = density_only ? (lattice ? 1 : 0) : nint_qmc(d.q);
-    const EstepWs L = estep_layout(d, J, logf_comp == nullptr);
+    const EstepWs L = estep_layout(d, J, logf_comp == nullptr, J > 0 ? coord_count(d, Q) : 0, Q);
     // surrogate workspace: need flags, and per dimension group features/outputs
     struct SurGroup { int m, idx0, cnt; long rows, rows_pad; size_t x0, out, inr, base; };
     SurGroup sg[3];
@@ -158,9 +174,14 @@ cfust_status run_estep(cfust_handle h, const double *y, const cfust_dims &d, con
         a.n = d.n; a.p = d.p; a.q = d.q; a.g = d.g; a.J = J; a.mixed = mixed ? 1 : 0;
         a.est = (double *)W(L.est); a.lnA = (double *)W(L.lnA); a.se = se;
         a.flag = (int32_t *)W(L.flag);
+        if (L.coordC > 0) {
+            a.coords = (const float *)W(L.coords);
+            a.coordC = L.coordC;
+            e = launch_lattice_coords(a.lat, L.coordC, (float *)W(L.coords), s);
+        }
         // integrals of equal dimension share a launch: (A, B) m = q, C_i m = q-1, D_ik m = q-2
         a.idx0 = 0;
-        e = timed_qmc(h, a, fixed_ws == nullptr, d.q, density_only ? 1 : 2, s);
+        if (e == hipSuccess) e = timed_qmc(h, a, fixed_ws == nullptr, d.q, density_only ? 1 : 2, s);
         if (e == hipSuccess && !density_only && d.q - 1 >= 2) {
             a.idx0 = 2;
             e = timed_qmc(h, a, fixed_ws == nullptr, d.q - 1, d.q, s);
@@ -399,7 +420,7 @@ cfust_status cfust_autotune(cfust_handle h, const double *y, cfust_dims d, const
     hipStream_t s = (hipStream_t)stream;
     const bool mixed = Q->precision == CFUST_MIXED;
     const int J = nint_qmc(d.q);
-    const EstepWs L = estep_layout(d, J, true);
+    const EstepWs L = estep_layout(d, J, true, coord_count(d, Q), Q);
     if ((st = ensure_ws(h, L.total)) != CFUST_OK) return st;
     if ((st = hip_check(h, hipSetDevice(h->device), "hipSetDevice")) != CFUST_OK) return st;
     CompPre *pre = at<CompPre>(h, L.pre);
@@ -415,6 +436,12 @@ cfust_status cfust_autotune(cfust_handle h, const double *y, cfust_dims d, const
     a.est = at<double>(h, L.est); a.lnA = at<double>(h, L.lnA); a.se = nullptr;
     a.flag = at<int32_t>(h, L.flag);
     a.need = nullptr;
+    if (L.coordC > 0) {
+        a.coords = at<float>(h, L.coords);
+        a.coordC = L.coordC;
+        if ((e = launch_lattice_coords(a.lat, L.coordC, at<float>(h, L.coords), s)) != hipSuccess)
+            return hip_check(h, e, "cfust_autotune");
+    }
     struct Group { int idx0, m, nidx; };
     Group groups[3] = {{0, d.q, 2}, {2, d.q - 1, d.q}, {2 + d.q, d.q - 2, npairs(d.q)}};
     hipEvent_t e0 = pool_event(h), e1 = pool_event(h);
@@ -545,8 +572,7 @@ cfust_status cfust_reserve(cfust_handle h, cfust_dims d, const cfust_qmc *qmc) {
     if (!h) return CFUST_EINVAL;
     cfust_status st;
     if ((st = check_dims(h, d)) != CFUST_OK) return st;
-    (void)qmc;
-    size_t need = estep_layout(d, nint_qmc(d.q), true).total;
+    size_t need = estep_layout(d, nint_qmc(d.q), true, coord_count(d, qmc), qmc).total;
     const size_t ms = mstep_bytes(d, h->ncu);
     if (ms > need) need = ms;
     if ((st = hip_check(h, hipSetDevice(h->device), "hipSetDevice")) != CFUST_OK) return st;

@@ -519,7 +519,7 @@ __device__ __attribute__((noinline)) ItemResult item_finish(const WaveItem *w, c
 // !MIXED: with T64 the FP64 integrand reads the FP64 dof tables of the
 // integral in tab64 (LDS); without, it uses the exact transforms (the redo
 // pass of mixed mode, whose FP32 tables do not serve it).
-template <int M, bool MIXED, int PPL, bool T64 = false>
+template <int M, bool MIXED, int PPL, bool T64 = false, bool COORDS = false>
 __device__ inline bool qmc_item(const EstepQmcArgs &a, int h, int idx, int j, const float *tab,
                                 const double *tab64, double *smean, WaveItem *w, int lane) {
     item_head(a.y, a.mu, a.pre, a.n, a.p, a.q, h, idx, j, w, !MIXED);
@@ -529,7 +529,8 @@ __device__ inline bool qmc_item(const EstepQmcArgs &a, int h, int idx, int j, co
     if (w->H.e0 > 0.0 || w->H.lne0 > -INFINITY) {
         if (MIXED) {
             const bool ok = normal ? sov_mixed_normal<M, PPL>(w->H, w->b, w->L, a.lat, tab, smean, lane)
-                                   : sov_mixed<M, PPL>(w->H, w->b, w->L, w->nu0, a.lat, tab, smean, lane);
+                                   : sov_mixed<M, PPL, COORDS>(w->H, w->b, w->L, w->nu0, a.lat, tab, smean, lane,
+                                                               a.coords, a.coordC);
             if (!ok) return false;
         } else if (T64) {
             sov_fp64_tab<M>(w->H, w->b, w->L, w->nu0, a.lat, tab64, smean, lane);
@@ -582,7 +583,7 @@ constexpr int fp32_min_blocks(int m) { return m == 5 ? 6 : m == 6 ? 5 : 1; }
 // product underflows are flagged for the FP64 pass.  !MIXED: FP64 integrand;
 // with FLAGGED_ONLY it processes only the flagged items.
 // The FP32 kernels are held to fp32_min_blocks(m) waves per SIMD.
-template <int M, bool MIXED, bool FLAGGED_ONLY, int PPL>
+template <int M, bool MIXED, bool FLAGGED_ONLY, int PPL, bool COORDS = false>
 __global__ __launch_bounds__(256, MIXED && PPL == 1 ? fp32_min_blocks(M) : 1) void k_estep_qmc(EstepQmcArgs a) {
     constexpr bool TAB64 = !MIXED && !FLAGGED_ONLY;
     __shared__ __align__(16) float tab[MIXED ? M * TAB_FLOATS : 4];
@@ -611,7 +612,7 @@ __global__ __launch_bounds__(256, MIXED && PPL == 1 ? fp32_min_blocks(M) : 1) vo
         if (lane == 0) a.flag[o] = 1;
         return;
     }
-    const bool ok = qmc_item<M, MIXED, PPL, TAB64>(a, h, idx, j, tab, tab64, smean[wave], &witem[wave], lane);
+    const bool ok = qmc_item<M, MIXED, PPL, TAB64, COORDS>(a, h, idx, j, tab, tab64, smean[wave], &witem[wave], lane);
     if ((MIXED || TAB64) && lane == 0) a.flag[o] = ok ? 0 : 1;
 }
 
@@ -1101,6 +1102,7 @@ static void launch_qmc_m(const EstepQmcArgs &a, int nidx, hipStream_t s, hipEven
     if (ev0) (void)hipEventRecord(ev0, s);
     if (a.mixed) {
         if (ppl == 2) hipLaunchKernelGGL((k_estep_qmc<M, true, false, 2>), grid, dim3(256), 0, s, a);
+        else if (a.coords) hipLaunchKernelGGL((k_estep_qmc<M, true, false, 1, true>), grid, dim3(256), 0, s, a);
         else hipLaunchKernelGGL((k_estep_qmc<M, true, false, 1>), grid, dim3(256), 0, s, a);
         if (ev1) (void)hipEventRecord(ev1, s);
         hipLaunchKernelGGL((k_estep_qmc<M, false, true, 1>), grid, dim3(256), 0, s, a);
@@ -1126,6 +1128,26 @@ hipError_t launch_estep_qmc(const EstepQmcArgs &a, int m, int nidx, hipStream_t 
     case 8: launch_qmc_m<8>(a, nidx, s, ev0, ev1, ppl); break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+// The lattice coordinates of every point, coordinate and shift, formed as the
+// FP32 integrand forms them (one thread per point; grid (N/256, C, S)).
+__global__ __launch_bounds__(256) void k_lattice_coords(LatticeArgs L, int C, float *__restrict__ coords) {
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y, s = blockIdx.z;
+    if (k >= (uint32_t)L.N) return;
+    const int sh = 32 - L.log2N;
+    const uint32_t t = ((k * (uint32_t)L.z[i]) << sh) + (uint32_t)(L.shifts[s * LATD + i] * 4294967296.0);
+    const float scale = i == 0 ? 1.0f : 4.656612873077393e-10f;      // 2^-31 past coordinate 0
+    float *row = coords + ((size_t)(s * C + i) * 2) * L.N;
+    row[k] = tent_units(t) * scale;
+    row[L.N + k] = tent_units(t ^ 0x80000000u) * scale;
+}
+
+hipError_t launch_lattice_coords(const LatticeArgs &L, int C, float *coords, hipStream_t s) {
+    if (C <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lattice_coords, dim3((L.N + 255) / 256, C, L.S), dim3(256), 0, s, L, C, coords);
     return hipGetLastError();
 }
 

@@ -26,6 +26,8 @@ struct EstepQmcArgs {
     double *se;                 // [g][n]  optional stderr of A
     int32_t *flag;              // [g][J][n] mixed: 1 where the FP32 estimate underflowed
     const int32_t *need;        // [g][J][n] or null: only items with need != 0 are evaluated
+    const float *coords = nullptr;   // mixed: lattice coordinate table [S][coordC][2][N] (see
+    int coordC = 0;                  // launch_lattice_coords), or null: formed in the loop
 };
 
 // Surrogate features of the lattice integrals of one dimension m: rows
@@ -220,6 +222,13 @@ hipError_t launch_tables64(const CompPre *pre, int p, int g, int ndof, double *t
 hipError_t launch_estep_qmc(const EstepQmcArgs &a, int m, int nidx, hipStream_t s,
                             hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, int ppl = 1);
 hipError_t launch_assemble(const EstepAsmArgs &a, hipStream_t s);
+// Table of the tent-transformed lattice coordinates 0 .. C-1 of every point
+// and shift (N a power of two >= 64): coords[((s C + i) 2 + r) N + k], r = 0
+// the coordinate, r = 1 its complement; coordinate 0 in units of 2^-31, the
+// others scaled (the values the FP32 integrand forms in its loop).
+hipError_t launch_lattice_coords(const LatticeArgs &L, int C, float *coords, hipStream_t s);
+// Floats of that table.
+inline size_t lattice_coords_floats(int N, int S, int C) { return (size_t)2 * C * N * S; }
 hipError_t launch_lse(const EstepLseArgs &a, double *loglik, hipStream_t s);
 hipError_t launch_mvt(const MvtArgs &a, hipStream_t s);
 hipError_t launch_mstep(const MstepArgs &r, const MsolveArgs &s, hipStream_t st);

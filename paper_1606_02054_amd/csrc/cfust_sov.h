@@ -268,16 +268,17 @@ struct Sov32Setup {
     bool low0;
 };
 
+// xu, xbu: the coordinate and its complement in units of 2^-31 (xbu unused
+// when LOW0).
 template <bool LOW0>
-__device__ __forceinline__ float quantile_step32_first(const Sov32Setup &P, uint32_t t, const float *tab, float &Q) {
-    const float xu = tent_units(t);
+__device__ __forceinline__ float quantile_step32_first_u(const Sov32Setup &P, float xu, float xbu, const float *tab,
+                                                         float &Q) {
     bool lower;
     float l2q;
     if (LOW0) {
         lower = true;
         l2q = flog2(xu) + P.l2e0m31;
     } else {
-        const float xbu = tent_units(t ^ 0x80000000u);
         const float p = xu * P.e0s;
         const float pb = fmaf(xbu, P.e0s, P.eb0);
         lower = p <= 0.5f;
@@ -288,6 +289,11 @@ __device__ __forceinline__ float quantile_step32_first(const Sov32Setup &P, uint
     const float sabs = 1.0f - tq;
     Q = fminf(Q * frsq(tq * (2.0f - tq)), 1e15f);
     return (lower ? -sabs : sabs) * Q;
+}
+
+template <bool LOW0>
+__device__ __forceinline__ float quantile_step32_first(const Sov32Setup &P, uint32_t t, const float *tab, float &Q) {
+    return quantile_step32_first_u<LOW0>(P, tent_units(t), LOW0 ? 0.0f : tent_units(t ^ 0x80000000u), tab, Q);
 }
 
 // Quantile step of coordinate i >= 1, given the lower-tail value small =
@@ -338,6 +344,76 @@ __device__ __forceinline__ float sov_point32(const Sov32Setup &P, const float *t
         }
     }
     return f;
+}
+
+// The same point, with its coordinates read from the E-step's coordinate
+// table instead of formed from the lattice: c[2i] is coordinate i and
+// c[2i + 1] its complement, coordinate 0 in units of 2^-31 and the others
+// scaled -- the values point32 / tent_units form, bit for bit.
+template <int M, bool LOW0>
+__device__ __forceinline__ float sov_point32_c(const Sov32Setup &P, const float *tabs, const float *c) {
+    float y[M];
+    float Q = P.sqrtnu;
+    y[0] = quantile_step32_first_u<LOW0>(P, c[0], c[1], tabs, Q);
+    float f = 1.0f;
+#pragma unroll
+    for (int i = 1; i < M; ++i) {
+        float num = P.b[i];
+#pragma unroll
+        for (int j = 0; j < i; ++j) num = fmaf(-P.L[i * M + j], y[j], num);
+        const float LQ = P.L[i * M + i] * Q;
+        const float K = LQ * LQ;
+        const float R = frsq(fmaf(num, num, K));
+        const float KR2 = K * R * R;
+        const float *tab = tabs + i * TAB_FLOATS;
+        const float l2 = fmaf(P.a[i], flog2(KR2), tab_cdf_H(tab, fmaf(-8.0f, fabsf(num) * R, 8.0f)));
+        const float small = fexp2(l2);
+        const float e = num <= 0.0f ? small : 1.0f - small;
+        f *= e;
+        if (i < M - 1) y[i] = quantile_step32(c[2 * i], c[2 * i + 1], e, small, tab, Q);
+    }
+    return f;
+}
+
+// Loads of one trip's coordinates through a buffer resource over the shift's
+// table (rows of N floats: 2i coordinate i, 2i + 1 its complement): the lane
+// offset is the vector offset and the row and trip go in the scalar offset,
+// so no vector instruction forms an address.  Under LOW0 the complement of
+// coordinate 0 is not read.
+constexpr int BUF_RSRC_WORD3 = 0x00020000;     // raw buffer, 32-bit elements (gfx9 family)
+
+template <int M, bool LOW0>
+__device__ __forceinline__ void load_coords(__amdgpu_buffer_rsrc_t r, int vo, int so, int row_bytes, float *c) {
+#pragma unroll
+    for (int i = 0; i < M - 1; ++i) {
+        c[2 * i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so + 2 * i * row_bytes, 0));
+        c[2 * i + 1] = (i == 0 && LOW0) ? 0.0f
+                     : __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so + (2 * i + 1) * row_bytes, 0));
+    }
+}
+
+// Per-lane FP32 sum over the shift's points from the coordinate table
+// `cshift` (N a multiple of 64; lane l takes points l, l + 64, ...).  The
+// loads of a trip are waited for where the point first needs them; the other
+// resident waves cover their latency.  The point's value is rounded before it
+// is added (no contraction of its last product into the sum), as in the loop
+// that forms the coordinates itself, so both give the same sums bit for bit.
+template <int M, bool LOW0>
+__device__ float sov_lane_sum32_c(const Sov32Setup &P, const float *tabs, const float *cshift, int N, int lane) {
+#pragma clang fp contract(off)
+    constexpr int R = 2 * (M - 1);
+    const int row_bytes = N * 4;
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void *)cshift, (short)0, R * row_bytes, BUF_RSRC_WORD3);
+    const int vo = lane * 4;
+    const int trips = N / 64;
+    float c[R];
+    float acc = 0.0f;
+    for (int it = 0; it < trips; ++it) {
+        load_coords<M, LOW0>(rs, vo, it * 256, row_bytes, c);
+        acc += sov_point32_c<M, LOW0>(P, tabs, c);
+    }
+    return acc;
 }
 
 // Normal limit, FP32, from the dof-free normal table (`tab`): the CDF rows
@@ -507,9 +583,12 @@ __device__ inline void sov_finish(const SovHead &H, const double *smean, int S,
 // FP32 lattice sums (mixed precision).  Returns false when the FP32 product
 // underflowed for the whole item (mean below 1e-30): the caller then redoes
 // the item in FP64.  tabs: LDS tables of dofs nu .. nu+M-1.
-template <int M, int PPL>
+// COORDS: the lattice coordinates come from the E-step's coordinate table
+// `coords` (C coordinates per point; N a multiple of 64, one point per lane
+// per trip) instead of being formed in the loop.
+template <int M, int PPL, bool COORDS = false>
 __device__ bool sov_mixed(const SovHead &H, const double *b, const double *L, double nu, const Lattice &Lt,
-                          const float *tabs, double *smean, int lane) {
+                          const float *tabs, double *smean, int lane, const float *coords = nullptr, int C = 0) {
     Sov32Setup P;
 #pragma unroll
     for (int i = 0; i < M; ++i) { P.b[i] = (float)b[i]; P.a[i] = (float)(0.5 * (nu + i)); }
@@ -526,7 +605,14 @@ __device__ bool sov_mixed(const SovHead &H, const double *b, const double *L, do
     for (int s = 0; s < Lt.S; ++s) {
 #pragma unroll
         for (int i = 0; i < M - 1; ++i) shfix[i] = (uint32_t)(Lt.shifts[s * LATD + i] * 4294967296.0);
-        const float ls = sov_lane_sum32<M, PPL, false>(P, tabs, zz, sh, shfix, Lt.N, lane);
+        float ls;
+        if (COORDS) {
+            const float *cshift = coords + (size_t)s * C * 2 * Lt.N;
+            ls = P.low0 ? sov_lane_sum32_c<M, true>(P, tabs, cshift, Lt.N, lane)
+                        : sov_lane_sum32_c<M, false>(P, tabs, cshift, Lt.N, lane);
+        } else {
+            ls = sov_lane_sum32<M, PPL, false>(P, tabs, zz, sh, shfix, Lt.N, lane);
+        }
         const double ms = wave_sum((double)ls) / (double)Lt.N;
         if (lane == 0) smean[s] = ms;
         tot += ms;
