@@ -677,7 +677,7 @@ def counter_sweep(cf, dev) -> None:
 
 def summarize_counters(dbs, points_per_wave: int) -> dict:
     """Per-dimension figures of the FP32 lattice kernel k_estep_qmc<m, FP32, 1
-    point per lane> from rocprofv3 databases (counter runs of the same
+    point per lane> (with or without the coordinate table) from rocprofv3 databases (counter runs of the same
     command): FP32 flops per lattice point (2 FMA + MUL + ADD + TRANS per
     wave / points per wave), VALU instructions per point, wave64 VALU
     instructions per CU per cycle (GRBM_GUI_ACTIVE summed over the 8 XCDs),
@@ -692,7 +692,7 @@ def summarize_counters(dbs, points_per_wave: int) -> dict:
         rows = con.execute("select dispatch_id, name, duration, counter_name, counter_value from pmc_events").fetchall()
         per = {}
         for did, name, dur, cn, cv in rows:
-            mm = re.search(r"k_estep_qmc<(\d), true, false, 1>", name)
+            mm = re.search(r"k_estep_qmc<(\d), true, false, 1(?:, (?:true|false))?>", name)
             if not mm:
                 continue
             e = per.setdefault(did, {"m": int(mm.group(1)), "dur": dur})

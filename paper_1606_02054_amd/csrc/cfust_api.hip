@@ -30,17 +30,8 @@ struct EstepWs {
     int coordC;
 };
 
-// Coordinates the FP32 integrand reads from a table (q - 1 of them: the
-// largest integral has dimension q), when the lattice allows it (mixed
-// precision, N a power of two >= 64) and the table stays small.
-constexpr size_t COORDS_MAX_BYTES = (size_t)16 << 20;
 int coord_count(const cfust_dims &d, const cfust_qmc *Q) {
-    if (!Q || Q->precision != CFUST_MIXED || d.q < 2 || d.n == 0) return 0;
-    const int lg = ilog2_exact(Q->N);
-    if (lg < 6) return 0;
-    const int C = d.q - 1;
-    if (lattice_coords_floats(Q->N, Q->S, C) * sizeof(float) > COORDS_MAX_BYTES) return 0;
-    return C;
+    return d.n == 0 ? 0 : lattice_coord_count(d.q, Q);
 }
 
 EstepWs estep_layout(const cfust_dims &d, int J, bool own_logf, int coordC = 0, const cfust_qmc *Q = nullptr) {

@@ -66,6 +66,8 @@ struct cfust_batch_ctx {
     int nfits = 0;
     bool mixed = false;
     LatticeArgs lat{};
+    float *coords = nullptr;         // lattice coordinate table (see lattice_coord_count), or null
+    int coordC = 0;
     std::vector<cfust_fit> fits;
     std::vector<char> dens;          // per fit: log-likelihood only
     bool any_density = false;
@@ -139,7 +141,7 @@ cfust_status upload_segments(cfust_batch b, Queue &Q) {
 // grid = 0 selects one block per tile (launch_queue_qmc).
 void set_grid(cfust_batch b, Queue &Q) {
     const int ncu = b->h->ncu > 0 ? b->h->ncu : 256;
-    Q.grid = Q.persist ? ncu * queue_qmc_occupancy(Q.m, b->mixed, Q.ppl) * Q.mult : 0;
+    Q.grid = Q.persist ? ncu * queue_qmc_occupancy(Q.m, b->mixed, Q.ppl, b->coordC > 0) * Q.mult : 0;
     Q.redo_grid = ncu * queue_redo_occupancy(Q.m);
 }
 
@@ -169,6 +171,7 @@ hipError_t enqueue_estep(cfust_batch b, hipStream_t s) {
     hipError_t e = launch_fill_i32(b->counters, 4 * b->queues.size(), 0, s);
     if (e == hipSuccess) e = launch_batch_precompute(A, b->nblocks[BK_PRE], s);
     if (e == hipSuccess) e = launch_batch_tables(A, b->nblocks[BK_TAB], s);
+    if (e == hipSuccess && b->coordC > 0) e = launch_lattice_coords(b->lat, b->coordC, b->coords, s);
     // timing events (cfust_profile_enable) only outside stream capture
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     const bool prof = b->h->prof && hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone;
@@ -177,7 +180,7 @@ hipError_t enqueue_estep(cfust_batch b, hipStream_t s) {
         const QueueArgs qa = queue_args(b, Q, Q.ntiles);
         ProfRec r{Q.m, prof ? pool_event(b->h) : nullptr, prof ? pool_event(b->h) : nullptr};
         if (r.e0) e = hipEventRecord(r.e0, s);
-        if (e == hipSuccess) e = launch_queue_qmc(qa, Q.m, b->mixed, Q.ppl, Q.grid, s);
+        if (e == hipSuccess) e = launch_queue_qmc(qa, Q.m, b->mixed, Q.ppl, Q.grid, s, b->coordC > 0);
         if (e == hipSuccess && r.e1) e = hipEventRecord(r.e1, s);
         if (r.e0 && r.e1) b->h->rec.push_back(r);
         // mixed: items whose FP32 product underflowed; FP64: items of integrals
@@ -228,9 +231,11 @@ cfust_status cfust_batch_create(cfust_handle h, int32_t nfits, const cfust_fit *
     if (!fits) return fail(h, CFUST_EINVAL, "fits is NULL");
     cfust_status st;
     bool lattice = false;
+    int maxq = 0;
     for (int f = 0; f < nfits; ++f) {
         if ((st = check_fit(h, f, fits[f])) != CFUST_OK) return st;
         lattice = lattice || fits[f].dims.q >= 2;
+        if (fits[f].dims.n > 0) maxq = std::max(maxq, fits[f].dims.q);
     }
     if ((st = check_qmc(h, qmc, lattice)) != CFUST_OK) return st;
     if ((st = hip_check(h, hipSetDevice(h->device), "hipSetDevice")) != CFUST_OK) return st;
@@ -241,6 +246,7 @@ cfust_status cfust_batch_create(cfust_handle h, int32_t nfits, const cfust_fit *
     b->nfits = nfits;
     b->mixed = qmc->precision == CFUST_MIXED;
     b->lat = lattice ? lattice_of(qmc) : LatticeArgs{};
+    b->coordC = lattice ? lattice_coord_count(maxq, qmc) : 0;
     b->fits.assign(fits, fits + nfits);
     b->dens.resize(nfits);
     for (int f = 0; f < nfits; ++f) {
@@ -291,6 +297,7 @@ cfust_status cfust_batch_create(cfust_handle h, int32_t nfits, const cfust_fit *
     const size_t o_hist = c.take<double>((size_t)2 * nfits);
     const size_t o_counters = c.take<int32_t>(4 * (b->queues.size() > 0 ? b->queues.size() : 1));
     const size_t o_ctl = c.take<BatchCtl>(1);
+    const size_t o_coords = c.take<float>(b->coordC > 0 ? lattice_coords_floats(b->lat.N, b->lat.S, b->coordC) : 1);
     std::vector<size_t> o_seg(b->queues.size()), o_redo(b->queues.size());
     for (size_t k = 0; k < b->queues.size(); ++k) {
         o_seg[k] = c.take<QSeg>(b->queues[k].seg_cap);
@@ -309,6 +316,7 @@ cfust_status cfust_batch_create(cfust_handle h, int32_t nfits, const cfust_fit *
     b->hist = bat<double>(b, o_hist);
     b->counters = bat<int32_t>(b, o_counters);
     b->ctl = bat<BatchCtl>(b, o_ctl);
+    if (b->coordC > 0) b->coords = bat<float>(b, o_coords);
     for (size_t k = 0; k < b->queues.size(); ++k) {
         Queue &Q = b->queues[k];
         Q.counter = (unsigned long long *)(b->counters + 4 * k);
@@ -343,6 +351,7 @@ cfust_status cfust_batch_create(cfust_handle h, int32_t nfits, const cfust_fit *
         q.y = F.y; q.mu = F.params.mu; q.pre = pre; q.tabs = tabs; q.tabs64 = D.tabs64; q.lat = b->lat;
         q.n = d.n; q.p = d.p; q.q = d.q; q.g = d.g; q.J = J > 0 ? J : 1; q.idx0 = 0; q.mixed = b->mixed;
         q.est = est; q.lnA = lnA; q.se = F.out.cdf_stderr; q.flag = nullptr; q.need = nullptr;
+        q.coords = b->coords; q.coordC = b->coordC;
         EstepAsmArgs &a = D.aa;
         a.y = F.y; a.mu = F.params.mu; a.pre = pre;
         a.n = d.n; a.p = d.p; a.q = d.q; a.g = d.g; a.J = J > 0 ? J : 1;
@@ -490,6 +499,7 @@ cfust_status cfust_batch_tune(cfust_batch b, int32_t *chosen, void *stream) {
     hipError_t e = launch_fill_i32(b->active, b->nfits, 1, s);
     if (e == hipSuccess) e = launch_batch_precompute(A, b->nblocks[BK_PRE], s);
     if (e == hipSuccess) e = launch_batch_tables(A, b->nblocks[BK_TAB], s);
+    if (e == hipSuccess && b->coordC > 0) e = launch_lattice_coords(b->lat, b->coordC, b->coords, s);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
@@ -523,7 +533,7 @@ cfust_status cfust_batch_tune(cfust_batch b, int32_t *chosen, void *stream) {
                 for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
                     e = launch_fill_i32(b->counters, 4 * b->queues.size(), 0, s);
                     if (e == hipSuccess) e = hipEventRecord(e0, s);
-                    if (e == hipSuccess) e = launch_queue_qmc(qa, Q.m, b->mixed, Q.ppl, Q.grid, s);
+                    if (e == hipSuccess) e = launch_queue_qmc(qa, Q.m, b->mixed, Q.ppl, Q.grid, s, b->coordC > 0);
                     if (e == hipSuccess) e = hipEventRecord(e1, s);
                     if (e == hipSuccess) e = hipEventSynchronize(e1);
                     if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);

@@ -1254,7 +1254,7 @@ __global__ __launch_bounds__(256) void k_batch_sum(BatchArgs B) {
 // Persistent lattice kernel: each block draws tiles from the queue until it
 // is empty; the 4 waves of a block share the tile's component and integral,
 // hence its LDS tables, and take its observations in turn.
-template <int M, bool MIXED, int PPL>
+template <int M, bool MIXED, int PPL, bool COORDS = false>
 __global__ __launch_bounds__(256, MIXED && PPL == 1 ? fp32_min_blocks(M) : 1) void k_queue_qmc(QueueArgs Q) {
     __shared__ __align__(16) float tab[MIXED ? M * TAB_FLOATS : 4];
     __shared__ double tab64[MIXED ? 1 : M * TAB64_DOUBLES];
@@ -1304,7 +1304,7 @@ __global__ __launch_bounds__(256, MIXED && PPL == 1 ? fp32_min_blocks(M) : 1) vo
         const bool exact = !MIXED && beyond_tab64<M>(a.pre, a.p, a.q, h, idx);
         for (int r = wave; r < S.rows; r += 4) {
             const int j = jb + r;
-            const bool ok = !exact && qmc_item<M, MIXED, PPL, !MIXED>(a, h, idx, j, tab, tab64, smean[wave],
+            const bool ok = !exact && qmc_item<M, MIXED, PPL, !MIXED, COORDS>(a, h, idx, j, tab, tab64, smean[wave],
                                                                       &witem[wave], lane);
             if (!ok && lane == 0) {
                 const unsigned slot = atomicAdd(Q.redo_count, 1u);
@@ -1320,7 +1320,7 @@ __global__ __launch_bounds__(256, MIXED && PPL == 1 ? fp32_min_blocks(M) : 1) vo
 // tiles of at most 4 observations, one per wave.  With no loop around the
 // item its registers are not held across items, which the persistent form
 // pays for; the autotuner picks between the two.  Block t = y * gridDim.x + x.
-template <int M, bool MIXED, int PPL>
+template <int M, bool MIXED, int PPL, bool COORDS = false>
 __global__ __launch_bounds__(256, MIXED && PPL == 1 ? fp32_min_blocks(M) : 1) void k_queue_grid(QueueArgs Q) {
     __shared__ __align__(16) float tab[MIXED ? M * TAB_FLOATS : 4];
     __shared__ double tab64[MIXED ? 1 : M * TAB64_DOUBLES];
@@ -1353,7 +1353,7 @@ __global__ __launch_bounds__(256, MIXED && PPL == 1 ? fp32_min_blocks(M) : 1) vo
     if (wave >= S.rows) return;
     const int j = S.j0 + rt * S.rows + wave;
     const bool exact = !MIXED && beyond_tab64<M>(a.pre, a.p, a.q, h, idx);
-    const bool ok = !exact && qmc_item<M, MIXED, PPL, !MIXED>(a, h, idx, j, tab, tab64, smean[wave],
+    const bool ok = !exact && qmc_item<M, MIXED, PPL, !MIXED, COORDS>(a, h, idx, j, tab, tab64, smean[wave],
                                                               &witem[wave], lane);
     if (!ok && lane == 0) {
         const unsigned slot = atomicAdd(Q.redo_count, 1u);
@@ -1453,25 +1453,29 @@ hipError_t launch_batch_check(const FitDesc *fits, int nfits, int32_t *active, i
     return hipGetLastError();
 }
 
+// coords: the fits' argument blocks carry the coordinate table (mixed, one
+// point per lane per trip only)
 template <int M>
-static const void *queue_kernel(bool mixed, int ppl, bool persist) {
+static const void *queue_kernel(bool mixed, int ppl, bool persist, bool coords) {
     if (persist) {
         if (!mixed) return (const void *)k_queue_qmc<M, false, 1>;
-        return ppl == 2 ? (const void *)k_queue_qmc<M, true, 2> : (const void *)k_queue_qmc<M, true, 1>;
+        if (ppl == 2) return (const void *)k_queue_qmc<M, true, 2>;
+        return coords ? (const void *)k_queue_qmc<M, true, 1, true> : (const void *)k_queue_qmc<M, true, 1>;
     }
     if (!mixed) return (const void *)k_queue_grid<M, false, 1>;
-    return ppl == 2 ? (const void *)k_queue_grid<M, true, 2> : (const void *)k_queue_grid<M, true, 1>;
+    if (ppl == 2) return (const void *)k_queue_grid<M, true, 2>;
+    return coords ? (const void *)k_queue_grid<M, true, 1, true> : (const void *)k_queue_grid<M, true, 1>;
 }
 
-static const void *queue_kernel_m(int m, bool mixed, int ppl, bool persist) {
+static const void *queue_kernel_m(int m, bool mixed, int ppl, bool persist, bool coords) {
     switch (m) {
-    case 2: return queue_kernel<2>(mixed, ppl, persist);
-    case 3: return queue_kernel<3>(mixed, ppl, persist);
-    case 4: return queue_kernel<4>(mixed, ppl, persist);
-    case 5: return queue_kernel<5>(mixed, ppl, persist);
-    case 6: return queue_kernel<6>(mixed, ppl, persist);
-    case 7: return queue_kernel<7>(mixed, ppl, persist);
-    case 8: return queue_kernel<8>(mixed, ppl, persist);
+    case 2: return queue_kernel<2>(mixed, ppl, persist, coords);
+    case 3: return queue_kernel<3>(mixed, ppl, persist, coords);
+    case 4: return queue_kernel<4>(mixed, ppl, persist, coords);
+    case 5: return queue_kernel<5>(mixed, ppl, persist, coords);
+    case 6: return queue_kernel<6>(mixed, ppl, persist, coords);
+    case 7: return queue_kernel<7>(mixed, ppl, persist, coords);
+    case 8: return queue_kernel<8>(mixed, ppl, persist, coords);
     default: return nullptr;
     }
 }
@@ -1489,9 +1493,9 @@ static const void *redo_kernel_m(int m) {
     }
 }
 
-hipError_t launch_queue_qmc(const QueueArgs &q, int m, bool mixed, int ppl, int grid, hipStream_t s) {
+hipError_t launch_queue_qmc(const QueueArgs &q, int m, bool mixed, int ppl, int grid, hipStream_t s, bool coords) {
     const bool persist = grid > 0;
-    const void *k = queue_kernel_m(m, mixed, ppl, persist);
+    const void *k = queue_kernel_m(m, mixed, ppl, persist, coords);
     if (!k) return hipErrorInvalidValue;
     void *args[] = {(void *)&q};
     if (persist) return hipLaunchKernel(k, dim3(grid), dim3(256), args, 0, s);
@@ -1509,8 +1513,8 @@ hipError_t launch_queue_redo(const QueueArgs &q, int m, int grid, hipStream_t s)
     return hipLaunchKernel(k, dim3(grid), dim3(256), args, 0, s);
 }
 
-int queue_qmc_occupancy(int m, bool mixed, int ppl) {
-    const void *k = queue_kernel_m(m, mixed, ppl, true);
+int queue_qmc_occupancy(int m, bool mixed, int ppl, bool coords) {
+    const void *k = queue_kernel_m(m, mixed, ppl, true, coords);
     int nb = 0;
     if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 256, 0) != hipSuccess) return 1;
     return nb > 0 ? nb : 1;

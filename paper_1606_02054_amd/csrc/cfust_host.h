@@ -99,6 +99,20 @@ inline int ilog2_exact(int N) {
     return k;
 }
 
+// Lattice coordinates the FP32 integrand reads from a table, for integrals of
+// dimension up to q: coordinates 0 .. q-2 (the largest integral has q - 1
+// lattice coordinates), when the lattice allows it (mixed precision, N a
+// power of two >= 64) and the table stays within COORDS_MAX_BYTES; else 0
+// (the integrand forms the coordinates itself).
+constexpr size_t COORDS_MAX_BYTES = (size_t)16 << 20;
+inline int lattice_coord_count(int q, const cfust_qmc *Q) {
+    if (!Q || Q->precision != CFUST_MIXED || q < 2) return 0;
+    if (ilog2_exact(Q->N) < 6) return 0;
+    const int C = q - 1;
+    if (lattice_coords_floats(Q->N, Q->S, C) * sizeof(float) > COORDS_MAX_BYTES) return 0;
+    return C;
+}
+
 inline cfust_status check_qmc(cfust_handle h, const cfust_qmc *Q, bool lattice_needed) {
     if (!Q) return fail(h, CFUST_EINVAL, "qmc is NULL");
     if (Q->precision != CFUST_FP64 && Q->precision != CFUST_MIXED)

@@ -170,11 +170,13 @@ size_t mstep_lds_bytes(int p, int q);
 // blocks draw tiles until the queue is empty; grid == 0: one block per tile
 // in queue order (tiles of at most 4 observations).  Mixed mode appends
 // underflowed items to the redo list and launch_queue_redo evaluates them
-// with the FP64 integrand.
-hipError_t launch_queue_qmc(const QueueArgs &q, int m, bool mixed, int ppl, int grid, hipStream_t s);
+// with the FP64 integrand.  coords: the fits' argument blocks point at a
+// lattice coordinate table (used in mixed mode at one point per lane).
+hipError_t launch_queue_qmc(const QueueArgs &q, int m, bool mixed, int ppl, int grid, hipStream_t s,
+                            bool coords = false);
 hipError_t launch_queue_redo(const QueueArgs &q, int m, int grid, hipStream_t s);
 // Resident blocks per compute unit of the queue kernels.
-int queue_qmc_occupancy(int m, bool mixed, int ppl);
+int queue_qmc_occupancy(int m, bool mixed, int ppl, bool coords = false);
 int queue_redo_occupancy(int m);
 // Arguments of a batched EM run that the captured iteration reads from
 // device memory, so that one graph serves every call.
