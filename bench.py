@@ -37,29 +37,29 @@ PEAK_FP32_TFLOPS = 157.3     # MI355X vector FP32 (chip figure: 2 wave64 FMA iss
 # again (profiles/k_estep_qmc_counters.md).
 TRAFFIC_SOURCES = ["paper_1606_02054_amd/csrc/cfust_sov.h", "paper_1606_02054_amd/csrc/cfust_devmath.h",
                    "paper_1606_02054_amd/csrc/cfust_estep.hip", "paper_1606_02054_amd/csrc/cfust_common.h"]
-KERNEL_DIGEST = "30184fc9e87f22e0"
+KERNEL_DIGEST = "d9e83375ad4a3318"
 # FP32 arithmetic of one lattice point of the m-variate integrand in the FP32
 # lattice kernel: (2 x SQ_INSTS_VALU_FMA_F32 + MUL_F32 + ADD_F32 + TRANS_F32)
 # of a launch divided by the lattice points it evaluates.
-LATTICE_FLOPS_PER_POINT = {2: 54.01, 3: 112.31, 4: 172.33, 5: 234.14, 6: 298.21, 7: 364.2, 8: 432.22}
+LATTICE_FLOPS_PER_POINT = {2: 53.01, 3: 109.31, 4: 167.33, 5: 227.14, 6: 289.21, 7: 353.2, 8: 419.22}
 # VALU issue of each kernel from SQ_INSTS_VALU, SQ_ACTIVE_INST_VALU2 and
 # GRBM_GUI_ACTIVE: wave64 VALU instructions per CU per cycle (the chip issues
 # at most 2: one pair per SIMD per 4-cycle slot) and the share of them issued
 # in pairs.
 LATTICE_VALU_ISSUE = {
-    2: {'valu_per_point': 58.6, 'valu_per_cu_cycle': 1.108, 'dual_issue_frac': 0.603, 'valu_slot_busy': 0.891},
-    3: {'valu_per_point': 119.5, 'valu_per_cu_cycle': 1.234, 'dual_issue_frac': 0.646, 'valu_slot_busy': 0.961},
-    4: {'valu_per_point': 181.7, 'valu_per_cu_cycle': 1.191, 'dual_issue_frac': 0.614, 'valu_slot_busy': 0.945},
-    5: {'valu_per_point': 243.9, 'valu_per_cu_cycle': 1.107, 'dual_issue_frac': 0.527, 'valu_slot_busy': 0.925},
-    6: {'valu_per_point': 309.3, 'valu_per_cu_cycle': 1.220, 'dual_issue_frac': 0.584, 'valu_slot_busy': 0.983},
-    7: {'valu_per_point': 374.5, 'valu_per_cu_cycle': 1.205, 'dual_issue_frac': 0.591, 'valu_slot_busy': 0.966},
-    8: {'valu_per_point': 440.3, 'valu_per_cu_cycle': 1.085, 'dual_issue_frac': 0.493, 'valu_slot_busy': 0.921},
+    2: {'valu_per_point': 54.1, 'valu_per_cu_cycle': 1.014, 'dual_issue_frac': 0.560, 'valu_slot_busy': 0.845},
+    3: {'valu_per_point': 106.5, 'valu_per_cu_cycle': 1.159, 'dual_issue_frac': 0.635, 'valu_slot_busy': 0.924},
+    4: {'valu_per_point': 160.6, 'valu_per_cu_cycle': 1.133, 'dual_issue_frac': 0.609, 'valu_slot_busy': 0.916},
+    5: {'valu_per_point': 215.0, 'valu_per_cu_cycle': 1.071, 'dual_issue_frac': 0.565, 'valu_slot_busy': 0.889},
+    6: {'valu_per_point': 272.3, 'valu_per_cu_cycle': 1.212, 'dual_issue_frac': 0.617, 'valu_slot_busy': 0.972},
+    7: {'valu_per_point': 329.4, 'valu_per_cu_cycle': 1.142, 'dual_issue_frac': 0.561, 'valu_slot_busy': 0.947},
+    8: {'valu_per_point': 387.1, 'valu_per_cu_cycle': 1.074, 'dual_issue_frac': 0.532, 'valu_slot_busy': 0.906},
 }
 # HBM bytes per launch of the FP32 lattice kernel of each dimension at the
 # default workload (MiB read, MiB written: FETCH_SIZE x 2 and WRITE_SIZE x 1 in
 # KiB, the factors that a 1 GiB device copy gives these counters).
-TRAFFIC_MIB = {4: (2 * 2530.1 / 1024, 6401.5 / 1024), 3: (2 * 1404.5 / 1024, 5800.2 / 1024),
-               2: (2 * 1409.0 / 1024, 7675.6 / 1024)}
+TRAFFIC_MIB = {4: (2 * 10714.2 / 1024, 7709.1 / 1024), 3: (2 * 4474.5 / 1024, 5939.9 / 1024),
+               2: (2 * 3454.5 / 1024, 7731.5 / 1024)}
 
 
 def kernel_digest() -> str:
