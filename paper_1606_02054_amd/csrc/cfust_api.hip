@@ -38,7 +38,7 @@ EstepWs estep_layout(const cfust_dims &d, int J, bool own_logf, int coordC = 0, 
     Carve c;
     EstepWs w;
     w.pre = c.take<CompPre>(d.g);
-    w.tabs = c.take<float>((size_t)d.g * NDOF * TAB_FLOATS);
+    w.tabs = c.take<float>((size_t)d.g * NDOF * TABF_FLOATS);
     w.tabs64 = c.take<double>((size_t)d.g * NDOF * TAB64_DOUBLES);
     w.est = c.take<double>((size_t)d.g * (J > 0 ? J : 1) * (d.n > 0 ? d.n : 1));
     w.lnA = c.take<double>((size_t)d.g * (d.n > 0 ? d.n : 1));

@@ -281,7 +281,7 @@ cfust_status cfust_batch_create(cfust_handle h, int32_t nfits, const cfust_fit *
         const bool dn = b->dens[f] != 0;
         const int J = dn ? (d.q >= 2 ? 1 : 0) : nint_qmc(d.q);
         fo[f].pre = c.take<CompPre>(d.g);
-        fo[f].tabs = c.take<float>(b->mixed && J > 0 ? (size_t)d.g * NDOF * TAB_FLOATS : 1);
+        fo[f].tabs = c.take<float>(b->mixed && J > 0 ? (size_t)d.g * NDOF * TABF_FLOATS : 1);
         fo[f].tabs64 = c.take<double>(!b->mixed && J > 0 ? (size_t)d.g * NDOF * TAB64_DOUBLES : 1);
         fo[f].est = c.take<double>((size_t)d.g * (J > 0 ? J : 1) * n1);
         fo[f].lnA = c.take<double>((size_t)d.g * n1);

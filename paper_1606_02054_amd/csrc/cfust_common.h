@@ -17,7 +17,9 @@ constexpr int MAXPAIR = MAXQ * (MAXQ - 1) / 2;
 constexpr int MAXJ = 2 + MAXQ + MAXPAIR;          // integrals per (obs, comp)
 constexpr int NDOF = MAXQ + 2;                    // dofs nu+p .. nu+p+q+1 per component
 
-// FP32 piecewise-polynomial tables of the univariate t law for one dof:
+// FP32 piecewise-polynomial tables of the univariate t law for one dof, in the
+// compact layout (the per-item tables of the batched T_m kernel, and the
+// dof-free normal-limit table):
 //   rows 0..7  : lower-tail CDF, H(tau) = log2 T_lower(tau) - a log2(tau (2 - tau))
 //                (a = nu/2) on 8 equal intervals of tau = 1 - |s| in [0,1],
 //                s = u / sqrt(nu+u^2);
@@ -31,6 +33,24 @@ constexpr int TAB_INV_ROWS = 11;
 constexpr int TAB_ROWS = 20;                      // 8 + 11 + 1 pad row
 constexpr int TAB_FLOATS = TAB_ROWS * 8;          // 160 floats per dof
 constexpr float INV_LAMBDA_MAX = 511.0f;
+
+// The E-step's FP32 tables of the t law ("fine" layout, one slot per dof), the
+// same two functions on narrower intervals, degree 3, so a lookup reads one
+// 16-byte row and takes three FMAs:
+//   rows 0..63   : H(tau) on 64 equal intervals of tau, a cubic in the
+//                  position inside the interval (fraction of 64 tau);
+//   rows 64..151 : log2 tau against lambda on the same 11 octaves of
+//                  lambda + 1/4, each cut into 8 equal parts, a cubic in the
+//                  position inside the part (the low 20 mantissa bits of
+//                  lambda + 1/4, whose exponent and top 3 mantissa bits give
+//                  the row).
+// A normal-limit slot (dof infinite) holds the dof-free table above in its
+// first TAB_FLOATS floats.
+constexpr int TABF_CDF_ROWS = 64;
+constexpr int TABF_INV_PARTS = 8;
+constexpr int TABF_INV_ROWS = TAB_INV_ROWS * TABF_INV_PARTS;     // 88
+constexpr int TABF_FLOATS = 4 * (TABF_CDF_ROWS + TABF_INV_ROWS);  // 608 floats per dof
+static_assert(TABF_FLOATS >= TAB_FLOATS, "a fine slot holds a normal-limit table");
 
 // FP64 tables of the univariate t law for one dof (FP64 integrand), the same
 // variables in natural logs, as Chebyshev series of degree TAB64_NC - 1:

@@ -320,6 +320,32 @@ __device__ __forceinline__ float tab_ncdf_l2(const float *tab, float v) {
     return tab_poly(tab + 8 * (e + 1), mant);           // rows are polynomials in mant
 }
 
+// The same two lookups in the fine layout (rows of 4 coefficients, cubic).
+__device__ __forceinline__ float tab_cubic(const float *row, float x) {
+    const float4 c = *reinterpret_cast<const float4 *>(row);
+    return fmaf(fmaf(fmaf(c.w, x, c.z), x, c.y), x, c.x);
+}
+
+// H(tau) at pos = 64 tau (clamped into the table, NaN included).
+__device__ __forceinline__ float tabf_cdf_H(const float *tab, float pos) {
+    pos = fminf(fmaxf(pos, 0.0f), 63.9999962f);
+    const int k = (int)pos;
+    return tab_cubic(tab + 4 * k, __builtin_amdgcn_fractf(pos));
+}
+
+// log2 tau at l2p = log2 p: zz = lambda + 1/4 clamped to [1/4, INV_LAMBDA_MAX
+// + 1/4] (NaN included) has a biased exponent of 125..135, so its bits >> 20
+// (exponent and top 3 mantissa bits) less 1000 are the row 0..87, and the
+// low 20 mantissa bits the position inside it: as the float 1 + low 2^-23 in
+// [1, 9/8), position = 8 (that - 1), exact.
+__device__ __forceinline__ float tabf_inv_G(const float *tab, float l2p) {
+    const float zz = fminf(fmaxf(-0.75f - l2p, 0.25f), INV_LAMBDA_MAX + 0.25f);
+    const uint32_t bits = __float_as_uint(zz);
+    const int row = (int)(bits >> 20) - 1000;
+    const float t = fmaf(__uint_as_float((bits & 0x000FFFFFu) | 0x3F800000u), 8.0f, -8.0f);
+    return tab_cubic(tab + 4 * (TABF_CDF_ROWS + row), t);
+}
+
 // log2 tau from the quantile rows, given l2p = log2 p of the tail probability
 // p <= 1/2; the table variable is lam = -log2(2p) = -1 - l2p, clamped to
 // [0, INV_LAMBDA_MAX] and offset by 1/4 (both folded into one clamp of

@@ -6,7 +6,9 @@
 //                  (Sec. 2 eq. 4), chol Lambda and the Cholesky factors of the
 //                  conditional matrices Lambda_{-i|i}, Lambda_{-ik|ik} that
 //                  the truncated-t moments need; log-density constants.
-//   k_tables       per (component, dof): FP32 tables of the t law (mixed mode).
+//   k_tables       per (component, dof): FP32 tables of the t law (mixed mode,
+//                  fine layout).
+//   k_lattice_coords  the lattice coordinates of every point (mixed mode).
 //   k_estep_qmc    one wave per (observation, component, integral): the
 //                  lattice estimate of one T_m (the hot loop).
 //   k_assemble     one thread per (observation, component): log f_h (eq. 4),
@@ -265,15 +267,38 @@ __device__ inline double row_alpha(int row, bool normal) { return row < TAB_CDF_
 __device__ inline double row_beta(int row, bool normal) { return row < TAB_CDF_ROWS && !normal ? -1.0 : -3.0; }
 
 constexpr int TAB_NODES = (TAB_CDF_ROWS + TAB_INV_ROWS) * 7;   // 133
+constexpr int TABF_NODES = (TABF_CDF_ROWS + TABF_INV_ROWS) * 4; // 608
+
+// Row of a fine-layout table (cubic): the Chebyshev fit of the 4 node values
+// at x_n = cos(pi (n + 1/2) / 4) on [-1, 1], stored as monomial coefficients
+// in the row's position v = (x + 1) / 2 in [0, 1).  cos4[j][n] = cos(pi j (n + 1/2) / 4).
+__device__ inline void table_fit_row4(const double *f, float *dst, const double *cos4) {
+    double c[4];
+    for (int j = 0; j < 4; ++j) {
+        double acc = 0.0;
+        for (int n = 0; n < 4; ++n) acc += f[n] * cos4[4 * j + n];
+        c[j] = 0.5 * acc;
+    }
+    c[0] *= 0.5;
+    // c0 T0 + c1 T1 + c2 T2 + c3 T3 in powers of x, then x = 2v - 1
+    const double m0 = c[0] - c[2], m1 = c[1] - 3.0 * c[3], m2 = 2.0 * c[2], m3 = 4.0 * c[3];
+    dst[0] = (float)(m0 - m1 + m2 - m3);
+    dst[1] = (float)(2.0 * m1 - 4.0 * m2 + 6.0 * m3);
+    dst[2] = (float)(4.0 * m2 - 12.0 * m3);
+    dst[3] = (float)(8.0 * m3);
+}
 
 // The cosines of the Chebyshev fits, computed once per block into LDS:
-// cos64[j][n] = cos(pi j (n + 1/2) / TAB64_NC), cos7[j][n] likewise for 7.
-// Every thread of the block takes part; a barrier follows.
-__device__ inline void fit_cosines(double *cos64, double *cos7) {
+// cos64[j][n] = cos(pi j (n + 1/2) / TAB64_NC), cos7[j][n] and cos4[j][n]
+// likewise for 7 and 4 nodes.  Every thread of the block takes part; a
+// barrier follows.
+__device__ inline void fit_cosines(double *cos64, double *cos7, double *cos4 = nullptr) {
     for (int t = threadIdx.x; t < TAB64_NC * TAB64_NC; t += blockDim.x)
         cos64[t] = cos(M_PI * (t / TAB64_NC) * ((t % TAB64_NC) + 0.5) / (double)TAB64_NC);
     if (cos7)
         for (int t = threadIdx.x; t < 49; t += blockDim.x) cos7[t] = cos(M_PI * (t / 7) * ((t % 7) + 0.5) / 7.0);
+    if (cos4)
+        for (int t = threadIdx.x; t < 16; t += blockDim.x) cos4[t] = cos(M_PI * (t / 4) * ((t % 4) + 0.5) / 4.0);
     __syncthreads();
 }
 
@@ -317,31 +342,45 @@ __device__ inline double table_node_from64(double nu, const double *h64, int row
     return tab64_l_solve(h64, -(lam + 1.0) * LN2, a, dm_lbeta_half(a)) / LN2;
 }
 
-// Block `bid` = (component, dof offset) of one parameter set; 192 threads.
-// Finite dof: the FP64 CDF rows first, then the 19 x 7 nodes from them;
-// infinite dof (normal limit): the dof-free closed forms.  One thread per row
-// fits and writes the row.
+// Node n of row `row` of a fine-layout table (finite dof) from the FP64 CDF
+// rows: H in log2 units on 64 equal intervals of tau, and log2 tau of the
+// quantile solved on those rows at lambda + 1/4 = 2^(k-2) (1 + (part + v)/8)
+// in part `part` of octave k.
+__device__ inline double tablef_node_from64(double nu, const double *h64, int row, int n) {
+    const double v = 0.5 * (cos(M_PI * (n + 0.5) / 4.0) + 1.0);
+    if (row < TABF_CDF_ROWS) return tab64_H(h64, (row + v) / (double)TABF_CDF_ROWS) / LN2;
+    const int r = row - TABF_CDF_ROWS, k = r / TABF_INV_PARTS, part = r % TABF_INV_PARTS;
+    const double lam = ldexp(1.0 + (part + v) / (double)TABF_INV_PARTS, k - 2) - 0.25;
+    const double a = 0.5 * nu;
+    return tab64_l_solve(h64, -(lam + 1.0) * LN2, a, dm_lbeta_half(a)) / LN2;
+}
+
+// Block `bid` = (component, dof offset) of one parameter set; 192 threads;
+// writes the slot in the fine layout.  Finite dof: the FP64 CDF rows first,
+// then the 152 x 4 nodes from them, one thread per row fitting it; infinite
+// dof (normal limit): the dof-free closed forms, in the compact layout at the
+// start of the slot, the rest of the slot zero.
 __device__ inline void tables_body(const CompPre *__restrict__ pre, int p, int ndof, float *__restrict__ tabs,
                                    int bid) {
     const int h = bid / ndof, off = bid % ndof;
     const double nu = pre[h].nu + p + off;
-    __shared__ double fv[TAB_NODES];
+    __shared__ double fv[TABF_NODES];
     __shared__ double fv64[TAB64_CDF_ROWS * TAB64_NC], h64[TAB64_CDF_ROWS * TAB64_NC];
-    __shared__ double cos64[TAB64_NC * TAB64_NC], cos7[49];
+    __shared__ double cos64[TAB64_NC * TAB64_NC], cos7[49], cos4[16];
     const int t = threadIdx.x;
-    fit_cosines(cos64, cos7);
+    fit_cosines(cos64, cos7, cos4);
+    float *dst = tabs + ((size_t)h * NDOF + off) * TABF_FLOATS;
     if (isinf(nu)) {
         if (t < TAB_NODES) fv[t] = table_node_value(nu, t / 7, t % 7);
+        __syncthreads();
+        if (t < TAB_CDF_ROWS + TAB_INV_ROWS)
+            table_fit_row(fv + 7 * t, dst + 8 * t, row_alpha(t, true), row_beta(t, true), cos7);
+        for (int u = 8 * (TAB_CDF_ROWS + TAB_INV_ROWS) + t; u < TABF_FLOATS; u += blockDim.x) dst[u] = 0.0f;
     } else {
         build_cdf64(nu, fv64, h64, cos64);
-        if (t < TAB_NODES) fv[t] = table_node_from64(nu, h64, t / 7, t % 7);
-    }
-    __syncthreads();
-    float *dst = tabs + ((size_t)h * NDOF + off) * TAB_FLOATS;
-    if (t < TAB_CDF_ROWS + TAB_INV_ROWS)
-        table_fit_row(fv + 7 * t, dst + 8 * t, row_alpha(t, isinf(nu)), row_beta(t, isinf(nu)), cos7);
-    if (t >= TAB_CDF_ROWS + TAB_INV_ROWS && t < TAB_ROWS) {   // pad row
-        for (int i = 0; i < 8; ++i) dst[8 * t + i] = 0.0f;
+        for (int u = t; u < TABF_NODES; u += blockDim.x) fv[u] = tablef_node_from64(nu, h64, u / 4, u % 4);
+        __syncthreads();
+        if (t < TABF_CDF_ROWS + TABF_INV_ROWS) table_fit_row4(fv + 4 * t, dst + 4 * t, cos4);
     }
 }
 
@@ -529,8 +568,8 @@ __device__ inline bool qmc_item(const EstepQmcArgs &a, int h, int idx, int j, co
     if (w->H.e0 > 0.0 || w->H.lne0 > -INFINITY) {
         if (MIXED) {
             const bool ok = normal ? sov_mixed_normal<M, PPL>(w->H, w->b, w->L, a.lat, tab, smean, lane)
-                                   : sov_mixed<M, PPL, COORDS>(w->H, w->b, w->L, w->nu0, a.lat, tab, smean, lane,
-                                                               a.coords, a.coordC);
+                                   : sov_mixed<M, PPL, COORDS, true>(w->H, w->b, w->L, w->nu0, a.lat, tab, smean,
+                                                                     lane, a.coords, a.coordC);
             if (!ok) return false;
         } else if (T64) {
             sov_fp64_tab<M>(w->H, w->b, w->L, w->nu0, a.lat, tab64, smean, lane);
@@ -550,11 +589,12 @@ __device__ inline bool qmc_item(const EstepQmcArgs &a, int h, int idx, int j, co
     return true;
 }
 
-// Stage the FP32 tables of the dofs an integral of dimension M uses.
+// Stage the FP32 tables (fine layout) of the dofs an integral of dimension M uses.
 template <int M>
 __device__ inline void load_tables(const float *__restrict__ tabs, int h, int dofoff, float *tab) {
-    const float *src = tabs + ((size_t)h * NDOF + dofoff) * TAB_FLOATS;
-    for (int t = threadIdx.x; t < M * TAB_FLOATS; t += blockDim.x) tab[t] = src[t];
+    const float4 *src = reinterpret_cast<const float4 *>(tabs + ((size_t)h * NDOF + dofoff) * TABF_FLOATS);
+    float4 *d = reinterpret_cast<float4 *>(tab);
+    for (int t = threadIdx.x; t < M * TABF_FLOATS / 4; t += blockDim.x) d[t] = src[t];
 }
 
 // True when integral idx of component h (dimension M) uses a finite dof past
@@ -586,7 +626,7 @@ constexpr int fp32_min_blocks(int m) { return m == 5 ? 6 : m == 6 ? 5 : 1; }
 template <int M, bool MIXED, bool FLAGGED_ONLY, int PPL, bool COORDS = false>
 __global__ __launch_bounds__(256, MIXED && PPL == 1 ? fp32_min_blocks(M) : 1) void k_estep_qmc(EstepQmcArgs a) {
     constexpr bool TAB64 = !MIXED && !FLAGGED_ONLY;
-    __shared__ __align__(16) float tab[MIXED ? M * TAB_FLOATS : 4];
+    __shared__ __align__(16) float tab[MIXED ? M * TABF_FLOATS : 4];
     __shared__ double tab64[TAB64 ? M * TAB64_DOUBLES : 1];
     __shared__ double smean[4][MAXS];
     __shared__ WaveItem witem[4];
@@ -1256,7 +1296,7 @@ __global__ __launch_bounds__(256) void k_batch_sum(BatchArgs B) {
 // hence its LDS tables, and take its observations in turn.
 template <int M, bool MIXED, int PPL, bool COORDS = false>
 __global__ __launch_bounds__(256, MIXED && PPL == 1 ? fp32_min_blocks(M) : 1) void k_queue_qmc(QueueArgs Q) {
-    __shared__ __align__(16) float tab[MIXED ? M * TAB_FLOATS : 4];
+    __shared__ __align__(16) float tab[MIXED ? M * TABF_FLOATS : 4];
     __shared__ double tab64[MIXED ? 1 : M * TAB64_DOUBLES];
     __shared__ double smean[4][MAXS];
     __shared__ WaveItem witem[4];
@@ -1322,7 +1362,7 @@ __global__ __launch_bounds__(256, MIXED && PPL == 1 ? fp32_min_blocks(M) : 1) vo
 // pays for; the autotuner picks between the two.  Block t = y * gridDim.x + x.
 template <int M, bool MIXED, int PPL, bool COORDS = false>
 __global__ __launch_bounds__(256, MIXED && PPL == 1 ? fp32_min_blocks(M) : 1) void k_queue_grid(QueueArgs Q) {
-    __shared__ __align__(16) float tab[MIXED ? M * TAB_FLOATS : 4];
+    __shared__ __align__(16) float tab[MIXED ? M * TABF_FLOATS : 4];
     __shared__ double tab64[MIXED ? 1 : M * TAB64_DOUBLES];
     __shared__ double smean[4][MAXS];
     __shared__ WaveItem witem[4];

@@ -14,7 +14,7 @@ struct EstepQmcArgs {
     const double *y;            // [p][n]
     const double *mu;           // [g][p]
     const CompPre *pre;         // [g]
-    const float *tabs;          // [g][NDOF][TAB_FLOATS] (mixed)
+    const float *tabs;          // [g][NDOF][TABF_FLOATS] (mixed; fine layout)
     const double *tabs64 = nullptr;   // [g][NDOF][TAB64_DOUBLES] (FP64 mode), or null: exact transforms
     LatticeArgs lat;
     int n, p, q, g;
@@ -113,7 +113,7 @@ struct FitDesc {
     int g;
     PrecompArgs pc;
     int ndof;                   // dof tables per component (mixed)
-    float *tabs;                // [g][NDOF][TAB_FLOATS]
+    float *tabs;                // [g][NDOF][TABF_FLOATS]
     double *tabs64;             // [g][NDOF][TAB64_DOUBLES] (FP64 batches) or null
     EstepQmcArgs qa;
     EstepAsmArgs aa;
