@@ -39,17 +39,18 @@ constexpr float INV_LAMBDA_MAX = 511.0f;
 // 16-byte row and takes three FMAs:
 //   rows 0..63   : H(tau) on 64 equal intervals of tau, a cubic in the
 //                  position inside the interval (fraction of 64 tau);
-//   rows 64..151 : log2 tau against lambda on the same 11 octaves of
-//                  lambda + 1/4, each cut into 8 equal parts, a cubic in the
-//                  position inside the part (the low 20 mantissa bits of
-//                  lambda + 1/4, whose exponent and top 3 mantissa bits give
+//   rows 64..135 : log2 tau against lambda on the 9 octaves of lambda + 1 =
+//                  -log2 p in [1, 512), each cut into 8 equal parts, a cubic
+//                  in the position inside the part (the low 20 mantissa bits
+//                  of -log2 p, whose exponent and top 3 mantissa bits give
 //                  the row).
 // A normal-limit slot (dof infinite) holds the dof-free table above in its
 // first TAB_FLOATS floats.
 constexpr int TABF_CDF_ROWS = 64;
+constexpr int TABF_INV_OCTAVES = 9;
 constexpr int TABF_INV_PARTS = 8;
-constexpr int TABF_INV_ROWS = TAB_INV_ROWS * TABF_INV_PARTS;     // 88
-constexpr int TABF_FLOATS = 4 * (TABF_CDF_ROWS + TABF_INV_ROWS);  // 608 floats per dof
+constexpr int TABF_INV_ROWS = TABF_INV_OCTAVES * TABF_INV_PARTS;  // 72
+constexpr int TABF_FLOATS = 4 * (TABF_CDF_ROWS + TABF_INV_ROWS);  // 544 floats per dof
 static_assert(TABF_FLOATS >= TAB_FLOATS, "a fine slot holds a normal-limit table");
 
 // FP64 tables of the univariate t law for one dof (FP64 integrand), the same

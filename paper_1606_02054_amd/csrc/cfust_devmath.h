@@ -333,15 +333,16 @@ __device__ __forceinline__ float tabf_cdf_H(const float *tab, float pos) {
     return tab_cubic(tab + 4 * k, __builtin_amdgcn_fractf(pos));
 }
 
-// log2 tau at l2p = log2 p: zz = lambda + 1/4 clamped to [1/4, INV_LAMBDA_MAX
-// + 1/4] (NaN included) has a biased exponent of 125..135, so its bits >> 20
-// (exponent and top 3 mantissa bits) less 1000 are the row 0..87, and the
-// low 20 mantissa bits the position inside it: as the float 1 + low 2^-23 in
-// [1, 9/8), position = 8 (that - 1), exact.
+// log2 tau at l2p = log2 p.  -l2p = lambda + 1, clamped to [1, 512): l2p is
+// clamped to [-512, -1) (NaN included) instead, whose bits carry the sign bit
+// above the same biased exponent 127..135, so bits >> 20 (sign, exponent and
+// top 3 mantissa bits) less 3064 are the row 0..71, and the low 20 mantissa
+// bits the position inside it: as the float 1 + low 2^-23 in [1, 9/8),
+// position = 8 (that - 1), exact.
 __device__ __forceinline__ float tabf_inv_G(const float *tab, float l2p) {
-    const float zz = fminf(fmaxf(-0.75f - l2p, 0.25f), INV_LAMBDA_MAX + 0.25f);
+    const float zz = fminf(fmaxf(l2p, -511.999969f), -1.0f);
     const uint32_t bits = __float_as_uint(zz);
-    const int row = (int)(bits >> 20) - 1000;
+    const int row = (int)(bits >> 20) - 3064;
     const float t = fmaf(__uint_as_float((bits & 0x000FFFFFu) | 0x3F800000u), 8.0f, -8.0f);
     return tab_cubic(tab + 4 * (TABF_CDF_ROWS + row), t);
 }

@@ -267,7 +267,7 @@ __device__ inline double row_alpha(int row, bool normal) { return row < TAB_CDF_
 __device__ inline double row_beta(int row, bool normal) { return row < TAB_CDF_ROWS && !normal ? -1.0 : -3.0; }
 
 constexpr int TAB_NODES = (TAB_CDF_ROWS + TAB_INV_ROWS) * 7;   // 133
-constexpr int TABF_NODES = (TABF_CDF_ROWS + TABF_INV_ROWS) * 4; // 608
+constexpr int TABF_NODES = (TABF_CDF_ROWS + TABF_INV_ROWS) * 4; // 544
 
 // Row of a fine-layout table (cubic): the Chebyshev fit of the 4 node values
 // at x_n = cos(pi (n + 1/2) / 4) on [-1, 1], stored as monomial coefficients
@@ -344,20 +344,20 @@ __device__ inline double table_node_from64(double nu, const double *h64, int row
 
 // Node n of row `row` of a fine-layout table (finite dof) from the FP64 CDF
 // rows: H in log2 units on 64 equal intervals of tau, and log2 tau of the
-// quantile solved on those rows at lambda + 1/4 = 2^(k-2) (1 + (part + v)/8)
-// in part `part` of octave k.
+// quantile solved on those rows at lambda + 1 = 2^k (1 + (part + v)/8) in
+// part `part` of octave k.
 __device__ inline double tablef_node_from64(double nu, const double *h64, int row, int n) {
     const double v = 0.5 * (cos(M_PI * (n + 0.5) / 4.0) + 1.0);
     if (row < TABF_CDF_ROWS) return tab64_H(h64, (row + v) / (double)TABF_CDF_ROWS) / LN2;
     const int r = row - TABF_CDF_ROWS, k = r / TABF_INV_PARTS, part = r % TABF_INV_PARTS;
-    const double lam = ldexp(1.0 + (part + v) / (double)TABF_INV_PARTS, k - 2) - 0.25;
+    const double lam = ldexp(1.0 + (part + v) / (double)TABF_INV_PARTS, k) - 1.0;
     const double a = 0.5 * nu;
     return tab64_l_solve(h64, -(lam + 1.0) * LN2, a, dm_lbeta_half(a)) / LN2;
 }
 
 // Block `bid` = (component, dof offset) of one parameter set; 192 threads;
 // writes the slot in the fine layout.  Finite dof: the FP64 CDF rows first,
-// then the 152 x 4 nodes from them, one thread per row fitting it; infinite
+// then the 136 x 4 nodes from them, one thread per row fitting it; infinite
 // dof (normal limit): the dof-free closed forms, in the compact layout at the
 // start of the slot, the rest of the slot zero.
 __device__ inline void tables_body(const CompPre *__restrict__ pre, int p, int ndof, float *__restrict__ tabs,
