@@ -37,29 +37,29 @@ PEAK_FP32_TFLOPS = 157.3     # MI355X vector FP32 (chip figure: 2 wave64 FMA iss
 # again (profiles/k_estep_qmc_counters.md).
 TRAFFIC_SOURCES = ["paper_1606_02054_amd/csrc/cfust_sov.h", "paper_1606_02054_amd/csrc/cfust_devmath.h",
                    "paper_1606_02054_amd/csrc/cfust_estep.hip", "paper_1606_02054_amd/csrc/cfust_common.h"]
-KERNEL_DIGEST = "d9e83375ad4a3318"
+KERNEL_DIGEST = "d5ba76a06a9c0fa1"
 # FP32 arithmetic of one lattice point of the m-variate integrand in the FP32
 # lattice kernel: (2 x SQ_INSTS_VALU_FMA_F32 + MUL_F32 + ADD_F32 + TRANS_F32)
 # of a launch divided by the lattice points it evaluates.
-LATTICE_FLOPS_PER_POINT = {2: 53.01, 3: 109.31, 4: 167.33, 5: 227.14, 6: 289.21, 7: 353.2, 8: 419.22}
+LATTICE_FLOPS_PER_POINT = {2: 41.99, 3: 87.3, 4: 134.32, 5: 183.13, 6: 234.19, 7: 287.19, 8: 342.21}
 # VALU issue of each kernel from SQ_INSTS_VALU, SQ_ACTIVE_INST_VALU2 and
 # GRBM_GUI_ACTIVE: wave64 VALU instructions per CU per cycle (the chip issues
 # at most 2: one pair per SIMD per 4-cycle slot) and the share of them issued
 # in pairs.
 LATTICE_VALU_ISSUE = {
-    2: {'valu_per_point': 54.1, 'valu_per_cu_cycle': 1.014, 'dual_issue_frac': 0.560, 'valu_slot_busy': 0.845},
-    3: {'valu_per_point': 106.5, 'valu_per_cu_cycle': 1.159, 'dual_issue_frac': 0.635, 'valu_slot_busy': 0.924},
-    4: {'valu_per_point': 160.6, 'valu_per_cu_cycle': 1.133, 'dual_issue_frac': 0.609, 'valu_slot_busy': 0.916},
-    5: {'valu_per_point': 215.0, 'valu_per_cu_cycle': 1.071, 'dual_issue_frac': 0.565, 'valu_slot_busy': 0.889},
-    6: {'valu_per_point': 272.3, 'valu_per_cu_cycle': 1.212, 'dual_issue_frac': 0.617, 'valu_slot_busy': 0.972},
-    7: {'valu_per_point': 329.4, 'valu_per_cu_cycle': 1.142, 'dual_issue_frac': 0.561, 'valu_slot_busy': 0.947},
-    8: {'valu_per_point': 387.1, 'valu_per_cu_cycle': 1.074, 'dual_issue_frac': 0.532, 'valu_slot_busy': 0.906},
+    2: {'valu_per_point': 47.0, 'valu_per_cu_cycle': 0.855, 'dual_issue_frac': 0.411, 'valu_slot_busy': 0.791},
+    3: {'valu_per_point': 94.5, 'valu_per_cu_cycle': 1.122, 'dual_issue_frac': 0.562, 'valu_slot_busy': 0.951},
+    4: {'valu_per_point': 142.6, 'valu_per_cu_cycle': 1.089, 'dual_issue_frac': 0.520, 'valu_slot_busy': 0.945},
+    5: {'valu_per_point': 191.0, 'valu_per_cu_cycle': 1.034, 'dual_issue_frac': 0.491, 'valu_slot_busy': 0.911},
+    6: {'valu_per_point': 242.3, 'valu_per_cu_cycle': 1.142, 'dual_issue_frac': 0.538, 'valu_slot_busy': 0.977},
+    7: {'valu_per_point': 293.4, 'valu_per_cu_cycle': 1.078, 'dual_issue_frac': 0.482, 'valu_slot_busy': 0.951},
+    8: {'valu_per_point': 345.1, 'valu_per_cu_cycle': 1.010, 'dual_issue_frac': 0.463, 'valu_slot_busy': 0.899},
 }
 # HBM bytes per launch of the FP32 lattice kernel of each dimension at the
 # default workload (MiB read, MiB written: FETCH_SIZE x 2 and WRITE_SIZE x 1 in
 # KiB, the factors that a 1 GiB device copy gives these counters).
-TRAFFIC_MIB = {4: (2 * 10714.2 / 1024, 7709.1 / 1024), 3: (2 * 4474.5 / 1024, 5939.9 / 1024),
-               2: (2 * 3454.5 / 1024, 7731.5 / 1024)}
+TRAFFIC_MIB = {4: (2 * 10744.8 / 1024, 7527.4 / 1024), 3: (2 * 4524.5 / 1024, 6044.8 / 1024),
+               2: (2 * 3488.5 / 1024, 7774.1 / 1024)}
 
 
 def kernel_digest() -> str:
