@@ -254,6 +254,12 @@ __device__ __forceinline__ void point32(uint32_t t, float &x, float &xb) {
     xb = tent_units(t ^ 0x80000000u) * 4.656612873077393e-10f;
 }
 
+// The quantile steps below carry the conditional scale Q = sqrt(nu + sum y^2)
+// and cap it at 1e15: a point whose tau = 2^G underflows (G far below -100,
+// where 1/sqrt(tau (2 - tau)) exceeds 2^49, so Q, at least sqrt(nu) >= 1.26
+// for dof >= 1.6, passes the cap anyway) draws y = +-1e15, its quantile at
+// the cap, with no clamp on G.
+//
 // Quantile step of coordinate 0 (the truncation probability e_0 is the same
 // for every point).  LOW0: e_0 is a lower-tail probability that may be far
 // below the FP32 range, so p = x e_0 <= 1/2 is taken in the log domain,
@@ -299,8 +305,7 @@ __device__ __forceinline__ float quantile_step32_first_u(const Sov32Setup &P, fl
         lower = p <= 0.5f;
         l2q = flog2(lower ? p : pb);
     }
-    const float G = fmaxf(tab_G<FINE>(tab, l2q), -100.0f);
-    const float tq = fexp2(G);
+    const float tq = fexp2(tab_G<FINE>(tab, l2q));
     const float sabs = 1.0f - tq;
     Q = fminf(Q * frsq(tq * (2.0f - tq)), 1e15f);
     return (lower ? -sabs : sabs) * Q;
@@ -323,8 +328,7 @@ __device__ __forceinline__ float quantile_step32(float x, float xb, float e, flo
     const float p = x * e;
     const float pb = fmaf(xb, e, small);
     const bool lower = p <= 0.5f;
-    const float G = fmaxf(tab_G<FINE>(tab, flog2(lower ? p : pb)), -100.0f);
-    const float tq = fexp2(G);
+    const float tq = fexp2(tab_G<FINE>(tab, flog2(lower ? p : pb)));
     const float sabs = 1.0f - tq;
     Q = fminf(Q * frsq(tq * (2.0f - tq)), 1e15f);
     return (lower ? -sabs : sabs) * Q;
