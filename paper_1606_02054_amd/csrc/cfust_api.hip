@@ -30,6 +30,10 @@ struct EstepWs {
     int coordC;
 };
 
+// Items of mvt_cdf_batch whose FP32 tables are built and used per launch pair
+// (mixed precision): 16384 items hold at most 16384 x 8 x 2176 B = 285 MB.
+constexpr int MVT_CHUNK = 16384;
+
 int coord_count(const cfust_dims &d, const cfust_qmc *Q) {
     return d.n == 0 ? 0 : lattice_coord_count(d.q, Q);
 }
@@ -387,15 +391,33 @@ cfust_status mvt_cdf_batch(cfust_handle h, int32_t m, int32_t batch, const doubl
     if (batch > 0 && (!b || !L || !mat_idx || !nu || !p))
         return fail(h, CFUST_EINVAL, "an mvt_cdf_batch array is NULL");
     const bool mixed = qmc->precision == CFUST_MIXED;
-    if ((st = ensure_ws(h, align256((size_t)(batch > 0 ? batch : 1) * sizeof(int32_t)))) != CFUST_OK) return st;
+    // workspace: flags [batch]; mixed (m >= 2): the tables of a chunk of items,
+    // the normal table, the lattice coordinates
+    Carve c;
+    const size_t o_flag = c.take<int32_t>(batch > 0 ? batch : 1);
+    MvtWork w;
+    size_t o_tabs = 0, o_ntab = 0, o_coords = 0;
+    if (mixed && m >= 2) {
+        w.chunk = batch < MVT_CHUNK ? (batch > 0 ? batch : 1) : MVT_CHUNK;
+        w.C = lattice_coord_count(m, qmc);
+        o_tabs = c.take<float>((size_t)w.chunk * m * TABF_FLOATS);
+        o_ntab = c.take<float>(TABF_FLOATS);
+        o_coords = c.take<float>(w.C > 0 ? lattice_coords_floats(qmc->N, qmc->S, w.C) : 1);
+    }
+    if ((st = ensure_ws(h, c.off)) != CFUST_OK) return st;
     if ((st = hip_check(h, hipSetDevice(h->device), "hipSetDevice")) != CFUST_OK) return st;
+    if (mixed && m >= 2) {
+        w.tabs = at<float>(h, o_tabs);
+        w.ntab = at<float>(h, o_ntab);
+        w.coords = at<float>(h, o_coords);
+    }
     MvtArgs a;
     a.m = m; a.batch = batch; a.mixed = mixed ? 1 : 0; a.nmat = nmat;
     a.b = b; a.L = L; a.nu = nu; a.mat_idx = mat_idx;
     a.lat = lattice_of(qmc);
     a.p = p; a.logp = logp; a.se = stderr_;
-    a.flag = at<int32_t>(h, 0);
-    return hip_check(h, launch_mvt(a, (hipStream_t)stream), "mvt_cdf_batch launch");
+    a.flag = at<int32_t>(h, o_flag);
+    return hip_check(h, launch_mvt(a, w, (hipStream_t)stream), "mvt_cdf_batch launch");
 }
 
 cfust_status cfust_autotune(cfust_handle h, const double *y, cfust_dims d, const cfust_params *P,

@@ -17,24 +17,22 @@ constexpr int MAXPAIR = MAXQ * (MAXQ - 1) / 2;
 constexpr int MAXJ = 2 + MAXQ + MAXPAIR;          // integrals per (obs, comp)
 constexpr int NDOF = MAXQ + 2;                    // dofs nu+p .. nu+p+q+1 per component
 
-// FP32 piecewise-polynomial tables of the univariate t law for one dof, in the
-// compact layout (the per-item tables of the batched T_m kernel, and the
-// dof-free normal-limit table):
-//   rows 0..7  : lower-tail CDF, H(tau) = log2 T_lower(tau) - a log2(tau (2 - tau))
-//                (a = nu/2) on 8 equal intervals of tau = 1 - |s| in [0,1],
-//                s = u / sqrt(nu+u^2);
-//   rows 8..18 : quantile, log2 tau as a function of lambda = -log2(2p) on the
-//                11 intervals [c(2^k - 1), c(2^{k+1} - 1)], c = 1/4.
-// Each row holds 7 monomial coefficients in the lookup's variable -- the
-// position inside the interval (fraction of 8 tau) for the CDF rows, the float
-// mantissa in [1/2, 1) for the geometric rows -- plus one pad float.
+// The dof-free FP32 table of the normal limit (compact layout: rows of 7
+// monomial coefficients plus one pad float):
+//   rows 0..7  : log2 Phi(-v) on the 8 intervals [c(2^k - 1), c(2^{k+1} - 1)]
+//                of v, c = 1/4;
+//   rows 8..18 : Phi^-1(2^-(lam+1)) on the 11 intervals of lambda of the same
+//                form, lambda = -log2(2p);
+// each row a polynomial in the float mantissa in [1/2, 1) of v + 1/4 (resp.
+// lambda + 1/4).
 constexpr int TAB_CDF_ROWS = 8;
 constexpr int TAB_INV_ROWS = 11;
 constexpr int TAB_ROWS = 20;                      // 8 + 11 + 1 pad row
 constexpr int TAB_FLOATS = TAB_ROWS * 8;          // 160 floats per dof
 constexpr float INV_LAMBDA_MAX = 511.0f;
 
-// The E-step's FP32 tables of the t law ("fine" layout, one slot per dof), the
+// The FP32 tables of the t law ("fine" layout, one slot per dof; the E-step and
+// the batched T_m kernels), the
 // same two functions on narrower intervals, degree 3, so a lookup reads one
 // 16-byte row and takes three FMAs:
 //   rows 0..63   : H(tau) on 64 equal intervals of tau, a cubic in the

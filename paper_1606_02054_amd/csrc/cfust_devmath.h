@@ -300,16 +300,6 @@ __device__ __forceinline__ float tab_poly(const float *row, float x) {
     return r;
 }
 
-// H(tau) = log2 T_lower - (nu/2) log2(tau (2 - tau)) from the CDF rows of one
-// dof's table, at pos = 8 tau in [0, 8) (8 equal intervals of tau = 1 - |s|).
-// Anything outside, NaN included, is clamped into the table so the index
-// stays in range; the rows are polynomials in the fraction of pos.
-__device__ __forceinline__ float tab_cdf_H(const float *tab, float pos) {
-    pos = fminf(fmaxf(pos, 0.0f), 7.99999952f);
-    const int k = (int)pos;
-    return tab_poly(tab + 8 * k, __builtin_amdgcn_fractf(pos));
-}
-
 // Normal limit: log2 Phi(-v), v >= 0, from the CDF rows of the dof-free
 // normal table (geometric intervals of v + 1/4; v is clamped to 63.5, where
 // the probability is far below any that matters).

@@ -203,38 +203,22 @@ __global__ void k_status_fold(const CompPre *__restrict__ pre, int g, int32_t *_
 
 // --------------------------------------------------------------- tables ----
 
-// One block per (component, dof offset): 19 rows x 7 nodes evaluated in
-// parallel, then one thread per row fits and writes the row.
-__device__ inline double table_node_value(double nu, int row, int n) {
+// Node n of row `row` of the dof-free normal table (compact layout, 7 nodes
+// per row): CDF rows hold log2 Phi(-v) on geometric intervals of v + 1/4,
+// quantile rows Phi^-1(2^-(lam+1)) on those of lam + 1/4.
+__device__ inline double normal_node_value(int row, int n) {
     const double x = cos(M_PI * (n + 0.5) / 7.0);
-    if (isinf(nu)) {
-        // normal limit (dof-free): CDF rows hold log2 Phi(-v) on geometric
-        // intervals of v + 1/4, quantile rows Phi^-1(2^-(lam+1)) on those of
-        // lam + 1/4 (the same interval layout as the t quantile rows)
-        const int k = row < TAB_CDF_ROWS ? row : row - TAB_CDF_ROWS;
-        const double w = 0.25 * (double)(1 << k);
-        const double v = w - 0.25 + w * 0.5 * (x + 1.0);
-        return row < TAB_CDF_ROWS ? dm_lnPhi_lower(-v) / LN2 : dm_ninv_lower(-(v + 1.0) * LN2);
-    }
-    const double a = 0.5 * nu, lb = dm_lbeta_half(a);
-    if (row < TAB_CDF_ROWS) {
-        const double tau = (row + 0.5 * (x + 1.0)) / 8.0;
-        const double s = 1.0 - tau;
-        const double lt = dm_lnT_lower(tau * (2.0 - tau), s * s, a, lb);
-        return lt / LN2 - a * log2(tau * (2.0 - tau));
-    }
-    const int k = row - TAB_CDF_ROWS;
+    const int k = row < TAB_CDF_ROWS ? row : row - TAB_CDF_ROWS;
     const double w = 0.25 * (double)(1 << k);
-    const double lam = w - 0.25 + w * 0.5 * (x + 1.0);
-    return log2(dm_tau_of_lnq(-(lam + 1.0) * LN2, a, lb));
+    const double v = w - 0.25 + w * 0.5 * (x + 1.0);
+    return row < TAB_CDF_ROWS ? dm_lnPhi_lower(-v) / LN2 : dm_ninv_lower(-(v + 1.0) * LN2);
 }
 
-// Row of an FP32 table: the Chebyshev fit of the 7 node values on x in
-// [-1, 1], stored as monomial coefficients in the lookup's own variable v,
-// x = alpha v + beta (v = the fraction of the position for the equal-width
-// CDF rows of the t tables, alpha = 2, beta = -1; v = the float mantissa in
-// [1/2, 1) for the geometric rows, alpha = 4, beta = -3), so a lookup
-// evaluates the polynomial at v directly.
+// Row of the compact normal table: the Chebyshev fit of the 7 node values on
+// x in [-1, 1], stored as monomial coefficients in the lookup's own variable
+// v, x = alpha v + beta (v = the float mantissa in [1/2, 1) of the geometric
+// rows, alpha = 4, beta = -3), so a lookup evaluates the polynomial at v
+// directly.
 // cos7: the 7 x 7 cosines cos(pi j (n + 1/2) / 7) at [j][n], or null to compute them here.
 __device__ inline void table_fit_row(const double *f, float *dst, double alpha, double beta,
                                      const double *cos7 = nullptr) {
@@ -260,11 +244,6 @@ __device__ inline void table_fit_row(const double *f, float *dst, double alpha, 
     for (int i = 0; i < 7; ++i) dst[i] = (float)r[i];
     dst[7] = 0.0f;
 }
-
-// Variable of row `row` (see table_fit_row): the t tables' CDF rows are
-// equal intervals of tau, every other row geometric.
-__device__ inline double row_alpha(int row, bool normal) { return row < TAB_CDF_ROWS && !normal ? 2.0 : 4.0; }
-__device__ inline double row_beta(int row, bool normal) { return row < TAB_CDF_ROWS && !normal ? -1.0 : -3.0; }
 
 constexpr int TAB_NODES = (TAB_CDF_ROWS + TAB_INV_ROWS) * 7;   // 133
 constexpr int TABF_NODES = (TABF_CDF_ROWS + TABF_INV_ROWS) * 4; // 544
@@ -331,17 +310,6 @@ __device__ inline void build_cdf64(double nu, double *fv, double *h64, const dou
     __syncthreads();
 }
 
-// Node of the FP32 tables (finite dof) from the FP64 CDF rows: H in log2
-// units, and log2 tau of the quantile solved on those rows.
-__device__ inline double table_node_from64(double nu, const double *h64, int row, int n) {
-    const double x = cos(M_PI * (n + 0.5) / 7.0);
-    const double a = 0.5 * nu;
-    if (row < TAB_CDF_ROWS) return tab64_H(h64, (row + 0.5 * (x + 1.0)) / 8.0) / LN2;
-    const double w = 0.25 * (double)(1 << (row - TAB_CDF_ROWS));
-    const double lam = w - 0.25 + w * 0.5 * (x + 1.0);
-    return tab64_l_solve(h64, -(lam + 1.0) * LN2, a, dm_lbeta_half(a)) / LN2;
-}
-
 // Node n of row `row` of a fine-layout table (finite dof) from the FP64 CDF
 // rows: H in log2 units on 64 equal intervals of tau, and log2 tau of the
 // quantile solved on those rows at lambda + 1 = 2^k (1 + (part + v)/8) in
@@ -355,26 +323,21 @@ __device__ inline double tablef_node_from64(double nu, const double *h64, int ro
     return tab64_l_solve(h64, -(lam + 1.0) * LN2, a, dm_lbeta_half(a)) / LN2;
 }
 
-// Block `bid` = (component, dof offset) of one parameter set; 192 threads;
-// writes the slot in the fine layout.  Finite dof: the FP64 CDF rows first,
-// then the 136 x 4 nodes from them, one thread per row fitting it; infinite
-// dof (normal limit): the dof-free closed forms, in the compact layout at the
-// start of the slot, the rest of the slot zero.
-__device__ inline void tables_body(const CompPre *__restrict__ pre, int p, int ndof, float *__restrict__ tabs,
-                                   int bid) {
-    const int h = bid / ndof, off = bid % ndof;
-    const double nu = pre[h].nu + p + off;
+// One table slot (fine layout) of dof nu, written by a block of 192 threads.
+// Finite dof: the FP64 CDF rows first, then the 136 x 4 nodes from them, one
+// thread per row fitting it; infinite dof (normal limit): the dof-free closed
+// forms, in the compact layout at the start of the slot, the rest of the slot
+// zero.  Every thread of the block takes part.
+__device__ inline void table_slot_body(double nu, float *__restrict__ dst) {
     __shared__ double fv[TABF_NODES];
     __shared__ double fv64[TAB64_CDF_ROWS * TAB64_NC], h64[TAB64_CDF_ROWS * TAB64_NC];
     __shared__ double cos64[TAB64_NC * TAB64_NC], cos7[49], cos4[16];
     const int t = threadIdx.x;
     fit_cosines(cos64, cos7, cos4);
-    float *dst = tabs + ((size_t)h * NDOF + off) * TABF_FLOATS;
     if (isinf(nu)) {
-        if (t < TAB_NODES) fv[t] = table_node_value(nu, t / 7, t % 7);
+        if (t < TAB_NODES) fv[t] = normal_node_value(t / 7, t % 7);
         __syncthreads();
-        if (t < TAB_CDF_ROWS + TAB_INV_ROWS)
-            table_fit_row(fv + 7 * t, dst + 8 * t, row_alpha(t, true), row_beta(t, true), cos7);
+        if (t < TAB_CDF_ROWS + TAB_INV_ROWS) table_fit_row(fv + 7 * t, dst + 8 * t, 4.0, -3.0, cos7);
         for (int u = 8 * (TAB_CDF_ROWS + TAB_INV_ROWS) + t; u < TABF_FLOATS; u += blockDim.x) dst[u] = 0.0f;
     } else {
         build_cdf64(nu, fv64, h64, cos64);
@@ -382,6 +345,13 @@ __device__ inline void tables_body(const CompPre *__restrict__ pre, int p, int n
         __syncthreads();
         if (t < TABF_CDF_ROWS + TABF_INV_ROWS) table_fit_row4(fv + 4 * t, dst + 4 * t, cos4);
     }
+}
+
+// Block `bid` = (component, dof offset) of one parameter set.
+__device__ inline void tables_body(const CompPre *__restrict__ pre, int p, int ndof, float *__restrict__ tabs,
+                                   int bid) {
+    const int h = bid / ndof, off = bid % ndof;
+    table_slot_body(pre[h].nu + p + off, tabs + ((size_t)h * NDOF + off) * TABF_FLOATS);
 }
 
 __global__ __launch_bounds__(192) void k_tables(const CompPre *__restrict__ pre, int p, int ndof,
@@ -568,8 +538,8 @@ __device__ inline bool qmc_item(const EstepQmcArgs &a, int h, int idx, int j, co
     if (w->H.e0 > 0.0 || w->H.lne0 > -INFINITY) {
         if (MIXED) {
             const bool ok = normal ? sov_mixed_normal<M, PPL>(w->H, w->b, w->L, a.lat, tab, smean, lane)
-                                   : sov_mixed<M, PPL, COORDS, true>(w->H, w->b, w->L, w->nu0, a.lat, tab, smean,
-                                                                     lane, a.coords, a.coordC);
+                                   : sov_mixed<M, PPL, COORDS>(w->H, w->b, w->L, w->nu0, a.lat, tab, smean, lane,
+                                                               a.coords, a.coordC);
             if (!ok) return false;
         } else if (T64) {
             sov_fp64_tab<M>(w->H, w->b, w->L, w->nu0, a.lat, tab64, smean, lane);
@@ -855,13 +825,88 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double *__restrict__
 
 // ------------------------------------------------------------ mvt batch ----
 
-// One wave per item.  MIXED: the wave first builds, in its own LDS slice, the
-// FP32 tables of the dofs nu .. nu+M-1 it needs; FP32 underflow is flagged for
-// the FP64 pass (FLAGGED_ONLY).
-template <int M, bool MIXED, bool FLAGGED_ONLY>
+// Mixed precision, in two kernels: the FP32 tables of every item of a chunk
+// (k_mvt_tables, one block per item and dof, into global memory; the
+// dof-free normal table once per call), then the lattice sums (k_mvt_qmc,
+// one wave per item, reading its tables from LDS) -- the table build and
+// its FP64 registers stay out of the integrand's kernel.
+
+// Block (local item, dof offset d) of the chunk starting at item it0.  Items
+// with an infinite dof use the shared normal slot and build nothing.
+__global__ __launch_bounds__(192) void k_mvt_tables(MvtArgs a, int it0, int M, float *__restrict__ tabs) {
+    const int local = blockIdx.x / M, d = blockIdx.x % M;
+    const double nu = a.nu[it0 + local];
+    if (isinf(nu)) return;
+    table_slot_body(nu + d, tabs + ((size_t)local * M + d) * TABF_FLOATS);
+}
+
+// The dof-free normal table (one block).
+__global__ __launch_bounds__(192) void k_mvt_normal_table(float *__restrict__ slot) {
+    table_slot_body(INFINITY, slot);
+}
+
+// The item's limits and Cholesky factor, staged in the wave's LDS slot; the
+// first SOV factor from the FP32 table (finite dof) or in FP64 (normal
+// limit).  Out of line for the same reason as item_head.
+__device__ __attribute__((noinline)) void mvt_item_head(const MvtArgs &a, int it, int mi, int M, double *b, double *L,
+                                                        double nu, const float *tab, SovHead *H) {
+    for (int i = 0; i < M; ++i) b[i] = a.b[(size_t)it * M + i];
+    for (int i = 0; i < M * M; ++i) L[i] = a.L[(size_t)mi * M * M + i];
+    *H = isinf(nu) ? sov_head(b, L, nu) : sov_head_tab(b, L, nu, tab);
+}
+
+// One wave per item of the chunk (blocks of 64 threads).  Writes the item's
+// flag: 1 when the FP32 product underflowed (the FP64 pass redoes it), else 0.
+template <int M>
+__global__ __launch_bounds__(64) void k_mvt_qmc(MvtArgs a, int it0, const float *__restrict__ tabs,
+                                                const float *__restrict__ ntab, const float *__restrict__ coords, int C) {
+    __shared__ __align__(16) float tab[M * TABF_FLOATS];
+    __shared__ double smean[MAXS];
+    __shared__ double bs[M], Ls[M * M];
+    __shared__ SovHead Hs;
+    const int lane = threadIdx.x;
+    const int it = it0 + blockIdx.x;
+    const int mi = a.mat_idx[it];
+    if (mi < 0 || mi >= a.nmat) {   // invalid matrix index: NaN result, no access
+        if (lane == 0) {
+            a.p[it] = NAN; if (a.logp) a.logp[it] = NAN; if (a.se) a.se[it] = NAN;
+            a.flag[it] = 0;
+        }
+        return;
+    }
+    const double nu = a.nu[it];
+    const bool normal = isinf(nu);
+    const float4 *src = reinterpret_cast<const float4 *>(normal ? ntab : tabs + (size_t)blockIdx.x * M * TABF_FLOATS);
+    float4 *dst = reinterpret_cast<float4 *>(tab);
+    for (int t = lane; t < (normal ? TABF_FLOATS : M * TABF_FLOATS) / 4; t += 64) dst[t] = src[t];
+    __syncthreads();
+    if (lane == 0) mvt_item_head(a, it, mi, M, bs, Ls, nu, tab, &Hs);
+    __syncthreads();
+    const SovHead H = Hs;
+    double est = 0.0, se = 0.0, lnest = -INFINITY;
+    if (H.e0 > 0.0 || H.lne0 > -INFINITY) {
+        bool ok;
+        if (normal) ok = sov_mixed_normal<M, 1>(H, bs, Ls, a.lat, tab, smean, lane);
+        else if (coords) ok = sov_mixed<M, 1, true>(H, bs, Ls, nu, a.lat, tab, smean, lane, coords, C);
+        else ok = sov_mixed<M, 1, false>(H, bs, Ls, nu, a.lat, tab, smean, lane);
+        if (!ok) {
+            if (lane == 0) a.flag[it] = 1;
+            return;
+        }
+        sov_finish(H, smean, a.lat.S, &est, &se, &lnest);
+    }
+    if (lane == 0) {
+        a.p[it] = est;
+        if (a.logp) a.logp[it] = lnest;
+        if (a.se) a.se[it] = se;
+        a.flag[it] = 0;
+    }
+}
+
+// FP64 integrand, one wave per item: FP64 mode, and (FLAGGED_ONLY) the items
+// whose FP32 product underflowed in k_mvt_qmc.
+template <int M, bool FLAGGED_ONLY>
 __global__ __launch_bounds__(256) void k_mvt(MvtArgs a) {
-    __shared__ __align__(16) float tab[4][MIXED ? M * TAB_FLOATS : 4];
-    __shared__ double fv[4][MIXED ? TAB_NODES : 1];
     __shared__ double smean[4][MAXS];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int it = blockIdx.x * 4 + wave;
@@ -881,41 +926,7 @@ __global__ __launch_bounds__(256) void k_mvt(MvtArgs a) {
     const SovHead H = sov_head(b, L, nu);
     double est = 0.0, se = 0.0, lnest = -INFINITY;
     if (H.e0 > 0.0 || H.lne0 > -INFINITY) {
-        if (MIXED && isinf(nu)) {
-            // the normal tables are dof-free: one slot serves every coordinate
-            for (int t = lane; t < TAB_NODES; t += 64) fv[wave][t] = table_node_value(nu, t / 7, t % 7);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            if (lane < TAB_CDF_ROWS + TAB_INV_ROWS)
-                table_fit_row(fv[wave] + 7 * lane, tab[wave] + 8 * lane, row_alpha(lane, true), row_beta(lane, true));
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const bool ok = (a.lat.N % 128 == 0) ? sov_mixed_normal<M, 2>(H, b, L, a.lat, tab[wave], smean[wave], lane)
-                                                 : sov_mixed_normal<M, 1>(H, b, L, a.lat, tab[wave], smean[wave], lane);
-            if (lane == 0) a.flag[it] = ok ? 0 : 1;
-            if (!ok) return;
-        } else if (MIXED) {
-            for (int dof = 0; dof < M; ++dof) {
-                for (int t = lane; t < TAB_NODES; t += 64) fv[wave][t] = table_node_value(nu + dof, t / 7, t % 7);
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                if (lane < TAB_CDF_ROWS + TAB_INV_ROWS)
-                    table_fit_row(fv[wave] + 7 * lane, tab[wave] + dof * TAB_FLOATS + 8 * lane, row_alpha(lane, false),
-                                  row_beta(lane, false));
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            }
-            const bool ok = (a.lat.N % 128 == 0) ? sov_mixed<M, 2>(H, b, L, nu, a.lat, tab[wave], smean[wave], lane)
-                                                 : sov_mixed<M, 1>(H, b, L, nu, a.lat, tab[wave], smean[wave], lane);
-            if (lane == 0) a.flag[it] = ok ? 0 : 1;
-            if (!ok) return;
-        } else {
-            sov_fp64<M>(H, b, L, nu, a.lat, smean[wave], lane);
-        }
+        sov_fp64<M>(H, b, L, nu, a.lat, smean[wave], lane);
         sov_finish(H, smean[wave], a.lat.S, &est, &se, &lnest);
     }
     if (lane == 0) {
@@ -1206,30 +1217,42 @@ hipError_t launch_lse(const EstepLseArgs &a, double *loglik, hipStream_t s) {
 }
 
 template <int M>
-static void launch_mvt_m(const MvtArgs &a, hipStream_t s) {
+static hipError_t launch_mvt_m(const MvtArgs &a, const MvtWork &w, hipStream_t s) {
     dim3 grid((a.batch + 3) / 4);
-    if (a.mixed) {
-        hipLaunchKernelGGL((k_mvt<M, true, false>), grid, dim3(256), 0, s, a);
-        hipLaunchKernelGGL((k_mvt<M, false, true>), grid, dim3(256), 0, s, a);
-    } else {
-        hipLaunchKernelGGL((k_mvt<M, false, false>), grid, dim3(256), 0, s, a);
+    if (!a.mixed) {
+        hipLaunchKernelGGL((k_mvt<M, false>), grid, dim3(256), 0, s, a);
+        return hipGetLastError();
     }
+    hipError_t e = hipSuccess;
+    if (w.C > 0) e = launch_lattice_coords(a.lat, w.C, w.coords, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_mvt_normal_table, dim3(1), dim3(192), 0, s, w.ntab);
+        e = hipGetLastError();
+    }
+    for (int it0 = 0; it0 < a.batch && e == hipSuccess; it0 += w.chunk) {
+        const int cnt = a.batch - it0 < w.chunk ? a.batch - it0 : w.chunk;
+        hipLaunchKernelGGL(k_mvt_tables, dim3(cnt * M), dim3(192), 0, s, a, it0, M, w.tabs);
+        hipLaunchKernelGGL((k_mvt_qmc<M>), dim3(cnt), dim3(64), 0, s, a, it0, (const float *)w.tabs,
+                           (const float *)w.ntab, (const float *)(w.C > 0 ? w.coords : nullptr), w.C);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) hipLaunchKernelGGL((k_mvt<M, true>), grid, dim3(256), 0, s, a);
+    return e == hipSuccess ? hipGetLastError() : e;
 }
 
-hipError_t launch_mvt(const MvtArgs &a, hipStream_t s) {
+hipError_t launch_mvt(const MvtArgs &a, const MvtWork &w, hipStream_t s) {
     if (a.batch == 0) return hipSuccess;
     switch (a.m) {
-    case 1: hipLaunchKernelGGL(k_mvt1, dim3((a.batch + 255) / 256), dim3(256), 0, s, a); break;
-    case 2: launch_mvt_m<2>(a, s); break;
-    case 3: launch_mvt_m<3>(a, s); break;
-    case 4: launch_mvt_m<4>(a, s); break;
-    case 5: launch_mvt_m<5>(a, s); break;
-    case 6: launch_mvt_m<6>(a, s); break;
-    case 7: launch_mvt_m<7>(a, s); break;
-    case 8: launch_mvt_m<8>(a, s); break;
+    case 1: hipLaunchKernelGGL(k_mvt1, dim3((a.batch + 255) / 256), dim3(256), 0, s, a); return hipGetLastError();
+    case 2: return launch_mvt_m<2>(a, w, s);
+    case 3: return launch_mvt_m<3>(a, w, s);
+    case 4: return launch_mvt_m<4>(a, w, s);
+    case 5: return launch_mvt_m<5>(a, w, s);
+    case 6: return launch_mvt_m<6>(a, w, s);
+    case 7: return launch_mvt_m<7>(a, w, s);
+    case 8: return launch_mvt_m<8>(a, w, s);
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 // ------------------------------------------------------------ batches ----

@@ -274,24 +274,17 @@ struct Sov32Setup {
     bool low0;
 };
 
-// The FP32 t-law lookups in either table layout: FINE, the E-step's slots
-// (TABF_FLOATS per dof, cubic rows); otherwise the compact slots (TAB_FLOATS
-// per dof, degree-6 rows) that the batched T_m kernel builds per item.
-template <bool FINE>
-__device__ __forceinline__ float tab_G(const float *tab, float l2p) {
-    return FINE ? tabf_inv_G(tab, l2p) : tab_inv_G(tab, l2p);
-}
-// log2 T_lower less a log2(tau (2 - tau)) at tau = 1 - |s|, given |s|.
-template <bool FINE>
+// The FP32 t-law lookups of the fine-layout slots (TABF_FLOATS per dof):
+// log2 tau of the quantile, and log2 T_lower less a log2(tau (2 - tau)) at
+// tau = 1 - |s|, given |s|.
+__device__ __forceinline__ float tab_G(const float *tab, float l2p) { return tabf_inv_G(tab, l2p); }
 __device__ __forceinline__ float tab_H_abs_s(const float *tab, float abs_s) {
-    return FINE ? tabf_cdf_H(tab, fmaf(-64.0f, abs_s, 64.0f)) : tab_cdf_H(tab, fmaf(-8.0f, abs_s, 8.0f));
+    return tabf_cdf_H(tab, fmaf(-64.0f, abs_s, 64.0f));
 }
-template <bool FINE>
-constexpr int tab_stride() { return FINE ? TABF_FLOATS : TAB_FLOATS; }
 
 // xu, xbu: the coordinate and its complement in units of 2^-31 (xbu unused
 // when LOW0).
-template <bool LOW0, bool FINE>
+template <bool LOW0>
 __device__ __forceinline__ float quantile_step32_first_u(const Sov32Setup &P, float xu, float xbu, const float *tab,
                                                          float &Q) {
     bool lower;
@@ -305,15 +298,15 @@ __device__ __forceinline__ float quantile_step32_first_u(const Sov32Setup &P, fl
         lower = p <= 0.5f;
         l2q = flog2(lower ? p : pb);
     }
-    const float tq = fexp2(tab_G<FINE>(tab, l2q));
+    const float tq = fexp2(tab_G(tab, l2q));
     const float sabs = 1.0f - tq;
     Q = fminf(Q * frsq(tq * (2.0f - tq)), 1e15f);
     return (lower ? -sabs : sabs) * Q;
 }
 
-template <bool LOW0, bool FINE>
+template <bool LOW0>
 __device__ __forceinline__ float quantile_step32_first(const Sov32Setup &P, uint32_t t, const float *tab, float &Q) {
-    return quantile_step32_first_u<LOW0, FINE>(P, tent_units(t), LOW0 ? 0.0f : tent_units(t ^ 0x80000000u), tab, Q);
+    return quantile_step32_first_u<LOW0>(P, tent_units(t), LOW0 ? 0.0f : tent_units(t ^ 0x80000000u), tab, Q);
 }
 
 // Quantile step of coordinate i >= 1, given the lower-tail value small =
@@ -322,24 +315,23 @@ __device__ __forceinline__ float quantile_step32_first(const Sov32Setup &P, uint
 // directly: a point whose factor e is below the FP32 range contributes 0 to
 // the product, whatever it draws.  When !lowt the complement is
 // 1 - x e = (1 - x) e + small.
-template <bool FINE>
 __device__ __forceinline__ float quantile_step32(float x, float xb, float e, float small, const float *tab,
                                                  float &Q) {
     const float p = x * e;
     const float pb = fmaf(xb, e, small);
     const bool lower = p <= 0.5f;
-    const float tq = fexp2(tab_G<FINE>(tab, flog2(lower ? p : pb)));
+    const float tq = fexp2(tab_G(tab, flog2(lower ? p : pb)));
     const float sabs = 1.0f - tq;
     Q = fminf(Q * frsq(tq * (2.0f - tq)), 1e15f);
     return (lower ? -sabs : sabs) * Q;
 }
 
 // Integrand value of lattice point k (FP32), product e_1 ... e_{M-1}.
-template <int M, bool LOW0, bool FINE>
+template <int M, bool LOW0>
 __device__ __forceinline__ float sov_point32(const Sov32Setup &P, const float *tabs, const uint32_t *t) {
     float y[M];
     float Q = P.sqrtnu;
-    y[0] = quantile_step32_first<LOW0, FINE>(P, t[0], tabs, Q);
+    y[0] = quantile_step32_first<LOW0>(P, t[0], tabs, Q);
     float f = 1.0f;
 #pragma unroll
     for (int i = 1; i < M; ++i) {
@@ -352,15 +344,15 @@ __device__ __forceinline__ float sov_point32(const Sov32Setup &P, const float *t
         const float K = LQ * LQ;
         const float R = frsq(fmaf(num, num, K));
         const float KR2 = K * R * R;
-        const float *tab = tabs + i * tab_stride<FINE>();
-        const float l2 = fmaf(P.a[i], flog2(KR2), tab_H_abs_s<FINE>(tab, fabsf(num) * R));
+        const float *tab = tabs + i * TABF_FLOATS;
+        const float l2 = fmaf(P.a[i], flog2(KR2), tab_H_abs_s(tab, fabsf(num) * R));
         const float small = fexp2(l2);
         const float e = num <= 0.0f ? small : 1.0f - small;
         f *= e;
         if (i < M - 1) {
             float x, xb;
             point32(t[i], x, xb);
-            y[i] = quantile_step32<FINE>(x, xb, e, small, tab, Q);
+            y[i] = quantile_step32(x, xb, e, small, tab, Q);
         }
     }
     return f;
@@ -374,7 +366,7 @@ template <int M, bool LOW0>
 __device__ __forceinline__ float sov_point32_c(const Sov32Setup &P, const float *tabs, const float *c) {
     float y[M];
     float Q = P.sqrtnu;
-    y[0] = quantile_step32_first_u<LOW0, true>(P, c[0], c[1], tabs, Q);
+    y[0] = quantile_step32_first_u<LOW0>(P, c[0], c[1], tabs, Q);
     float f = 1.0f;
 #pragma unroll
     for (int i = 1; i < M; ++i) {
@@ -386,11 +378,11 @@ __device__ __forceinline__ float sov_point32_c(const Sov32Setup &P, const float 
         const float R = frsq(fmaf(num, num, K));
         const float KR2 = K * R * R;
         const float *tab = tabs + i * TABF_FLOATS;
-        const float l2 = fmaf(P.a[i], flog2(KR2), tab_H_abs_s<true>(tab, fabsf(num) * R));
+        const float l2 = fmaf(P.a[i], flog2(KR2), tab_H_abs_s(tab, fabsf(num) * R));
         const float small = fexp2(l2);
         const float e = num <= 0.0f ? small : 1.0f - small;
         f *= e;
-        if (i < M - 1) y[i] = quantile_step32<true>(c[2 * i], c[2 * i + 1], e, small, tab, Q);
+        if (i < M - 1) y[i] = quantile_step32(c[2 * i], c[2 * i + 1], e, small, tab, Q);
     }
     return f;
 }
@@ -484,7 +476,7 @@ __device__ __forceinline__ float sov_point32_normal(const Sov32Setup &P, const f
 // is counted in scalar registers; N < 64 (PPL 1) is one weighted trip.  NORMAL
 // selects the normal-limit integrand; LOW0 (t integrand) the form of the
 // first coordinate.
-template <int M, int PPL, bool NORMAL, bool LOW0, bool FINE>
+template <int M, int PPL, bool NORMAL, bool LOW0>
 __device__ float sov_lane_sum32_f(const Sov32Setup &P, const float *tabs, const uint32_t *zz, int sh,
                                   const uint32_t *shfix, int N, int lane) {
     uint32_t t[PPL][M], step[M];
@@ -495,7 +487,7 @@ __device__ float sov_lane_sum32_f(const Sov32Setup &P, const float *tabs, const 
         for (int u = 0; u < PPL; ++u) t[u][i] = (((uint32_t)(lane + 64 * u) * zz[i]) << sh) + shfix[i];
     }
     auto point = [&](const uint32_t *tt) {
-        return NORMAL ? sov_point32_normal<M>(P, tabs, tt) : sov_point32<M, LOW0, FINE>(P, tabs, tt);
+        return NORMAL ? sov_point32_normal<M>(P, tabs, tt) : sov_point32<M, LOW0>(P, tabs, tt);
     };
     // N < 64 (PPL 1): one trip in which the lanes at or past N weigh 0
     const float wl = (N >= 64 * PPL || lane < N) ? 1.0f : 0.0f;
@@ -517,12 +509,12 @@ __device__ float sov_lane_sum32_f(const Sov32Setup &P, const float *tabs, const 
 
 // The first coordinate's form is the same for every point of an item, so the
 // choice between the two loops is uniform across the wave.
-template <int M, int PPL, bool NORMAL, bool FINE = false>
+template <int M, int PPL, bool NORMAL>
 __device__ float sov_lane_sum32(const Sov32Setup &P, const float *tabs, const uint32_t *zz, int sh,
                                 const uint32_t *shfix, int N, int lane) {
-    if (NORMAL) return sov_lane_sum32_f<M, PPL, true, false, false>(P, tabs, zz, sh, shfix, N, lane);
-    if (P.low0) return sov_lane_sum32_f<M, PPL, false, true, FINE>(P, tabs, zz, sh, shfix, N, lane);
-    return sov_lane_sum32_f<M, PPL, false, false, FINE>(P, tabs, zz, sh, shfix, N, lane);
+    if (NORMAL) return sov_lane_sum32_f<M, PPL, true, false>(P, tabs, zz, sh, shfix, N, lane);
+    if (P.low0) return sov_lane_sum32_f<M, PPL, false, true>(P, tabs, zz, sh, shfix, N, lane);
+    return sov_lane_sum32_f<M, PPL, false, false>(P, tabs, zz, sh, shfix, N, lane);
 }
 
 // ------------------------------------------------------------- driver -------
@@ -605,9 +597,8 @@ __device__ inline void sov_finish(const SovHead &H, const double *smean, int S,
 // the item in FP64.  tabs: LDS tables of dofs nu .. nu+M-1.
 // COORDS: the lattice coordinates come from the E-step's coordinate table
 // `coords` (C coordinates per point; N a multiple of 64, one point per lane
-// per trip) instead of being formed in the loop.  FINE: `tabs` are the
-// E-step's slots (fine layout; COORDS needs them), else compact slots.
-template <int M, int PPL, bool COORDS = false, bool FINE = false>
+// per trip) instead of being formed in the loop.  `tabs`: fine-layout slots.
+template <int M, int PPL, bool COORDS = false>
 __device__ bool sov_mixed(const SovHead &H, const double *b, const double *L, double nu, const Lattice &Lt,
                           const float *tabs, double *smean, int lane, const float *coords = nullptr, int C = 0) {
     Sov32Setup P;
@@ -623,7 +614,6 @@ __device__ bool sov_mixed(const SovHead &H, const double *b, const double *L, do
 #pragma unroll
     for (int i = 0; i < M - 1; ++i) zz[i] = (uint32_t)Lt.z[i];
     double tot = 0.0;
-    static_assert(FINE || !COORDS, "the coordinate-table loop reads fine-layout tables");
     for (int s = 0; s < Lt.S; ++s) {
 #pragma unroll
         for (int i = 0; i < M - 1; ++i) shfix[i] = (uint32_t)(Lt.shifts[s * LATD + i] * 4294967296.0);
@@ -633,7 +623,7 @@ __device__ bool sov_mixed(const SovHead &H, const double *b, const double *L, do
             ls = P.low0 ? sov_lane_sum32_c<M, true>(P, tabs, cshift, Lt.N, lane)
                         : sov_lane_sum32_c<M, false>(P, tabs, cshift, Lt.N, lane);
         } else {
-            ls = sov_lane_sum32<M, PPL, false, FINE>(P, tabs, zz, sh, shfix, Lt.N, lane);
+            ls = sov_lane_sum32<M, PPL, false>(P, tabs, zz, sh, shfix, Lt.N, lane);
         }
         const double ms = wave_sum((double)ls) / (double)Lt.N;
         if (lane == 0) smean[s] = ms;
