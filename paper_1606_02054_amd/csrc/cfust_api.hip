@@ -30,8 +30,8 @@ struct EstepWs {
     int coordC;
 };
 
-// Items of mvt_cdf_batch whose FP32 tables are built and used per launch pair
-// (mixed precision): 16384 items hold at most 16384 x 8 x 2176 B = 285 MB.
+// Items of mvt_cdf_batch whose tables are built and used per launch pair:
+// 16384 items hold at most 16384 x 8 x (2176 + 2976) B = 675 MB.
 constexpr int MVT_CHUNK = 16384;
 
 int coord_count(const cfust_dims &d, const cfust_qmc *Q) {
@@ -391,14 +391,18 @@ cfust_status mvt_cdf_batch(cfust_handle h, int32_t m, int32_t batch, const doubl
     if (batch > 0 && (!b || !L || !mat_idx || !nu || !p))
         return fail(h, CFUST_EINVAL, "an mvt_cdf_batch array is NULL");
     const bool mixed = qmc->precision == CFUST_MIXED;
-    // workspace: flags [batch]; mixed (m >= 2): the tables of a chunk of items,
-    // the normal table, the lattice coordinates
+    // workspace: flags [batch]; m >= 2: the FP64 tables of a chunk of items,
+    // and in mixed precision their FP32 tables, the normal table and the
+    // lattice coordinates
     Carve c;
     const size_t o_flag = c.take<int32_t>(batch > 0 ? batch : 1);
     MvtWork w;
-    size_t o_tabs = 0, o_ntab = 0, o_coords = 0;
-    if (mixed && m >= 2) {
+    size_t o_tabs = 0, o_ntab = 0, o_coords = 0, o_tabs64 = 0;
+    if (m >= 2) {
         w.chunk = batch < MVT_CHUNK ? (batch > 0 ? batch : 1) : MVT_CHUNK;
+        o_tabs64 = c.take<double>((size_t)w.chunk * m * TAB64_DOUBLES);
+    }
+    if (mixed && m >= 2) {
         w.C = lattice_coord_count(m, qmc);
         o_tabs = c.take<float>((size_t)w.chunk * m * TABF_FLOATS);
         o_ntab = c.take<float>(TABF_FLOATS);
@@ -406,6 +410,7 @@ cfust_status mvt_cdf_batch(cfust_handle h, int32_t m, int32_t batch, const doubl
     }
     if ((st = ensure_ws(h, c.off)) != CFUST_OK) return st;
     if ((st = hip_check(h, hipSetDevice(h->device), "hipSetDevice")) != CFUST_OK) return st;
+    if (m >= 2) w.tabs64 = at<double>(h, o_tabs64);
     if (mixed && m >= 2) {
         w.tabs = at<float>(h, o_tabs);
         w.ntab = at<float>(h, o_ntab);

@@ -363,12 +363,8 @@ __global__ __launch_bounds__(192) void k_tables(const CompPre *__restrict__ pre,
 // quantile node solved on them, one per thread, and one thread per row for
 // the fits.  A component with infinite dof (normal limit) has no t tables:
 // zeros.
-__device__ inline void tables64_body(const CompPre *__restrict__ pre, int p, int ndof, double *__restrict__ tabs,
-                                     int bid) {
-    const int h = bid / ndof, off = bid % ndof;
-    const double nu = pre[h].nu + p + off;
+__device__ inline void table64_slot_body(double nu, double *__restrict__ dst) {
     __shared__ double fv64[TAB64_DOUBLES], t64[TAB64_DOUBLES], cos64[TAB64_NC * TAB64_NC];
-    double *dst = tabs + ((size_t)h * NDOF + off) * TAB64_DOUBLES;
     if (isinf(nu)) {
         for (int t = threadIdx.x; t < TAB64_DOUBLES; t += blockDim.x) dst[t] = 0.0;
         return;
@@ -388,6 +384,12 @@ __device__ inline void tables64_body(const CompPre *__restrict__ pre, int p, int
     cheb_fit64_rows(fv64, t64, TAB64_CDF_ROWS, TAB64_INV_ROWS, cos64);
     __syncthreads();
     for (int t = threadIdx.x; t < TAB64_DOUBLES; t += blockDim.x) dst[t] = t64[t];
+}
+
+__device__ inline void tables64_body(const CompPre *__restrict__ pre, int p, int ndof, double *__restrict__ tabs,
+                                     int bid) {
+    const int h = bid / ndof, off = bid % ndof;
+    table64_slot_body(pre[h].nu + p + off, tabs + ((size_t)h * NDOF + off) * TAB64_DOUBLES);
 }
 
 __global__ __launch_bounds__(192) void k_tables64(const CompPre *__restrict__ pre, int p, int ndof,
@@ -846,13 +848,71 @@ __global__ __launch_bounds__(192) void k_mvt_normal_table(float *__restrict__ sl
 }
 
 // The item's limits and Cholesky factor, staged in the wave's LDS slot; the
-// first SOV factor from the FP32 table (finite dof) or in FP64 (normal
-// limit).  Out of line for the same reason as item_head.
+// first SOV factor from the FP32 table (finite dof, tab given) or in FP64
+// (normal limit, or tab null).  Out of line for the same reason as item_head.
 __device__ __attribute__((noinline)) void mvt_item_head(const MvtArgs &a, int it, int mi, int M, double *b, double *L,
                                                         double nu, const float *tab, SovHead *H) {
     for (int i = 0; i < M; ++i) b[i] = a.b[(size_t)it * M + i];
     for (int i = 0; i < M * M; ++i) L[i] = a.L[(size_t)mi * M * M + i];
-    *H = isinf(nu) ? sov_head(b, L, nu) : sov_head_tab(b, L, nu, tab);
+    *H = (isinf(nu) || !tab) ? sov_head(b, L, nu) : sov_head_tab(b, L, nu, tab);
+}
+
+// FP64 with per-item FP64 tables: FP64 mode, and the items whose FP32 product
+// underflowed in mixed mode -- every item with flag 1 whose dofs are within
+// the tables' range (infinite dof included: the normal integrand needs no
+// table); the others keep their flag for the exact transforms (k_mvt).
+__device__ inline bool mvt_tab64_item(double nu, int M) { return isinf(nu) || nu + (M - 1) <= TAB64_NU_MAX; }
+
+// Block (local item, dof offset d) of the chunk at it0: the FP64 table of
+// dof nu + d of a flagged item.
+__global__ __launch_bounds__(192) void k_mvt_tables64(MvtArgs a, int it0, int M, double *__restrict__ tabs64) {
+    const int local = blockIdx.x / M, d = blockIdx.x % M;
+    const int it = it0 + local;
+    if (a.flag[it] == 0) return;
+    const double nu = a.nu[it];
+    if (isinf(nu) || !mvt_tab64_item(nu, M)) return;
+    table64_slot_body(nu + d, tabs64 + ((size_t)local * M + d) * TAB64_DOUBLES);
+}
+
+// One flagged item per wave (blocks of 64 threads): the FP64 integrand on the
+// item's FP64 tables in LDS; clears the flag.
+template <int M>
+__global__ __launch_bounds__(64) void k_mvt_fp64tab(MvtArgs a, int it0, const double *__restrict__ tabs64) {
+    __shared__ double tab64[M * TAB64_DOUBLES];
+    __shared__ double smean[MAXS];
+    __shared__ double bs[M], Ls[M * M];
+    __shared__ SovHead Hs;
+    const int lane = threadIdx.x;
+    const int it = it0 + blockIdx.x;
+    if (a.flag[it] == 0) return;
+    const double nu = a.nu[it];
+    if (!mvt_tab64_item(nu, M)) return;
+    const int mi = a.mat_idx[it];
+    if (mi < 0 || mi >= a.nmat) {   // invalid matrix index: NaN result, no access
+        if (lane == 0) {
+            a.p[it] = NAN; if (a.logp) a.logp[it] = NAN; if (a.se) a.se[it] = NAN;
+            a.flag[it] = 0;
+        }
+        return;
+    }
+    if (!isinf(nu)) {
+        const double *src = tabs64 + (size_t)blockIdx.x * M * TAB64_DOUBLES;
+        for (int t = lane; t < M * TAB64_DOUBLES; t += 64) tab64[t] = src[t];
+    }
+    if (lane == 0) mvt_item_head(a, it, mi, M, bs, Ls, nu, nullptr, &Hs);
+    __syncthreads();
+    const SovHead H = Hs;
+    double est = 0.0, se = 0.0, lnest = -INFINITY;
+    if (H.e0 > 0.0 || H.lne0 > -INFINITY) {
+        sov_fp64_tab<M>(H, bs, Ls, nu, a.lat, tab64, smean, lane);
+        sov_finish(H, smean, a.lat.S, &est, &se, &lnest);
+    }
+    if (lane == 0) {
+        a.p[it] = est;
+        if (a.logp) a.logp[it] = lnest;
+        if (a.se) a.se[it] = se;
+        a.flag[it] = 0;
+    }
 }
 
 // One wave per item of the chunk (blocks of 64 threads).  Writes the item's
@@ -903,15 +963,15 @@ __global__ __launch_bounds__(64) void k_mvt_qmc(MvtArgs a, int it0, const float 
     }
 }
 
-// FP64 integrand, one wave per item: FP64 mode, and (FLAGGED_ONLY) the items
-// whose FP32 product underflowed in k_mvt_qmc.
-template <int M, bool FLAGGED_ONLY>
+// FP64 integrand with the exact transforms, one wave per item: the items still
+// flagged after k_mvt_fp64tab (a dof past the FP64 tables' range).
+template <int M>
 __global__ __launch_bounds__(256) void k_mvt(MvtArgs a) {
     __shared__ double smean[4][MAXS];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int it = blockIdx.x * 4 + wave;
     if (it >= a.batch) return;
-    if (FLAGGED_ONLY && a.flag[it] == 0) return;
+    if (a.flag[it] == 0) return;
     const double nu = a.nu[it];
     double b[M], L[M * M];
     const int mi = a.mat_idx[it];
@@ -1216,27 +1276,33 @@ hipError_t launch_lse(const EstepLseArgs &a, double *loglik, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Mixed: per chunk the FP32 tables and integrand (flagging underflows), then
+// the FP64 tables and integrand of the flagged items; FP64 mode: every item
+// flagged, the FP64 passes only.  Last, the exact transforms for what is left.
 template <int M>
 static hipError_t launch_mvt_m(const MvtArgs &a, const MvtWork &w, hipStream_t s) {
-    dim3 grid((a.batch + 3) / 4);
-    if (!a.mixed) {
-        hipLaunchKernelGGL((k_mvt<M, false>), grid, dim3(256), 0, s, a);
-        return hipGetLastError();
-    }
     hipError_t e = hipSuccess;
-    if (w.C > 0) e = launch_lattice_coords(a.lat, w.C, w.coords, s);
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_mvt_normal_table, dim3(1), dim3(192), 0, s, w.ntab);
-        e = hipGetLastError();
+    if (a.mixed) {
+        if (w.C > 0) e = launch_lattice_coords(a.lat, w.C, w.coords, s);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_mvt_normal_table, dim3(1), dim3(192), 0, s, w.ntab);
+            e = hipGetLastError();
+        }
+    } else {
+        e = launch_fill_i32(a.flag, (size_t)a.batch, 1, s);
     }
     for (int it0 = 0; it0 < a.batch && e == hipSuccess; it0 += w.chunk) {
         const int cnt = a.batch - it0 < w.chunk ? a.batch - it0 : w.chunk;
-        hipLaunchKernelGGL(k_mvt_tables, dim3(cnt * M), dim3(192), 0, s, a, it0, M, w.tabs);
-        hipLaunchKernelGGL((k_mvt_qmc<M>), dim3(cnt), dim3(64), 0, s, a, it0, (const float *)w.tabs,
-                           (const float *)w.ntab, (const float *)(w.C > 0 ? w.coords : nullptr), w.C);
+        if (a.mixed) {
+            hipLaunchKernelGGL(k_mvt_tables, dim3(cnt * M), dim3(192), 0, s, a, it0, M, w.tabs);
+            hipLaunchKernelGGL((k_mvt_qmc<M>), dim3(cnt), dim3(64), 0, s, a, it0, (const float *)w.tabs,
+                               (const float *)w.ntab, (const float *)(w.C > 0 ? w.coords : nullptr), w.C);
+        }
+        hipLaunchKernelGGL(k_mvt_tables64, dim3(cnt * M), dim3(192), 0, s, a, it0, M, w.tabs64);
+        hipLaunchKernelGGL((k_mvt_fp64tab<M>), dim3(cnt), dim3(64), 0, s, a, it0, (const double *)w.tabs64);
         e = hipGetLastError();
     }
-    if (e == hipSuccess) hipLaunchKernelGGL((k_mvt<M, true>), grid, dim3(256), 0, s, a);
+    if (e == hipSuccess) hipLaunchKernelGGL((k_mvt<M>), dim3((a.batch + 3) / 4), dim3(256), 0, s, a);
     return e == hipSuccess ? hipGetLastError() : e;
 }
 

@@ -232,13 +232,14 @@ hipError_t launch_lattice_coords(const LatticeArgs &L, int C, float *coords, hip
 // Floats of that table.
 inline size_t lattice_coords_floats(int N, int S, int C) { return (size_t)2 * C * N * S; }
 hipError_t launch_lse(const EstepLseArgs &a, double *loglik, hipStream_t s);
-// Mixed-precision work areas of mvt_cdf_batch: the FP32 tables of a chunk
-// of items ([chunk][m][TABF_FLOATS]), the dof-free normal table
-// ([TABF_FLOATS]) and the lattice coordinate table (C > 0, see
-// launch_lattice_coords).
+// Work areas of mvt_cdf_batch (m >= 2): per chunk of items the FP64 tables
+// ([chunk][m][TAB64_DOUBLES]) and, in mixed precision, the FP32 tables
+// ([chunk][m][TABF_FLOATS]); mixed: the dof-free normal table ([TABF_FLOATS])
+// and the lattice coordinate table (C > 0, see launch_lattice_coords).
 struct MvtWork {
     int chunk = 0;
     float *tabs = nullptr, *ntab = nullptr, *coords = nullptr;
+    double *tabs64 = nullptr;
     int C = 0;
 };
 hipError_t launch_mvt(const MvtArgs &a, const MvtWork &w, hipStream_t s);
