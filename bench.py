@@ -692,7 +692,7 @@ def summarize_counters(dbs, points_per_wave: int) -> dict:
         rows = con.execute("select dispatch_id, name, duration, counter_name, counter_value from pmc_events").fetchall()
         per = {}
         for did, name, dur, cn, cv in rows:
-            mm = re.search(r"k_estep_qmc<(\d), true, false, 1(?:, (?:true|false))?>", name)
+            mm = re.search(r"k_estep_qmc<(\d), true, 1(?:, (?:true|false))?>", name)
             if not mm:
                 continue
             e = per.setdefault(did, {"m": int(mm.group(1)), "dur": dur})

@@ -592,12 +592,13 @@ constexpr int fp32_min_blocks(int m) { return m == 5 ? 6 : m == 6 ? 5 : 1; }
 
 // One wave per (observation j, integral idx, component h); 4 observations per
 // block share the integral's tables.  MIXED: FP32 integrand, items whose FP32
-// product underflows are flagged for the FP64 pass.  !MIXED: FP64 integrand;
-// with FLAGGED_ONLY it processes only the flagged items.
-// The FP32 kernels are held to fp32_min_blocks(m) waves per SIMD.
-template <int M, bool MIXED, bool FLAGGED_ONLY, int PPL, bool COORDS = false>
+// product underflows are flagged for the FP64 pass (k_estep_flagged).
+// !MIXED: FP64 integrand on the FP64 tables, items whose dof is past the
+// tables flagged for the same pass.  The FP32 kernels are held to
+// fp32_min_blocks(m) waves per SIMD.
+template <int M, bool MIXED, int PPL, bool COORDS = false>
 __global__ __launch_bounds__(256, MIXED && PPL == 1 ? fp32_min_blocks(M) : 1) void k_estep_qmc(EstepQmcArgs a) {
-    constexpr bool TAB64 = !MIXED && !FLAGGED_ONLY;
+    constexpr bool TAB64 = !MIXED;
     __shared__ __align__(16) float tab[MIXED ? M * TABF_FLOATS : 4];
     __shared__ double tab64[TAB64 ? M * TAB64_DOUBLES : 1];
     __shared__ double smean[4][MAXS];
@@ -615,9 +616,8 @@ __global__ __launch_bounds__(256, MIXED && PPL == 1 ? fp32_min_blocks(M) : 1) vo
     const int j = blockIdx.x * 4 + wave;
     if (j >= a.n) return;
     const size_t o = ((size_t)h * a.J + idx) * a.n + j;
-    if (FLAGGED_ONLY && a.flag[o] == 0) return;
-    if (!FLAGGED_ONLY && a.need && a.need[o] == 0) {   // answered by the surrogate
-        if ((MIXED || TAB64) && lane == 0) a.flag[o] = 0;
+    if (a.need && a.need[o] == 0) {   // answered by the surrogate
+        if (lane == 0) a.flag[o] = 0;
         return;
     }
     if (TAB64 && beyond_tab64<M>(a.pre, a.p, a.q, h, idx)) {   // left to the exact pass
@@ -625,7 +625,41 @@ __global__ __launch_bounds__(256, MIXED && PPL == 1 ? fp32_min_blocks(M) : 1) vo
         return;
     }
     const bool ok = qmc_item<M, MIXED, PPL, TAB64, COORDS>(a, h, idx, j, tab, tab64, smean[wave], &witem[wave], lane);
-    if ((MIXED || TAB64) && lane == 0) a.flag[o] = ok ? 0 : 1;
+    if (lane == 0) a.flag[o] = ok ? 0 : 1;
+}
+
+// The flagged items of a launch's integrals (mixed: FP32 underflow; FP64
+// mode: a dof past the FP64 tables), evaluated with the exact FP64
+// transforms.  Each wave scans 64 consecutive items u of [g][nidx][n] (one
+// flag per lane) and evaluates the flagged ones in turn, so a pass with
+// nothing flagged costs one coalesced read per 64 items instead of a wave
+// per item.
+template <int M>
+__global__ __launch_bounds__(256) void k_estep_flagged(EstepQmcArgs a, int nidx) {
+    __shared__ double smean[4][MAXS];
+    __shared__ WaveItem witem[4];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const long long total = (long long)a.g * nidx * a.n;
+    const long long u = ((long long)blockIdx.x * 4 + wave) * 64 + lane;
+    int flagged = 0;
+    size_t o = 0;
+    int h = 0, idx = 0, j = 0;
+    if (u < total) {
+        j = (int)(u % a.n);
+        const long long r = u / a.n;
+        idx = a.idx0 + (int)(r % nidx);
+        h = (int)(r / nidx);
+        o = ((size_t)h * a.J + idx) * a.n + j;
+        flagged = a.flag[o] != 0;
+    }
+    uint64_t mask = __ballot(flagged);
+    while (mask) {
+        const int src = __ffsll((unsigned long long)mask) - 1;
+        mask &= mask - 1;
+        const int hs = __shfl(h, src), is = __shfl(idx, src), js = __shfl(j, src);
+        qmc_item<M, false, 1>(a, hs, is, js, nullptr, nullptr, smean[wave], &witem[wave], lane);
+        if (lane == src) a.flag[o] = 0;
+    }
 }
 
 // ------------------------------------------------------------- assembly ----
@@ -1212,17 +1246,17 @@ static void launch_qmc_m(const EstepQmcArgs &a, int nidx, hipStream_t s, hipEven
     dim3 grid((a.n + 3) / 4, nidx, a.g);
     if (ev0) (void)hipEventRecord(ev0, s);
     if (a.mixed) {
-        if (ppl == 2) hipLaunchKernelGGL((k_estep_qmc<M, true, false, 2>), grid, dim3(256), 0, s, a);
-        else if (a.coords) hipLaunchKernelGGL((k_estep_qmc<M, true, false, 1, true>), grid, dim3(256), 0, s, a);
-        else hipLaunchKernelGGL((k_estep_qmc<M, true, false, 1>), grid, dim3(256), 0, s, a);
-        if (ev1) (void)hipEventRecord(ev1, s);
-        hipLaunchKernelGGL((k_estep_qmc<M, false, true, 1>), grid, dim3(256), 0, s, a);
+        if (ppl == 2) hipLaunchKernelGGL((k_estep_qmc<M, true, 2>), grid, dim3(256), 0, s, a);
+        else if (a.coords) hipLaunchKernelGGL((k_estep_qmc<M, true, 1, true>), grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_estep_qmc<M, true, 1>), grid, dim3(256), 0, s, a);
     } else {
-        hipLaunchKernelGGL((k_estep_qmc<M, false, false, 1>), grid, dim3(256), 0, s, a);
-        if (ev1) (void)hipEventRecord(ev1, s);
-        // integrals whose dof is past the FP64 tables: exact transforms
-        hipLaunchKernelGGL((k_estep_qmc<M, false, true, 1>), grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_estep_qmc<M, false, 1>), grid, dim3(256), 0, s, a);
     }
+    if (ev1) (void)hipEventRecord(ev1, s);
+    // flagged items (mixed: FP32 underflow; FP64: a dof past the FP64 tables)
+    const long long total = (long long)a.g * nidx * a.n;
+    const long long blocks = (total + 255) / 256;
+    hipLaunchKernelGGL((k_estep_flagged<M>), dim3((unsigned)blocks), dim3(256), 0, s, a, nidx);
 }
 
 hipError_t launch_estep_qmc(const EstepQmcArgs &a, int m, int nidx, hipStream_t s, hipEvent_t ev0,

@@ -96,7 +96,7 @@ def test_bench_counter_summary(tmp_path):
             "SQ_INSTS_VALU_ADD_F32": 20.0, "SQ_INSTS_VALU_TRANS_F32": 10.0, "SQ_INSTS_VALU": 512.0,
             "SQ_ACTIVE_INST_VALU2": 128.0, "GRBM_GUI_ACTIVE": 8.0}
     for k, v in vals.items():
-        con.execute("insert into pmc_events values (1, 'void cfust::k_estep_qmc<3, true, false, 1, true>(x)', 1.0, ?, ?)",
+        con.execute("insert into pmc_events values (1, 'void cfust::k_estep_qmc<3, true, 1, true>(x)', 1.0, ?, ?)",
                     (k, v))
     con.execute("insert into pmc_events values (2, 'void cfust::k_mstep_reduce(x)', 1.0, 'SQ_WAVES', 5.0)")
     con.commit()
