@@ -411,7 +411,7 @@ __device__ __forceinline__ void load_coords(__amdgpu_buffer_rsrc_t r, int vo, in
 // is added (no contraction of its last product into the sum), as in the loop
 // that forms the coordinates itself, so both give the same sums bit for bit.
 template <int M, bool LOW0>
-__device__ float sov_lane_sum32_c(const Sov32Setup &P, const float *tabs, const float *cshift, int N, int lane) {
+__device__ __forceinline__ float sov_lane_sum32_c(const Sov32Setup &P, const float *tabs, const float *cshift, int N, int lane) {
 #pragma clang fp contract(off)
     constexpr int R = 2 * (M - 1);
     const int row_bytes = N * 4;
@@ -477,7 +477,7 @@ __device__ __forceinline__ float sov_point32_normal(const Sov32Setup &P, const f
 // selects the normal-limit integrand; LOW0 (t integrand) the form of the
 // first coordinate.
 template <int M, int PPL, bool NORMAL, bool LOW0>
-__device__ float sov_lane_sum32_f(const Sov32Setup &P, const float *tabs, const uint32_t *zz, int sh,
+__device__ __forceinline__ float sov_lane_sum32_f(const Sov32Setup &P, const float *tabs, const uint32_t *zz, int sh,
                                   const uint32_t *shfix, int N, int lane) {
     uint32_t t[PPL][M], step[M];
 #pragma unroll
@@ -510,7 +510,7 @@ __device__ float sov_lane_sum32_f(const Sov32Setup &P, const float *tabs, const 
 // The first coordinate's form is the same for every point of an item, so the
 // choice between the two loops is uniform across the wave.
 template <int M, int PPL, bool NORMAL>
-__device__ float sov_lane_sum32(const Sov32Setup &P, const float *tabs, const uint32_t *zz, int sh,
+__device__ __forceinline__ float sov_lane_sum32(const Sov32Setup &P, const float *tabs, const uint32_t *zz, int sh,
                                 const uint32_t *shfix, int N, int lane) {
     if (NORMAL) return sov_lane_sum32_f<M, PPL, true, false>(P, tabs, zz, sh, shfix, N, lane);
     if (P.low0) return sov_lane_sum32_f<M, PPL, false, true>(P, tabs, zz, sh, shfix, N, lane);
@@ -599,7 +599,7 @@ __device__ inline void sov_finish(const SovHead &H, const double *smean, int S,
 // `coords` (C coordinates per point; N a multiple of 64, one point per lane
 // per trip) instead of being formed in the loop.  `tabs`: fine-layout slots.
 template <int M, int PPL, bool COORDS = false>
-__device__ bool sov_mixed(const SovHead &H, const double *b, const double *L, double nu, const Lattice &Lt,
+__device__ __forceinline__ bool sov_mixed(const SovHead &H, const double *b, const double *L, double nu, const Lattice &Lt,
                           const float *tabs, double *smean, int lane, const float *coords = nullptr, int C = 0) {
     Sov32Setup P;
 #pragma unroll
@@ -637,7 +637,7 @@ __device__ bool sov_mixed(const SovHead &H, const double *b, const double *L, do
 // below 2^-480 (past the quantile table's range) is left to the FP64
 // integrand (returns false).
 template <int M, int PPL>
-__device__ bool sov_mixed_normal(const SovHead &H, const double *b, const double *L, const Lattice &Lt,
+__device__ __forceinline__ bool sov_mixed_normal(const SovHead &H, const double *b, const double *L, const Lattice &Lt,
                                  const float *tab, double *smean, int lane) {
     if (H.low0 && H.lne0 < -480.0 * LN2) return false;
     Sov32Setup P;
