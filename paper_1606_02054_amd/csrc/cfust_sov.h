@@ -405,13 +405,19 @@ __device__ __forceinline__ void load_coords(__amdgpu_buffer_rsrc_t r, int vo, in
 }
 
 // Per-lane FP32 sum over the shift's points from the coordinate table
-// `cshift` (N a multiple of 64; lane l takes points l, l + 64, ...).  The
-// loads of a trip are waited for where the point first needs them; the other
-// resident waves cover their latency.  The point's value is rounded before it
-// is added (no contraction of its last product into the sum), as in the loop
-// that forms the coordinates itself, so both give the same sums bit for bit.
+// `cshift` (N a multiple of 64; lane l takes points l, l + 64, ...).  At
+// m = 2 a point is short (about 45 VALU), so its coordinates are loaded one
+// trip ahead into an alternating pair of register sets (the load after the
+// last even trip re-reads that trip's own coordinates, so every load stays
+// inside the table); at larger m the loads of a trip are waited for where
+// the point first needs them and the other resident waves cover their
+// latency (loading ahead there only cost registers).  The point's value is
+// rounded before it is added (no contraction of its last product into the
+// sum), as in the loop that forms the coordinates itself, so both give the
+// same sums bit for bit.
 template <int M, bool LOW0>
-__device__ __forceinline__ float sov_lane_sum32_c(const Sov32Setup &P, const float *tabs, const float *cshift, int N, int lane) {
+__device__ __forceinline__ float sov_lane_sum32_c(const Sov32Setup &P, const float *tabs, const float *cshift, int N,
+                                                  int lane) {
 #pragma clang fp contract(off)
     constexpr int R = 2 * (M - 1);
     const int row_bytes = N * 4;
@@ -419,11 +425,24 @@ __device__ __forceinline__ float sov_lane_sum32_c(const Sov32Setup &P, const flo
         __builtin_amdgcn_make_buffer_rsrc((void *)cshift, (short)0, R * row_bytes, BUF_RSRC_WORD3);
     const int vo = lane * 4;
     const int trips = N / 64;
-    float c[R];
     float acc = 0.0f;
-    for (int it = 0; it < trips; ++it) {
-        load_coords<M, LOW0>(rs, vo, it * 256, row_bytes, c);
-        acc += sov_point32_c<M, LOW0>(P, tabs, c);
+    if constexpr (M == 2) {
+        float c0[R], c1[R];
+        load_coords<M, LOW0>(rs, vo, 0, row_bytes, c0);
+        int it = 0;
+        for (; it + 2 <= trips; it += 2) {
+            load_coords<M, LOW0>(rs, vo, (it + 1) * 256, row_bytes, c1);
+            acc += sov_point32_c<M, LOW0>(P, tabs, c0);
+            load_coords<M, LOW0>(rs, vo, min(it + 2, trips - 1) * 256, row_bytes, c0);
+            acc += sov_point32_c<M, LOW0>(P, tabs, c1);
+        }
+        if (it < trips) acc += sov_point32_c<M, LOW0>(P, tabs, c0);
+    } else {
+        float c[R];
+        for (int it = 0; it < trips; ++it) {
+            load_coords<M, LOW0>(rs, vo, it * 256, row_bytes, c);
+            acc += sov_point32_c<M, LOW0>(P, tabs, c);
+        }
     }
     return acc;
 }
