@@ -128,7 +128,9 @@ cfust_status run_estep(cfust_handle h, const double *y, const cfust_dims &d, con
     double *lfc = logf_comp ? logf_comp : (double *)W(L.logf);
     hipError_t e = launch_precompute(*P, d.p, d.q, d.g, pre, s);
     if (e == hipSuccess && mixed && J > 0) e = launch_tables(pre, d.p, d.g, d.q + 2, (float *)W(L.tabs), s);
-    if (e == hipSuccess && !mixed && J > 0) e = launch_tables64(pre, d.p, d.g, d.q + 2, (double *)W(L.tabs64), s);
+    // FP64 tables: the FP64 integrand (FP64 mode) and, in mixed mode, the
+    // items whose FP32 product underflows
+    if (e == hipSuccess && J > 0) e = launch_tables64(pre, d.p, d.g, d.q + 2, (double *)W(L.tabs64), s);
     int32_t *need = nullptr;
     if (e == hipSuccess && sur && J > 0) {
         need = (int32_t *)W(need_off);
@@ -164,7 +166,7 @@ cfust_status run_estep(cfust_handle h, const double *y, const cfust_dims &d, con
         EstepQmcArgs a;
         a.need = need;
         a.y = y; a.mu = P->mu; a.pre = pre; a.tabs = (float *)W(L.tabs);
-        a.tabs64 = mixed ? nullptr : (double *)W(L.tabs64);
+        a.tabs64 = (double *)W(L.tabs64);
         a.lat = lattice_of(Q);
         a.n = d.n; a.p = d.p; a.q = d.q; a.g = d.g; a.J = J; a.mixed = mixed ? 1 : 0;
         a.est = (double *)W(L.est); a.lnA = (double *)W(L.lnA); a.se = se;

@@ -36,7 +36,7 @@ struct Queue {
     unsigned int *redo_count = nullptr;
     int rows = 4, mult = 1, ppl = 1;
     bool persist = false;                   // persistent blocks, or one block per tile (default)
-    int grid = 0, redo_grid = 0;
+    int grid = 0, redo_grid = 0, redo_grid64 = 0;
 };
 
 struct Group {
@@ -142,7 +142,8 @@ cfust_status upload_segments(cfust_batch b, Queue &Q) {
 void set_grid(cfust_batch b, Queue &Q) {
     const int ncu = b->h->ncu > 0 ? b->h->ncu : 256;
     Q.grid = Q.persist ? ncu * queue_qmc_occupancy(Q.m, b->mixed, Q.ppl, b->coordC > 0) * Q.mult : 0;
-    Q.redo_grid = ncu * queue_redo_occupancy(Q.m);
+    Q.redo_grid = ncu * queue_redo_occupancy(Q.m, false);
+    Q.redo_grid64 = ncu * queue_redo_occupancy(Q.m, true);
 }
 
 QueueArgs queue_args(cfust_batch b, const Queue &Q, long long ntiles) {
@@ -185,7 +186,7 @@ hipError_t enqueue_estep(cfust_batch b, hipStream_t s) {
         if (r.e0 && r.e1) b->h->rec.push_back(r);
         // mixed: items whose FP32 product underflowed; FP64: items of integrals
         // whose dof is past the FP64 tables
-        if (e == hipSuccess) e = launch_queue_redo(qa, Q.m, Q.redo_grid, s);
+        if (e == hipSuccess) e = launch_queue_redo(qa, Q.m, Q.redo_grid, Q.redo_grid64, s);
     }
     if (e == hipSuccess) e = launch_batch_assemble(A, b->nblocks[BK_ASM], s);
     if (e == hipSuccess) e = launch_batch_lse(A, b->nblocks[BK_LSE], s);
@@ -282,7 +283,7 @@ cfust_status cfust_batch_create(cfust_handle h, int32_t nfits, const cfust_fit *
         const int J = dn ? (d.q >= 2 ? 1 : 0) : nint_qmc(d.q);
         fo[f].pre = c.take<CompPre>(d.g);
         fo[f].tabs = c.take<float>(b->mixed && J > 0 ? (size_t)d.g * NDOF * TABF_FLOATS : 1);
-        fo[f].tabs64 = c.take<double>(!b->mixed && J > 0 ? (size_t)d.g * NDOF * TAB64_DOUBLES : 1);
+        fo[f].tabs64 = c.take<double>(J > 0 ? (size_t)d.g * NDOF * TAB64_DOUBLES : 1);
         fo[f].est = c.take<double>((size_t)d.g * (J > 0 ? J : 1) * n1);
         fo[f].lnA = c.take<double>((size_t)d.g * n1);
         fo[f].logf = c.take<double>(fits[f].out.logf_comp ? 1 : (size_t)d.g * n1);
@@ -346,7 +347,7 @@ cfust_status cfust_batch_create(cfust_handle h, int32_t nfits, const cfust_fit *
         D.pc.p = d.p; D.pc.q = d.q; D.pc.pre = pre;
         D.ndof = d.q + 2;
         D.tabs = tabs;
-        D.tabs64 = !b->mixed && J > 0 ? bat<double>(b, fo[f].tabs64) : nullptr;
+        D.tabs64 = J > 0 ? bat<double>(b, fo[f].tabs64) : nullptr;   // mixed: for the redo list
         EstepQmcArgs &q = D.qa;
         q.y = F.y; q.mu = F.params.mu; q.pre = pre; q.tabs = tabs; q.tabs64 = D.tabs64; q.lat = b->lat;
         q.n = d.n; q.p = d.p; q.q = d.q; q.g = d.g; q.J = J > 0 ? J : 1; q.idx0 = 0; q.mixed = b->mixed;

@@ -662,6 +662,46 @@ __global__ __launch_bounds__(256) void k_estep_flagged(EstepQmcArgs a, int nidx)
     }
 }
 
+// Mixed mode, before k_estep_flagged: the flagged items whose dofs are within
+// the FP64 tables' range, on the components' FP64 tables (a.tabs64), one
+// wave per block scanning 64 items; clears their flags.
+template <int M>
+__global__ __launch_bounds__(64) void k_estep_flagged64(EstepQmcArgs a, int nidx) {
+    __shared__ double tab64[M * TAB64_DOUBLES];
+    __shared__ double smean[MAXS];
+    __shared__ WaveItem witem;
+    const int lane = threadIdx.x;
+    const long long total = (long long)a.g * nidx * a.n;
+    const long long u = (long long)blockIdx.x * 64 + lane;
+    int flagged = 0;
+    size_t o = 0;
+    int h = 0, idx = 0, j = 0;
+    if (u < total) {
+        j = (int)(u % a.n);
+        const long long r = u / a.n;
+        idx = a.idx0 + (int)(r % nidx);
+        h = (int)(r / nidx);
+        o = ((size_t)h * a.J + idx) * a.n + j;
+        flagged = a.flag[o] != 0 && !beyond_tab64<M>(a.pre, a.p, a.q, h, idx);
+    }
+    uint64_t mask = __ballot(flagged);
+    int cur_h = -1, cur_idx = -1;
+    while (mask) {
+        const int src = __ffsll((unsigned long long)mask) - 1;
+        mask &= mask - 1;
+        const int hs = __shfl(h, src), is = __shfl(idx, src), js = __shfl(j, src);
+        if (hs != cur_h || is != cur_idx) {
+            __syncthreads();
+            load_tables64<M>(a.tabs64, hs, int_desc(a.q, is).dofoff, tab64);
+            __syncthreads();
+            cur_h = hs;
+            cur_idx = is;
+        }
+        qmc_item<M, false, 1, true>(a, hs, is, js, nullptr, tab64, smean, &witem, lane);
+        if (lane == src) a.flag[o] = 0;
+    }
+}
+
 // ------------------------------------------------------------- assembly ----
 
 // Value of integral idx of the pair: lattice estimate (m >= 2) or closed form.
@@ -1253,8 +1293,11 @@ static void launch_qmc_m(const EstepQmcArgs &a, int nidx, hipStream_t s, hipEven
         hipLaunchKernelGGL((k_estep_qmc<M, false, 1>), grid, dim3(256), 0, s, a);
     }
     if (ev1) (void)hipEventRecord(ev1, s);
-    // flagged items (mixed: FP32 underflow; FP64: a dof past the FP64 tables)
+    // flagged items (mixed: FP32 underflow; FP64: a dof past the FP64 tables):
+    // in mixed mode on the FP64 tables where they reach, the rest exact
     const long long total = (long long)a.g * nidx * a.n;
+    if (a.mixed && a.tabs64)
+        hipLaunchKernelGGL((k_estep_flagged64<M>), dim3((unsigned)((total + 63) / 64)), dim3(64), 0, s, a, nidx);
     const long long blocks = (total + 255) / 256;
     hipLaunchKernelGGL((k_estep_flagged<M>), dim3((unsigned)blocks), dim3(256), 0, s, a, nidx);
 }
@@ -1381,8 +1424,9 @@ __global__ __launch_bounds__(192) void k_batch_tables(BatchArgs B) {
     const int f = batch_fit(pf, B.nfits, blockIdx.x);
     if (!B.active[f]) return;
     const FitDesc &F = B.fits[f];
+    // mixed: the FP32 tables, and the FP64 ones for the redo list; FP64: FP64 tables
+    if (F.qa.mixed) tables_body(F.pc.pre, F.pc.p, F.ndof, F.tabs, blockIdx.x - pf[f]);
     if (F.tabs64) tables64_body(F.pc.pre, F.pc.p, F.ndof, F.tabs64, blockIdx.x - pf[f]);
-    else tables_body(F.pc.pre, F.pc.p, F.ndof, F.tabs, blockIdx.x - pf[f]);
 }
 
 __global__ __launch_bounds__(128) void k_batch_assemble(BatchArgs B) {
@@ -1525,21 +1569,39 @@ __global__ __launch_bounds__(256, MIXED && PPL == 1 ? fp32_min_blocks(M) : 1) vo
     }
 }
 
-// FP64 integrand for the items of the redo list; one wave per entry.
-template <int M>
-__global__ __launch_bounds__(256) void k_queue_redo(QueueArgs Q) {
-    __shared__ double smean[4][MAXS];
-    __shared__ WaveItem witem[4];
+// FP64 integrand for the items of the redo list, one wave per entry, in two
+// passes: TABLES, the entries whose fit has FP64 tables (mixed: every fit)
+// and whose dofs they reach, on those tables (one wave per block, the
+// entry's tables in its LDS), each marked done (~0) afterwards; then the
+// rest with the exact transforms.
+constexpr unsigned long long REDO_DONE = ~0ULL;
+
+template <int M, bool TABLES>
+__global__ __launch_bounds__(TABLES ? 64 : 256) void k_queue_redo(QueueArgs Q) {
+    constexpr int W = TABLES ? 1 : 4;
+    __shared__ double tab64[TABLES ? M * TAB64_DOUBLES : 1];
+    __shared__ double smean[W][MAXS];
+    __shared__ WaveItem witem[W];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const unsigned cnt = Q.redo_count[0];
-    for (unsigned e = blockIdx.x * 4 + wave; e < cnt; e += gridDim.x * 4) {
+    for (unsigned e = blockIdx.x * W + wave; e < cnt; e += gridDim.x * W) {
         const unsigned long long v0 = Q.redo[e];
         const unsigned long long v = ((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(v0 >> 32)) << 32) |
                                      (unsigned)__builtin_amdgcn_readfirstlane((unsigned)v0);
+        if (v == REDO_DONE) continue;
         const int f = (int)(v >> 43), h = (int)((v >> 37) & 63), idx = (int)((v >> 31) & 63);
         const int j = (int)(v & 0x7fffffffULL);
         const EstepQmcArgs a = Q.fits[f].qa;
-        qmc_item<M, false, 1>(a, h, idx, j, nullptr, nullptr, smean[wave], &witem[wave], lane);
+        if (TABLES) {
+            if (!a.tabs64 || beyond_tab64<M>(a.pre, a.p, a.q, h, idx)) continue;
+            __syncthreads();
+            load_tables64<M>(a.tabs64, h, int_desc(a.q, idx).dofoff, tab64);
+            __syncthreads();
+            qmc_item<M, false, 1, true>(a, h, idx, j, nullptr, tab64, smean[wave], &witem[wave], lane);
+            if (lane == 0) Q.redo[e] = REDO_DONE;
+        } else {
+            qmc_item<M, false, 1>(a, h, idx, j, nullptr, nullptr, smean[wave], &witem[wave], lane);
+        }
     }
 }
 
@@ -1643,15 +1705,16 @@ static const void *queue_kernel_m(int m, bool mixed, int ppl, bool persist, bool
     }
 }
 
+template <bool TABLES>
 static const void *redo_kernel_m(int m) {
     switch (m) {
-    case 2: return (const void *)k_queue_redo<2>;
-    case 3: return (const void *)k_queue_redo<3>;
-    case 4: return (const void *)k_queue_redo<4>;
-    case 5: return (const void *)k_queue_redo<5>;
-    case 6: return (const void *)k_queue_redo<6>;
-    case 7: return (const void *)k_queue_redo<7>;
-    case 8: return (const void *)k_queue_redo<8>;
+    case 2: return (const void *)k_queue_redo<2, TABLES>;
+    case 3: return (const void *)k_queue_redo<3, TABLES>;
+    case 4: return (const void *)k_queue_redo<4, TABLES>;
+    case 5: return (const void *)k_queue_redo<5, TABLES>;
+    case 6: return (const void *)k_queue_redo<6, TABLES>;
+    case 7: return (const void *)k_queue_redo<7, TABLES>;
+    case 8: return (const void *)k_queue_redo<8, TABLES>;
     default: return nullptr;
     }
 }
@@ -1669,11 +1732,13 @@ hipError_t launch_queue_qmc(const QueueArgs &q, int m, bool mixed, int ppl, int 
     return hipLaunchKernel(k, dim3((unsigned)gx, (unsigned)gy), dim3(256), args, 0, s);
 }
 
-hipError_t launch_queue_redo(const QueueArgs &q, int m, int grid, hipStream_t s) {
-    const void *k = redo_kernel_m(m);
-    if (!k || grid < 1) return hipErrorInvalidValue;
+hipError_t launch_queue_redo(const QueueArgs &q, int m, int grid, int grid64, hipStream_t s) {
+    const void *k64 = redo_kernel_m<true>(m), *k = redo_kernel_m<false>(m);
+    if (!k || !k64 || grid < 1 || grid64 < 1) return hipErrorInvalidValue;
     void *args[] = {(void *)&q};
-    return hipLaunchKernel(k, dim3(grid), dim3(256), args, 0, s);
+    hipError_t e = hipLaunchKernel(k64, dim3(grid64), dim3(64), args, 0, s);
+    if (e == hipSuccess) e = hipLaunchKernel(k, dim3(grid), dim3(256), args, 0, s);
+    return e;
 }
 
 int queue_qmc_occupancy(int m, bool mixed, int ppl, bool coords) {
@@ -1683,10 +1748,10 @@ int queue_qmc_occupancy(int m, bool mixed, int ppl, bool coords) {
     return nb > 0 ? nb : 1;
 }
 
-int queue_redo_occupancy(int m) {
-    const void *k = redo_kernel_m(m);
+int queue_redo_occupancy(int m, bool tables) {
+    const void *k = tables ? redo_kernel_m<true>(m) : redo_kernel_m<false>(m);
     int nb = 0;
-    if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 256, 0) != hipSuccess) return 1;
+    if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, tables ? 64 : 256, 0) != hipSuccess) return 1;
     return nb > 0 ? nb : 1;
 }
 

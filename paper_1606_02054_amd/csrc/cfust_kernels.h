@@ -174,10 +174,12 @@ size_t mstep_lds_bytes(int p, int q);
 // lattice coordinate table (used in mixed mode at one point per lane).
 hipError_t launch_queue_qmc(const QueueArgs &q, int m, bool mixed, int ppl, int grid, hipStream_t s,
                             bool coords = false);
-hipError_t launch_queue_redo(const QueueArgs &q, int m, int grid, hipStream_t s);
+// The FP64 pass over the redo list: the entries the fits' FP64 tables reach
+// first (grid64 blocks of one wave), then the rest exact (grid blocks).
+hipError_t launch_queue_redo(const QueueArgs &q, int m, int grid, int grid64, hipStream_t s);
 // Resident blocks per compute unit of the queue kernels.
 int queue_qmc_occupancy(int m, bool mixed, int ppl, bool coords = false);
-int queue_redo_occupancy(int m);
+int queue_redo_occupancy(int m, bool tables);
 // Arguments of a batched EM run that the captured iteration reads from
 // device memory, so that one graph serves every call.
 struct BatchCtl {
