@@ -37,7 +37,7 @@ PEAK_FP32_TFLOPS = 157.3     # MI355X vector FP32 (chip figure: 2 wave64 FMA iss
 # again (profiles/k_estep_qmc_counters.md).
 TRAFFIC_SOURCES = ["paper_1606_02054_amd/csrc/cfust_sov.h", "paper_1606_02054_amd/csrc/cfust_devmath.h",
                    "paper_1606_02054_amd/csrc/cfust_estep.hip", "paper_1606_02054_amd/csrc/cfust_common.h"]
-KERNEL_DIGEST = "d327406a31c27702"
+KERNEL_DIGEST = "6056f3f912cebef6"
 # FP32 arithmetic of one lattice point of the m-variate integrand in the FP32
 # lattice kernel: (2 x SQ_INSTS_VALU_FMA_F32 + MUL_F32 + ADD_F32 + TRANS_F32)
 # of a launch divided by the lattice points it evaluates.
@@ -47,19 +47,19 @@ LATTICE_FLOPS_PER_POINT = {2: 41.99, 3: 87.3, 4: 134.32, 5: 183.13, 6: 234.19, 7
 # at most 2: one pair per SIMD per 4-cycle slot) and the share of them issued
 # in pairs.
 LATTICE_VALU_ISSUE = {
-    2: {'valu_per_point': 46.0, 'valu_per_cu_cycle': 0.840, 'dual_issue_frac': 0.403, 'valu_slot_busy': 0.783},
-    3: {'valu_per_point': 92.5, 'valu_per_cu_cycle': 1.093, 'dual_issue_frac': 0.553, 'valu_slot_busy': 0.934},
-    4: {'valu_per_point': 139.6, 'valu_per_cu_cycle': 1.056, 'dual_issue_frac': 0.510, 'valu_slot_busy': 0.924},
-    5: {'valu_per_point': 187.0, 'valu_per_cu_cycle': 1.001, 'dual_issue_frac': 0.476, 'valu_slot_busy': 0.892},
-    6: {'valu_per_point': 237.3, 'valu_per_cu_cycle': 1.128, 'dual_issue_frac': 0.526, 'valu_slot_busy': 0.975},
-    7: {'valu_per_point': 287.4, 'valu_per_cu_cycle': 1.061, 'dual_issue_frac': 0.470, 'valu_slot_busy': 0.946},
-    8: {'valu_per_point': 338.1, 'valu_per_cu_cycle': 0.997, 'dual_issue_frac': 0.447, 'valu_slot_busy': 0.899},
+    2: {'valu_per_point': 45.0, 'valu_per_cu_cycle': 0.951, 'dual_issue_frac': 0.414, 'valu_slot_busy': 0.884},
+    3: {'valu_per_point': 92.5, 'valu_per_cu_cycle': 1.107, 'dual_issue_frac': 0.553, 'valu_slot_busy': 0.947},
+    4: {'valu_per_point': 139.6, 'valu_per_cu_cycle': 1.071, 'dual_issue_frac': 0.510, 'valu_slot_busy': 0.938},
+    5: {'valu_per_point': 187.0, 'valu_per_cu_cycle': 1.004, 'dual_issue_frac': 0.476, 'valu_slot_busy': 0.895},
+    6: {'valu_per_point': 237.3, 'valu_per_cu_cycle': 1.130, 'dual_issue_frac': 0.526, 'valu_slot_busy': 0.976},
+    7: {'valu_per_point': 287.4, 'valu_per_cu_cycle': 1.061, 'dual_issue_frac': 0.470, 'valu_slot_busy': 0.945},
+    8: {'valu_per_point': 338.1, 'valu_per_cu_cycle': 0.992, 'dual_issue_frac': 0.447, 'valu_slot_busy': 0.894},
 }
 # HBM bytes per launch of the FP32 lattice kernel of each dimension at the
 # default workload (MiB read, MiB written: FETCH_SIZE x 2 and WRITE_SIZE x 1 in
 # KiB, the factors that a 1 GiB device copy gives these counters).
-TRAFFIC_MIB = {4: (2 * 10798.8 / 1024, 7519.3 / 1024), 3: (2 * 4527.5 / 1024, 6043.3 / 1024),
-               2: (2 * 3494.0 / 1024, 7776.3 / 1024)}
+TRAFFIC_MIB = {4: (2 * 11111.3 / 1024, 7490.9 / 1024), 3: (2 * 4528.5 / 1024, 6044.8 / 1024),
+               2: (2 * 3498.0 / 1024, 7752.3 / 1024)}
 
 
 def kernel_digest() -> str:
