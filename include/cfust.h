@@ -98,13 +98,15 @@ enum { CFUST_FP64 = 0, CFUST_MIXED = 1 };
 
 /* Lattice rule.  Point k (0 <= k < N) of shift s in coordinate j is
  *   t = frac(k z[j] / N + shifts[s][j]),  x = 1 - |2t - 1|  (clamped to [2^-24, 1-2^-24]).
- * precision: CFUST_FP64 evaluates everything in FP64 (in the E-step the
- * univariate t probabilities and quantiles of the integrand come from FP64
- * Chebyshev tables of each dof, within about 1e-14 of the exact values, the
- * quantile polished by a Newton step; mvt_cdf_batch uses the exact
- * continued-fraction transforms); CFUST_MIXED evaluates the lattice integrand
- * in FP32 (per-shift FP32 sums, combined in FP64) and keeps the Cholesky
- * factors, log-densities, log-sum-exp and M-step in FP64. */
+ * precision: CFUST_FP64 evaluates everything in FP64 (the univariate t
+ * probabilities and quantiles of the integrand come from FP64 Chebyshev
+ * tables of each dof, within about 1e-14 of the exact values, the quantile
+ * polished by a Newton step; an integral with a dof above 1000, past the
+ * tables, takes the exact continued-fraction transforms); CFUST_MIXED
+ * evaluates the lattice integrand in FP32 on FP32 tables of each dof
+ * (per-shift FP32 sums, combined in FP64; an integral whose FP32 product
+ * underflows is redone in FP64) and keeps the Cholesky factors,
+ * log-densities, log-sum-exp and M-step in FP64. */
 typedef struct {
     int32_t N;               /* 2 <= N <= 65536 points per shift */
     int32_t S;               /* 1 <= S <= CFUST_MAX_SHIFTS shifts */
