@@ -1320,7 +1320,11 @@ hipError_t launch_estep_qmc(const EstepQmcArgs &a, int m, int nidx, hipStream_t 
 }
 
 // The lattice coordinates of every point, coordinate and shift, formed as the
-// FP32 integrand forms them (one thread per point; grid (N/256, C, S)).
+// FP32 integrand forms them (one thread per point; grid (N/256, C, S)), and
+// log2 of coordinate 0, all the first quantile step takes of it when the
+// item's first limit is in the lower half.  Per shift 2C + 1 rows of N
+// floats: row 0 that logarithm, row 1 + 2i coordinate i, row 2 + 2i its
+// complement.
 __global__ __launch_bounds__(256) void k_lattice_coords(LatticeArgs L, int C, float *__restrict__ coords) {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     const int i = blockIdx.y, s = blockIdx.z;
@@ -1328,9 +1332,12 @@ __global__ __launch_bounds__(256) void k_lattice_coords(LatticeArgs L, int C, fl
     const int sh = 32 - L.log2N;
     const uint32_t t = ((k * (uint32_t)L.z[i]) << sh) + (uint32_t)(L.shifts[s * LATD + i] * 4294967296.0);
     const float scale = i == 0 ? 1.0f : 4.656612873077393e-10f;      // 2^-31 past coordinate 0
-    float *row = coords + ((size_t)(s * C + i) * 2) * L.N;
-    row[k] = tent_units(t) * scale;
+    float *shift = coords + (size_t)s * (2 * C + 1) * L.N;
+    float *row = shift + (size_t)(1 + 2 * i) * L.N;
+    const float v = tent_units(t) * scale;
+    row[k] = v;
     row[L.N + k] = tent_units(t ^ 0x80000000u) * scale;
+    if (i == 0) shift[k] = flog2(v);
 }
 
 hipError_t launch_lattice_coords(const LatticeArgs &L, int C, float *coords, hipStream_t s) {

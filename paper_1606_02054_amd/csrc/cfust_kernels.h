@@ -232,7 +232,7 @@ hipError_t launch_assemble(const EstepAsmArgs &a, hipStream_t s);
 // others scaled (the values the FP32 integrand forms in its loop).
 hipError_t launch_lattice_coords(const LatticeArgs &L, int C, float *coords, hipStream_t s);
 // Floats of that table.
-inline size_t lattice_coords_floats(int N, int S, int C) { return (size_t)2 * C * N * S; }
+inline size_t lattice_coords_floats(int N, int S, int C) { return (size_t)(2 * C + 1) * N * S; }
 hipError_t launch_lse(const EstepLseArgs &a, double *loglik, hipStream_t s);
 // Work areas of mvt_cdf_batch (m >= 2): per chunk of items the FP64 tables
 // ([chunk][m][TAB64_DOUBLES]) and, in mixed precision, the FP32 tables

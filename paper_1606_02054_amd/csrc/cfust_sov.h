@@ -283,15 +283,15 @@ __device__ __forceinline__ float tab_H_abs_s(const float *tab, float abs_s) {
 }
 
 // xu, xbu: the coordinate and its complement in units of 2^-31 (xbu unused
-// when LOW0).
-template <bool LOW0>
+// when LOW0); with L2X (LOW0 only), xu is already log2 of the coordinate.
+template <bool LOW0, bool L2X = false>
 __device__ __forceinline__ float quantile_step32_first_u(const Sov32Setup &P, float xu, float xbu, const float *tab,
                                                          float &Q) {
     bool lower;
     float l2q;
     if (LOW0) {
         lower = true;
-        l2q = flog2(xu) + P.l2e0m31;
+        l2q = (L2X ? xu : flog2(xu)) + P.l2e0m31;
     } else {
         const float p = xu * P.e0s;
         const float pb = fmaf(xbu, P.e0s, P.eb0);
@@ -361,12 +361,14 @@ __device__ __forceinline__ float sov_point32(const Sov32Setup &P, const float *t
 // The same point (E-step tables, fine layout), with its coordinates read from
 // the E-step's coordinate table instead of formed from the lattice: c[2i] is coordinate i and
 // c[2i + 1] its complement, coordinate 0 in units of 2^-31 and the others
-// scaled -- the values point32 / tent_units form, bit for bit.
+// scaled -- the values point32 / tent_units form, bit for bit.  Under LOW0,
+// c[0] is log2 of coordinate 0 (in those units), the value the first quantile
+// step would take of it.
 template <int M, bool LOW0>
 __device__ __forceinline__ float sov_point32_c(const Sov32Setup &P, const float *tabs, const float *c) {
     float y[M];
     float Q = P.sqrtnu;
-    y[0] = quantile_step32_first_u<LOW0>(P, c[0], c[1], tabs, Q);
+    y[0] = quantile_step32_first_u<LOW0, LOW0>(P, c[0], c[1], tabs, Q);
     float f = 1.0f;
 #pragma unroll
     for (int i = 1; i < M; ++i) {
@@ -388,19 +390,22 @@ __device__ __forceinline__ float sov_point32_c(const Sov32Setup &P, const float 
 }
 
 // Loads of one trip's coordinates through a buffer resource over the shift's
-// table (rows of N floats: 2i coordinate i, 2i + 1 its complement): the lane
-// offset is the vector offset and the row and trip go in the scalar offset,
-// so no vector instruction forms an address.  Under LOW0 the complement of
-// coordinate 0 is not read.
+// table (rows of N floats: row 0 log2 of coordinate 0, row 1 + 2i coordinate
+// i, row 2 + 2i its complement): the lane offset is the vector offset and
+// the row and trip go in the scalar offset, so no vector instruction forms an
+// address.  Under LOW0 the first quantile needs only log2 of coordinate 0, so
+// c[0] is that logarithm and coordinate 0 itself and its complement are not
+// read.
 constexpr int BUF_RSRC_WORD3 = 0x00020000;     // raw buffer, 32-bit elements (gfx9 family)
 
 template <int M, bool LOW0>
 __device__ __forceinline__ void load_coords(__amdgpu_buffer_rsrc_t r, int vo, int so, int row_bytes, float *c) {
 #pragma unroll
     for (int i = 0; i < M - 1; ++i) {
-        c[2 * i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so + 2 * i * row_bytes, 0));
+        const int row = (i == 0 && LOW0) ? 0 : 1 + 2 * i;
+        c[2 * i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so + row * row_bytes, 0));
         c[2 * i + 1] = (i == 0 && LOW0) ? 0.0f
-                     : __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so + (2 * i + 1) * row_bytes, 0));
+                     : __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so + (2 + 2 * i) * row_bytes, 0));
     }
 }
 
@@ -419,10 +424,10 @@ template <int M, bool LOW0>
 __device__ __forceinline__ float sov_lane_sum32_c(const Sov32Setup &P, const float *tabs, const float *cshift, int N,
                                                   int lane) {
 #pragma clang fp contract(off)
-    constexpr int R = 2 * (M - 1);
+    constexpr int R = 2 * (M - 1);              // coordinates and complements per point
     const int row_bytes = N * 4;
     const __amdgpu_buffer_rsrc_t rs =
-        __builtin_amdgcn_make_buffer_rsrc((void *)cshift, (short)0, R * row_bytes, BUF_RSRC_WORD3);
+        __builtin_amdgcn_make_buffer_rsrc((void *)cshift, (short)0, (R + 1) * row_bytes, BUF_RSRC_WORD3);
     const int vo = lane * 4;
     const int trips = N / 64;
     float acc = 0.0f;
@@ -638,7 +643,7 @@ __device__ __forceinline__ bool sov_mixed(const SovHead &H, const double *b, con
         for (int i = 0; i < M - 1; ++i) shfix[i] = (uint32_t)(Lt.shifts[s * LATD + i] * 4294967296.0);
         float ls;
         if (COORDS) {
-            const float *cshift = coords + (size_t)s * C * 2 * Lt.N;
+            const float *cshift = coords + (size_t)s * (2 * C + 1) * Lt.N;
             ls = P.low0 ? sov_lane_sum32_c<M, true>(P, tabs, cshift, Lt.N, lane)
                         : sov_lane_sum32_c<M, false>(P, tabs, cshift, Lt.N, lane);
         } else {
