@@ -37,29 +37,29 @@ PEAK_FP32_TFLOPS = 157.3     # MI355X vector FP32 (chip figure: 2 wave64 FMA iss
 # again (profiles/k_estep_qmc_counters.md).
 TRAFFIC_SOURCES = ["paper_1606_02054_amd/csrc/cfust_sov.h", "paper_1606_02054_amd/csrc/cfust_devmath.h",
                    "paper_1606_02054_amd/csrc/cfust_estep.hip", "paper_1606_02054_amd/csrc/cfust_common.h"]
-KERNEL_DIGEST = "6056f3f912cebef6"
+KERNEL_DIGEST = "33be3e2e90605150"
 # FP32 arithmetic of one lattice point of the m-variate integrand in the FP32
 # lattice kernel: (2 x SQ_INSTS_VALU_FMA_F32 + MUL_F32 + ADD_F32 + TRANS_F32)
 # of a launch divided by the lattice points it evaluates.
-LATTICE_FLOPS_PER_POINT = {2: 41.99, 3: 87.3, 4: 134.32, 5: 183.13, 6: 234.19, 7: 287.19, 8: 342.21}
+LATTICE_FLOPS_PER_POINT = {2: 41.49, 3: 86.95, 4: 133.98, 5: 182.69, 6: 233.78, 7: 286.78, 8: 341.81}
 # VALU issue of each kernel from SQ_INSTS_VALU, SQ_ACTIVE_INST_VALU2 and
 # GRBM_GUI_ACTIVE: wave64 VALU instructions per CU per cycle (the chip issues
 # at most 2: one pair per SIMD per 4-cycle slot) and the share of them issued
 # in pairs.
 LATTICE_VALU_ISSUE = {
-    2: {'valu_per_point': 45.0, 'valu_per_cu_cycle': 0.951, 'dual_issue_frac': 0.414, 'valu_slot_busy': 0.884},
-    3: {'valu_per_point': 92.5, 'valu_per_cu_cycle': 1.107, 'dual_issue_frac': 0.553, 'valu_slot_busy': 0.947},
-    4: {'valu_per_point': 139.6, 'valu_per_cu_cycle': 1.071, 'dual_issue_frac': 0.510, 'valu_slot_busy': 0.938},
-    5: {'valu_per_point': 187.0, 'valu_per_cu_cycle': 1.004, 'dual_issue_frac': 0.476, 'valu_slot_busy': 0.895},
-    6: {'valu_per_point': 237.3, 'valu_per_cu_cycle': 1.130, 'dual_issue_frac': 0.526, 'valu_slot_busy': 0.976},
-    7: {'valu_per_point': 287.4, 'valu_per_cu_cycle': 1.061, 'dual_issue_frac': 0.470, 'valu_slot_busy': 0.945},
-    8: {'valu_per_point': 338.1, 'valu_per_cu_cycle': 0.992, 'dual_issue_frac': 0.447, 'valu_slot_busy': 0.894},
+    2: {'valu_per_point': 44.5, 'valu_per_cu_cycle': 0.963, 'dual_issue_frac': 0.432, 'valu_slot_busy': 0.877},
+    3: {'valu_per_point': 92.1, 'valu_per_cu_cycle': 1.120, 'dual_issue_frac': 0.559, 'valu_slot_busy': 0.951},
+    4: {'valu_per_point': 139.2, 'valu_per_cu_cycle': 1.077, 'dual_issue_frac': 0.514, 'valu_slot_busy': 0.939},
+    5: {'valu_per_point': 186.6, 'valu_per_cu_cycle': 1.012, 'dual_issue_frac': 0.481, 'valu_slot_busy': 0.898},
+    6: {'valu_per_point': 236.9, 'valu_per_cu_cycle': 1.134, 'dual_issue_frac': 0.531, 'valu_slot_busy': 0.976},
+    7: {'valu_per_point': 286.9, 'valu_per_cu_cycle': 1.067, 'dual_issue_frac': 0.472, 'valu_slot_busy': 0.949},
+    8: {'valu_per_point': 337.7, 'valu_per_cu_cycle': 0.992, 'dual_issue_frac': 0.446, 'valu_slot_busy': 0.893},
 }
 # HBM bytes per launch of the FP32 lattice kernel of each dimension at the
 # default workload (MiB read, MiB written: FETCH_SIZE x 2 and WRITE_SIZE x 1 in
 # KiB, the factors that a 1 GiB device copy gives these counters).
-TRAFFIC_MIB = {4: (2 * 11111.3 / 1024, 7490.9 / 1024), 3: (2 * 4528.5 / 1024, 6044.8 / 1024),
-               2: (2 * 3498.0 / 1024, 7752.3 / 1024)}
+TRAFFIC_MIB = {4: (2 * 12142.7 / 1024, 8148.2 / 1024), 3: (2 * 5036.5 / 1024, 6453.3 / 1024),
+               2: (2 * 4006.0 / 1024, 7854.1 / 1024)}
 
 
 def kernel_digest() -> str:
