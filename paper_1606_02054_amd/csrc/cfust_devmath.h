@@ -323,6 +323,18 @@ __device__ __forceinline__ float tabf_cdf_H(const float *tab, float pos) {
     return tab_cubic(tab + 4 * k, __builtin_amdgcn_fractf(pos));
 }
 
+// H(tau) given x = 1 + tau (clamped into [1, 2), NaN included): the top 6
+// mantissa bits of x are the row (the integer part of 64 tau) and the other
+// 17 the position inside it, as the float 1 + low 2^-23 in [1, 1 + 1/64),
+// position = 64 (that - 1), exact.  No conversion instruction is needed.
+static_assert(TABF_CDF_ROWS == 64, "the CDF rows are indexed by 6 mantissa bits");
+__device__ __forceinline__ float tabf_cdf_H_1p(const float *tab, float x) {
+    x = fminf(fmaxf(x, 1.0f), 1.99999988f);
+    const uint32_t bits = __float_as_uint(x);
+    const float t = fmaf(__uint_as_float((bits & 0x0001FFFFu) | 0x3F800000u), 64.0f, -64.0f);
+    return tab_cubic(reinterpret_cast<const float *>(reinterpret_cast<const char *>(tab) + ((bits >> 13) & 0x3F0u)), t);
+}
+
 // log2 tau at l2p = log2 p.  -l2p = lambda + 1, clamped to [1, 512): l2p is
 // clamped to [-512, -1) (NaN included) instead, whose bits carry the sign bit
 // above the same biased exponent 127..135, so bits >> 20 (sign, exponent and

@@ -268,7 +268,7 @@ __device__ __forceinline__ void point32(uint32_t t, float &x, float &xb) {
 struct Sov32Setup {
     float b[MAXQ];
     float L[MAXQ * MAXQ];      // row-major, stride M
-    float a[MAXQ];             // (nu + i)/2
+    float a[MAXQ];             // nu + i (mixed t path); 1 / L_ii (normal limit)
     float e0s, eb0, l2e0m31, sqrtnu;   // 2^-31 e_0, 1 - e_0, log2 e_0 - 31
     float e0, l2e0;                     // e_0, log2 e_0 (normal limit)
     bool low0;
@@ -276,10 +276,10 @@ struct Sov32Setup {
 
 // The FP32 t-law lookups of the fine-layout slots (TABF_FLOATS per dof):
 // log2 tau of the quantile, and log2 T_lower less a log2(tau (2 - tau)) at
-// tau = 1 - |s|, given |s|.
+// tau = 1 - |s|, given s = num R (1 + tau = 2 - |num| R, one FMA).
 __device__ __forceinline__ float tab_G(const float *tab, float l2p) { return tabf_inv_G(tab, l2p); }
-__device__ __forceinline__ float tab_H_abs_s(const float *tab, float abs_s) {
-    return tabf_cdf_H(tab, fmaf(-64.0f, abs_s, 64.0f));
+__device__ __forceinline__ float tab_H_num_R(const float *tab, float num, float R) {
+    return tabf_cdf_H_1p(tab, fmaf(-fabsf(num), R, 2.0f));
 }
 
 // xu, xbu: the coordinate and its complement in units of 2^-31 (xbu unused
@@ -300,7 +300,7 @@ __device__ __forceinline__ float quantile_step32_first_u(const Sov32Setup &P, fl
     }
     const float tq = fexp2(tab_G(tab, l2q));
     const float sabs = 1.0f - tq;
-    Q = fminf(Q * frsq(tq * (2.0f - tq)), 1e15f);
+    Q = fminf(Q * frsq(fmaf(tq, sabs, tq)), 1e15f);      // tau (2 - tau) = tau + tau (1 - tau)
     return (lower ? -sabs : sabs) * Q;
 }
 
@@ -322,7 +322,7 @@ __device__ __forceinline__ float quantile_step32(float x, float xb, float e, flo
     const bool lower = p <= 0.5f;
     const float tq = fexp2(tab_G(tab, flog2(lower ? p : pb)));
     const float sabs = 1.0f - tq;
-    Q = fminf(Q * frsq(tq * (2.0f - tq)), 1e15f);
+    Q = fminf(Q * frsq(fmaf(tq, sabs, tq)), 1e15f);      // tau (2 - tau) = tau + tau (1 - tau)
     return (lower ? -sabs : sabs) * Q;
 }
 
@@ -338,14 +338,13 @@ __device__ __forceinline__ float sov_point32(const Sov32Setup &P, const float *t
         float num = P.b[i];
 #pragma unroll
         for (int j = 0; j < i; ++j) num = fmaf(-P.L[i * M + j], y[j], num);
-        // lower-tail probability of the conditional t: with s = num / sqrt(num^2 + K),
-        // log2 T_lower = a log2(1 - s^2) + H(1 - |s|), and 1 - s^2 = K R^2 needs no division
-        const float LQ = P.L[i * M + i] * Q;
-        const float K = LQ * LQ;
-        const float R = frsq(fmaf(num, num, K));
-        const float KR2 = K * R * R;
+        // lower-tail probability of the conditional t (row i of b and L divided by
+        // L_ii): with R = 1 / sqrt(num^2 + Q^2) and s = num R, log2 T_lower =
+        // ((nu + i)/2) log2(1 - s^2) + H(1 - |s|), and 1 - s^2 = (Q R)^2, so the
+        // power law is (nu + i) log2(Q R): no division
+        const float R = frsq(fmaf(num, num, Q * Q));
         const float *tab = tabs + i * TABF_FLOATS;
-        const float l2 = fmaf(P.a[i], flog2(KR2), tab_H_abs_s(tab, fabsf(num) * R));
+        const float l2 = fmaf(P.a[i], flog2(Q * R), tab_H_num_R(tab, num, R));
         const float small = fexp2(l2);
         const float e = num <= 0.0f ? small : 1.0f - small;
         f *= e;
@@ -375,12 +374,9 @@ __device__ __forceinline__ float sov_point32_c(const Sov32Setup &P, const float 
         float num = P.b[i];
 #pragma unroll
         for (int j = 0; j < i; ++j) num = fmaf(-P.L[i * M + j], y[j], num);
-        const float LQ = P.L[i * M + i] * Q;
-        const float K = LQ * LQ;
-        const float R = frsq(fmaf(num, num, K));
-        const float KR2 = K * R * R;
+        const float R = frsq(fmaf(num, num, Q * Q));
         const float *tab = tabs + i * TABF_FLOATS;
-        const float l2 = fmaf(P.a[i], flog2(KR2), tab_H_abs_s(tab, fabsf(num) * R));
+        const float l2 = fmaf(P.a[i], flog2(Q * R), tab_H_num_R(tab, num, R));
         const float small = fexp2(l2);
         const float e = num <= 0.0f ? small : 1.0f - small;
         f *= e;
@@ -626,10 +622,16 @@ template <int M, int PPL, bool COORDS = false>
 __device__ __forceinline__ bool sov_mixed(const SovHead &H, const double *b, const double *L, double nu, const Lattice &Lt,
                           const float *tabs, double *smean, int lane, const float *coords = nullptr, int C = 0) {
     Sov32Setup P;
+    // rows 1.. of b and L divided by their diagonal (FP64, then rounded): the
+    // conditional limit of coordinate i is then num / Q, with no product by L_ii
 #pragma unroll
-    for (int i = 0; i < M; ++i) { P.b[i] = (float)b[i]; P.a[i] = (float)(0.5 * (nu + i)); }
+    for (int i = 0; i < M; ++i) {
+        const double d = i > 0 ? L[i * M + i] : 1.0;
+        P.b[i] = (float)(b[i] / d);
+        P.a[i] = (float)(nu + i);
 #pragma unroll
-    for (int i = 0; i < M * M; ++i) P.L[i] = (float)L[i];
+        for (int j = 0; j < M; ++j) P.L[i * M + j] = (float)(L[i * M + j] / d);
+    }
     P.e0s = (float)(H.e0 * 4.656612873077393e-10); P.eb0 = (float)H.eb0;
     P.l2e0m31 = (float)(H.lne0 / LN2 - 31.0); P.low0 = H.low0;
     P.sqrtnu = (float)sqrt(nu);
