@@ -148,7 +148,7 @@ cfust_status cfust_estep(cfust_handle handle, const double *y, cfust_dims dims,
  * that the library holds on every device it is loaded on until the process
  * ends (its address is looked up once per device by cfust_create).  The call
  * makes no hipMalloc, hipFree or other allocating call and records no
- * profiling events.  Workspace needed: about g n (12 J + 16) bytes plus 76 KB
+ * profiling events.  Workspace needed: about g n (12 J + 16) bytes plus 85 KB
  * per component, J = lattice integrals per pair (2 at q = 2, 12 at q = 4,
  * 38 at q = 8), plus (8 (q - 1) + 4) N S bytes of lattice coordinates in mixed
  * precision when that table is at most 16 MB (e.g. n up to ~26000 at

@@ -37,18 +37,26 @@ constexpr float INV_LAMBDA_MAX = 511.0f;
 // 16-byte row and takes three FMAs:
 //   rows 0..63   : H(tau) on 64 equal intervals of tau, a cubic in the
 //                  position inside the interval (fraction of 64 tau);
-//   rows 64..135 : log2 tau against lambda on the 9 octaves of lambda + 1 =
+//   rows 64..191 : log2 tau against lambda on the 9 octaves of lambda + 1 =
 //                  -log2 p in [1, 512), each cut into 8 equal parts, a cubic
 //                  in the position inside the part (the low 20 mantissa bits
-//                  of -log2 p, whose exponent and top 3 mantissa bits give
-//                  the row).
+//                  of log2 p).  The part's row is the low 4 bits of the
+//                  exponent of log2 p and its top 3 mantissa bits, so no
+//                  offset is subtracted in the lookup: octaves 2^1 .. 2^8
+//                  (exponents 128..135) are rows 64 + 0..63, octave 2^0
+//                  (exponent 127) rows 64 + 120..127, and rows 64 + 64..119
+//                  are unused (zero).
 // A normal-limit slot (dof infinite) holds the dof-free table above in its
 // first TAB_FLOATS floats.
 constexpr int TABF_CDF_ROWS = 64;
 constexpr int TABF_INV_OCTAVES = 9;
 constexpr int TABF_INV_PARTS = 8;
-constexpr int TABF_INV_ROWS = TABF_INV_OCTAVES * TABF_INV_PARTS;  // 72
-constexpr int TABF_FLOATS = 4 * (TABF_CDF_ROWS + TABF_INV_ROWS);  // 544 floats per dof
+constexpr int TABF_INV_ROWS = TABF_INV_OCTAVES * TABF_INV_PARTS;  // 72 rows with values
+constexpr int TABF_INV_SLOTS = 128;                               // rows they span
+constexpr int TABF_FLOATS = 4 * (TABF_CDF_ROWS + TABF_INV_SLOTS); // 768 floats per dof
+static_assert(TABF_INV_OCTAVES <= 16 && TABF_INV_PARTS == 8, "octave rows are indexed by 4 exponent bits");
+// Slot of quantile row r (r = 8 octave + part, octave 0 the one of lambda + 1 in [1, 2)).
+__host__ __device__ constexpr int tabf_inv_slot(int r) { return (r + 15 * TABF_INV_PARTS) & (TABF_INV_SLOTS - 1); }
 static_assert(TABF_FLOATS >= TAB_FLOATS, "a fine slot holds a normal-limit table");
 
 // FP64 tables of the univariate t law for one dof (FP64 integrand), the same

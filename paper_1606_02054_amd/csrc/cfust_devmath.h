@@ -336,17 +336,17 @@ __device__ __forceinline__ float tabf_cdf_H_1p(const float *tab, float x) {
 }
 
 // log2 tau at l2p = log2 p.  -l2p = lambda + 1, clamped to [1, 512): l2p is
-// clamped to [-512, -1) (NaN included) instead, whose bits carry the sign bit
-// above the same biased exponent 127..135, so bits >> 20 (sign, exponent and
-// top 3 mantissa bits) less 3064 are the row 0..71, and the low 20 mantissa
-// bits the position inside it: as the float 1 + low 2^-23 in [1, 9/8),
-// position = 8 (that - 1), exact.
+// clamped to [-512, -1) (NaN included) instead, whose biased exponent is
+// 127..135, so bits 20..26 (low 4 exponent bits and top 3 mantissa bits) are
+// the quantile slot (tabf_inv_slot) with no offset to subtract, and the low
+// 20 mantissa bits the position inside it: as the float 1 + low 2^-23 in
+// [1, 9/8), position = 8 (that - 1), exact.
 __device__ __forceinline__ float tabf_inv_G(const float *tab, float l2p) {
     const float zz = fminf(fmaxf(l2p, -511.999969f), -1.0f);
     const uint32_t bits = __float_as_uint(zz);
-    const int row = (int)(bits >> 20) - 3064;
     const float t = fmaf(__uint_as_float((bits & 0x000FFFFFu) | 0x3F800000u), 8.0f, -8.0f);
-    return tab_cubic(tab + 4 * (TABF_CDF_ROWS + row), t);
+    return tab_cubic(reinterpret_cast<const float *>(reinterpret_cast<const char *>(tab + 4 * TABF_CDF_ROWS) +
+                                                     ((bits >> 16) & 0x7F0u)), t);
 }
 
 // log2 tau from the quantile rows, given l2p = log2 p of the tail probability

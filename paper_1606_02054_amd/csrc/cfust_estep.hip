@@ -246,7 +246,7 @@ __device__ inline void table_fit_row(const double *f, float *dst, double alpha, 
 }
 
 constexpr int TAB_NODES = (TAB_CDF_ROWS + TAB_INV_ROWS) * 7;   // 133
-constexpr int TABF_NODES = (TABF_CDF_ROWS + TABF_INV_ROWS) * 4; // 544
+constexpr int TABF_NODES = (TABF_CDF_ROWS + TABF_INV_ROWS) * 4; // 544 node values per finite-dof slot
 
 // Row of a fine-layout table (cubic): the Chebyshev fit of the 4 node values
 // at x_n = cos(pi (n + 1/2) / 4) on [-1, 1], stored as monomial coefficients
@@ -325,9 +325,10 @@ __device__ inline double tablef_node_from64(double nu, const double *h64, int ro
 
 // One table slot (fine layout) of dof nu, written by a block of 192 threads.
 // Finite dof: the FP64 CDF rows first, then the 136 x 4 nodes from them, one
-// thread per row fitting it; infinite dof (normal limit): the dof-free closed
-// forms, in the compact layout at the start of the slot, the rest of the slot
-// zero.  Every thread of the block takes part.
+// thread per row fitting it into its slot row (the quantile rows at
+// tabf_inv_slot, the unused slot rows zero); infinite dof (normal limit): the
+// dof-free closed forms, in the compact layout at the start of the slot, the
+// rest of the slot zero.  Every thread of the block takes part.
 __device__ inline void table_slot_body(double nu, float *__restrict__ dst) {
     __shared__ double fv[TABF_NODES];
     __shared__ double fv64[TAB64_CDF_ROWS * TAB64_NC], h64[TAB64_CDF_ROWS * TAB64_NC];
@@ -343,7 +344,13 @@ __device__ inline void table_slot_body(double nu, float *__restrict__ dst) {
         build_cdf64(nu, fv64, h64, cos64);
         for (int u = t; u < TABF_NODES; u += blockDim.x) fv[u] = tablef_node_from64(nu, h64, u / 4, u % 4);
         __syncthreads();
-        if (t < TABF_CDF_ROWS + TABF_INV_ROWS) table_fit_row4(fv + 4 * t, dst + 4 * t, cos4);
+        if (t < TABF_CDF_ROWS + TABF_INV_ROWS) {
+            const int row = t < TABF_CDF_ROWS ? t : TABF_CDF_ROWS + tabf_inv_slot(t - TABF_CDF_ROWS);
+            table_fit_row4(fv + 4 * t, dst + 4 * row, cos4);
+        }
+        for (int u = 4 * (TABF_CDF_ROWS + tabf_inv_slot(TABF_INV_ROWS)) + t;
+             u < 4 * (TABF_CDF_ROWS + tabf_inv_slot(0)); u += blockDim.x)
+            dst[u] = 0.0f;
     }
 }
 
