@@ -254,11 +254,13 @@ __device__ __forceinline__ void point32(uint32_t t, float &x, float &xb) {
     xb = tent_units(t ^ 0x80000000u) * 4.656612873077393e-10f;
 }
 
-// The quantile steps below carry the conditional scale Q = sqrt(nu + sum y^2)
-// and cap it at 1e15: a point whose tau = 2^G underflows (G far below -100,
-// where 1/sqrt(tau (2 - tau)) exceeds 2^49, so Q, at least sqrt(nu) >= 1.26
-// for dof >= 1.6, passes the cap anyway) draws y = +-1e15, its quantile at
-// the cap, with no clamp on G.
+// The quantile steps below carry the conditional scale sqrt(nu + sum y^2) in
+// units of sqrt(nu), Q = sqrt(1 + sum y^2 / nu) (the draws y and the limits
+// are in the same units: the setup divides b_i by L_ii sqrt(nu)), and cap Q
+// at 1e15: a point whose tau = 2^G underflows (G below about -100, where
+// 1/sqrt(tau (2 - tau)) and so Q, at least 1, exceed 1e15) draws its quantile
+// at the cap, with no clamp on G.  What follows such a draw depends on the
+// cap only through limits of order b / 1e15.
 //
 // Quantile step of coordinate 0 (the truncation probability e_0 is the same
 // for every point).  LOW0: e_0 is a lower-tail probability that may be far
@@ -269,7 +271,7 @@ struct Sov32Setup {
     float b[MAXQ];
     float L[MAXQ * MAXQ];      // row-major, stride M
     float a[MAXQ];             // nu + i (mixed t path); 1 / L_ii (normal limit)
-    float e0s, eb0, l2e0m31, sqrtnu;   // 2^-31 e_0, 1 - e_0, log2 e_0 - 31
+    float e0s, eb0, l2e0m31;           // 2^-31 e_0, 1 - e_0, log2 e_0 - 31
     float e0, l2e0;                     // e_0, log2 e_0 (normal limit)
     bool low0;
 };
@@ -326,11 +328,13 @@ __device__ __forceinline__ float quantile_step32(float x, float xb, float e, flo
     return (lower ? -sabs : sabs) * Q;
 }
 
-// Integrand value of lattice point k (FP32), product e_1 ... e_{M-1}.
+// Integrand value of lattice point k (FP32), the product e_1 ... e_{M-1},
+// added to acc with weight w, its last factor in the same FMA.
 template <int M, bool LOW0>
-__device__ __forceinline__ float sov_point32(const Sov32Setup &P, const float *tabs, const uint32_t *t) {
+__device__ __forceinline__ void sov_point32(const Sov32Setup &P, const float *tabs, const uint32_t *t, float w,
+                                            float &acc) {
     float y[M];
-    float Q = P.sqrtnu;
+    float Q = 1.0f;
     y[0] = quantile_step32_first<LOW0>(P, t[0], tabs, Q);
     float f = 1.0f;
 #pragma unroll
@@ -347,14 +351,15 @@ __device__ __forceinline__ float sov_point32(const Sov32Setup &P, const float *t
         const float l2 = fmaf(P.a[i], flog2(Q * R), tab_H_num_R(tab, num, R));
         const float small = fexp2(l2);
         const float e = num <= 0.0f ? small : 1.0f - small;
-        f *= e;
         if (i < M - 1) {
+            f *= e;
             float x, xb;
             point32(t[i], x, xb);
             y[i] = quantile_step32(x, xb, e, small, tab, Q);
+        } else {
+            acc = fmaf(f, e * w, acc);      // w = 0 or 1: the same sum as the coordinate-table form
         }
     }
-    return f;
 }
 
 // The same point (E-step tables, fine layout), with its coordinates read from
@@ -362,11 +367,12 @@ __device__ __forceinline__ float sov_point32(const Sov32Setup &P, const float *t
 // c[2i + 1] its complement, coordinate 0 in units of 2^-31 and the others
 // scaled -- the values point32 / tent_units form, bit for bit.  Under LOW0,
 // c[0] is log2 of coordinate 0 (in those units), the value the first quantile
-// step would take of it.
+// step would take of it.  The point's product is added to acc, its last
+// factor in the same FMA.
 template <int M, bool LOW0>
-__device__ __forceinline__ float sov_point32_c(const Sov32Setup &P, const float *tabs, const float *c) {
+__device__ __forceinline__ void sov_point32_c(const Sov32Setup &P, const float *tabs, const float *c, float &acc) {
     float y[M];
-    float Q = P.sqrtnu;
+    float Q = 1.0f;
     y[0] = quantile_step32_first_u<LOW0, LOW0>(P, c[0], c[1], tabs, Q);
     float f = 1.0f;
 #pragma unroll
@@ -379,10 +385,13 @@ __device__ __forceinline__ float sov_point32_c(const Sov32Setup &P, const float 
         const float l2 = fmaf(P.a[i], flog2(Q * R), tab_H_num_R(tab, num, R));
         const float small = fexp2(l2);
         const float e = num <= 0.0f ? small : 1.0f - small;
-        f *= e;
-        if (i < M - 1) y[i] = quantile_step32(c[2 * i], c[2 * i + 1], e, small, tab, Q);
+        if (i < M - 1) {
+            f *= e;
+            y[i] = quantile_step32(c[2 * i], c[2 * i + 1], e, small, tab, Q);
+        } else {
+            acc = fmaf(f, e, acc);
+        }
     }
-    return f;
 }
 
 // Loads of one trip's coordinates through a buffer resource over the shift's
@@ -407,15 +416,14 @@ __device__ __forceinline__ void load_coords(__amdgpu_buffer_rsrc_t r, int vo, in
 
 // Per-lane FP32 sum over the shift's points from the coordinate table
 // `cshift` (N a multiple of 64; lane l takes points l, l + 64, ...).  At
-// m = 2 a point is short (about 45 VALU), so its coordinates are loaded one
+// m = 2 a point is short (about 40 VALU), so its coordinates are loaded one
 // trip ahead into an alternating pair of register sets (the load after the
 // last even trip re-reads that trip's own coordinates, so every load stays
 // inside the table); at larger m the loads of a trip are waited for where
 // the point first needs them and the other resident waves cover their
-// latency (loading ahead there only cost registers).  The point's value is
-// rounded before it is added (no contraction of its last product into the
-// sum), as in the loop that forms the coordinates itself, so both give the
-// same sums bit for bit.
+// latency (loading ahead there only cost registers).  Each point's product
+// enters the sum with its last factor in one FMA, as in the loop that forms
+// the coordinates itself, so both give the same sums bit for bit.
 template <int M, bool LOW0>
 __device__ __forceinline__ float sov_lane_sum32_c(const Sov32Setup &P, const float *tabs, const float *cshift, int N,
                                                   int lane) {
@@ -433,16 +441,16 @@ __device__ __forceinline__ float sov_lane_sum32_c(const Sov32Setup &P, const flo
         int it = 0;
         for (; it + 2 <= trips; it += 2) {
             load_coords<M, LOW0>(rs, vo, (it + 1) * 256, row_bytes, c1);
-            acc += sov_point32_c<M, LOW0>(P, tabs, c0);
+            sov_point32_c<M, LOW0>(P, tabs, c0, acc);
             load_coords<M, LOW0>(rs, vo, min(it + 2, trips - 1) * 256, row_bytes, c0);
-            acc += sov_point32_c<M, LOW0>(P, tabs, c1);
+            sov_point32_c<M, LOW0>(P, tabs, c1, acc);
         }
-        if (it < trips) acc += sov_point32_c<M, LOW0>(P, tabs, c0);
+        if (it < trips) sov_point32_c<M, LOW0>(P, tabs, c0, acc);
     } else {
         float c[R];
         for (int it = 0; it < trips; ++it) {
             load_coords<M, LOW0>(rs, vo, it * 256, row_bytes, c);
-            acc += sov_point32_c<M, LOW0>(P, tabs, c);
+            sov_point32_c<M, LOW0>(P, tabs, c, acc);
         }
     }
     return acc;
@@ -506,19 +514,18 @@ __device__ __forceinline__ float sov_lane_sum32_f(const Sov32Setup &P, const flo
 #pragma unroll
         for (int u = 0; u < PPL; ++u) t[u][i] = (((uint32_t)(lane + 64 * u) * zz[i]) << sh) + shfix[i];
     }
-    auto point = [&](const uint32_t *tt) {
-        return NORMAL ? sov_point32_normal<M>(P, tabs, tt) : sov_point32<M, LOW0>(P, tabs, tt);
+    // a point's product into acc, weighted by w (0 or 1)
+    auto point = [&](const uint32_t *tt, float w, float &a) {
+        if constexpr (NORMAL) a = fmaf(sov_point32_normal<M>(P, tabs, tt), w, a);
+        else sov_point32<M, LOW0>(P, tabs, tt, w, a);
     };
     // N < 64 (PPL 1): one trip in which the lanes at or past N weigh 0
     const float wl = (N >= 64 * PPL || lane < N) ? 1.0f : 0.0f;
     const int trips = max(N / (64 * PPL), 1);
     float acc = 0.0f;
     for (int it = 0; it < trips; ++it) {
-        float f[PPL];
 #pragma unroll
-        for (int u = 0; u < PPL; ++u) f[u] = point(t[u]);
-#pragma unroll
-        for (int u = 0; u < PPL; ++u) acc = fmaf(f[u], wl, acc);
+        for (int u = 0; u < PPL; ++u) point(t[u], wl, acc);
 #pragma unroll
         for (int u = 0; u < PPL; ++u)
 #pragma unroll
@@ -622,19 +629,20 @@ template <int M, int PPL, bool COORDS = false>
 __device__ __forceinline__ bool sov_mixed(const SovHead &H, const double *b, const double *L, double nu, const Lattice &Lt,
                           const float *tabs, double *smean, int lane, const float *coords = nullptr, int C = 0) {
     Sov32Setup P;
-    // rows 1.. of b and L divided by their diagonal (FP64, then rounded): the
-    // conditional limit of coordinate i is then num / Q, with no product by L_ii
+    // rows 1.. of b and L divided by their diagonal, b also by sqrt(nu) (FP64,
+    // then rounded): the conditional limit of coordinate i is then num / Q,
+    // with no product by L_ii or sqrt(nu) in the loop
+    const double rnu = sqrt(nu);
 #pragma unroll
     for (int i = 0; i < M; ++i) {
         const double d = i > 0 ? L[i * M + i] : 1.0;
-        P.b[i] = (float)(b[i] / d);
+        P.b[i] = (float)(i > 0 ? b[i] / (d * rnu) : b[i]);
         P.a[i] = (float)(nu + i);
 #pragma unroll
         for (int j = 0; j < M; ++j) P.L[i * M + j] = (float)(L[i * M + j] / d);
     }
     P.e0s = (float)(H.e0 * 4.656612873077393e-10); P.eb0 = (float)H.eb0;
     P.l2e0m31 = (float)(H.lne0 / LN2 - 31.0); P.low0 = H.low0;
-    P.sqrtnu = (float)sqrt(nu);
     uint32_t zz[M], shfix[M];
     const int sh = 32 - Lt.log2N;
 #pragma unroll
@@ -674,7 +682,6 @@ __device__ __forceinline__ bool sov_mixed_normal(const SovHead &H, const double 
     P.e0s = (float)(H.e0 * 4.656612873077393e-10); P.eb0 = (float)H.eb0;
     P.l2e0m31 = (float)(H.lne0 / LN2 - 31.0); P.low0 = H.low0;
     P.e0 = (float)H.e0; P.l2e0 = (float)(H.lne0 / LN2);
-    P.sqrtnu = 1.0f;
     uint32_t zz[M], shfix[M];
     const int sh = 32 - Lt.log2N;
 #pragma unroll
