@@ -340,9 +340,15 @@ __device__ __forceinline__ float tabf_cdf_H_1p(const float *tab, float x) {
 // 127..135, so bits 20..26 (low 4 exponent bits and top 3 mantissa bits) are
 // the quantile slot (tabf_inv_slot) with no offset to subtract, and the low
 // 20 mantissa bits the position inside it: as the float 1 + low 2^-23 in
-// [1, 9/8), position = 8 (that - 1), exact.
+// [1, 9/8), position = 8 (that - 1), exact.  Without CLAMP, l2p must be at
+// least -512 and at most -1 or log2 of an FP32 p in [0, 1/2] (rounded up to
+// 1/2 + ulp at most): log2 p is
+// then in [-149, -1] (exponents 127..134, inside the rows), -inf at p = 0
+// reads a valid row, and a p just above 1/2 (exponent 126) reads an unused
+// zero row, log2 tau = 0, the centre, as it should.
+template <bool CLAMP = true>
 __device__ __forceinline__ float tabf_inv_G(const float *tab, float l2p) {
-    const float zz = fminf(fmaxf(l2p, -511.999969f), -1.0f);
+    const float zz = CLAMP ? fminf(fmaxf(l2p, -511.999969f), -1.0f) : l2p;
     const uint32_t bits = __float_as_uint(zz);
     const float t = fmaf(__uint_as_float((bits & 0x000FFFFFu) | 0x3F800000u), 8.0f, -8.0f);
     return tab_cubic(reinterpret_cast<const float *>(reinterpret_cast<const char *>(tab + 4 * TABF_CDF_ROWS) +

@@ -280,6 +280,8 @@ struct Sov32Setup {
 // log2 tau of the quantile, and log2 T_lower less a log2(tau (2 - tau)) at
 // tau = 1 - |s|, given s = num R (1 + tau = 2 - |num| R, one FMA).
 __device__ __forceinline__ float tab_G(const float *tab, float l2p) { return tabf_inv_G(tab, l2p); }
+// The same for l2p = log2 p of an FP32 p in [0, 1/2] (no clamp needed).
+__device__ __forceinline__ float tab_G_p(const float *tab, float l2p) { return tabf_inv_G<false>(tab, l2p); }
 __device__ __forceinline__ float tab_H_num_R(const float *tab, float num, float R) {
     return tabf_cdf_H_1p(tab, fmaf(-fabsf(num), R, 2.0f));
 }
@@ -300,7 +302,9 @@ __device__ __forceinline__ float quantile_step32_first_u(const Sov32Setup &P, fl
         lower = p <= 0.5f;
         l2q = flog2(lower ? p : pb);
     }
-    const float tq = fexp2(tab_G(tab, l2q));
+    // LOW0: log2 e_0 may be far below the FP32 range, so l2q is clamped
+    // below (above, l2q <= log2 e_0 <= -1 already)
+    const float tq = fexp2(tab_G_p(tab, LOW0 ? fmaxf(l2q, -511.999969f) : l2q));
     const float sabs = 1.0f - tq;
     Q = fminf(Q * frsq(fmaf(tq, sabs, tq)), 1e15f);      // tau (2 - tau) = tau + tau (1 - tau)
     return (lower ? -sabs : sabs) * Q;
@@ -322,7 +326,7 @@ __device__ __forceinline__ float quantile_step32(float x, float xb, float e, flo
     const float p = x * e;
     const float pb = fmaf(xb, e, small);
     const bool lower = p <= 0.5f;
-    const float tq = fexp2(tab_G(tab, flog2(lower ? p : pb)));
+    const float tq = fexp2(tab_G_p(tab, flog2(lower ? p : pb)));
     const float sabs = 1.0f - tq;
     Q = fminf(Q * frsq(fmaf(tq, sabs, tq)), 1e15f);      // tau (2 - tau) = tau + tau (1 - tau)
     return (lower ? -sabs : sabs) * Q;
