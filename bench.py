@@ -37,7 +37,7 @@ PEAK_FP32_TFLOPS = 157.3     # MI355X vector FP32 (chip figure: 2 wave64 FMA iss
 # again (profiles/k_estep_qmc_counters.md).
 TRAFFIC_SOURCES = ["paper_1606_02054_amd/csrc/cfust_sov.h", "paper_1606_02054_amd/csrc/cfust_devmath.h",
                    "paper_1606_02054_amd/csrc/cfust_estep.hip", "paper_1606_02054_amd/csrc/cfust_common.h"]
-KERNEL_DIGEST = "fcaa27ef4561d7e3"
+KERNEL_DIGEST = "f55a6781832900f4"
 # FP32 arithmetic of one lattice point of the m-variate integrand in the FP32
 # lattice kernel: (2 x SQ_INSTS_VALU_FMA_F32 + MUL_F32 + ADD_F32 + TRANS_F32)
 # of a launch divided by the lattice points it evaluates.
@@ -47,19 +47,19 @@ LATTICE_FLOPS_PER_POINT = {2: 39.49, 3: 83.95, 4: 129.98, 5: 177.69, 6: 227.78, 
 # at most 2: one pair per SIMD per 4-cycle slot) and the share of them issued
 # in pairs.
 LATTICE_VALU_ISSUE = {
-    2: {'valu_per_point': 39.6, 'valu_per_cu_cycle': 0.960, 'dual_issue_frac': 0.483, 'valu_slot_busy': 0.865},
-    3: {'valu_per_point': 82.2, 'valu_per_cu_cycle': 1.092, 'dual_issue_frac': 0.559, 'valu_slot_busy': 0.944},
-    4: {'valu_per_point': 125.4, 'valu_per_cu_cycle': 1.068, 'dual_issue_frac': 0.521, 'valu_slot_busy': 0.942},
-    5: {'valu_per_point': 168.9, 'valu_per_cu_cycle': 0.995, 'dual_issue_frac': 0.487, 'valu_slot_busy': 0.894},
-    6: {'valu_per_point': 215.3, 'valu_per_cu_cycle': 1.119, 'dual_issue_frac': 0.531, 'valu_slot_busy': 0.977},
-    7: {'valu_per_point': 261.5, 'valu_per_cu_cycle': 1.058, 'dual_issue_frac': 0.483, 'valu_slot_busy': 0.948},
-    8: {'valu_per_point': 308.5, 'valu_per_cu_cycle': 1.000, 'dual_issue_frac': 0.467, 'valu_slot_busy': 0.902},
+    2: {'valu_per_point': 39.1, 'valu_per_cu_cycle': 0.960, 'dual_issue_frac': 0.482, 'valu_slot_busy': 0.868},
+    3: {'valu_per_point': 80.6, 'valu_per_cu_cycle': 1.084, 'dual_issue_frac': 0.558, 'valu_slot_busy': 0.941},
+    4: {'valu_per_point': 122.8, 'valu_per_cu_cycle': 1.056, 'dual_issue_frac': 0.520, 'valu_slot_busy': 0.936},
+    5: {'valu_per_point': 165.3, 'valu_per_cu_cycle': 0.991, 'dual_issue_frac': 0.487, 'valu_slot_busy': 0.893},
+    6: {'valu_per_point': 210.7, 'valu_per_cu_cycle': 1.112, 'dual_issue_frac': 0.533, 'valu_slot_busy': 0.973},
+    7: {'valu_per_point': 256.0, 'valu_per_cu_cycle': 1.039, 'dual_issue_frac': 0.473, 'valu_slot_busy': 0.939},
+    8: {'valu_per_point': 301.9, 'valu_per_cu_cycle': 0.984, 'dual_issue_frac': 0.469, 'valu_slot_busy': 0.891},
 }
 # HBM bytes per launch of the FP32 lattice kernel of each dimension at the
 # default workload (MiB read, MiB written: FETCH_SIZE x 2 and WRITE_SIZE x 1 in
 # KiB, the factors that a 1 GiB device copy gives these counters).
-TRAFFIC_MIB = {4: (2 * 12177.6 / 1024, 8085.0 / 1024), 3: (2 * 5069.0 / 1024, 6470.4 / 1024),
-               2: (2 * 4030.5 / 1024, 7760.2 / 1024)}
+TRAFFIC_MIB = {4: (2 * 12222.8 / 1024, 8080.4 / 1024), 3: (2 * 5074.0 / 1024, 6518.6 / 1024),
+               2: (2 * 4029.0 / 1024, 7761.2 / 1024)}
 
 
 def kernel_digest() -> str:
